@@ -1,0 +1,49 @@
+"""The Conjugate Gradient algorithm of Sec. 3.1 (Alg. 1), in FP64 (oracle).
+
+Inputs as in Alg. 1: a product v -> K v (the covariance matrix-vector product), the
+right-hand side b, the initial vector s_0, the threshold epsilon and the maximum number
+of iterations T.  The residual e is the algorithm's recursively updated one, not
+b - K s recomputed.  Reading taken for T: at most T products K d_i inside the loop.
+"""
+import numpy as np
+
+
+def cg_iterates(matvec, b, s0):
+    """Yield (i, s_i, e_i, delta_i) for i = 1, 2, ... following Alg. 1.
+
+    delta_i = s_i - s_{i-1} = alpha_{i-1} d_{i-1} is the increment that the ULISSE
+    series of Sec. 4 is written in.
+    """
+    b = np.asarray(b, dtype=np.float64)
+    s = np.array(s0, dtype=np.float64, copy=True)
+    e = b - matvec(s)
+    d = e.copy()
+    rho = e @ e
+    i = 0
+    while True:
+        q = matvec(d)
+        alpha = rho / (d @ q)
+        delta = alpha * d
+        s = s + delta
+        e = e - alpha * q
+        i += 1
+        yield i, s, e, delta
+        rho_next = e @ e
+        beta = rho_next / rho
+        d = e + beta * d
+        rho = rho_next
+
+
+def cg(matvec, b, s0, eps, max_iter):
+    """Plain Alg. 1: returns (s, iterations, converged, ||e||)."""
+    b = np.asarray(b, dtype=np.float64)
+    s = np.array(s0, dtype=np.float64, copy=True)
+    e0 = b - matvec(s)
+    if np.linalg.norm(e0) < eps:
+        return s, 0, True, np.linalg.norm(e0)
+    for i, s, e, _ in cg_iterates(matvec, b, s0):
+        r = np.linalg.norm(e)
+        if r < eps:
+            return s, i, True, r
+        if i >= max_iter:
+            return s, i, False, r

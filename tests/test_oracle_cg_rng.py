@@ -1,0 +1,119 @@
+"""Pins for oracle.cg (Alg. 1) and oracle.rng (Philox4x64-10 and the draw mappings)."""
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.sparse.linalg as ssl
+import scipy.stats as st
+
+from oracle import cg, gp, rng
+
+
+def _spd(n=30, lam=0.1, seed=0):
+    r = np.random.default_rng(seed)
+    X = r.uniform(size=(n, 2)).astype(np.float32)
+    psi = np.log([1.0, 0.3, 0.3, lam])
+    return gp.kernel_matrix(X, psi), r.standard_normal(n)
+
+
+def test_cg_matches_cholesky_solution():
+    # the paper's solver error: ||s_CG - s_Cholesky|| (Sec. 3.2)
+    K, b = _spd()
+    s, it, ok, res = cg.cg(lambda v: K @ v, b, np.zeros_like(b), 1e-10, 10 * len(b))
+    ref = sla.cho_solve(sla.cho_factor(K), b)
+    assert ok
+    assert np.linalg.norm(s - ref) <= 1e-8 * np.linalg.norm(ref)
+
+
+def test_cg_exact_in_at_most_n_steps_well_conditioned():
+    r = np.random.default_rng(2)
+    A = r.standard_normal((8, 8))
+    K = A @ A.T + 8 * np.eye(8)
+    b = r.standard_normal(8)
+    s, it, ok, _ = cg.cg(lambda v: K @ v, b, np.zeros(8), 1e-10, 100)
+    assert ok and it <= 8
+    np.testing.assert_allclose(K @ s, b, atol=1e-9)
+
+
+def test_cg_matches_scipy_and_recursive_residual():
+    K, b = _spd(40, seed=3)
+    s0 = np.random.default_rng(4).standard_normal(40)
+    for i, s, e, delta in cg.cg_iterates(lambda v: K @ v, b, s0):
+        np.testing.assert_allclose(e, b - K @ s, atol=1e-9)
+        if i == 10:
+            break
+    s, _, ok, _ = cg.cg(lambda v: K @ v, b, s0, 1e-11, 1000)
+    ref, info = ssl.cg(K, b, x0=s0, rtol=1e-13, atol=0, maxiter=1000)
+    assert ok and info == 0
+    np.testing.assert_allclose(s, ref, rtol=1e-8, atol=1e-9)
+
+
+def test_cg_iterations_grow_with_condition_number():
+    # Sec. 3: iterations grow with kappa; here kappa is raised by shrinking the noise
+    its = []
+    for lam in [1.0, 1e-1, 1e-2, 1e-3]:
+        K, b = _spd(60, lam=lam, seed=5)
+        _, it, ok, _ = cg.cg(lambda v: K @ v, b, np.zeros(60), 1e-8, 100000)
+        assert ok
+        its.append(it)
+    assert its == sorted(its) and its[-1] > its[0]
+
+
+def _philox_reference(ctr, key):
+    """Philox4x64-10 round function written from its published definition."""
+    M0, M1 = 0xD2E7470EE14C6C93, 0xCA5A826395121157
+    W0, W1 = 0x9E3779B97F4A7C15, 0xBB67AE8584CAA73B
+    mask = (1 << 64) - 1
+    c, k = list(ctr), list(key)
+    for _ in range(10):
+        p0, p1 = M0 * c[0], M1 * c[2]
+        c = [(p1 >> 64) ^ c[1] ^ k[0], p1 & mask, (p0 >> 64) ^ c[3] ^ k[1], p0 & mask]
+        k = [(k[0] + W0) & mask, (k[1] + W1) & mask]
+    return c
+
+
+def test_philox_known_answers(golden_dir):
+    rows = [l.split() for l in open(os.path.join(golden_dir, "philox4x64_10_kat.txt"))
+            if l.strip() and not l.startswith("#")]
+    assert len(rows) == 2
+    for r in rows:
+        v = [int(x, 16) for x in r]
+        ctr, key, out = v[0:4], v[4:6], v[6:10]
+        got = rng.blocks(key[0], key[1], ctr[1], ctr[2], ctr[3], 1, first_block=ctr[0])
+        assert [int(x) for x in got[0]] == out
+        assert _philox_reference(ctr, key) == out
+
+
+@pytest.mark.parametrize("w1,purpose,step,first", [(0, 1, 0, 0), (5, 2, 9, 3), (17, 3, 2**40, 0)])
+def test_counter_layout_block_by_block(w1, purpose, step, first):
+    got = rng.blocks(123, 456, w1, purpose, step, 5, first_block=first)
+    for b in range(5):
+        ref = _philox_reference([first + b, w1, purpose, step], [123, 456])
+        assert [int(x) for x in got[b]] == ref
+
+
+def test_mappings_distributions():
+    x = rng.words(7, 8, 0, rng.PROBE, 0, 200000)
+    u = rng.uniform_co(x)
+    assert u.min() >= 0.0 and u.max() < 1.0
+    assert st.kstest(u, "uniform").pvalue > 1e-3
+    assert rng.uniform_oc(np.array([0], dtype=np.uint64))[0] == 2.0 ** -53
+    assert rng.uniform_co(np.array([2**64 - 1], dtype=np.uint64))[0] == 1.0 - 2.0 ** -53
+    z = rng.gaussians(7, 8, 1, rng.PROBE, 0, 200000)
+    assert st.kstest(z, "norm").pvalue > 1e-3
+    s = rng.rademacher(x)
+    assert set(np.unique(s)) == {-1.0, 1.0}
+    assert abs(s.mean()) < 5 / np.sqrt(len(s))
+    # Rademacher = top bit; Box-Muller pairs words (0,1) and (2,3)
+    blk = rng.blocks(7, 8, 1, rng.PROBE, 0, 1)[0]
+    za, zb = rng.box_muller(blk[0:1], blk[1:2])
+    np.testing.assert_array_equal(z[:2], [za[0], zb[0]])
+
+
+def test_probe_matrix_columns_are_independent_streams():
+    R = rng.probes(1, 2, 3, 100, 3, kind=0)
+    assert R.shape == (100, 3)
+    np.testing.assert_array_equal(R[:, 1], rng.gaussians(1, 2, 1, rng.PROBE, 3, 100))
+    Rr = rng.probes(1, 2, 3, 100, 2, kind=1)
+    assert set(np.unique(Rr)) == {-1.0, 1.0}

@@ -1,0 +1,179 @@
+/*
+ * ulisse_gp.h -- C ABI of the MI355X (gfx950) library for the hot path of SGLD with the
+ * ULISSE solver for Gaussian-process covariance parameters (Filippone & Engler, ICML 2015).
+ *
+ * Conventions shared by every entry point
+ *   - Array arguments are DEVICE pointers unless stated otherwise.  The caller owns them;
+ *     the library never returns memory it allocated.  The handle owns only its workspace
+ *     (grown on demand with hipMalloc), a pinned host word used to follow the solver,
+ *     and the RNG seed.
+ *   - Work is ordered on `stream` (a hipStream_t passed as void*; NULL = default stream).
+ *     gp_kmv, gp_dkmv, sgld_step, gp_draw_probes and gp_philox only enqueue work.
+ *     ulisse_solve and gp_stoch_grad enqueue work and also wait on the host for the
+ *     solver's per-iteration "systems still running" count, because the length of the
+ *     randomly truncated series is only known on the device; their outputs are still
+ *     delivered in stream order.
+ *   - Inputs X (n x d) are row-major FP32 with leading dimension ldx >= d.  Vectors and
+ *     multi-right-hand-side blocks are column-major: column c of V starts at V + c*ldv.
+ *   - Log-parameters psi are FP64 on the device, in the fixed order
+ *       psi = (log sigma^2, log ell_1, ..., log ell_d, log lambda),  P = d + 2.
+ *   - Validation is synchronous: bad sizes, null or misaligned pointers return GP_EINVAL;
+ *     a failed HIP call or launch returns GP_EDEVICE; in both cases gp_last_error() gives
+ *     a message.  Numerical outcomes of the solver (no convergence within max_iter,
+ *     breakdown) are reported per system in ulisse_sysstat.flags, never as return codes.
+ *   - One handle per host thread.  Limits: 1 <= n <= 2^26, 1 <= d <= 16, 1 <= m <= 64.
+ */
+#ifndef ULISSE_GP_H
+#define ULISSE_GP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gp_handle gp_handle;
+
+typedef enum {
+    GP_OK = 0,
+    GP_EINVAL = -1,
+    GP_ENOMEM = -2,
+    GP_EDEVICE = -3,
+    GP_EUNSUPPORTED = -4
+} gp_status;
+
+/* Arithmetic of the K-tile x V contraction.  GP_FP32: K entries and products in FP32.
+ * GP_BF16_SPLIT_V: K rounded to BF16, V split as V_hi + V_lo (both BF16), FP32
+ * accumulation.  GP_BF16_SPLIT_KV: K and V both split, three BF16 products.  Distances
+ * and exponentials are FP32 in every mode. */
+typedef enum { GP_FP32 = 0, GP_BF16_SPLIT_V = 1, GP_BF16_SPLIT_KV = 2 } gp_precision;
+
+/* Inputs x_1..x_n, row-major FP32, device memory. */
+typedef struct {
+    const float* X;
+    int64_t n;
+    int32_t d;
+    int64_t ldx;
+} gp_data;
+
+/* Create a handle on HIP device `device`.  `seed` is the first Philox key word of every
+ * draw the library makes (probes, ULISSE uniforms, SGLD noise). */
+gp_status gp_create(gp_handle** h, int device, uint64_t seed);
+void gp_destroy(gp_handle* h);
+/* Message of the last failure on this host thread ("" if none).  Owned by the library. */
+const char* gp_last_error(void);
+
+/*
+ * Covariance matrix-vector products (Sec. 3: the CMVP, O(n^2) time and O(n) memory, K is
+ * never stored).  out = K(psi) V with
+ *   K_ij = sigma^2 exp(-1/2 sum_k (x_ik - x_jk)^2 / ell_k^2) + lambda delta_ij
+ * (the covariance function of Sec. 2 in its ARD form).  V is n x m (ldv >= n), out is
+ * n x m (ldo >= n); out must not overlap V.  Tiles of K are rebuilt from X on the fly.
+ */
+gp_status gp_kmv(gp_handle* h, gp_data X, const double* psi, const float* V, int32_t m,
+                 int64_t ldv, float* out, int64_t ldo, gp_precision prec, void* stream);
+
+/*
+ * Products with every derivative of K (used by the exact gradient of Sec. 2.1):
+ *   block j of out (j = 0..d+1) = dK/dpsi_j V, at out + j*block_stride, n x m, ldo >= n,
+ *   dK/dpsi_0 = K_f (signal part), dK/dpsi_k = K_f o (x_.k - x_.k)^2 / ell_k^2,
+ *   dK/dpsi_{d+1} = lambda I.  block_stride >= ldo*m.  FP32 only (prec must be GP_FP32).
+ */
+gp_status gp_dkmv(gp_handle* h, gp_data X, const double* psi, const float* V, int32_t m,
+                  int64_t ldv, float* out, int64_t ldo, int64_t block_stride,
+                  gp_precision prec, void* stream);
+
+/* Parameters of one ULISSE solve (Sec. 3.1 Alg. 1 and Sec. 4). */
+typedef struct {
+    double q;               /* early-stop threshold alpha = q sqrt(n)                      */
+    double rate;            /* weights w_r = exp(rate r); the paper's experiments: 1      */
+    double eps;             /* CG convergence: ||e||_2 < eps (or eps ||b||_2, see below)   */
+    int32_t eps_relative;   /* 1: threshold eps ||b||_2 per system; 0: absolute eps        */
+    int32_t max_iter;       /* T of Alg. 1: at most this many products K d per system     */
+    int32_t two_track_first;/* 1: system 0 keeps two estimates drawn independently        */
+    int32_t reserved;
+    uint64_t rng_stream;    /* second Philox key word                                       */
+    uint64_t rng_counter;   /* step word of the Philox counter                              */
+    gp_precision prec;      /* arithmetic of the products K d                               */
+} ulisse_params;
+
+/* Per-system outcome, written by the device.  J_b = -1 for a single-track system. */
+typedef struct {
+    int32_t l;       /* first iteration with ||e|| below alpha (0: never reached)           */
+    int32_t J_a;     /* last kept tail index of track a                                     */
+    int32_t J_b;     /* last kept tail index of track b                                     */
+    int32_t iters;   /* products K d taken (excluding the warm-start residual)              */
+    double final_res;/* ||e|| of Alg. 1's recursive residual at the last iteration         */
+    uint32_t flags;  /* ULISSE_NOTCONV | ULISSE_BREAKDOWN                                   */
+    uint32_t pad;
+} ulisse_sysstat;
+
+#define ULISSE_NOTCONV 1u    /* max_iter reached before the series ended (biased estimate) */
+#define ULISSE_BREAKDOWN 2u  /* d^T K d <= 0 or a non-finite scalar; the system stopped    */
+
+/*
+ * Unbiased solves K s = b_c for the m columns of B (n x m FP32, ldb >= n) by the ULISSE
+ * series over one CG run per system (Sec. 4).  S0 (n x m FP64, ld n) is the warm start,
+ * NULL for zero.  Output S_tilde is n x (m + two_track_first) FP64 with ld n: with
+ * two_track_first, columns 0 and 1 are the two estimates for system 0 and column c+1
+ * holds system c >= 1; otherwise column c holds system c.  S_cg (nullable, n x m FP64,
+ * ld n) receives each system's last CG iterate, the vector to warm-start a later solve
+ * with.  stats: m entries, device memory (nullable).
+ * The u_j of system c, track t are Philox words j of key (seed, rng_stream) and counter
+ * (j/4, 2c+t, 2, rng_counter).
+ */
+gp_status ulisse_solve(gp_handle* h, gp_data X, const double* psi, const float* B,
+                       int32_t m, int64_t ldb, const double* S0, const ulisse_params* params,
+                       double* S_tilde, double* S_cg, ulisse_sysstat* stats, void* stream);
+
+/*
+ * One unbiased estimate of the gradient of log p(y | psi, X) with respect to psi
+ * (eq. gradient:unbiased with the two-estimate quadratic term of Sec. 4.1):
+ *   g_j = 1/2 s_a^T dK_j s_b - 1/(2 N_r) sum_c r_c^T dK_j s_c.
+ * y: n FP32.  R: n x n_probes FP32 (ld n), or NULL to draw the probes with key
+ * (seed, rng_stream) and counter (i/4, c, 1, rng_counter) -- probe_kind 0 Gaussian
+ * (Box-Muller), 1 Rademacher.  S_warm (nullable, n x (1 + n_probes) FP64, ld n): warm
+ * starts in, last CG iterates out; when R is NULL only its column 0 (y) is used as a warm
+ * start, because freshly drawn probes make the old probe solutions useless.
+ * g: d + 2 FP64 (device).  stats: 1 + n_probes entries (nullable).
+ */
+gp_status gp_stoch_grad(gp_handle* h, gp_data X, const double* psi, const float* y,
+                        const float* R, int32_t n_probes, int32_t probe_kind,
+                        const ulisse_params* params, double* S_warm, double* g,
+                        ulisse_sysstat* stats, void* stream);
+
+/* Prior on psi: kind 0 flat; kind 1 psi_j ~ N(a_j, b_j^2); kind 2 exp(psi_j) ~ Gamma(shape
+ * a_j, rate b_j) with the Jacobian of the log transform.  a, b: P FP64 device (NULL for
+ * kind 0). */
+typedef struct {
+    int32_t kind;
+    int32_t reserved;
+    const double* a;
+    const double* b;
+} gp_prior;
+
+/*
+ * SGLD update of Sec. 2.1, in place on psi (P = d + 2 FP64 device):
+ *   psi += eps_t/2 M (g + grad log p(psi)) + sqrt(eps_t) L xi,   M = L L^T,
+ * with L = M_chol (P x P lower-triangular, column-major FP64 device; NULL = identity) and
+ * xi standard normals from key (seed, rng_stream), counter (i/4, 0, 3, rng_counter).
+ */
+gp_status sgld_step(gp_handle* h, int32_t P, double* psi, const double* g,
+                    const gp_prior* prior, const double* M_chol, double eps_t,
+                    uint64_t rng_stream, uint64_t rng_counter, void* stream);
+
+/* Probe matrix R (n x n_probes FP32, ld ldr >= n) as drawn by gp_stoch_grad. */
+gp_status gp_draw_probes(gp_handle* h, int64_t n, int32_t n_probes, int32_t probe_kind,
+                         uint64_t rng_stream, uint64_t rng_counter, float* R, int64_t ldr,
+                         void* stream);
+
+/* Raw Philox4x64-10 blocks (Salmon et al., SC 2011): out[4b + w] = word w of the block at
+ * counter (first_block + b, w1, w2, w3) with key (k0, k1).  out: 4 * nblocks uint64 device. */
+gp_status gp_philox(uint64_t k0, uint64_t k1, uint64_t first_block, uint64_t w1, uint64_t w2,
+                    uint64_t w3, int64_t nblocks, uint64_t* out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ULISSE_GP_H */

@@ -1,0 +1,274 @@
+"""ctypes binding of libulisse_gp.so with the C ABI's names (argument marshalling only).
+
+Device arrays are torch tensors on a ROCm device; every computation runs in the HIP
+library.  Conventions of the Python side:
+  * X is an (n, d) float32 tensor with unit stride along d (row-major, ldx = X.stride(0));
+  * a block of m vectors of length n is an (n, m) tensor with unit stride along n
+    (column-major, ld = stride(1)) -- ``colmajor(n, m)`` allocates one; a single vector
+    may be a 1-D tensor;
+  * psi and g are float64 device tensors; the stream is torch's current stream unless
+    one is given.
+If the shared library has not been built, every call raises: there is no fallback.
+"""
+import ctypes
+import os
+import re
+from ctypes import POINTER, Structure, c_char_p, c_double, c_int, c_int32, c_int64, c_uint32, c_uint64, c_void_p
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libulisse_gp.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "ulisse_gp.h")
+
+GP_OK, GP_EINVAL, GP_ENOMEM, GP_EDEVICE, GP_EUNSUPPORTED = 0, -1, -2, -3, -4
+GP_FP32, GP_BF16_SPLIT_V, GP_BF16_SPLIT_KV = 0, 1, 2
+ULISSE_NOTCONV, ULISSE_BREAKDOWN = 1, 2
+PROBE_GAUSSIAN, PROBE_RADEMACHER = 0, 1
+
+
+class gp_data(Structure):
+    _fields_ = [("X", c_void_p), ("n", c_int64), ("d", c_int32), ("ldx", c_int64)]
+
+
+class ulisse_params(Structure):
+    _fields_ = [("q", c_double), ("rate", c_double), ("eps", c_double),
+                ("eps_relative", c_int32), ("max_iter", c_int32),
+                ("two_track_first", c_int32), ("reserved", c_int32),
+                ("rng_stream", c_uint64), ("rng_counter", c_uint64), ("prec", c_int)]
+
+
+class ulisse_sysstat(Structure):
+    _fields_ = [("l", c_int32), ("J_a", c_int32), ("J_b", c_int32), ("iters", c_int32),
+                ("final_res", c_double), ("flags", c_uint32), ("pad", c_uint32)]
+
+
+class gp_prior(Structure):
+    _fields_ = [("kind", c_int32), ("reserved", c_int32), ("a", c_void_p), ("b", c_void_p)]
+
+
+SYSSTAT_BYTES = ctypes.sizeof(ulisse_sysstat)
+
+_lib = None
+
+
+class LibraryMissing(RuntimeError):
+    pass
+
+
+class GPError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"status {status}: {msg}")
+        self.status = status
+
+
+def lib():
+    """Load the shared library once; raise if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise LibraryMissing(f"{LIB_PATH} is missing: build it with `python -m paper_1501_05427_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    L.gp_last_error.restype = c_char_p
+    L.gp_last_error.argtypes = []
+    L.gp_create.restype = c_int
+    L.gp_create.argtypes = [POINTER(c_void_p), c_int, c_uint64]
+    L.gp_destroy.restype = None
+    L.gp_destroy.argtypes = [c_void_p]
+    L.gp_kmv.restype = c_int
+    L.gp_kmv.argtypes = [c_void_p, gp_data, c_void_p, c_void_p, c_int32, c_int64, c_void_p, c_int64, c_int, c_void_p]
+    L.gp_dkmv.restype = c_int
+    L.gp_dkmv.argtypes = [c_void_p, gp_data, c_void_p, c_void_p, c_int32, c_int64, c_void_p, c_int64, c_int64, c_int, c_void_p]
+    L.ulisse_solve.restype = c_int
+    L.ulisse_solve.argtypes = [c_void_p, gp_data, c_void_p, c_void_p, c_int32, c_int64, c_void_p,
+                               POINTER(ulisse_params), c_void_p, c_void_p, c_void_p, c_void_p]
+    L.gp_stoch_grad.restype = c_int
+    L.gp_stoch_grad.argtypes = [c_void_p, gp_data, c_void_p, c_void_p, c_void_p, c_int32, c_int32,
+                                POINTER(ulisse_params), c_void_p, c_void_p, c_void_p, c_void_p]
+    L.sgld_step.restype = c_int
+    L.sgld_step.argtypes = [c_void_p, c_int32, c_void_p, c_void_p, POINTER(gp_prior), c_void_p,
+                            c_double, c_uint64, c_uint64, c_void_p]
+    L.gp_draw_probes.restype = c_int
+    L.gp_draw_probes.argtypes = [c_void_p, c_int64, c_int32, c_int32, c_uint64, c_uint64, c_void_p, c_int64, c_void_p]
+    L.gp_philox.restype = c_int
+    L.gp_philox.argtypes = [c_uint64, c_uint64, c_uint64, c_uint64, c_uint64, c_uint64, c_int64, c_void_p, c_void_p]
+    _lib = L
+    return L
+
+
+def header_functions():
+    """Names of the functions declared in include/ulisse_gp.h."""
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*([a-z_][a-z0-9_]*)\s*\(",
+                                 src, flags=re.M)))
+
+
+def _check(status):
+    if status != GP_OK:
+        raise GPError(status, lib().gp_last_error().decode())
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        return c_void_p(torch.cuda.current_stream().cuda_stream)
+    return c_void_p(stream)
+
+
+def _ptr(t):
+    return c_void_p(0 if t is None else t.data_ptr())
+
+
+def _ld(t, n):
+    """Leading dimension of a column-major (n, m) tensor or a vector."""
+    if t.dim() == 1:
+        return n
+    if t.shape[1] > 1 and t.stride(0) != 1:
+        raise ValueError("blocks of vectors must be column-major: (n, m) with stride (1, ld)")
+    return t.stride(1) if t.shape[1] > 1 else max(n, t.stride(1))
+
+
+def _cols(t):
+    return 1 if t.dim() == 1 else t.shape[1]
+
+
+def colmajor(n, m, dtype=None, device="cuda"):
+    import torch
+    return torch.zeros((m, n), dtype=dtype or torch.float32, device=device).t()
+
+
+def _data(X):
+    if X.dim() != 2 or X.stride(1) != 1:
+        raise ValueError("X must be an (n, d) tensor with unit stride along d")
+    return gp_data(X.data_ptr(), X.shape[0], X.shape[1], X.stride(0))
+
+
+class Handle:
+    """gp_create / gp_destroy."""
+
+    def __init__(self, device=0, seed=0):
+        self.ptr = c_void_p()
+        _check(lib().gp_create(ctypes.byref(self.ptr), int(device), int(seed)))
+        self.seed = int(seed)
+
+    def close(self):
+        if self.ptr:
+            lib().gp_destroy(self.ptr)
+            self.ptr = c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def gp_create(device=0, seed=0):
+    return Handle(device, seed)
+
+
+def gp_destroy(h):
+    h.close()
+
+
+def gp_last_error():
+    return lib().gp_last_error().decode()
+
+
+def gp_kmv(h, X, psi, V, out=None, prec=GP_FP32, stream=None):
+    n = X.shape[0]
+    m = _cols(V)
+    if out is None:
+        out = colmajor(n, m, device=V.device) if V.dim() == 2 else V.new_zeros(n)
+    _check(lib().gp_kmv(h.ptr, _data(X), _ptr(psi), _ptr(V), m, _ld(V, n), _ptr(out), _ld(out, n),
+                        int(prec), _stream(stream)))
+    return out
+
+
+def gp_dkmv(h, X, psi, V, out=None, prec=GP_FP32, stream=None):
+    """Returns a (d + 2, m, n) tensor: block j column c = (dK/dpsi_j V)[:, c]."""
+    import torch
+    n, d = X.shape
+    m = _cols(V)
+    if out is None:
+        out = torch.zeros((d + 2, m, n), dtype=torch.float32, device=V.device)
+    _check(lib().gp_dkmv(h.ptr, _data(X), _ptr(psi), _ptr(V), m, _ld(V, n), _ptr(out), out.stride(1),
+                         out.stride(0), int(prec), _stream(stream)))
+    return out
+
+
+def make_params(q=1.0, rate=1.0, eps=1e-6, eps_relative=1, max_iter=1000, two_track_first=0,
+                rng_stream=0, rng_counter=0, prec=GP_FP32):
+    return ulisse_params(q, rate, eps, eps_relative, max_iter, two_track_first, 0,
+                         rng_stream, rng_counter, prec)
+
+
+def stats_tensor(m, device="cuda"):
+    import torch
+    return torch.zeros(m * SYSSTAT_BYTES, dtype=torch.uint8, device=device)
+
+
+def decode_stats(raw):
+    """Device stats buffer -> list of dicts (copies to the host)."""
+    b = bytes(raw.cpu().numpy().tobytes())
+    out = []
+    for k in range(len(b) // SYSSTAT_BYTES):
+        s = ulisse_sysstat.from_buffer_copy(b[k * SYSSTAT_BYTES:(k + 1) * SYSSTAT_BYTES])
+        out.append(dict(l=s.l, J_a=s.J_a, J_b=s.J_b, iters=s.iters, final_res=s.final_res, flags=s.flags))
+    return out
+
+
+def ulisse_solve(h, X, psi, B, params, S0=None, S_tilde=None, S_cg=None, stats=None, stream=None):
+    import torch
+    n = X.shape[0]
+    m = _cols(B)
+    mt = m + (1 if params.two_track_first else 0)
+    if S_tilde is None:
+        S_tilde = torch.zeros((mt, n), dtype=torch.float64, device=B.device).t()
+    if stats is None:
+        stats = stats_tensor(m, B.device)
+    _check(lib().ulisse_solve(h.ptr, _data(X), _ptr(psi), _ptr(B), m, _ld(B, n), _ptr(S0),
+                              ctypes.byref(params), _ptr(S_tilde), _ptr(S_cg), _ptr(stats),
+                              _stream(stream)))
+    return S_tilde, stats
+
+
+def gp_stoch_grad(h, X, psi, y, params, R=None, n_probes=None, probe_kind=PROBE_GAUSSIAN,
+                  S_warm=None, g=None, stats=None, stream=None):
+    import torch
+    d = X.shape[1]
+    if R is not None:
+        n_probes = _cols(R)
+    if g is None:
+        g = torch.zeros(d + 2, dtype=torch.float64, device=y.device)
+    if stats is None:
+        stats = stats_tensor(1 + n_probes, y.device)
+    _check(lib().gp_stoch_grad(h.ptr, _data(X), _ptr(psi), _ptr(y), _ptr(R), int(n_probes),
+                               int(probe_kind), ctypes.byref(params), _ptr(S_warm), _ptr(g),
+                               _ptr(stats), _stream(stream)))
+    return g, stats
+
+
+def sgld_step(h, psi, g, eps_t, rng_stream=0, rng_counter=0, prior_kind=0, prior_a=None,
+              prior_b=None, M_chol=None, stream=None):
+    pr = gp_prior(int(prior_kind), 0, 0 if prior_a is None else prior_a.data_ptr(),
+                  0 if prior_b is None else prior_b.data_ptr())
+    _check(lib().sgld_step(h.ptr, psi.shape[0], _ptr(psi), _ptr(g), ctypes.byref(pr), _ptr(M_chol),
+                           float(eps_t), int(rng_stream), int(rng_counter), _stream(stream)))
+    return psi
+
+
+def gp_draw_probes(h, n, n_probes, probe_kind, rng_stream, rng_counter, R=None, stream=None):
+    if R is None:
+        R = colmajor(n, n_probes)
+    _check(lib().gp_draw_probes(h.ptr, n, n_probes, probe_kind, rng_stream, rng_counter, _ptr(R),
+                                _ld(R, n), _stream(stream)))
+    return R
+
+
+def gp_philox(k0, k1, first_block, w1, w2, w3, nblocks, out=None, stream=None):
+    import torch
+    if out is None:
+        out = torch.zeros(4 * nblocks, dtype=torch.int64, device="cuda")
+    _check(lib().gp_philox(k0, k1, first_block, w1, w2, w3, nblocks, _ptr(out), _stream(stream)))
+    return out

@@ -1,0 +1,405 @@
+// C ABI of the library: argument validation, the per-handle workspace and the host-side
+// orchestration of the kernels (covariance products, ULISSE iterations, gradient
+// assembly, SGLD update).  Nothing here computes on the host beyond launch shapes.
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <algorithm>
+
+#include "gp_common.h"
+#include "internal.h"
+#include "solver.h"
+#include "ulisse_gp.h"
+
+using namespace gpk;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+gp_status fail(gp_status st, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return st;
+}
+
+#define GP_HIP(expr)                                                                       \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess) return fail(GP_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+#define GP_CHECK(cond, ...)                                  \
+    do {                                                     \
+        if (!(cond)) return fail(GP_EINVAL, __VA_ARGS__);    \
+    } while (0)
+
+enum Slot {
+    kSlotZ, kSlotKP, kSlotVP, kSlotPart, kSlotQ, kSlotS, kSlotE, kSlotD, kSlotP1, kSlotP2,
+    kSlotCounter, kSlotActive, kSlotState, kSlotStats, kSlotR, kSlotB, kSlotSt, kSlotS0,
+    kSlotA32, kSlotB32, kSlotGpart, kNumSlots
+};
+
+bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+}  // namespace
+
+struct gp_handle {
+    int device = 0;
+    uint64_t seed = 0;
+    void* buf[kNumSlots] = {};
+    size_t bytes[kNumSlots] = {};
+    int* pinned = nullptr;  // two words: systems still running after iteration it (it % 2)
+    hipEvent_t ev[2] = {nullptr, nullptr};
+};
+
+namespace {
+
+// Grow-only workspace slot; growing waits for the device so no queued kernel still uses
+// the old buffer.  Fresh buffers are zeroed.
+gp_status ensure(gp_handle* h, int slot, size_t bytes, void** out) {
+    bytes = std::max<size_t>(bytes, 256);
+    if (h->bytes[slot] < bytes) {
+        GP_HIP(hipDeviceSynchronize());
+        if (h->buf[slot]) GP_HIP(hipFree(h->buf[slot]));
+        h->buf[slot] = nullptr;
+        h->bytes[slot] = 0;
+        const size_t rb = (size_t)round_up((int64_t)bytes, 1 << 16);
+        if (hipMalloc(&h->buf[slot], rb) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(GP_ENOMEM, "workspace allocation of %zu bytes failed", rb);
+        }
+        GP_HIP(hipMemset(h->buf[slot], 0, rb));
+        h->bytes[slot] = rb;
+    }
+    *out = h->buf[slot];
+    return GP_OK;
+}
+
+template <typename T>
+gp_status ws(gp_handle* h, int slot, size_t count, T** out) {
+    void* p = nullptr;
+    gp_status st = ensure(h, slot, count * sizeof(T), &p);
+    *out = static_cast<T*>(p);
+    return st;
+}
+
+#define GP_TRY(expr)                    \
+    do {                                \
+        gp_status s_ = (expr);          \
+        if (s_ != GP_OK) return s_;     \
+    } while (0)
+
+gp_status check_handle(gp_handle* h) {
+    GP_CHECK(h != nullptr, "null handle");
+    GP_HIP(hipSetDevice(h->device));
+    return GP_OK;
+}
+
+gp_status check_data(const gp_data& X) {
+    GP_CHECK(X.X != nullptr, "X is null");
+    GP_CHECK(aligned(X.X, 4), "X must be 4-byte aligned");
+    GP_CHECK(X.n >= 1 && X.n <= (int64_t(1) << 26), "n = %lld outside [1, 2^26]", (long long)X.n);
+    GP_CHECK(X.d >= 1 && X.d <= kMaxD, "d = %d outside [1, 16]", X.d);
+    GP_CHECK(X.ldx >= X.d, "ldx = %lld < d", (long long)X.ldx);
+    return GP_OK;
+}
+
+gp_status check_params(const ulisse_params* p) {
+    GP_CHECK(p != nullptr, "params is null");
+    GP_CHECK(p->q >= 0.0, "q must be >= 0");
+    GP_CHECK(p->rate > 0.0, "rate must be > 0");
+    GP_CHECK(p->eps >= 0.0, "eps must be >= 0");
+    GP_CHECK(p->max_iter >= 1, "max_iter must be >= 1");
+    GP_CHECK(p->prec == GP_FP32 || p->prec == GP_BF16_SPLIT_V || p->prec == GP_BF16_SPLIT_KV,
+             "unknown precision");
+    return GP_OK;
+}
+
+// psi -> KParams and scaled inputs in the workspace.
+gp_status prep(gp_handle* h, const gp_data& X, const double* psi, int64_t n_pad, float** Z,
+               KParams** kp, hipStream_t s) {
+    GP_CHECK(psi != nullptr && aligned(psi, 8), "psi must be a non-null 8-byte aligned pointer");
+    GP_TRY(ws(h, kSlotZ, (size_t)n_pad * dpad(X.d), Z));
+    GP_TRY(ws(h, kSlotKP, 1, kp));
+    GP_HIP(launch_prep(X.X, X.n, X.d, X.ldx, psi, *Z, n_pad, *kp, s));
+    return GP_OK;
+}
+
+// The ULISSE iterations for m systems whose right-hand sides are B (ld ldb); Z and kp
+// already prepared.
+gp_status solve_core(gp_handle* h, int64_t n, int d, const float* Z, const KParams* kp,
+                     const float* B, int64_t ldb, int m, const double* S0,
+                     const ulisse_params& p, double* St, double* S_cg, ulisse_sysstat* stats,
+                     hipStream_t s) {
+    if (p.prec != GP_FP32) return fail(GP_EUNSUPPORTED, "only GP_FP32 products are available in the solver");
+    const KmvShape sh = kmv_shape(n, d, m, p.prec);
+    const int64_t n_pad = sh.n_pad;
+    SolverArgs a{};
+    a.n = n;
+    a.n_pad = n_pad;
+    a.m = m;
+    a.mp = sh.mp;
+    a.split = sh.split;
+    a.nb = (int)((n + kWG - 1) / kWG);
+    a.ldb = ldb;
+    a.B = B;
+    a.S0 = S0;
+    float* kpart = nullptr;
+    GP_TRY(ws(h, kSlotPart, (size_t)sh.split * sh.mp * n_pad, &kpart));
+    GP_TRY(ws(h, kSlotQ, (size_t)n_pad * m, &a.Q));
+    GP_TRY(ws(h, kSlotS, (size_t)n_pad * m, &a.S));
+    GP_TRY(ws(h, kSlotE, (size_t)n_pad * m, &a.E));
+    GP_TRY(ws(h, kSlotD, (size_t)n_pad * sh.mp, &a.D));
+    GP_TRY(ws(h, kSlotP1, (size_t)a.nb * m, &a.part));
+    GP_TRY(ws(h, kSlotP2, (size_t)a.nb * m, &a.part2));
+    GP_TRY(ws(h, kSlotCounter, 1, &a.counter));
+    GP_TRY(ws(h, kSlotActive, 1, &a.n_active));
+    GP_TRY(ws(h, kSlotState, (size_t)m, &a.state));
+    if (stats == nullptr) GP_TRY(ws(h, kSlotStats, (size_t)m, &stats));
+    a.St = St;
+    a.kpart = kpart;
+    a.kp = kp;
+    a.stats = stats;
+    a.q = p.q;
+    a.rate = p.rate;
+    a.eps = p.eps;
+    a.eps_relative = p.eps_relative;
+    a.max_iter = p.max_iter;
+    a.two_track = p.two_track_first ? 1 : 0;
+    a.seed = h->seed;
+    a.rng_stream = p.rng_stream;
+    a.rng_counter = p.rng_counter;
+
+    GP_HIP(hipMemsetAsync(a.D, 0, (size_t)n_pad * sh.mp * sizeof(float), s));
+    const int warm = S0 != nullptr;
+    if (warm) {
+        GP_HIP(launch_pack_f64(S0, n, m, a.D, n_pad, s));
+        GP_HIP(launch_kmv_partials(sh, d, Z, a.D, kp, kpart, nullptr, p.prec, s));
+    }
+    GP_HIP(solver_init(a, warm, s));
+    for (int it = 0; it <= p.max_iter; ++it) {
+        GP_HIP(launch_kmv_partials(sh, d, Z, a.D, kp, kpart, a.n_active, p.prec, s));
+        GP_HIP(solver_reduce(a, s));
+        GP_HIP(solver_update(a, s));
+        GP_HIP(solver_direction(a, s));
+        GP_HIP(hipMemcpyAsync(h->pinned + (it & 1), a.n_active, sizeof(int), hipMemcpyDeviceToHost, s));
+        GP_HIP(hipEventRecord(h->ev[it & 1], s));
+        if (it >= 1) {
+            GP_HIP(hipEventSynchronize(h->ev[(it - 1) & 1]));
+            if (h->pinned[(it - 1) & 1] == 0) break;
+        }
+    }
+    if (S_cg != nullptr) GP_HIP(solver_copy_s(a, S_cg, s));
+    return GP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* gp_last_error(void) { return g_err; }
+
+gp_status gp_create(gp_handle** out, int device, uint64_t seed) {
+    GP_CHECK(out != nullptr, "null output pointer");
+    int count = 0;
+    GP_HIP(hipGetDeviceCount(&count));
+    GP_CHECK(device >= 0 && device < count, "device %d not present (%d devices)", device, count);
+    GP_HIP(hipSetDevice(device));
+    gp_handle* h = new gp_handle();
+    h->device = device;
+    h->seed = seed;
+    if (hipHostMalloc((void**)&h->pinned, 2 * sizeof(int), hipHostMallocDefault) != hipSuccess ||
+        hipEventCreateWithFlags(&h->ev[0], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&h->ev[1], hipEventDisableTiming) != hipSuccess) {
+        gp_destroy(h);
+        return fail(GP_EDEVICE, "handle setup failed: %s", hipGetErrorString(hipGetLastError()));
+    }
+    h->pinned[0] = h->pinned[1] = 1;
+    *out = h;
+    return GP_OK;
+}
+
+void gp_destroy(gp_handle* h) {
+    if (!h) return;
+    (void)hipSetDevice(h->device);
+    (void)hipDeviceSynchronize();
+    for (int i = 0; i < kNumSlots; ++i)
+        if (h->buf[i]) (void)hipFree(h->buf[i]);
+    for (int i = 0; i < 2; ++i)
+        if (h->ev[i]) (void)hipEventDestroy(h->ev[i]);
+    if (h->pinned) (void)hipHostFree(h->pinned);
+    delete h;
+}
+
+gp_status gp_kmv(gp_handle* h, gp_data X, const double* psi, const float* V, int32_t m,
+                 int64_t ldv, float* out, int64_t ldo, gp_precision prec, void* stream) {
+    GP_TRY(check_handle(h));
+    GP_TRY(check_data(X));
+    GP_CHECK(m >= 1 && m <= kMaxSys, "m = %d outside [1, 64]", m);
+    GP_CHECK(V != nullptr && out != nullptr && aligned(V, 4) && aligned(out, 4), "V/out null or misaligned");
+    GP_CHECK(ldv >= X.n && ldo >= X.n, "ldv and ldo must be >= n");
+    if (prec != GP_FP32) return fail(GP_EUNSUPPORTED, "precision mode %d not available", (int)prec);
+    hipStream_t s = (hipStream_t)stream;
+    const KmvShape sh = kmv_shape(X.n, X.d, m, prec);
+    float* Z;
+    KParams* kp;
+    GP_TRY(prep(h, X, psi, sh.n_pad, &Z, &kp, s));
+    float *Vp, *part;
+    GP_TRY(ws(h, kSlotVP, (size_t)sh.n_pad * sh.mp, &Vp));
+    GP_TRY(ws(h, kSlotPart, (size_t)sh.split * sh.mp * sh.n_pad, &part));
+    GP_HIP(launch_pack(V, X.n, m, ldv, Vp, sh.n_pad, sh.mp, s));
+    GP_HIP(launch_kmv_partials(sh, X.d, Z, Vp, kp, part, nullptr, prec, s));
+    GP_HIP(launch_kmv_reduce(sh, part, Vp, kp, X.n, m, out, ldo, s));
+    return GP_OK;
+}
+
+gp_status gp_dkmv(gp_handle* h, gp_data X, const double* psi, const float* V, int32_t m,
+                  int64_t ldv, float* out, int64_t ldo, int64_t block_stride,
+                  gp_precision prec, void* stream) {
+    GP_TRY(check_handle(h));
+    GP_TRY(check_data(X));
+    GP_CHECK(m >= 1 && m <= kMaxSys, "m = %d outside [1, 64]", m);
+    GP_CHECK(V != nullptr && out != nullptr && aligned(V, 4) && aligned(out, 4), "V/out null or misaligned");
+    GP_CHECK(ldv >= X.n && ldo >= X.n, "ldv and ldo must be >= n");
+    GP_CHECK(block_stride >= ldo * m, "block_stride must be >= ldo * m");
+    if (prec != GP_FP32) return fail(GP_EUNSUPPORTED, "gp_dkmv computes in GP_FP32 only");
+    hipStream_t s = (hipStream_t)stream;
+    const KmvShape sh = dkmv_shape(X.n, X.d, m);
+    float* Z;
+    KParams* kp;
+    GP_TRY(prep(h, X, psi, sh.n_pad, &Z, &kp, s));
+    const int mtot = (int)round_up(m, sh.mp);
+    float *Vp, *part;
+    GP_TRY(ws(h, kSlotVP, (size_t)sh.n_pad * mtot, &Vp));
+    GP_TRY(ws(h, kSlotPart, dkmv_part_floats(sh, X.d), &part));
+    GP_HIP(launch_pack(V, X.n, m, ldv, Vp, sh.n_pad, mtot, s));
+    GP_HIP(launch_dkmv(sh, X.d, Z, Vp, kp, part, X.n, m, out, ldo, block_stride, s));
+    return GP_OK;
+}
+
+gp_status ulisse_solve(gp_handle* h, gp_data X, const double* psi, const float* B,
+                       int32_t m, int64_t ldb, const double* S0, const ulisse_params* params,
+                       double* S_tilde, double* S_cg, ulisse_sysstat* stats, void* stream) {
+    GP_TRY(check_handle(h));
+    GP_TRY(check_data(X));
+    GP_TRY(check_params(params));
+    GP_CHECK(m >= 1 && m + (params->two_track_first ? 1 : 0) <= kMaxSys, "too many systems");
+    GP_CHECK(B != nullptr && aligned(B, 4) && ldb >= X.n, "B null, misaligned or ldb < n");
+    GP_CHECK(S_tilde != nullptr && aligned(S_tilde, 8), "S_tilde null or misaligned");
+    GP_CHECK(S0 == nullptr || aligned(S0, 8), "S0 misaligned");
+    GP_CHECK(S_cg == nullptr || aligned(S_cg, 8), "S_cg misaligned");
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n_pad = round_up(X.n, kRowPad);
+    float* Z;
+    KParams* kp;
+    GP_TRY(prep(h, X, psi, n_pad, &Z, &kp, s));
+    return solve_core(h, X.n, X.d, Z, kp, B, ldb, m, S0, *params, S_tilde, S_cg, stats, s);
+}
+
+gp_status gp_stoch_grad(gp_handle* h, gp_data X, const double* psi, const float* y,
+                        const float* R, int32_t n_probes, int32_t probe_kind,
+                        const ulisse_params* params, double* S_warm, double* g,
+                        ulisse_sysstat* stats, void* stream) {
+    GP_TRY(check_handle(h));
+    GP_TRY(check_data(X));
+    GP_TRY(check_params(params));
+    GP_CHECK(n_probes >= 1 && n_probes + 2 <= kMaxSys, "n_probes = %d outside [1, 62]", n_probes);
+    GP_CHECK(probe_kind == 0 || probe_kind == 1, "probe_kind must be 0 or 1");
+    GP_CHECK(y != nullptr && aligned(y, 4), "y null or misaligned");
+    GP_CHECK(R == nullptr || aligned(R, 4), "R misaligned");
+    GP_CHECK(g != nullptr && aligned(g, 8), "g null or misaligned");
+    GP_CHECK(S_warm == nullptr || aligned(S_warm, 8), "S_warm misaligned");
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n = X.n;
+    const int d = X.d;
+    const int m = 1 + n_probes;
+    const int64_t n_pad = round_up(n, kRowPad);
+    float* Z;
+    KParams* kp;
+    GP_TRY(prep(h, X, psi, n_pad, &Z, &kp, s));
+
+    float* Bm;
+    GP_TRY(ws(h, kSlotB, (size_t)n * m, &Bm));
+    GP_HIP(hipMemcpyAsync(Bm, y, n * sizeof(float), hipMemcpyDeviceToDevice, s));
+    if (R == nullptr) {
+        GP_HIP(launch_probes(n, n_probes, probe_kind, h->seed, params->rng_stream,
+                             params->rng_counter, Bm + n, n, s));
+    } else {
+        GP_HIP(hipMemcpyAsync(Bm + n, R, (size_t)n * n_probes * sizeof(float), hipMemcpyDeviceToDevice, s));
+    }
+    const float* Rp = Bm + n;
+
+    const double* S0 = nullptr;
+    if (S_warm != nullptr) {
+        if (R == nullptr) {
+            double* S0b;
+            GP_TRY(ws(h, kSlotS0, (size_t)n * m, &S0b));
+            GP_HIP(hipMemsetAsync(S0b, 0, (size_t)n * m * sizeof(double), s));
+            GP_HIP(hipMemcpyAsync(S0b, S_warm, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+            S0 = S0b;
+        } else {
+            S0 = S_warm;
+        }
+    }
+    double* St;
+    GP_TRY(ws(h, kSlotSt, (size_t)n * (m + 1), &St));
+    ulisse_params p = *params;
+    p.two_track_first = 1;
+    GP_TRY(solve_core(h, n, d, Z, kp, Bm, n, m, S0, p, St, S_warm, stats, s));
+
+    const DquadShape dq = dquad_shape(n, d, m);
+    float *A32, *B32;
+    double* gpart;
+    GP_TRY(ws(h, kSlotA32, (size_t)dq.n_pad * dq.mq4, &A32));
+    GP_TRY(ws(h, kSlotB32, (size_t)dq.n_pad * dq.mq4, &B32));
+    GP_TRY(ws(h, kSlotGpart, (size_t)dq.nwg * (d + 1), &gpart));
+    GP_HIP(launch_build_ab(St, Rp, n, n, n_probes, A32, B32, dq.n_pad, dq.mq4, s));
+    GP_HIP(launch_dquad(dq, d, Z, A32, B32, kp, gpart, s));
+    GP_HIP(launch_grad_finish(St, Rp, n, n, n_probes, gpart, dq.nwg, d, kp, g, s));
+    return GP_OK;
+}
+
+gp_status sgld_step(gp_handle* h, int32_t P, double* psi, const double* g,
+                    const gp_prior* prior, const double* M_chol, double eps_t,
+                    uint64_t rng_stream, uint64_t rng_counter, void* stream) {
+    GP_TRY(check_handle(h));
+    GP_CHECK(P >= 3 && P <= kMaxP, "P = %d outside [3, 18]", P);
+    GP_CHECK(psi != nullptr && g != nullptr && aligned(psi, 8) && aligned(g, 8), "psi/g null or misaligned");
+    GP_CHECK(eps_t >= 0.0, "eps_t must be >= 0");
+    int kind = prior ? prior->kind : 0;
+    GP_CHECK(kind >= 0 && kind <= 2, "prior kind must be 0, 1 or 2");
+    const double* pa = prior ? prior->a : nullptr;
+    const double* pb = prior ? prior->b : nullptr;
+    GP_CHECK(kind == 0 || (pa != nullptr && pb != nullptr), "prior a/b required for kind %d", kind);
+    GP_HIP(launch_sgld(P, psi, g, kind, pa, pb, M_chol, eps_t, h->seed, rng_stream, rng_counter,
+                       (hipStream_t)stream));
+    return GP_OK;
+}
+
+gp_status gp_draw_probes(gp_handle* h, int64_t n, int32_t n_probes, int32_t probe_kind,
+                         uint64_t rng_stream, uint64_t rng_counter, float* R, int64_t ldr,
+                         void* stream) {
+    GP_TRY(check_handle(h));
+    GP_CHECK(n >= 1 && n_probes >= 1, "n and n_probes must be >= 1");
+    GP_CHECK(probe_kind == 0 || probe_kind == 1, "probe_kind must be 0 or 1");
+    GP_CHECK(R != nullptr && aligned(R, 4) && ldr >= n, "R null, misaligned or ldr < n");
+    GP_HIP(launch_probes(n, n_probes, probe_kind, h->seed, rng_stream, rng_counter, R, ldr,
+                         (hipStream_t)stream));
+    return GP_OK;
+}
+
+gp_status gp_philox(uint64_t k0, uint64_t k1, uint64_t first_block, uint64_t w1, uint64_t w2,
+                    uint64_t w3, int64_t nblocks, uint64_t* out, void* stream) {
+    GP_CHECK(nblocks >= 0, "nblocks must be >= 0");
+    GP_CHECK(out != nullptr && aligned(out, 8), "out null or misaligned");
+    if (nblocks == 0) return GP_OK;
+    GP_HIP(launch_philox(k0, k1, first_block, w1, w2, w3, nblocks, out, (hipStream_t)stream));
+    return GP_OK;
+}
+
+}  // extern "C"

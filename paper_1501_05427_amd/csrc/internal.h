@@ -1,0 +1,63 @@
+// Host-side declarations shared by the translation units of the HIP library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gp_common.h"
+#include "ulisse_gp.h"
+
+namespace gpk {
+
+inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+inline int dpad(int d) { return (d + 3) & ~3; }
+
+// Launch shape of one covariance product, chosen on the host.
+struct KmvShape {
+    bool mfma;        // MFMA contraction (m >= 16) or VALU contraction (m < 16)
+    int mp;           // padded column count of V seen by the kernel
+    int rows_per_wg;  // rows of K handled by one workgroup
+    int split;        // column chunks (split-K), chunk index = blockIdx % split
+    int chunk;        // columns of K per chunk (multiple of 64)
+    int64_t n_pad;
+};
+
+KmvShape kmv_shape(int64_t n, int d, int m, gp_precision prec);
+KmvShape dkmv_shape(int64_t n, int d, int m);
+
+// psi -> KParams and the scaled, padded inputs Z (n_pad x dpad(d), zero rows past n).
+hipError_t launch_prep(const float* X, int64_t n, int d, int64_t ldx, const double* psi,
+                       float* Z, int64_t n_pad, KParams* kp, hipStream_t s);
+// Copy V (n x m, ldv) into a zero-padded n_pad x mp buffer (ld n_pad).
+hipError_t launch_pack(const float* V, int64_t n, int m, int64_t ldv, float* Vp, int64_t n_pad,
+                       int mp, hipStream_t s);
+// Split-K partial products K V into part[split][mp][n_pad].  Vp is n_pad x mp, ld n_pad.
+// If n_active is non-null and *n_active == 0 on the device, the launch does nothing.
+hipError_t launch_kmv_partials(const KmvShape& sh, int d, const float* Z, const float* Vp,
+                               const KParams* kp, float* part, const int* n_active,
+                               gp_precision prec, hipStream_t s);
+// out[c*ldo + i] = sum_s part + lambda V  for i < n, c < m.
+hipError_t launch_kmv_reduce(const KmvShape& sh, const float* part, const float* Vp,
+                             const KParams* kp, int64_t n, int m, float* out, int64_t ldo,
+                             hipStream_t s);
+// Derivative products; see gp_dkmv.
+hipError_t launch_dkmv(const KmvShape& sh, int d, const float* Z, const float* Vp,
+                       const KParams* kp, float* part, int64_t n, int m, float* out,
+                       int64_t ldo, int64_t block_stride, hipStream_t s);
+size_t dkmv_part_floats(const KmvShape& sh, int d);
+
+// Fused gradient reduction g_j = sum_ik dK_j(i,k) G(i,k), G = A B^T (A, B: n_pad x mq4,
+// ld n_pad, zero padded).  Writes per-workgroup FP64 partials for j = 0..d.
+struct DquadShape {
+    int mq4;          // padded column count of A and B (multiple of 16)
+    int rows_per_wg;
+    int split;
+    int chunk;
+    int64_t n_pad;
+    int nwg;
+};
+DquadShape dquad_shape(int64_t n, int d, int mcols);
+hipError_t launch_dquad(const DquadShape& sh, int d, const float* Z, const float* A,
+                        const float* B, const KParams* kp, double* gpart, hipStream_t s);
+
+}  // namespace gpk

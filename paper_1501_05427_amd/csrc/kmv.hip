@@ -1,0 +1,657 @@
+// Matrix-free covariance products for the squared-exponential ARD kernel plus noise.
+//
+// K(i, j) = sigma^2 exp(-1/2 sum_k (x_ik - x_jk)^2 / ell_k^2) + lambda delta_ij is never
+// stored: every workgroup rebuilds its tiles of K from the pre-scaled inputs
+// z_ik = x_ik sqrt(log2(e)/2) / ell_k, so that K_f(i, j) = exp2(log2 sigma^2 - |z_i - z_j|^2)
+// with the distance formed from explicit FP32 differences.  The product with V is a
+// VALU contraction for fewer than 16 right-hand sides and an FP32 MFMA contraction
+// (v_mfma_f32_16x16x4f32) otherwise, with K generated directly in the MFMA A-operand
+// layout.  Work is split over (row tile, column chunk); chunk partials are summed in a
+// fixed order by a second kernel in FP64, which also adds lambda V.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "gp_common.h"
+#include "internal.h"
+
+namespace gpk {
+
+constexpr int kJS = 64;  // columns of K per LDS stage
+
+// ---------------------------------------------------------------------------------------
+// psi -> parameters and scaled inputs
+// ---------------------------------------------------------------------------------------
+__global__ void prep_kernel(const float* __restrict__ X, int64_t n, int d, int64_t ldx,
+                            const double* __restrict__ psi, float* __restrict__ Z, int64_t n_pad,
+                            KParams* __restrict__ kp) {
+    const int dp = (d + 3) & ~3;
+    const double base = sqrt(0.5 / M_LN2);  // sqrt(log2(e) / 2)
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t == 0) {
+        KParams p;
+        p.c0 = (float)(psi[0] / M_LN2);
+        p.sigma2 = exp(psi[0]);
+        p.lam64 = exp(psi[d + 1]);
+        p.lam = (float)p.lam64;
+        for (int k = 0; k < kMaxD; ++k) p.sc[k] = k < d ? (float)(base * exp(-psi[1 + k])) : 0.f;
+        for (int k = 0; k < kMaxP; ++k) p.psi[k] = k < d + 2 ? psi[k] : 0.0;
+        *kp = p;
+    }
+    const int64_t total = n_pad * dp;
+    for (int64_t e = t; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e / dp;
+        const int k = (int)(e % dp);
+        float z = 0.f;
+        if (i < n && k < d) z = (float)((double)X[i * ldx + k] * (base * exp(-psi[1 + k])));
+        Z[e] = z;
+    }
+}
+
+__global__ void pack_kernel(const float* __restrict__ V, int64_t n, int m, int64_t ldv,
+                            float* __restrict__ Vp, int64_t n_pad, int mp) {
+    const int64_t total = n_pad * mp;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int c = (int)(e / n_pad);
+        const int64_t i = e % n_pad;
+        Vp[e] = (i < n && c < m) ? V[c * ldv + i] : 0.f;
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// Stage loader: JS rows of Z (row-major, DP floats each) and JS entries of MP columns of
+// V (column-major, ld n_pad) through registers into LDS.  V is stored in LDS either
+// column-major with a padded stride (MFMA B-operand reads) or row-major (VALU broadcast).
+// ---------------------------------------------------------------------------------------
+template <int DP, int MP, bool VROWMAJOR>
+struct Stage {
+    static constexpr int NZ4 = kJS * DP / 4;
+    static constexpr int NV4 = MP * kJS / 4;
+    static constexpr int NL = (NZ4 + NV4 + kWG - 1) / kWG;
+    static constexpr int VST = VROWMAJOR ? MP : (kJS + 4);
+    static constexpr int VSIZE = VROWMAJOR ? kJS * MP : MP * (kJS + 4);
+
+    __device__ static void load(const float* __restrict__ Z, const float* __restrict__ V,
+                                int64_t ldv, int64_t j0, float4 (&buf)[NL]) {
+#pragma unroll
+        for (int t = 0; t < NL; ++t) {
+            const int idx = threadIdx.x + t * kWG;
+            if (idx < NZ4) {
+                buf[t] = reinterpret_cast<const float4*>(Z + j0 * DP)[idx];
+            } else if (idx < NZ4 + NV4) {
+                const int v = idx - NZ4;
+                const int c = v / (kJS / 4);
+                const int jj = (v % (kJS / 4)) * 4;
+                buf[t] = *reinterpret_cast<const float4*>(V + c * ldv + j0 + jj);
+            }
+        }
+    }
+    __device__ static void store(float4* __restrict__ zs, float* __restrict__ vs,
+                                 const float4 (&buf)[NL]) {
+#pragma unroll
+        for (int t = 0; t < NL; ++t) {
+            const int idx = threadIdx.x + t * kWG;
+            if (idx < NZ4) {
+                zs[idx] = buf[t];
+            } else if (idx < NZ4 + NV4) {
+                const int v = idx - NZ4;
+                const int c = v / (kJS / 4);
+                const int jj = (v % (kJS / 4)) * 4;
+                if (VROWMAJOR) {
+                    vs[(jj + 0) * MP + c] = buf[t].x;
+                    vs[(jj + 1) * MP + c] = buf[t].y;
+                    vs[(jj + 2) * MP + c] = buf[t].z;
+                    vs[(jj + 3) * MP + c] = buf[t].w;
+                } else {
+                    *reinterpret_cast<float4*>(vs + c * VST + jj) = buf[t];
+                }
+            }
+        }
+    }
+};
+
+template <int D>
+__device__ inline void load_row(const float* __restrict__ p, float (&z)[D]) {
+    constexpr int DP = (D + 3) & ~3;
+    float tmp[DP];
+#pragma unroll
+    for (int k = 0; k < DP; k += 4) {
+        const float4 v = *reinterpret_cast<const float4*>(p + k);
+        tmp[k] = v.x;
+        tmp[k + 1] = v.y;
+        tmp[k + 2] = v.z;
+        tmp[k + 3] = v.w;
+    }
+#pragma unroll
+    for (int k = 0; k < D; ++k) z[k] = tmp[k];
+}
+
+// exp2(c0 - |zi - zj|^2): acc starts at -c0, the FMA chain adds the squared differences.
+template <int D>
+__device__ inline float kf_entry(const float (&zi)[D], const float (&zj)[D], float negc0) {
+    float a = negc0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        const float t = zi[k] - zj[k];
+        a = __builtin_fmaf(t, t, a);
+    }
+    return __builtin_amdgcn_exp2f(-a);
+}
+
+// ---------------------------------------------------------------------------------------
+// MFMA FP32 product: each wave owns R blocks of 16 rows; each lane keeps z_i of its row
+// (lane % 16) for every block.  Inside a 16-column group, lane l takes columns
+// j = 4 (l / 16) + s for s = 0..3 -- the k-slot of v_mfma_f32_16x16x4f32 is l / 16 -- so
+// the B operand of four consecutive MFMA steps is one 16-byte LDS read.
+// ---------------------------------------------------------------------------------------
+template <int D, int NB, int R>
+__global__ __launch_bounds__(kWG) void kmv_mfma_f32_kernel(
+    const float* __restrict__ Z, const float* __restrict__ V, int64_t ldv,
+    float* __restrict__ part, int64_t n_pad, int chunk, int split,
+    const KParams* __restrict__ kp, const int* __restrict__ n_active) {
+    if (n_active != nullptr && *n_active == 0) return;
+    constexpr int DP = (D + 3) & ~3;
+    constexpr int MP = NB * 16;
+    using S = Stage<DP, MP, false>;
+    __shared__ float4 zs[2][S::NZ4];
+    __shared__ float vs[2][S::VSIZE];
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int q = lane >> 4, col = lane & 15;
+    const int cidx = blockIdx.x % split;
+    const int64_t rt = blockIdx.x / split;
+    const int64_t row0 = rt * (64 * R) + wave * (16 * R);
+    const int64_t jb = (int64_t)cidx * chunk;
+    const int64_t je = min(jb + (int64_t)chunk, n_pad);
+    const float negc0 = -kp->c0;
+
+    float zi[R][D];
+#pragma unroll
+    for (int r = 0; r < R; ++r) load_row<D>(Z + (row0 + r * 16 + col) * DP, zi[r]);
+
+    floatx4 acc[R][NB];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int cb = 0; cb < NB; ++cb) acc[r][cb] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+    float4 pre[S::NL];
+    if (jb < je) {
+        S::load(Z, V, ldv, jb, pre);
+        S::store(zs[0], vs[0], pre);
+    }
+    __syncthreads();
+    int buf = 0;
+    for (int64_t j0 = jb; j0 < je; j0 += kJS) {
+        const bool more = j0 + kJS < je;
+        if (more) S::load(Z, V, ldv, j0 + kJS, pre);
+        const float* zsb = reinterpret_cast<const float*>(zs[buf]);
+        const float* vsb = vs[buf];
+#pragma unroll 1
+        for (int g = 0; g < kJS / 16; ++g) {
+            float4 vv[NB];
+#pragma unroll
+            for (int cb = 0; cb < NB; ++cb)
+                vv[cb] = *reinterpret_cast<const float4*>(vsb + (cb * 16 + col) * S::VST + g * 16 + 4 * q);
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                float zj[D];
+                load_row<D>(zsb + (g * 16 + 4 * q + s) * DP, zj);
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const float kv = kf_entry<D>(zi[r], zj, negc0);
+#pragma unroll
+                    for (int cb = 0; cb < NB; ++cb) {
+                        const float b = s == 0 ? vv[cb].x : s == 1 ? vv[cb].y : s == 2 ? vv[cb].z : vv[cb].w;
+                        acc[r][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(kv, b, acc[r][cb], 0, 0, 0);
+                    }
+                }
+            }
+        }
+        if (more) S::store(zs[buf ^ 1], vs[buf ^ 1], pre);
+        __syncthreads();
+        buf ^= 1;
+    }
+    // lane holds rows 4q..4q+3 of column cb*16 + col: one 16-byte store per block
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int cb = 0; cb < NB; ++cb) {
+            const int64_t i = row0 + r * 16 + 4 * q;
+            const int c = cb * 16 + col;
+            float4 o;
+            o.x = acc[r][cb][0];
+            o.y = acc[r][cb][1];
+            o.z = acc[r][cb][2];
+            o.w = acc[r][cb][3];
+            *reinterpret_cast<float4*>(part + ((int64_t)cidx * MP + c) * n_pad + i) = o;
+        }
+}
+
+// ---------------------------------------------------------------------------------------
+// VALU product for MC (= 4, 8, 12) columns: one row per lane and per R; every column j of
+// the stage is read by all lanes at once (LDS broadcast).
+// ---------------------------------------------------------------------------------------
+template <int D, int MC, int R>
+__global__ __launch_bounds__(kWG) void kmv_valu_kernel(
+    const float* __restrict__ Z, const float* __restrict__ V, int64_t ldv,
+    float* __restrict__ part, int64_t n_pad, int chunk, int split,
+    const KParams* __restrict__ kp, const int* __restrict__ n_active) {
+    if (n_active != nullptr && *n_active == 0) return;
+    constexpr int DP = (D + 3) & ~3;
+    using S = Stage<DP, MC, true>;
+    __shared__ float4 zs[2][S::NZ4];
+    __shared__ float vs[2][S::VSIZE];
+
+    const int cidx = blockIdx.x % split;
+    const int64_t rt = blockIdx.x / split;
+    const int64_t row0 = rt * (kWG * R);
+    const int64_t jb = (int64_t)cidx * chunk;
+    const int64_t je = min(jb + (int64_t)chunk, n_pad);
+    const float negc0 = -kp->c0;
+
+    float zi[R][D];
+#pragma unroll
+    for (int r = 0; r < R; ++r) load_row<D>(Z + (row0 + r * kWG + threadIdx.x) * DP, zi[r]);
+    float acc[R][MC];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int c = 0; c < MC; ++c) acc[r][c] = 0.f;
+
+    float4 pre[S::NL];
+    if (jb < je) {
+        S::load(Z, V, ldv, jb, pre);
+        S::store(zs[0], vs[0], pre);
+    }
+    __syncthreads();
+    int buf = 0;
+    for (int64_t j0 = jb; j0 < je; j0 += kJS) {
+        const bool more = j0 + kJS < je;
+        if (more) S::load(Z, V, ldv, j0 + kJS, pre);
+        const float* zsb = reinterpret_cast<const float*>(zs[buf]);
+        const float* vsb = vs[buf];
+#pragma unroll 4
+        for (int j = 0; j < kJS; ++j) {
+            float zj[D];
+            load_row<D>(zsb + j * DP, zj);
+            float vj[MC];
+#pragma unroll
+            for (int c = 0; c < MC; c += 4) {
+                const float4 v4 = *reinterpret_cast<const float4*>(vsb + j * MC + c);
+                vj[c] = v4.x;
+                vj[c + 1] = v4.y;
+                vj[c + 2] = v4.z;
+                vj[c + 3] = v4.w;
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const float kv = kf_entry<D>(zi[r], zj, negc0);
+#pragma unroll
+                for (int c = 0; c < MC; ++c) acc[r][c] = __builtin_fmaf(kv, vj[c], acc[r][c]);
+            }
+        }
+        if (more) S::store(zs[buf ^ 1], vs[buf ^ 1], pre);
+        __syncthreads();
+        buf ^= 1;
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int c = 0; c < MC; ++c)
+            part[((int64_t)cidx * MC + c) * n_pad + row0 + r * kWG + threadIdx.x] = acc[r][c];
+}
+
+// ---------------------------------------------------------------------------------------
+// Derivative products.  MFMA form for 16 columns per pass (one accumulator set per
+// derivative), VALU form for 4 columns per pass.  part layout: [split][D+1][MP][n_pad];
+// block 0 is K_f V, block k is (K_f o dz_k^2) V, still to be scaled by 2 ln 2.
+// ---------------------------------------------------------------------------------------
+template <int D>
+__global__ __launch_bounds__(kWG) void dkmv_mfma_kernel(
+    const float* __restrict__ Z, const float* __restrict__ V, int64_t ldv,
+    float* __restrict__ part, int64_t n_pad, int chunk, int split,
+    const KParams* __restrict__ kp) {
+    constexpr int DP = (D + 3) & ~3;
+    constexpr int MP = 16;
+    using S = Stage<DP, MP, false>;
+    __shared__ float4 zs[2][S::NZ4];
+    __shared__ float vs[2][S::VSIZE];
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int q = lane >> 4, col = lane & 15;
+    const int cidx = blockIdx.x % split;
+    const int64_t rt = blockIdx.x / split;
+    const int64_t row0 = rt * 64 + wave * 16;
+    const int64_t jb = (int64_t)cidx * chunk;
+    const int64_t je = min(jb + (int64_t)chunk, n_pad);
+    const float negc0 = -kp->c0;
+
+    float zi[D];
+    load_row<D>(Z + (row0 + col) * DP, zi);
+    floatx4 acc[D + 1];
+#pragma unroll
+    for (int p = 0; p <= D; ++p) acc[p] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+    float4 pre[S::NL];
+    if (jb < je) {
+        S::load(Z, V, ldv, jb, pre);
+        S::store(zs[0], vs[0], pre);
+    }
+    __syncthreads();
+    int buf = 0;
+    for (int64_t j0 = jb; j0 < je; j0 += kJS) {
+        const bool more = j0 + kJS < je;
+        if (more) S::load(Z, V, ldv, j0 + kJS, pre);
+        const float* zsb = reinterpret_cast<const float*>(zs[buf]);
+        const float* vsb = vs[buf];
+#pragma unroll 1
+        for (int g = 0; g < kJS / 16; ++g) {
+            const float4 vv = *reinterpret_cast<const float4*>(vsb + col * S::VST + g * 16 + 4 * q);
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                float zj[D];
+                load_row<D>(zsb + (g * 16 + 4 * q + s) * DP, zj);
+                float sq[D];
+                float a = negc0;
+#pragma unroll
+                for (int k = 0; k < D; ++k) {
+                    const float t = zi[k] - zj[k];
+                    sq[k] = t * t;
+                    a += sq[k];
+                }
+                const float kv = __builtin_amdgcn_exp2f(-a);
+                const float b = s == 0 ? vv.x : s == 1 ? vv.y : s == 2 ? vv.z : vv.w;
+                acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(kv, b, acc[0], 0, 0, 0);
+#pragma unroll
+                for (int k = 0; k < D; ++k)
+                    acc[k + 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(kv * sq[k], b, acc[k + 1], 0, 0, 0);
+            }
+        }
+        if (more) S::store(zs[buf ^ 1], vs[buf ^ 1], pre);
+        __syncthreads();
+        buf ^= 1;
+    }
+#pragma unroll
+    for (int p = 0; p <= D; ++p) {
+        float4 o;
+        o.x = acc[p][0];
+        o.y = acc[p][1];
+        o.z = acc[p][2];
+        o.w = acc[p][3];
+        *reinterpret_cast<float4*>(part + (((int64_t)cidx * (D + 1) + p) * MP + col) * n_pad + row0 + 4 * q) = o;
+    }
+}
+
+template <int D>
+__global__ __launch_bounds__(kWG) void dkmv_valu_kernel(
+    const float* __restrict__ Z, const float* __restrict__ V, int64_t ldv,
+    float* __restrict__ part, int64_t n_pad, int chunk, int split,
+    const KParams* __restrict__ kp) {
+    constexpr int DP = (D + 3) & ~3;
+    constexpr int MC = 4;
+    using S = Stage<DP, MC, true>;
+    __shared__ float4 zs[2][S::NZ4];
+    __shared__ float vs[2][S::VSIZE];
+
+    const int cidx = blockIdx.x % split;
+    const int64_t rt = blockIdx.x / split;
+    const int64_t i = rt * kWG + threadIdx.x;
+    const int64_t jb = (int64_t)cidx * chunk;
+    const int64_t je = min(jb + (int64_t)chunk, n_pad);
+    const float negc0 = -kp->c0;
+
+    float zi[D];
+    load_row<D>(Z + i * DP, zi);
+    float acc[D + 1][MC];
+#pragma unroll
+    for (int p = 0; p <= D; ++p)
+#pragma unroll
+        for (int c = 0; c < MC; ++c) acc[p][c] = 0.f;
+
+    float4 pre[S::NL];
+    if (jb < je) {
+        S::load(Z, V, ldv, jb, pre);
+        S::store(zs[0], vs[0], pre);
+    }
+    __syncthreads();
+    int buf = 0;
+    for (int64_t j0 = jb; j0 < je; j0 += kJS) {
+        const bool more = j0 + kJS < je;
+        if (more) S::load(Z, V, ldv, j0 + kJS, pre);
+        const float* zsb = reinterpret_cast<const float*>(zs[buf]);
+        const float* vsb = vs[buf];
+#pragma unroll 2
+        for (int j = 0; j < kJS; ++j) {
+            float zj[D];
+            load_row<D>(zsb + j * DP, zj);
+            const float4 v4 = *reinterpret_cast<const float4*>(vsb + j * MC);
+            const float vj[4] = {v4.x, v4.y, v4.z, v4.w};
+            float sq[D];
+            float a = negc0;
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                const float t = zi[k] - zj[k];
+                sq[k] = t * t;
+                a += sq[k];
+            }
+            const float kv = __builtin_amdgcn_exp2f(-a);
+#pragma unroll
+            for (int c = 0; c < MC; ++c) acc[0][c] = __builtin_fmaf(kv, vj[c], acc[0][c]);
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                const float w = kv * sq[k];
+#pragma unroll
+                for (int c = 0; c < MC; ++c) acc[k + 1][c] = __builtin_fmaf(w, vj[c], acc[k + 1][c]);
+            }
+        }
+        if (more) S::store(zs[buf ^ 1], vs[buf ^ 1], pre);
+        __syncthreads();
+        buf ^= 1;
+    }
+#pragma unroll
+    for (int p = 0; p <= D; ++p)
+#pragma unroll
+        for (int c = 0; c < MC; ++c)
+            part[(((int64_t)cidx * (D + 1) + p) * MC + c) * n_pad + i] = acc[p][c];
+}
+
+// ---------------------------------------------------------------------------------------
+// Fixed-order combination of the chunk partials.
+// ---------------------------------------------------------------------------------------
+__global__ void kmv_reduce_kernel(const float* __restrict__ part, int split, int mp,
+                                  int64_t n_pad, const float* __restrict__ Vp,
+                                  const KParams* __restrict__ kp, int64_t n, int m,
+                                  float* __restrict__ out, int64_t ldo) {
+    const double lam = kp->lam64;
+    const int64_t total = n * m;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int c = (int)(e / n);
+        const int64_t i = e % n;
+        double s = 0.0;
+        for (int k = 0; k < split; ++k) s += (double)part[((int64_t)k * mp + c) * n_pad + i];
+        s += lam * (double)Vp[c * n_pad + i];
+        out[c * ldo + i] = (float)s;
+    }
+}
+
+__global__ void dkmv_reduce_kernel(const float* __restrict__ part, int split, int d, int mp,
+                                   int64_t n_pad, const float* __restrict__ Vp,
+                                   const KParams* __restrict__ kp, int64_t n, int mcols,
+                                   float* __restrict__ out, int64_t ldo, int64_t bstride) {
+    const double lam = kp->lam64;
+    const double two_ln2 = 2.0 * M_LN2;
+    const int64_t total = n * mcols * (int64_t)(d + 2);
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e % n;
+        const int c = (int)((e / n) % mcols);
+        const int p = (int)(e / (n * mcols));
+        double s = 0.0;
+        if (p <= d) {
+            for (int k = 0; k < split; ++k)
+                s += (double)part[(((int64_t)k * (d + 1) + p) * mp + c) * n_pad + i];
+            if (p > 0) s *= two_ln2;
+        } else {
+            s = lam * (double)Vp[c * n_pad + i];
+        }
+        out[p * bstride + c * ldo + i] = (float)s;
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------------------
+static int grid_for(int64_t total, int per = kWG) {
+    int64_t g = (total + per - 1) / per;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(g, 65536));
+}
+
+static void pick_split(KmvShape& sh, int target_wg) {
+    const int64_t row_tiles = sh.n_pad / sh.rows_per_wg;
+    const int64_t max_split = sh.n_pad / kJS;
+    int64_t split = std::max<int64_t>(1, target_wg / std::max<int64_t>(1, row_tiles));
+    split = std::min<int64_t>(split, max_split);
+    if (split >= 8) split = split / 8 * 8;  // chunk index = blockIdx % split: XCD-aligned
+    sh.chunk = (int)round_up((sh.n_pad + split - 1) / split, kJS);
+    sh.split = (int)((sh.n_pad + sh.chunk - 1) / sh.chunk);
+}
+
+KmvShape kmv_shape(int64_t n, int d, int m, gp_precision prec) {
+    (void)prec;
+    KmvShape sh;
+    sh.n_pad = round_up(std::max<int64_t>(n, 1), kRowPad);
+    sh.mfma = m >= 16;
+    if (sh.mfma) {
+        sh.mp = (int)round_up(m, 16);
+        const int R = d <= 8 ? 4 : 2;
+        sh.rows_per_wg = 64 * R;
+    } else {
+        sh.mp = (int)round_up(m, 4);
+        sh.rows_per_wg = kWG;
+    }
+    pick_split(sh, 2048);
+    return sh;
+}
+
+KmvShape dkmv_shape(int64_t n, int d, int m) {
+    KmvShape sh;
+    sh.n_pad = round_up(std::max<int64_t>(n, 1), kRowPad);
+    sh.mfma = m >= 16;
+    sh.mp = sh.mfma ? 16 : 4;  // columns per pass
+    sh.rows_per_wg = sh.mfma ? 64 : kWG;
+    (void)d;
+    pick_split(sh, 2048);
+    return sh;
+}
+
+size_t dkmv_part_floats(const KmvShape& sh, int d) {
+    return (size_t)sh.split * (d + 1) * sh.mp * sh.n_pad;
+}
+
+hipError_t launch_prep(const float* X, int64_t n, int d, int64_t ldx, const double* psi,
+                       float* Z, int64_t n_pad, KParams* kp, hipStream_t s) {
+    prep_kernel<<<grid_for(n_pad * dpad(d)), kWG, 0, s>>>(X, n, d, ldx, psi, Z, n_pad, kp);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack(const float* V, int64_t n, int m, int64_t ldv, float* Vp, int64_t n_pad,
+                       int mp, hipStream_t s) {
+    pack_kernel<<<grid_for(n_pad * mp), kWG, 0, s>>>(V, n, m, ldv, Vp, n_pad, mp);
+    return hipGetLastError();
+}
+
+template <int D>
+static hipError_t kmv_d(const KmvShape& sh, const float* Z, const float* Vp, const KParams* kp,
+                        float* part, const int* n_active, hipStream_t s) {
+    const int64_t tiles = sh.n_pad / sh.rows_per_wg;
+    const dim3 grid((unsigned)(tiles * sh.split));
+    if (sh.mfma) {
+        constexpr int R = D <= 8 ? 4 : 2;
+        switch (sh.mp) {
+            case 16: kmv_mfma_f32_kernel<D, 1, R><<<grid, kWG, 0, s>>>(Z, Vp, sh.n_pad, part, sh.n_pad, sh.chunk, sh.split, kp, n_active); break;
+            case 32: kmv_mfma_f32_kernel<D, 2, R><<<grid, kWG, 0, s>>>(Z, Vp, sh.n_pad, part, sh.n_pad, sh.chunk, sh.split, kp, n_active); break;
+            case 48: kmv_mfma_f32_kernel<D, 3, R><<<grid, kWG, 0, s>>>(Z, Vp, sh.n_pad, part, sh.n_pad, sh.chunk, sh.split, kp, n_active); break;
+            case 64: kmv_mfma_f32_kernel<D, 4, R><<<grid, kWG, 0, s>>>(Z, Vp, sh.n_pad, part, sh.n_pad, sh.chunk, sh.split, kp, n_active); break;
+            default: return hipErrorInvalidValue;
+        }
+    } else {
+        switch (sh.mp) {
+            case 4: kmv_valu_kernel<D, 4, 1><<<grid, kWG, 0, s>>>(Z, Vp, sh.n_pad, part, sh.n_pad, sh.chunk, sh.split, kp, n_active); break;
+            case 8: kmv_valu_kernel<D, 8, 1><<<grid, kWG, 0, s>>>(Z, Vp, sh.n_pad, part, sh.n_pad, sh.chunk, sh.split, kp, n_active); break;
+            case 12: kmv_valu_kernel<D, 12, 1><<<grid, kWG, 0, s>>>(Z, Vp, sh.n_pad, part, sh.n_pad, sh.chunk, sh.split, kp, n_active); break;
+            case 16: kmv_valu_kernel<D, 16, 1><<<grid, kWG, 0, s>>>(Z, Vp, sh.n_pad, part, sh.n_pad, sh.chunk, sh.split, kp, n_active); break;
+            default: return hipErrorInvalidValue;
+        }
+    }
+    return hipGetLastError();
+}
+
+#define GPK_DISPATCH_D(d, FN, ...)                    \
+    switch (d) {                                      \
+        case 1: return FN<1>(__VA_ARGS__);            \
+        case 2: return FN<2>(__VA_ARGS__);            \
+        case 3: return FN<3>(__VA_ARGS__);            \
+        case 4: return FN<4>(__VA_ARGS__);            \
+        case 5: return FN<5>(__VA_ARGS__);            \
+        case 6: return FN<6>(__VA_ARGS__);            \
+        case 7: return FN<7>(__VA_ARGS__);            \
+        case 8: return FN<8>(__VA_ARGS__);            \
+        case 9: return FN<9>(__VA_ARGS__);            \
+        case 10: return FN<10>(__VA_ARGS__);          \
+        case 11: return FN<11>(__VA_ARGS__);          \
+        case 12: return FN<12>(__VA_ARGS__);          \
+        case 13: return FN<13>(__VA_ARGS__);          \
+        case 14: return FN<14>(__VA_ARGS__);          \
+        case 15: return FN<15>(__VA_ARGS__);          \
+        case 16: return FN<16>(__VA_ARGS__);          \
+        default: return hipErrorInvalidValue;         \
+    }
+
+hipError_t launch_kmv_partials(const KmvShape& sh, int d, const float* Z, const float* Vp,
+                               const KParams* kp, float* part, const int* n_active,
+                               gp_precision prec, hipStream_t s) {
+    if (prec != GP_FP32) return hipErrorInvalidValue;
+    GPK_DISPATCH_D(d, kmv_d, sh, Z, Vp, kp, part, n_active, s);
+}
+
+hipError_t launch_kmv_reduce(const KmvShape& sh, const float* part, const float* Vp,
+                             const KParams* kp, int64_t n, int m, float* out, int64_t ldo,
+                             hipStream_t s) {
+    kmv_reduce_kernel<<<grid_for(n * m), kWG, 0, s>>>(part, sh.split, sh.mp, sh.n_pad, Vp, kp,
+                                                       n, m, out, ldo);
+    return hipGetLastError();
+}
+
+template <int D>
+static hipError_t dkmv_d(const KmvShape& sh, const float* Z, const float* Vp, const KParams* kp,
+                         float* part, int64_t n, int m, float* out, int64_t ldo,
+                         int64_t bstride, hipStream_t s) {
+    const int64_t tiles = sh.n_pad / sh.rows_per_wg;
+    const dim3 grid((unsigned)(tiles * sh.split));
+    for (int c0 = 0; c0 < m; c0 += sh.mp) {
+        const int mc = std::min(sh.mp, m - c0);
+        const float* Vc = Vp + (int64_t)c0 * sh.n_pad;
+        if (sh.mfma)
+            dkmv_mfma_kernel<D><<<grid, kWG, 0, s>>>(Z, Vc, sh.n_pad, part, sh.n_pad, sh.chunk, sh.split, kp);
+        else
+            dkmv_valu_kernel<D><<<grid, kWG, 0, s>>>(Z, Vc, sh.n_pad, part, sh.n_pad, sh.chunk, sh.split, kp);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        dkmv_reduce_kernel<<<grid_for(n * mc * (int64_t)(D + 2)), kWG, 0, s>>>(
+            part, sh.split, D, sh.mp, sh.n_pad, Vc, kp, n, mc, out + c0 * ldo, ldo, bstride);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_dkmv(const KmvShape& sh, int d, const float* Z, const float* Vp,
+                       const KParams* kp, float* part, int64_t n, int m, float* out,
+                       int64_t ldo, int64_t block_stride, hipStream_t s) {
+    GPK_DISPATCH_D(d, dkmv_d, sh, Z, Vp, kp, part, n, m, out, ldo, block_stride, s);
+}
+
+}  // namespace gpk

@@ -1,0 +1,85 @@
+// Solver state shared by solver.hip and the host orchestration in api.hip.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gp_common.h"
+#include "ulisse_gp.h"
+
+namespace gpk {
+
+constexpr int kMaxSys = 64;
+enum { kPre = 0, kTail = 1, kDone = 2 };
+
+// Per-system state of one ULISSE solve (device memory, one entry per system).
+struct SysState {
+    double rho;        // e^T e of the current iterate
+    double alpha;      // step of the current iteration
+    double beta;
+    double thr_alpha;  // early-stop threshold q sqrt(n)
+    double thr_eps;    // convergence threshold
+    double res;        // ||e|| after the last iteration
+    double W[2];       // weight of the increment of the current iteration, per track (0: done)
+    int32_t phase[2];  // kPre, kTail, kDone
+    int32_t j[2];      // tail index of the increment of the current iteration
+    int32_t ntracks;
+    int32_t l, iters, flags;
+    int32_t active;    // the CG run of this system continues
+    int32_t apply;     // alpha of the current iteration is valid
+};
+
+// Column of the series estimate of track t of system c in the output block.
+__host__ __device__ inline int sys_col(int two_track, int c, int t) {
+    return two_track ? (c == 0 ? t : c + 1) : c;
+}
+
+struct SolverArgs {
+    int64_t n, n_pad;
+    int32_t m;       // systems
+    int32_t mp;      // padded columns of the product partials
+    int32_t split;   // chunks of the product partials
+    int32_t nb;      // workgroups of the vector kernels (256 rows each)
+    int64_t ldb;
+    const float* B;
+    const double* S0;
+    double* Q;       // K d (FP64), ld n_pad
+    double* S;       // CG iterate, ld n_pad
+    double* E;       // residual, ld n_pad
+    float* D;        // direction (FP32), ld n_pad, zero rows past n
+    double* St;      // series estimates, ld n
+    const float* kpart;
+    const KParams* kp;
+    double* part;
+    double* part2;
+    unsigned* counter;
+    int* n_active;
+    SysState* state;
+    ulisse_sysstat* stats;
+    double q, rate, eps;
+    int32_t eps_relative, max_iter, two_track, pad_;
+    uint64_t seed, rng_stream, rng_counter;
+};
+
+hipError_t solver_init(const SolverArgs& a, int warm, hipStream_t s);
+hipError_t solver_reduce(const SolverArgs& a, hipStream_t s);
+hipError_t solver_update(const SolverArgs& a, hipStream_t s);
+hipError_t solver_direction(const SolverArgs& a, hipStream_t s);
+hipError_t solver_copy_s(const SolverArgs& a, double* out, hipStream_t s);
+hipError_t launch_pack_f64(const double* S0, int64_t n, int m, float* D, int64_t n_pad,
+                           hipStream_t s);
+hipError_t launch_probes(int64_t n, int nprobes, int kind, uint64_t k0, uint64_t k1,
+                         uint64_t step, float* R, int64_t ldr, hipStream_t s);
+hipError_t launch_philox(uint64_t k0, uint64_t k1, uint64_t first, uint64_t w1, uint64_t w2,
+                         uint64_t w3, int64_t nblocks, uint64_t* out, hipStream_t s);
+hipError_t launch_build_ab(const double* St, const float* R, int64_t ldr, int64_t n,
+                           int nprobes, float* A, float* Bm, int64_t n_pad, int mq4,
+                           hipStream_t s);
+hipError_t launch_grad_finish(const double* St, const float* R, int64_t ldr, int64_t n,
+                              int nprobes, const double* gpart, int nwg, int d,
+                              const KParams* kp, double* g, hipStream_t s);
+hipError_t launch_sgld(int P, double* psi, const double* g, int prior_kind, const double* pa,
+                       const double* pb, const double* L, double eps, uint64_t k0,
+                       uint64_t k1, uint64_t step, hipStream_t s);
+
+}  // namespace gpk

@@ -1,0 +1,517 @@
+// ULISSE on the GPU: the per-iteration vector work of Alg. 1 (CG) with the randomly
+// truncated series of Sec. 4, plus the draws (probes, u_j, SGLD noise), the assembly of
+// the stochastic gradient from the solutions and the SGLD update.
+//
+// Every system (column) keeps FP64 iterate s, FP64 residual e (Alg. 1's recursive one),
+// an FP32 direction d (the vector the covariance product consumes) and one FP64 series
+// estimate per track.  Dot products are FP64 per workgroup; the last workgroup to finish
+// combines the partials in a fixed order and runs the per-system decisions (threshold l,
+// tail draws, convergence, iteration cap), so the result does not depend on scheduling.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "gp_common.h"
+#include "internal.h"
+#include "solver.h"
+
+namespace gpk {
+
+// Sum of the per-workgroup column partials; one thread per system, fixed order.
+__device__ inline double sum_partials(const double* __restrict__ part, int nb, int m, int c) {
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += part[(int64_t)b * m + c];
+    return s;
+}
+
+// Wave-level partial of every column into red[wave][c], then one barrier and the
+// per-column workgroup total written to part[blockIdx.x * m + c].
+__device__ inline void column_partials(double v, int c, double (*red)[kMaxSys]) {
+    const double w = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][c] = w;
+}
+
+__device__ inline bool last_block(unsigned* counter) {
+    __shared__ bool last;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned prev = atomicAdd(counter, 1u);
+        last = (prev == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (last) __threadfence();
+    return last;
+}
+
+__device__ inline void write_stat(const SysState& st, ulisse_sysstat* out) {
+    ulisse_sysstat r;
+    r.l = st.l;
+    r.J_a = st.j[0];
+    r.J_b = st.ntracks > 1 ? st.j[1] : -1;
+    r.iters = st.iters;
+    r.final_res = st.res;
+    r.flags = (uint32_t)st.flags;
+    r.pad = 0;
+    *out = r;
+}
+
+// ---------------------------------------------------------------------------------------
+// Initialisation: e = b - K s0, d = e, s~ = s0, rho = e^T e.
+// ---------------------------------------------------------------------------------------
+__global__ __launch_bounds__(kWG) void ulisse_init_kernel(SolverArgs a, int warm) {
+    __shared__ double red[4][kMaxSys];
+    __shared__ double red2[4][kMaxSys];
+    const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    const bool in = i < a.n;
+    for (int c = 0; c < a.m; ++c) {
+        double e = 0.0, b = 0.0;
+        if (in) {
+            b = (double)a.B[c * a.ldb + i];
+            const double s0 = warm ? a.S0[c * a.n + i] : 0.0;
+            if (warm) {  // K s0 from the chunk partials of the product with fp32(s0) in D
+                double kq = 0.0;
+                for (int k = 0; k < a.split; ++k) kq += (double)a.kpart[((int64_t)k * a.mp + c) * a.n_pad + i];
+                kq += a.kp->lam64 * (double)a.D[c * a.n_pad + i];
+                e = b - kq;
+            } else {
+                e = b;
+            }
+            a.S[c * a.n_pad + i] = s0;
+            a.E[c * a.n_pad + i] = e;
+            a.D[c * a.n_pad + i] = (float)e;
+            const int nt = (a.two_track && c == 0) ? 2 : 1;
+            for (int t = 0; t < nt; ++t) a.St[(int64_t)sys_col(a.two_track, c, t) * a.n + i] = s0;
+        }
+        column_partials(e * e, c, red);
+        column_partials(b * b, c, red2);
+    }
+    __syncthreads();
+    if (threadIdx.x < a.m) {
+        const int c = threadIdx.x;
+        a.part[(int64_t)blockIdx.x * a.m + c] = (red[0][c] + red[1][c]) + (red[2][c] + red[3][c]);
+        a.part2[(int64_t)blockIdx.x * a.m + c] = (red2[0][c] + red2[1][c]) + (red2[2][c] + red2[3][c]);
+    }
+    if (!last_block(a.counter)) return;
+    if (threadIdx.x < a.m) {
+        const int c = threadIdx.x;
+        const double rho = sum_partials(a.part, gridDim.x, a.m, c);
+        const double bb = sum_partials(a.part2, gridDim.x, a.m, c);
+        SysState st;
+        st.rho = rho;
+        st.alpha = 0.0;
+        st.beta = 0.0;
+        st.thr_alpha = a.q * sqrt((double)a.n);
+        st.thr_eps = a.eps_relative ? a.eps * sqrt(bb) : a.eps;
+        st.res = sqrt(rho);
+        st.ntracks = (a.two_track && c == 0) ? 2 : 1;
+        for (int t = 0; t < 2; ++t) {
+            st.W[t] = t < st.ntracks ? 1.0 : 0.0;
+            st.phase[t] = t < st.ntracks ? kPre : kDone;
+            st.j[t] = 0;
+        }
+        st.l = 0;
+        st.iters = 0;
+        st.flags = 0;
+        st.active = 1;
+        st.apply = 0;
+        a.state[c] = st;
+    }
+    if (threadIdx.x == 0) {
+        *a.n_active = a.m;
+        *a.counter = 0u;
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// After the covariance product: Q = sum of chunk partials + lambda d (FP64), gamma = d^T Q,
+// alpha = rho / gamma.
+// ---------------------------------------------------------------------------------------
+__global__ __launch_bounds__(kWG) void ulisse_reduce_kernel(SolverArgs a) {
+    if (*a.n_active == 0) return;
+    __shared__ double red[4][kMaxSys];
+    const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    const bool in = i < a.n;
+    const double lam = a.kp->lam64;
+    for (int c = 0; c < a.m; ++c) {
+        if (!a.state[c].active) continue;  // uniform over the workgroup
+        double dq = 0.0;
+        if (in) {
+            double s = 0.0;
+            for (int k = 0; k < a.split; ++k) s += (double)a.kpart[((int64_t)k * a.mp + c) * a.n_pad + i];
+            const double dv = (double)a.D[c * a.n_pad + i];
+            s += lam * dv;
+            a.Q[c * a.n_pad + i] = s;
+            dq = dv * s;
+        }
+        column_partials(dq, c, red);
+    }
+    __syncthreads();
+    if (threadIdx.x < a.m && a.state[threadIdx.x].active) {
+        const int c = threadIdx.x;
+        a.part[(int64_t)blockIdx.x * a.m + c] = (red[0][c] + red[1][c]) + (red[2][c] + red[3][c]);
+    }
+    if (!last_block(a.counter)) return;
+    if (threadIdx.x < a.m) {
+        const int c = threadIdx.x;
+        SysState& st = a.state[c];
+        if (st.active) {
+            const double gamma = sum_partials(a.part, gridDim.x, a.m, c);
+            const double alpha = st.rho / gamma;
+            if (!(gamma > 0.0) || !isfinite(alpha)) {
+                st.apply = 0;
+                st.active = 0;
+                st.flags |= (int)ULISSE_BREAKDOWN;
+                for (int t = 0; t < 2; ++t) {
+                    st.phase[t] = kDone;
+                    st.W[t] = 0.0;
+                }
+                write_stat(st, a.stats + c);
+            } else {
+                st.apply = 1;
+                st.alpha = alpha;
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int cnt = 0;
+        for (int c = 0; c < a.m; ++c) cnt += a.state[c].active;
+        *a.n_active = cnt;
+        *a.counter = 0u;
+    }
+}
+
+// u_j of track t of system c: word j of Philox stream (key (seed, stream), counter
+// (j/4, 2c + t, 2, step)), mapped to [0, 1).
+__device__ inline double ulisse_u(const SolverArgs& a, int c, int t, int j) {
+    const u64x4 w = philox4x64_10((uint64_t)(j >> 2), (uint64_t)(2 * c + t), kPurposeUlisse,
+                                  a.rng_counter, a.seed, a.rng_stream);
+    return u01_co(w.v[j & 3]);
+}
+
+// The increment with tail index j[t] has just been added: continue or stop the track.
+__device__ inline void tail_decide(const SolverArgs& a, SysState& st, int c, int t) {
+    if (st.res < st.thr_eps) {
+        st.phase[t] = kDone;
+    } else if (st.iters >= a.max_iter) {
+        st.phase[t] = kDone;
+        st.flags |= (int)ULISSE_NOTCONV;
+    } else {
+        const int jn = st.j[t] + 1;
+        if (ulisse_u(a, c, t, jn) < exp(-a.rate * (double)jn)) {
+            st.phase[t] = kTail;
+            st.j[t] = jn;
+            st.W[t] = exp(a.rate * (double)jn * (double)(jn + 1) * 0.5);
+        } else {
+            st.phase[t] = kDone;
+        }
+    }
+    if (st.phase[t] == kDone) st.W[t] = 0.0;
+}
+
+// ---------------------------------------------------------------------------------------
+// delta = alpha d;  s += delta;  e -= alpha Q;  s~_t += W_t delta;  rho' = e^T e, then the
+// per-system decisions and beta = rho' / rho.
+// ---------------------------------------------------------------------------------------
+__global__ __launch_bounds__(kWG) void ulisse_update_kernel(SolverArgs a) {
+    if (*a.n_active == 0) return;
+    __shared__ double red[4][kMaxSys];
+    const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    const bool in = i < a.n;
+    for (int c = 0; c < a.m; ++c) {
+        const SysState& st = a.state[c];
+        if (!st.active || !st.apply) continue;
+        double ee = 0.0;
+        if (in) {
+            const double al = st.alpha;
+            const double delta = al * (double)a.D[c * a.n_pad + i];
+            a.S[c * a.n_pad + i] += delta;
+            const double e = a.E[c * a.n_pad + i] - al * a.Q[c * a.n_pad + i];
+            a.E[c * a.n_pad + i] = e;
+            ee = e * e;
+            for (int t = 0; t < st.ntracks; ++t)
+                if (st.W[t] != 0.0) a.St[(int64_t)sys_col(a.two_track, c, t) * a.n + i] += st.W[t] * delta;
+        }
+        column_partials(ee, c, red);
+    }
+    __syncthreads();
+    if (threadIdx.x < a.m) {
+        const int c = threadIdx.x;
+        if (a.state[c].active && a.state[c].apply)
+            a.part[(int64_t)blockIdx.x * a.m + c] = (red[0][c] + red[1][c]) + (red[2][c] + red[3][c]);
+    }
+    if (!last_block(a.counter)) return;
+    if (threadIdx.x < a.m) {
+        const int c = threadIdx.x;
+        SysState st = a.state[c];
+        if (st.active && st.apply) {
+            const double rho_new = sum_partials(a.part, gridDim.x, a.m, c);
+            st.res = sqrt(rho_new);
+            st.iters += 1;
+            for (int t = 0; t < st.ntracks; ++t) {
+                if (st.phase[t] == kDone) continue;
+                if (st.phase[t] == kPre) {
+                    if (st.res < st.thr_alpha || st.res < st.thr_eps) {
+                        st.l = st.iters;  // this increment was delta_l, kept with W_0 = 1
+                        st.j[t] = 0;
+                        tail_decide(a, st, c, t);
+                    } else if (st.iters >= a.max_iter) {
+                        st.phase[t] = kDone;
+                        st.W[t] = 0.0;
+                        st.flags |= (int)ULISSE_NOTCONV;
+                    }
+                } else {
+                    tail_decide(a, st, c, t);
+                }
+            }
+            bool done = true;
+            for (int t = 0; t < st.ntracks; ++t) done = done && st.phase[t] == kDone;
+            if (!isfinite(rho_new)) {
+                done = true;
+                st.flags |= (int)ULISSE_BREAKDOWN;
+            }
+            st.beta = rho_new / st.rho;
+            st.rho = rho_new;
+            st.apply = 0;
+            if (done) {
+                st.active = 0;
+                write_stat(st, a.stats + c);
+            }
+            a.state[c] = st;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int cnt = 0;
+        for (int c = 0; c < a.m; ++c) cnt += a.state[c].active;
+        *a.n_active = cnt;
+        *a.counter = 0u;
+    }
+}
+
+// d = e + beta d (rounded to FP32 for the next covariance product).
+__global__ __launch_bounds__(kWG) void ulisse_direction_kernel(SolverArgs a) {
+    if (*a.n_active == 0) return;
+    const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    if (i >= a.n) return;
+    for (int c = 0; c < a.m; ++c) {
+        const SysState& st = a.state[c];
+        if (!st.active) continue;
+        const int64_t o = c * a.n_pad + i;
+        a.D[o] = (float)(a.E[o] + st.beta * (double)a.D[o]);
+    }
+}
+
+// S_cg = last CG iterate (ld n).
+__global__ void ulisse_copy_s_kernel(SolverArgs a, double* __restrict__ out) {
+    const int64_t total = a.n * a.m;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int c = (int)(e / a.n);
+        const int64_t i = e % a.n;
+        out[c * a.n + i] = a.S[c * a.n_pad + i];
+    }
+}
+
+// FP32 copy of the warm start, zero padded, as the input of K s0.
+__global__ void pack_f64_kernel(const double* __restrict__ S0, int64_t n, int m,
+                                float* __restrict__ D, int64_t n_pad) {
+    const int64_t total = n_pad * m;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int c = (int)(e / n_pad);
+        const int64_t i = e % n_pad;
+        D[e] = i < n ? (float)S0[c * n + i] : 0.f;
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// Draws
+// ---------------------------------------------------------------------------------------
+__global__ void probes_kernel(int64_t n, int nprobes, int kind, uint64_t k0, uint64_t k1,
+                              uint64_t step, float* __restrict__ R, int64_t ldr) {
+    const int64_t nblk = (n + 3) / 4;
+    const int64_t total = nblk * nprobes;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int c = (int)(e / nblk);
+        const int64_t b = e % nblk;
+        const u64x4 w = philox4x64_10((uint64_t)b, (uint64_t)c, kPurposeProbe, step, k0, k1);
+        double z[4];
+        if (kind == 0) {
+            box_muller(w.v[0], w.v[1], &z[0], &z[1]);
+            box_muller(w.v[2], w.v[3], &z[2], &z[3]);
+        } else {
+            for (int u = 0; u < 4; ++u) z[u] = (w.v[u] >> 63) ? -1.0 : 1.0;
+        }
+        for (int u = 0; u < 4; ++u) {
+            const int64_t i = 4 * b + u;
+            if (i < n) R[c * ldr + i] = (float)z[u];
+        }
+    }
+}
+
+__global__ void philox_kernel(uint64_t k0, uint64_t k1, uint64_t first, uint64_t w1,
+                              uint64_t w2, uint64_t w3, int64_t nblocks, uint64_t* __restrict__ out) {
+    for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nblocks;
+         b += (int64_t)gridDim.x * blockDim.x) {
+        const u64x4 w = philox4x64_10(first + (uint64_t)b, w1, w2, w3, k0, k1);
+        for (int u = 0; u < 4; ++u) out[4 * b + u] = w.v[u];
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// Gradient assembly
+// ---------------------------------------------------------------------------------------
+// A = [1/2 s_a, -r_1/(2 N_r), ...],  B = [s_b, s_1, ...]  as zero-padded FP32 (ld n_pad).
+__global__ void build_ab_kernel(const double* __restrict__ St, const float* __restrict__ R,
+                                int64_t ldr, int64_t n, int nprobes, float* __restrict__ A,
+                                float* __restrict__ Bm, int64_t n_pad, int mq4) {
+    const int64_t total = n_pad * mq4;
+    const double w = -1.0 / (2.0 * nprobes);
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int c = (int)(e / n_pad);
+        const int64_t i = e % n_pad;
+        float av = 0.f, bv = 0.f;
+        if (i < n && c <= nprobes) {
+            if (c == 0) {
+                av = (float)(0.5 * St[i]);
+                bv = (float)St[n + i];
+            } else {
+                av = (float)(w * (double)R[(c - 1) * ldr + i]);
+                bv = (float)St[(int64_t)(c + 1) * n + i];
+            }
+        }
+        A[e] = av;
+        Bm[e] = bv;
+    }
+}
+
+// Diagonal (noise) term sum_i G_ii in FP64 from the FP64 solutions, then the final
+// fixed-order sum of the tile partials: g_0, 2 ln 2 * (g_1..g_d), lambda * diag.
+__global__ __launch_bounds__(kWG) void grad_finish_kernel(
+    const double* __restrict__ St, const float* __restrict__ R, int64_t ldr, int64_t n,
+    int nprobes, const double* __restrict__ gpart, int nwg, int d,
+    const KParams* __restrict__ kp, double* __restrict__ g) {
+    __shared__ double scratch[4];
+    double acc = 0.0;
+    const double w = 1.0 / (2.0 * nprobes);
+    for (int64_t i = threadIdx.x; i < n; i += kWG) {
+        double v = 0.5 * St[i] * St[n + i];
+        for (int c = 0; c < nprobes; ++c) v -= w * (double)R[c * ldr + i] * St[(int64_t)(c + 2) * n + i];
+        acc += v;
+    }
+    const double diag = block_sum256(acc, scratch);
+    if (threadIdx.x <= d) {
+        const int p = threadIdx.x;
+        double s = 0.0;
+        for (int b = 0; b < nwg; ++b) s += gpart[(int64_t)b * (d + 1) + p];
+        g[p] = p == 0 ? s : 2.0 * M_LN2 * s;
+    }
+    if (threadIdx.x == 0) g[d + 1] = kp->lam64 * diag;
+}
+
+// ---------------------------------------------------------------------------------------
+// SGLD update (one small problem: a single thread does it in FP64).
+// ---------------------------------------------------------------------------------------
+__global__ void sgld_kernel(int P, double* __restrict__ psi, const double* __restrict__ g,
+                            int prior_kind, const double* __restrict__ pa,
+                            const double* __restrict__ pb, const double* __restrict__ L,
+                            double eps, uint64_t k0, uint64_t k1, uint64_t step) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double v[kMaxP], xi[kMaxP + 3], t[kMaxP];
+    for (int i = 0; i < P; ++i) {
+        double pg = 0.0;
+        if (prior_kind == 1) pg = -(psi[i] - pa[i]) / (pb[i] * pb[i]);
+        if (prior_kind == 2) pg = pa[i] - pb[i] * exp(psi[i]);
+        v[i] = g[i] + pg;
+    }
+    for (int b = 0; b < (P + 3) / 4; ++b) {
+        const u64x4 w = philox4x64_10((uint64_t)b, 0, kPurposeSgld, step, k0, k1);
+        box_muller(w.v[0], w.v[1], &xi[4 * b], &xi[4 * b + 1]);
+        box_muller(w.v[2], w.v[3], &xi[4 * b + 2], &xi[4 * b + 3]);
+    }
+    // t = L^T v, then M v = L t
+    for (int j = 0; j < P; ++j) {
+        double s = 0.0;
+        for (int i = 0; i < P; ++i) s += (L ? L[i + j * P] : (i == j ? 1.0 : 0.0)) * v[i];
+        t[j] = s;
+    }
+    const double se = sqrt(eps);
+    double out[kMaxP];
+    for (int i = 0; i < P; ++i) {
+        double mv = 0.0, lx = 0.0;
+        for (int j = 0; j < P; ++j) {
+            const double lij = L ? L[i + j * P] : (i == j ? 1.0 : 0.0);
+            mv += lij * t[j];
+            lx += lij * xi[j];
+        }
+        out[i] = psi[i] + 0.5 * eps * mv + se * lx;
+    }
+    for (int i = 0; i < P; ++i) psi[i] = out[i];
+}
+
+// ---------------------------------------------------------------------------------------
+// Host launchers
+// ---------------------------------------------------------------------------------------
+static int grid_of(int64_t total) {
+    return (int)std::max<int64_t>(1, std::min<int64_t>((total + kWG - 1) / kWG, 65536));
+}
+
+hipError_t solver_init(const SolverArgs& a, int warm, hipStream_t s) {
+    ulisse_init_kernel<<<(unsigned)a.nb, kWG, 0, s>>>(a, warm);
+    return hipGetLastError();
+}
+hipError_t solver_reduce(const SolverArgs& a, hipStream_t s) {
+    ulisse_reduce_kernel<<<(unsigned)a.nb, kWG, 0, s>>>(a);
+    return hipGetLastError();
+}
+hipError_t solver_update(const SolverArgs& a, hipStream_t s) {
+    ulisse_update_kernel<<<(unsigned)a.nb, kWG, 0, s>>>(a);
+    return hipGetLastError();
+}
+hipError_t solver_direction(const SolverArgs& a, hipStream_t s) {
+    ulisse_direction_kernel<<<(unsigned)a.nb, kWG, 0, s>>>(a);
+    return hipGetLastError();
+}
+hipError_t solver_copy_s(const SolverArgs& a, double* out, hipStream_t s) {
+    ulisse_copy_s_kernel<<<grid_of(a.n * a.m), kWG, 0, s>>>(a, out);
+    return hipGetLastError();
+}
+hipError_t launch_pack_f64(const double* S0, int64_t n, int m, float* D, int64_t n_pad,
+                           hipStream_t s) {
+    pack_f64_kernel<<<grid_of(n_pad * m), kWG, 0, s>>>(S0, n, m, D, n_pad);
+    return hipGetLastError();
+}
+hipError_t launch_probes(int64_t n, int nprobes, int kind, uint64_t k0, uint64_t k1,
+                         uint64_t step, float* R, int64_t ldr, hipStream_t s) {
+    probes_kernel<<<grid_of((n + 3) / 4 * nprobes), kWG, 0, s>>>(n, nprobes, kind, k0, k1, step, R, ldr);
+    return hipGetLastError();
+}
+hipError_t launch_philox(uint64_t k0, uint64_t k1, uint64_t first, uint64_t w1, uint64_t w2,
+                         uint64_t w3, int64_t nblocks, uint64_t* out, hipStream_t s) {
+    philox_kernel<<<grid_of(nblocks), kWG, 0, s>>>(k0, k1, first, w1, w2, w3, nblocks, out);
+    return hipGetLastError();
+}
+hipError_t launch_build_ab(const double* St, const float* R, int64_t ldr, int64_t n,
+                           int nprobes, float* A, float* Bm, int64_t n_pad, int mq4,
+                           hipStream_t s) {
+    build_ab_kernel<<<grid_of(n_pad * mq4), kWG, 0, s>>>(St, R, ldr, n, nprobes, A, Bm, n_pad, mq4);
+    return hipGetLastError();
+}
+hipError_t launch_grad_finish(const double* St, const float* R, int64_t ldr, int64_t n,
+                              int nprobes, const double* gpart, int nwg, int d,
+                              const KParams* kp, double* g, hipStream_t s) {
+    grad_finish_kernel<<<1, kWG, 0, s>>>(St, R, ldr, n, nprobes, gpart, nwg, d, kp, g);
+    return hipGetLastError();
+}
+hipError_t launch_sgld(int P, double* psi, const double* g, int prior_kind, const double* pa,
+                       const double* pb, const double* L, double eps, uint64_t k0,
+                       uint64_t k1, uint64_t step, hipStream_t s) {
+    sgld_kernel<<<1, 64, 0, s>>>(P, psi, g, prior_kind, pa, pb, L, eps, k0, k1, step);
+    return hipGetLastError();
+}
+
+}  // namespace gpk

@@ -1,0 +1,66 @@
+"""CPU checks of the C ABI library: it builds for gfx950, loads, and exports every
+function that include/ulisse_gp.h declares.  No compute call is made (no GPU here)."""
+import ctypes
+import os
+import subprocess
+
+import pytest
+
+from paper_1501_05427_amd import binding, build
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(binding.LIB_PATH):
+        build.build()
+    return binding.lib()
+
+
+def test_header_declares_the_boundary():
+    names = binding.header_functions()
+    for f in ["gp_create", "gp_destroy", "gp_last_error", "gp_kmv", "gp_dkmv", "ulisse_solve",
+              "gp_stoch_grad", "sgld_step", "gp_draw_probes", "gp_philox"]:
+        assert f in names, f
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in binding.header_functions():
+        assert hasattr(lib, name), name
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    # the C compiler's view of the structs (size and every field offset) vs ctypes
+    structs = {"gp_data": binding.gp_data, "ulisse_params": binding.ulisse_params,
+               "ulisse_sysstat": binding.ulisse_sysstat, "gp_prior": binding.gp_prior}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "ulisse_gp.h"', "int main(void) {"]
+    for cname, cls in structs.items():
+        lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'printf("{cname}.{fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    inc = os.path.dirname(binding.HEADER)
+    subprocess.run(["gcc", "-I", inc, str(src), "-o", str(exe)], check=True)
+    out = dict(l.split() for l in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                 check=True).stdout.splitlines())
+    for cname, cls in structs.items():
+        assert int(out[cname]) == ctypes.sizeof(cls), cname
+        for fname, _ in cls._fields_:
+            assert int(out[f"{cname}.{fname}"]) == getattr(cls, fname).offset, (cname, fname)
+
+
+def test_validation_is_synchronous_and_host_side(lib):
+    # bad sizes are rejected before any device work: the null handle is caught first
+    st = lib.gp_kmv(None, binding.gp_data(0, 0, 0, 0), None, None, 0, 0, None, 0, 0, None)
+    assert st == binding.GP_EINVAL
+    assert b"handle" in lib.gp_last_error()
+    st = lib.gp_philox(0, 0, 0, 0, 0, 0, -1, None, None)
+    assert st == binding.GP_EINVAL
+
+
+def test_sources_are_gfx950_only():
+    src = open(os.path.join(binding.HERE, "build.py")).read()
+    assert "--offload-arch={ARCH}" in src and 'ARCH = "gfx950"' in src
+    assert "-packed-fp32-ops" in src

@@ -1,0 +1,349 @@
+"""GPU parity of the HIP path against the FP64 oracle, through the C ABI.
+
+Tolerances:
+  * covariance products (FP32): per column ||out - ref||_2 / ||ref||_2 <= 1e-5;
+  * raw Philox words and Rademacher probes: bit-exact;
+  * Gaussian probes: the FP64 Box-Muller values agree to 1e-12 relative before the
+    rounding to FP32, so the FP32 probes agree to 1 ulp;
+  * ULISSE and the gradient, draw for draw: the discrete decisions (l, J, iteration
+    counts) exactly; the FP64 series estimates within 2e-4 normwise, the size of the FP32
+    product error (about 1e-6) amplified by the conditioning of the test systems.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from oracle import cg as ocg
+from oracle import gp as ogp
+from oracle import rng as orng
+from oracle import sgld as osgld
+from oracle import stoch_grad as osg
+from oracle import ulisse as oul
+
+pytestmark = pytest.mark.gpu
+
+pb = pytest.importorskip("paper_1501_05427_amd.binding")
+
+
+@pytest.fixture(autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+@pytest.fixture(scope="module")
+def h():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return pb.Handle(0, seed=1234)
+
+
+def dev(a, dtype=None):
+    t = torch.as_tensor(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def colm(a, dtype=torch.float32):
+    """(n, m) numpy -> column-major device tensor."""
+    a = np.asarray(a)
+    return dev(np.ascontiguousarray(a.T), dtype).t()
+
+
+def problem(n, d, seed, lam=0.1, ell=(0.3, 0.8)):
+    r = np.random.default_rng(seed)
+    X = r.uniform(size=(n, d)).astype(np.float32)
+    psi = np.concatenate([[np.log(1.2)], np.log(r.uniform(*ell, d)), [np.log(lam)]])
+    return X, psi
+
+
+def colwise_rel(out, ref):
+    out = np.asarray(out, dtype=np.float64)
+    num = np.linalg.norm(out - ref, axis=0)
+    den = np.linalg.norm(ref, axis=0)
+    return num / np.maximum(den, 1e-300)
+
+
+# ---------------------------------------------------------------------------------------
+# RNG
+# ---------------------------------------------------------------------------------------
+@pytest.mark.parametrize("k0,k1,first,w1,w2,w3", [(0, 0, 0, 0, 0, 0), (1234, 7, 5, 3, 2, 11),
+                                                   (2**64 - 1, 2**63, 2**40, 17, 1, 2**33)])
+def test_philox_bitexact(k0, k1, first, w1, w2, w3):
+    nb = 1000
+    out = pb.gp_philox(k0, k1, first, w1, w2, w3, nb)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().view(np.uint64).reshape(nb, 4)
+    ref = orng.blocks(k0, k1, w1, w2, w3, nb, first_block=first)
+    np.testing.assert_array_equal(got, ref)
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+@pytest.mark.parametrize("n", [1, 7, 1001])
+def test_probe_draws(h, kind, n):
+    R = pb.gp_draw_probes(h, n, 3, kind, 99, 5)
+    torch.cuda.synchronize()
+    got = R.cpu().numpy()
+    ref = orng.probes(h.seed, 99, 5, n, 3, kind).astype(np.float32)
+    if kind == 1:
+        np.testing.assert_array_equal(got, ref)
+    else:
+        np.testing.assert_allclose(got, ref, rtol=2.0 ** -23, atol=1e-30)
+
+
+# ---------------------------------------------------------------------------------------
+# Covariance products
+# ---------------------------------------------------------------------------------------
+KMV_CASES = [
+    (1, 1, 1), (17, 2, 5), (300, 3, 15), (1000, 2, 5), (1000, 8, 16), (1000, 8, 17),
+    (777, 16, 32), (2049, 8, 64), (513, 5, 33), (1500, 4, 1), (256, 8, 12),
+]
+
+
+@pytest.mark.parametrize("n,d,m", KMV_CASES)
+def test_kmv_parity(h, n, d, m):
+    X, psi = problem(n, d, seed=n * 31 + d)
+    V = np.random.default_rng(m).standard_normal((n, m)).astype(np.float32)
+    out = pb.gp_kmv(h, dev(X), dev(psi), colm(V))
+    torch.cuda.synchronize()
+    ref = ogp.kmv(X, psi, V)
+    assert colwise_rel(out.cpu().numpy(), ref).max() <= 1e-5
+
+
+@pytest.mark.parametrize("case", ["duplicates", "tiny_ell", "huge_ell", "noise_dominated"])
+def test_kmv_edge_cases(h, case):
+    n, d, m = 600, 3, 17
+    r = np.random.default_rng(5)
+    X = r.uniform(size=(n, d)).astype(np.float32)
+    psi = np.log([1.0, 0.4, 0.4, 0.4, 0.1])
+    if case == "duplicates":
+        X[1::2] = X[0::2]
+    elif case == "tiny_ell":      # K ~ (sigma^2 + lambda) I
+        psi[1:4] = np.log(1e-4)
+    elif case == "huge_ell":      # K ~ sigma^2 11^T + lambda I
+        psi[1:4] = np.log(1e4)
+    else:                         # sigma^2 << lambda
+        psi[0], psi[-1] = np.log(1e-6), np.log(3.0)
+    V = r.standard_normal((n, m)).astype(np.float32)
+    out = pb.gp_kmv(h, dev(X), dev(psi), colm(V))
+    torch.cuda.synchronize()
+    ref = ogp.kmv(X, psi, V)
+    assert colwise_rel(out.cpu().numpy(), ref).max() <= 1e-5
+
+
+def test_kmv_leading_dimensions(h):
+    n, d, m = 300, 2, 6
+    X, psi = problem(n, d, 3)
+    Xp = np.zeros((n, 5), np.float32)
+    Xp[:, :d] = X
+    V = np.random.default_rng(0).standard_normal((n, m)).astype(np.float32)
+    Vbig = torch.zeros((m, n + 13), device="cuda")
+    Vbig[:, :n] = dev(V.T)
+    Vv = Vbig.t()[:n]
+    outbig = torch.full((m, n + 7), 7.0, device="cuda")
+    Xt = dev(Xp)[:, :d]
+    pb.gp_kmv(h, Xt, dev(psi), Vv, out=outbig.t()[:n])
+    torch.cuda.synchronize()
+    got = outbig.cpu().numpy()
+    assert colwise_rel(got[:, :n].T, ogp.kmv(X, psi, V)).max() <= 1e-5
+    assert np.all(got[:, n:] == 7.0)  # nothing written past n
+
+
+@pytest.mark.parametrize("n,d,m", [(400, 2, 3), (700, 8, 16), (333, 3, 20), (257, 16, 5)])
+def test_dkmv_parity(h, n, d, m):
+    X, psi = problem(n, d, seed=7 * n)
+    V = np.random.default_rng(1).standard_normal((n, m)).astype(np.float32)
+    out = pb.gp_dkmv(h, dev(X), dev(psi), colm(V))
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()            # (P, m, n)
+    ref = ogp.dkmv(X, psi, V)          # (P, n, m)
+    for j in range(d + 2):
+        assert colwise_rel(got[j].T, ref[j]).max() <= 1e-5, j
+
+
+@pytest.mark.parametrize("rows_seed", [0, 1])
+def test_kmv_full_size_sampled(h, rows_seed):
+    # the benchmark's workload (n = 65536, d = 8, m = 32) in the benchmark's launch shape;
+    # the oracle computes a sample of output rows one by one
+    w = workloads.rff_gp(n=65536, d=8, seed=2)
+    X, psi = w["X"], w["psi"]
+    V = workloads.gaussian_matrix(65536, 32, seed=11)
+    out = pb.gp_kmv(h, dev(X), dev(psi), colm(V))
+    torch.cuda.synchronize()
+    rows = np.sort(np.random.default_rng(rows_seed).choice(65536, 48, replace=False))
+    rows[-1] = 65535
+    got = out.cpu().numpy()[rows]
+    ref = ogp.kmv(X, psi, V, rows=rows)
+    assert colwise_rel(got, ref).max() <= 1e-5
+
+
+# ---------------------------------------------------------------------------------------
+# ULISSE, draw for draw
+# ---------------------------------------------------------------------------------------
+def _safe_q(K, b, s0, target_l):
+    """q whose threshold q sqrt(n) lies midway (log scale) between two residual norms."""
+    norms = []
+    for i, s, e, dl in ocg.cg_iterates(lambda v: K @ v, b, s0):
+        norms.append(np.linalg.norm(e))
+        if i >= target_l:
+            break
+    hi = min(norms[:target_l - 1]) if target_l >= 2 else 10 * norms[0]
+    lo = norms[target_l - 1]
+    assert hi > 1.5 * lo
+    return np.sqrt(hi * lo) / np.sqrt(len(b))
+
+
+@pytest.mark.parametrize("two_track,warm,m", [(0, False, 3), (1, False, 5), (1, True, 4), (0, True, 17)])
+def test_ulisse_draw_for_draw(h, two_track, warm, m):
+    n, d = 400, 2
+    X, psi = problem(n, d, seed=40 + m, lam=0.2, ell=(0.2, 0.4))
+    K = ogp.kernel_matrix(X, psi)
+    Bm = np.random.default_rng(m).standard_normal((n, m)).astype(np.float32)
+    S0 = None
+    if warm:
+        S0 = 0.9 * ogp.solve(X, psi, Bm.astype(np.float64))
+    q = _safe_q(K, Bm[:, 0].astype(np.float64), np.zeros(n) if S0 is None else S0[:, 0], 3)
+    eps, rate = 1e-6, 0.7
+    params = pb.make_params(q=q, rate=rate, eps=eps, eps_relative=1, max_iter=200,
+                            two_track_first=two_track, rng_stream=77, rng_counter=3)
+    Scg = torch.zeros((m, n), dtype=torch.float64, device="cuda").t()
+    St, stats = pb.ulisse_solve(h, dev(X), dev(psi), colm(Bm), params,
+                                S0=None if S0 is None else colm(S0, torch.float64), S_cg=Scg)
+    torch.cuda.synchronize()
+    st_gpu = pb.decode_stats(stats)
+    ref_St, ref_Scg, ref_stats = oul.solve_systems(
+        lambda v: K @ v, Bm.astype(np.float64), S0, q, rate, eps, 200, h.seed, 77, 3,
+        two_track_first=bool(two_track), eps_relative=True)
+    for c in range(m):
+        g, r = st_gpu[c], ref_stats[c]
+        assert g["l"] == r["l"] and g["iters"] == r["iters"], (c, g, r)
+        assert g["J_a"] == r["J"][0], (c, g, r)
+        if two_track and c == 0:
+            assert g["J_b"] == r["J"][1]
+        assert g["flags"] == r["flags"]
+    assert colwise_rel(St.cpu().numpy(), ref_St).max() <= 2e-4
+    assert colwise_rel(Scg.cpu().numpy(), ref_Scg).max() <= 2e-4
+
+
+def test_ulisse_cap_sets_notconv(h):
+    n, d, m = 300, 2, 2
+    X, psi = problem(n, d, seed=3, lam=1e-3)
+    Bm = np.random.default_rng(0).standard_normal((n, m)).astype(np.float32)
+    params = pb.make_params(q=1e-9, rate=1.0, eps=1e-12, eps_relative=1, max_iter=4)
+    St, stats = pb.ulisse_solve(h, dev(X), dev(psi), colm(Bm), params)
+    torch.cuda.synchronize()
+    for s in pb.decode_stats(stats):
+        assert s["iters"] == 4 and (s["flags"] & pb.ULISSE_NOTCONV)
+
+
+def test_ulisse_converged_series_is_the_solution(h):
+    # small q and tiny rate: the tail runs to convergence, s~ = s_T ~ K^-1 b
+    n, d, m = 500, 3, 4
+    X, psi = problem(n, d, seed=9, lam=0.3)
+    Bm = np.random.default_rng(2).standard_normal((n, m)).astype(np.float32)
+    params = pb.make_params(q=1e-12, rate=1e-9, eps=1e-6, eps_relative=1, max_iter=500)
+    St, stats = pb.ulisse_solve(h, dev(X), dev(psi), colm(Bm), params)
+    torch.cuda.synchronize()
+    ref = ogp.solve(X, psi, Bm.astype(np.float64))
+    assert colwise_rel(St.cpu().numpy(), ref).max() <= 1e-4
+
+
+# ---------------------------------------------------------------------------------------
+# Stochastic gradient and SGLD
+# ---------------------------------------------------------------------------------------
+@pytest.mark.parametrize("given_probes", [True, False])
+@pytest.mark.parametrize("n,d,nr", [(300, 2, 4), (600, 8, 16)])
+def test_stoch_grad_draw_for_draw(h, given_probes, n, d, nr):
+    X, psi = problem(n, d, seed=n + d, lam=0.2, ell=(0.3, 1.0))
+    K = ogp.kernel_matrix(X, psi)
+    y = (np.linalg.cholesky(K) @ np.random.default_rng(1).standard_normal(n)).astype(np.float32)
+    stream, counter = 5, 9
+    if given_probes:
+        R = workloads.gaussian_matrix(n, nr, seed=3)
+    else:
+        R = orng.probes(h.seed, stream, counter, n, nr, 0).astype(np.float32)
+    q = _safe_q(K, y.astype(np.float64), np.zeros(n), 2)
+    eps, rate = 1e-6, 1.0
+    params = pb.make_params(q=q, rate=rate, eps=eps, eps_relative=1, max_iter=300,
+                            rng_stream=stream, rng_counter=counter)
+    g, stats = pb.gp_stoch_grad(h, dev(X), dev(psi), dev(y), params,
+                                R=colm(R) if given_probes else None, n_probes=nr)
+    torch.cuda.synchronize()
+    g_ref, St, Scg, ref_stats = osg.stoch_grad(X, psi, y, R, q, rate, eps, 300, h.seed, stream,
+                                               counter, eps_relative=True)
+    st_gpu = pb.decode_stats(stats)
+    same = all(st_gpu[c]["l"] == ref_stats[c]["l"] and st_gpu[c]["iters"] == ref_stats[c]["iters"]
+               for c in range(nr + 1))
+    assert same, (st_gpu, ref_stats)
+    got = g.cpu().numpy()
+    scale = np.abs(g_ref).max()
+    np.testing.assert_allclose(got, g_ref, rtol=2e-4, atol=2e-4 * scale)
+
+
+def test_stoch_grad_exact_solve_mean_matches_exact_gradient(h):
+    # with converged solves (tiny q and rate) the estimator is Hutchinson's; its mean over
+    # many probe draws is the exact gradient, within Monte Carlo error
+    n, d, nr = 200, 2, 8
+    X, psi = problem(n, d, seed=2, lam=0.3)
+    K = ogp.kernel_matrix(X, psi)
+    y = (np.linalg.cholesky(K) @ np.random.default_rng(4).standard_normal(n)).astype(np.float32)
+    g_exact = ogp.exact_gradient(X, psi, y.astype(np.float64))
+    params = pb.make_params(q=1e-12, rate=1e-9, eps=1e-6, eps_relative=1, max_iter=400)
+    Xd, psid, yd = dev(X), dev(psi), dev(y)
+    N = 400
+    gs = []
+    for k in range(N):
+        params.rng_counter = k
+        g, _ = pb.gp_stoch_grad(h, Xd, psid, yd, params, n_probes=nr)
+        gs.append(g)
+    gs = torch.stack(gs).cpu().numpy()
+    se = gs.std(axis=0, ddof=1) / np.sqrt(N)
+    z = (gs.mean(axis=0) - g_exact) / se
+    assert np.all(np.abs(z) < 4.5), z
+
+
+def test_stoch_grad_full_size_consistency(h):
+    # n = 65536, d = 8, 31 probes: the fused gradient reduction agrees with covariance
+    # products of the same series estimates, through dK/dpsi_0 + dK/dpsi_{d+1} = K
+    n, d, nr = 65536, 8, 31
+    w = workloads.rff_gp(n=n, d=d, seed=2)
+    Xd, psid, yd = dev(w["X"]), dev(w["psi"]), dev(w["y"])
+    R = workloads.gaussian_matrix(n, nr, seed=12)
+    Rd = colm(R)
+    params = pb.make_params(q=1.0, rate=1.0, eps=1e-6, eps_relative=1, max_iter=500,
+                            rng_stream=3, rng_counter=1)
+    g, stats = pb.gp_stoch_grad(h, Xd, psid, yd, params, R=Rd)
+    B = torch.cat([yd[:, None], Rd], dim=1).t().contiguous().t()
+    p2 = pb.make_params(q=1.0, rate=1.0, eps=1e-6, eps_relative=1, max_iter=500,
+                        two_track_first=1, rng_stream=3, rng_counter=1)
+    St, stats2 = pb.ulisse_solve(h, Xd, psid, B, p2)
+    KS = pb.gp_kmv(h, Xd, psid, St.float().t().contiguous().t())
+    torch.cuda.synchronize()
+    assert pb.decode_stats(stats) == pb.decode_stats(stats2)
+    Stn, KSn = St.cpu().numpy(), KS.cpu().numpy().astype(np.float64)
+    lhs = 0.5 * Stn[:, 0] @ KSn[:, 1] - sum(R[:, c].astype(np.float64) @ KSn[:, c + 2]
+                                            for c in range(nr)) / (2 * nr)
+    gn = g.cpu().numpy()
+    assert np.all(np.isfinite(gn))
+    assert abs((gn[0] + gn[-1]) - lhs) <= 1e-4 * (abs(lhs) + np.abs(gn).max())
+    for s in pb.decode_stats(stats):
+        assert s["l"] >= 1 and s["iters"] == s["l"] + max(s["J_a"], s["J_b"]) and s["flags"] == 0
+
+
+@pytest.mark.parametrize("prior_kind", [0, 1, 2])
+def test_sgld_step_parity(h, prior_kind):
+    P = 6
+    r = np.random.default_rng(prior_kind)
+    psi = r.standard_normal(P)
+    g = r.standard_normal(P) * 10
+    A = r.standard_normal((P, P))
+    L = np.linalg.cholesky(A @ A.T + P * np.eye(P))
+    a, b = r.uniform(1, 3, P), r.uniform(0.5, 2, P)
+    psid = dev(psi)
+    pb.sgld_step(h, psid, dev(g), 1e-3, rng_stream=4, rng_counter=8, prior_kind=prior_kind,
+                 prior_a=dev(a), prior_b=dev(b), M_chol=dev(L.ravel(order="F")))
+    torch.cuda.synchronize()
+    ref = osgld.step_drawn(psi, g, 1e-3, h.seed, 4, 8, L, prior_kind, a, b)
+    np.testing.assert_allclose(psid.cpu().numpy(), ref, rtol=1e-13, atol=1e-14)

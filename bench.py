@@ -1,0 +1,240 @@
+"""Benchmark of the hot path: one SGLD step = one unbiased gradient estimate (ULISSE solves
+for y and 31 Gaussian probes, fused gradient reduction) + the SGLD update, on the
+n = 65536, d = 8 synthetic GP workload (32 right-hand sides).
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+
+Prints one JSON line.  `value` is gradient estimates per second over the K timed steps
+(inputs resident in HBM).  The roofline object is for the dominant kernel, the
+covariance product (kmv): algorithmic flops per launch n^2 (3d + 2m) divided by its
+average launch time, taken from hipEvents recorded by the library on the launch stream
+during the timed steps.  HBM traffic per launch comes from the committed rocprofv3
+counter summary if it was taken on the current kmv source, else null.
+
+    python bench.py --profile-kmv     a short run for rocprofv3: 5 kmv launches at the
+                                      same shape plus a 1 GiB copy (counter calibration)
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+N, D, NPROBES = 65536, 8, 31
+PROBE_PERIOD = 20
+M = 1 + NPROBES
+WORKLOAD = "rff_n65536_d8_m32"
+VALU_FP32_PEAK_TFLOPS = 157.3   # 256 CU x 2.4 GHz x 256 flop/CU/clk (datasheet FP32 vector)
+KMV_SRC = os.path.join(ROOT, "paper_1501_05427_amd", "csrc", "kmv.hip")
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "kmv_rff_n65536_d8_m32_pmc.txt")
+
+
+def kmv_flops(n, d, m):
+    return float(n) * n * (3 * d + 2 * m)
+
+
+def kmv_source_hash():
+    return hashlib.sha256(open(KMV_SRC, "rb").read()).hexdigest()[:16]
+
+
+def traffic_from_profile():
+    """HBM bytes per kmv launch from the committed counter summary (None if stale/absent)."""
+    if not os.path.exists(PMC_SUMMARY):
+        return None
+    vals = {}
+    for line in open(PMC_SUMMARY):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kmv_source_sha256_16") != kmv_source_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(X, psi, passes_per_estimate, budget_rows=(768, 256)):
+    """The FP64 oracle on a bounded sample of the same workload, scaled to estimates/s.
+
+    Times oracle.gp.kmv on `budget_rows[0]` rows (all 65536 columns, 32 right-hand sides)
+    and the oracle's gradient assembly on `budget_rows[1]` rows (the P = 10 derivative
+    blocks times the solutions); both scale linearly in the number of rows.  One estimate
+    costs `passes_per_estimate` full products plus one full assembly.
+    """
+    import numpy as np
+    from threadpoolctl import threadpool_info
+
+    from oracle import gp as ogp
+    r = np.random.default_rng(0)
+    V = r.standard_normal((N, M))
+    rows_k = np.arange(budget_rows[0])
+    t0 = time.perf_counter()
+    ogp.kmv(X, psi, V, rows=rows_k)
+    t_kmv = (time.perf_counter() - t0) * N / len(rows_k)
+    rows_a = np.arange(budget_rows[1])
+    t0 = time.perf_counter()
+    dK = ogp.kernel_derivatives(X, psi, rows=rows_a)
+    for Dj in dK:
+        _ = Dj @ V
+    t_asm = (time.perf_counter() - t0) * N / len(rows_a)
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    per_est = passes_per_estimate * t_kmv + t_asm
+    return dict(value=1.0 / per_est, unit="grad_estimates/s", cores=int(threads), kind="oracle",
+                sample=(f"oracle FP64 K.V on {budget_rows[0]} of {N} rows and gradient assembly on "
+                        f"{budget_rows[1]} rows of the n={N}, d={D}, m={M} workload, scaled by rows "
+                        f"to {passes_per_estimate:.2f} products + 1 assembly per estimate"),
+                kmv_s_full=t_kmv, assembly_s_full=t_asm)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--fresh-steps", type=int, default=4)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-kmv", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_1501_05427_amd import binding as pb
+
+    if not os.path.exists(pb.LIB_PATH):
+        from paper_1501_05427_amd import build as _b
+        _b.build()
+    torch.cuda.init()
+    w = workloads.rff_gp(n=N, d=D, seed=2)
+    X = torch.from_numpy(w["X"]).cuda()
+    psi0 = torch.from_numpy(w["psi"]).cuda()
+    y = torch.from_numpy(w["y"]).cuda()
+    h = pb.Handle(0, seed=2015)
+
+    if args.profile_kmv:
+        V = pb.colmajor(N, M)
+        V.copy_(torch.from_numpy(workloads.gaussian_matrix(N, M, seed=11)).cuda())
+        out = pb.colmajor(N, M)
+        for _ in range(5):
+            pb.gp_kmv(h, X, psi0, V, out=out)
+        a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")  # 1 GiB
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_kmv": "done", "copy_bytes": a.numel() * 4,
+                          "kmv_source_sha256_16": kmv_source_hash()}), flush=True)
+        return
+
+    params = pb.make_params(q=1.0, rate=1.0, eps=1e-6, eps_relative=1, max_iter=1000,
+                            rng_stream=1, rng_counter=0)
+    psi = psi0.clone()
+    prior_a = torch.zeros(D + 2, dtype=torch.float64, device="cuda")
+    prior_b = torch.full((D + 2,), 3.0, dtype=torch.float64, device="cuda")
+    S_warm = torch.zeros((M, N), dtype=torch.float64, device="cuda").t()
+    R = pb.colmajor(N, NPROBES)
+    g = torch.zeros(D + 2, dtype=torch.float64, device="cuda")
+    stats = pb.stats_tensor(M)
+    eps_t = 1e-3
+    # SGLD preconditioner M = I / n: the log-likelihood gradient grows like n, so the
+    # drift eps_t / 2 M g stays O(eps_t) per step (the paper scales M the same way through
+    # the inverse Hessian of a data subset)
+    M_chol = torch.diag(torch.full((D + 2,), N ** -0.5, dtype=torch.float64)).t().contiguous().cuda()
+    flagged = torch.zeros((), dtype=torch.int64, device="cuda")
+
+    def step(t, period):
+        # the paper's protocol: probes redrawn every `period` steps, every system warm
+        # started from its last CG iterate; period 1 = fresh probes every step, where only
+        # the y system is warm started
+        params.rng_counter = t
+        if period > 1:
+            if t % period == 0:
+                pb.gp_draw_probes(h, N, NPROBES, pb.PROBE_GAUSSIAN, 7, t // period, R=R)
+                S_warm[:, 1:].zero_()
+            pb.gp_stoch_grad(h, X, psi, y, params, R=R, S_warm=S_warm, g=g, stats=stats)
+        else:
+            pb.gp_stoch_grad(h, X, psi, y, params, n_probes=NPROBES, probe_kind=pb.PROBE_GAUSSIAN,
+                             S_warm=S_warm, g=g, stats=stats)
+        pb.sgld_step(h, psi, g, eps_t, rng_stream=1, rng_counter=t, prior_kind=1,
+                     prior_a=prior_a, prior_b=prior_b, M_chol=M_chol)
+        flagged.add_(stats.view(M, -1)[:, 24:28].view(torch.int32).ne(0).any().to(torch.int64))
+
+    def timed(first, count, period):
+        torch.cuda.synchronize()
+        pb.gp_profile(h, 1)
+        t0 = time.perf_counter()
+        for t in range(first, first + count):
+            step(t, period)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        pr = pb.gp_profile_read(h)
+        pb.gp_profile(h, 0)
+        return el, pr
+
+    period = PROBE_PERIOD
+    for t in range(args.warmup):
+        step(t, period)
+    elapsed, prof = timed(args.warmup, args.steps, period)
+    final_stats = pb.decode_stats(stats)
+    # fresh probes every step, for reference (a few steps; not the headline)
+    el_fresh, prof_fresh = timed(10 ** 6, args.fresh_steps, 1) if args.fresh_steps else (None, None)
+
+    K = args.steps
+    value = K / elapsed
+    kmv_avg_s = prof["kmv_ms"] / max(1, prof["kmv_launches"]) / 1e3
+    flops = kmv_flops(N, D, M)
+    achieved = flops / kmv_avg_s / 1e12
+    dq_avg_ms = prof["dquad_ms"] / max(1, prof["dquad_launches"])
+    passes = prof["kmv_passes"] / max(1, K)
+    traffic = traffic_from_profile()
+
+    rec = {
+        "metric": "unbiased grad estimates/s and K.V TFLOP/s at n=65536 (plain FP32 path)",
+        "value": value,
+        "unit": "grad_estimates/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD, "n": N, "d": D, "rhs": M, "probes": NPROBES,
+                   "probe_kind": "gaussian", "probe_period": period, "q": 1.0, "rate": 1.0,
+                   "eps_rel": 1e-6, "warm_start": "last CG iterate, every system",
+                   "sgld_eps": eps_t, "sgld_M": "I/n", "precision": "fp32"},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_FP32_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / VALU_FP32_PEAK_TFLOPS,
+                     "traffic": traffic, "kernel": "kmv_mfma_f32 (K.V, m=32)",
+                     "avg_launch_ms": kmv_avg_s * 1e3, "launches": prof["kmv_launches"]},
+        "kv_tflops": achieved,
+        "kmv_passes_per_estimate": passes,
+        "fresh_probes_every_step": None if el_fresh is None else {
+            "grad_estimates_per_s": args.fresh_steps / el_fresh,
+            "kmv_passes_per_estimate": prof_fresh["kmv_passes"] / args.fresh_steps,
+            "steps": args.fresh_steps},
+        "dquad_avg_ms": dq_avg_ms,
+        "exp_per_s": N * float(N) / kmv_avg_s,
+        "last_step_stats": {"l": [s["l"] for s in final_stats],
+                            "J_max": max(max(s["J_a"], s["J_b"]) for s in final_stats)},
+        "steps_with_flagged_systems": int(flagged.item()),
+        "psi_final_finite": bool(torch.isfinite(psi).all().item()),
+    }
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = cpu_baseline(w["X"], w["psi"], passes)
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

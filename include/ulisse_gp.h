@@ -172,6 +172,27 @@ gp_status gp_draw_probes(gp_handle* h, int64_t n, int32_t n_probes, int32_t prob
 gp_status gp_philox(uint64_t k0, uint64_t k1, uint64_t first_block, uint64_t w1, uint64_t w2,
                     uint64_t w3, int64_t nblocks, uint64_t* out, void* stream);
 
+/*
+ * Kernel timing for measurement.  While enabled, the handle records a pair of hipEvents on
+ * the launch stream around every covariance-product launch that does work (kmv, in the
+ * solver and in gp_kmv) and around every fused gradient reduction (dquad).
+ * gp_profile(h, 1) clears the totals and starts recording, gp_profile(h, 0) stops.
+ * gp_profile_read waits for the recorded events, returns the totals since the last
+ * gp_profile(h, 1) and keeps recording if enabled.  kmv_passes counts the products taken
+ * by ULISSE solves (warm-start residual products included).
+ */
+typedef struct {
+    int64_t kmv_launches;
+    double kmv_ms;
+    int64_t dquad_launches;
+    double dquad_ms;
+    int64_t solves;
+    int64_t kmv_passes;
+} gp_profile_stats;
+
+gp_status gp_profile(gp_handle* h, int32_t enable);
+gp_status gp_profile_read(gp_handle* h, gp_profile_stats* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -45,6 +45,11 @@ class gp_prior(Structure):
     _fields_ = [("kind", c_int32), ("reserved", c_int32), ("a", c_void_p), ("b", c_void_p)]
 
 
+class gp_profile_stats(Structure):
+    _fields_ = [("kmv_launches", c_int64), ("kmv_ms", c_double), ("dquad_launches", c_int64),
+                ("dquad_ms", c_double), ("solves", c_int64), ("kmv_passes", c_int64)]
+
+
 SYSSTAT_BYTES = ctypes.sizeof(ulisse_sysstat)
 
 _lib = None
@@ -91,6 +96,10 @@ def lib():
     L.gp_draw_probes.argtypes = [c_void_p, c_int64, c_int32, c_int32, c_uint64, c_uint64, c_void_p, c_int64, c_void_p]
     L.gp_philox.restype = c_int
     L.gp_philox.argtypes = [c_uint64, c_uint64, c_uint64, c_uint64, c_uint64, c_uint64, c_int64, c_void_p, c_void_p]
+    L.gp_profile.restype = c_int
+    L.gp_profile.argtypes = [c_void_p, c_int32]
+    L.gp_profile_read.restype = c_int
+    L.gp_profile_read.argtypes = [c_void_p, POINTER(gp_profile_stats)]
     _lib = L
     return L
 
@@ -272,3 +281,13 @@ def gp_philox(k0, k1, first_block, w1, w2, w3, nblocks, out=None, stream=None):
         out = torch.zeros(4 * nblocks, dtype=torch.int64, device="cuda")
     _check(lib().gp_philox(k0, k1, first_block, w1, w2, w3, nblocks, _ptr(out), _stream(stream)))
     return out
+
+
+def gp_profile(h, enable):
+    _check(lib().gp_profile(h.ptr, int(bool(enable))))
+
+
+def gp_profile_read(h):
+    st = gp_profile_stats()
+    _check(lib().gp_profile_read(h.ptr, ctypes.byref(st)))
+    return {f: getattr(st, f) for f, _ in gp_profile_stats._fields_}

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <algorithm>
+#include <vector>
 
 #include "gp_common.h"
 #include "internal.h"
@@ -41,7 +42,7 @@ gp_status fail(gp_status st, const char* fmt, ...) {
 enum Slot {
     kSlotZ, kSlotKP, kSlotVP, kSlotPart, kSlotQ, kSlotS, kSlotE, kSlotD, kSlotP1, kSlotP2,
     kSlotCounter, kSlotActive, kSlotState, kSlotStats, kSlotR, kSlotB, kSlotSt, kSlotS0,
-    kSlotA32, kSlotB32, kSlotGpart, kNumSlots
+    kSlotA32, kSlotB32, kSlotGpart, kSlotWork, kNumSlots
 };
 
 bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
@@ -55,6 +56,15 @@ struct gp_handle {
     size_t bytes[kNumSlots] = {};
     int* pinned = nullptr;  // two words: systems still running after iteration it (it % 2)
     hipEvent_t ev[2] = {nullptr, nullptr};
+    // kernel timing (gp_profile)
+    bool prof = false;
+    std::vector<hipEvent_t> pool;
+    std::vector<hipEvent_t> kmv_ev, dq_ev;  // start/stop pairs
+    int64_t solves = 0, passes = 0;
+    // work table of the gradient reduction currently in the workspace
+    int64_t work_npad = -1;
+    int work_L = -1;
+    void* work_ptr = nullptr;
 };
 
 namespace {
@@ -93,6 +103,42 @@ gp_status ws(gp_handle* h, int slot, size_t count, T** out) {
         gp_status s_ = (expr);          \
         if (s_ != GP_OK) return s_;     \
     } while (0)
+
+hipEvent_t take_event(gp_handle* h) {
+    if (!h->pool.empty()) {
+        hipEvent_t e = h->pool.back();
+        h->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Record a start event before a timed launch (nullptr when timing is off).
+hipEvent_t prof_start(gp_handle* h, hipStream_t s) {
+    if (!h->prof) return nullptr;
+    hipEvent_t e = take_event(h);
+    if (e) (void)hipEventRecord(e, s);
+    return e;
+}
+
+void prof_stop(gp_handle* h, hipEvent_t start, std::vector<hipEvent_t>& into, hipStream_t s) {
+    if (!start) return;
+    hipEvent_t e = take_event(h);
+    if (!e) return;
+    (void)hipEventRecord(e, s);
+    into.push_back(start);
+    into.push_back(e);
+}
+
+void prof_drop_last(gp_handle* h, std::vector<hipEvent_t>& v) {
+    if (v.size() < 2) return;
+    h->pool.push_back(v.back());
+    v.pop_back();
+    h->pool.push_back(v.back());
+    v.pop_back();
+}
 
 gp_status check_handle(gp_handle* h) {
     GP_CHECK(h != nullptr, "null handle");
@@ -145,7 +191,7 @@ gp_status solve_core(gp_handle* h, int64_t n, int d, const float* Z, const KPara
     a.m = m;
     a.mp = sh.mp;
     a.split = sh.split;
-    a.nb = (int)((n + kWG - 1) / kWG);
+    a.nb = solver_blocks(n);
     a.ldb = ldb;
     a.B = B;
     a.S0 = S0;
@@ -157,9 +203,10 @@ gp_status solve_core(gp_handle* h, int64_t n, int d, const float* Z, const KPara
     GP_TRY(ws(h, kSlotD, (size_t)n_pad * sh.mp, &a.D));
     GP_TRY(ws(h, kSlotP1, (size_t)a.nb * m, &a.part));
     GP_TRY(ws(h, kSlotP2, (size_t)a.nb * m, &a.part2));
-    GP_TRY(ws(h, kSlotCounter, 1, &a.counter));
     GP_TRY(ws(h, kSlotActive, 1, &a.n_active));
-    GP_TRY(ws(h, kSlotState, (size_t)m, &a.state));
+    SysState* states;
+    GP_TRY(ws(h, kSlotState, (size_t)2 * m, &states));
+    a.state = states;
     if (stats == nullptr) GP_TRY(ws(h, kSlotStats, (size_t)m, &stats));
     a.St = St;
     a.kpart = kpart;
@@ -179,21 +226,35 @@ gp_status solve_core(gp_handle* h, int64_t n, int d, const float* Z, const KPara
     const int warm = S0 != nullptr;
     if (warm) {
         GP_HIP(launch_pack_f64(S0, n, m, a.D, n_pad, s));
+        hipEvent_t t0 = prof_start(h, s);
         GP_HIP(launch_kmv_partials(sh, d, Z, a.D, kp, kpart, nullptr, p.prec, s));
+        prof_stop(h, t0, h->kmv_ev, s);
+        h->passes += 1;
     }
     GP_HIP(solver_init(a, warm, s));
     for (int it = 0; it <= p.max_iter; ++it) {
+        hipEvent_t t0 = prof_start(h, s);
         GP_HIP(launch_kmv_partials(sh, d, Z, a.D, kp, kpart, a.n_active, p.prec, s));
+        prof_stop(h, t0, h->kmv_ev, s);
         GP_HIP(solver_reduce(a, s));
         GP_HIP(solver_update(a, s));
-        GP_HIP(solver_direction(a, s));
+        SysState* next = states + ((it + 1) & 1) * m;
+        GP_HIP(solver_direction(a, next, s));
+        a.state = next;
         GP_HIP(hipMemcpyAsync(h->pinned + (it & 1), a.n_active, sizeof(int), hipMemcpyDeviceToHost, s));
         GP_HIP(hipEventRecord(h->ev[it & 1], s));
+        h->passes += 1;
         if (it >= 1) {
             GP_HIP(hipEventSynchronize(h->ev[(it - 1) & 1]));
-            if (h->pinned[(it - 1) & 1] == 0) break;
+            if (h->pinned[(it - 1) & 1] == 0) {
+                // this iteration's launches found no running system and did nothing
+                if (t0) prof_drop_last(h, h->kmv_ev);
+                h->passes -= 1;
+                break;
+            }
         }
     }
+    h->solves += 1;
     if (S_cg != nullptr) GP_HIP(solver_copy_s(a, S_cg, s));
     return GP_OK;
 }
@@ -233,6 +294,9 @@ void gp_destroy(gp_handle* h) {
     for (int i = 0; i < 2; ++i)
         if (h->ev[i]) (void)hipEventDestroy(h->ev[i]);
     if (h->pinned) (void)hipHostFree(h->pinned);
+    for (hipEvent_t e : h->pool) (void)hipEventDestroy(e);
+    for (hipEvent_t e : h->kmv_ev) (void)hipEventDestroy(e);
+    for (hipEvent_t e : h->dq_ev) (void)hipEventDestroy(e);
     delete h;
 }
 
@@ -253,7 +317,9 @@ gp_status gp_kmv(gp_handle* h, gp_data X, const double* psi, const float* V, int
     GP_TRY(ws(h, kSlotVP, (size_t)sh.n_pad * sh.mp, &Vp));
     GP_TRY(ws(h, kSlotPart, (size_t)sh.split * sh.mp * sh.n_pad, &part));
     GP_HIP(launch_pack(V, X.n, m, ldv, Vp, sh.n_pad, sh.mp, s));
+    hipEvent_t t0 = prof_start(h, s);
     GP_HIP(launch_kmv_partials(sh, X.d, Z, Vp, kp, part, nullptr, prec, s));
+    prof_stop(h, t0, h->kmv_ev, s);
     GP_HIP(launch_kmv_reduce(sh, part, Vp, kp, X.n, m, out, ldo, s));
     return GP_OK;
 }
@@ -358,9 +424,61 @@ gp_status gp_stoch_grad(gp_handle* h, gp_data X, const double* psi, const float*
     GP_TRY(ws(h, kSlotA32, (size_t)dq.n_pad * dq.mq4, &A32));
     GP_TRY(ws(h, kSlotB32, (size_t)dq.n_pad * dq.mq4, &B32));
     GP_TRY(ws(h, kSlotGpart, (size_t)dq.nwg * (d + 1), &gpart));
+    int2* work;
+    GP_TRY(ws(h, kSlotWork, (size_t)dq.nwg, &work));
+    if (h->work_npad != dq.n_pad || h->work_L != dq.chunk || h->work_ptr != (void*)work) {
+        std::vector<int2> tab;
+        dquad_work(dq, tab);
+        GP_HIP(hipStreamSynchronize(s));
+        GP_HIP(hipMemcpy(work, tab.data(), tab.size() * sizeof(int2), hipMemcpyHostToDevice));
+        h->work_npad = dq.n_pad;
+        h->work_L = dq.chunk;
+        h->work_ptr = work;
+    }
     GP_HIP(launch_build_ab(St, Rp, n, n, n_probes, A32, B32, dq.n_pad, dq.mq4, s));
-    GP_HIP(launch_dquad(dq, d, Z, A32, B32, kp, gpart, s));
-    GP_HIP(launch_grad_finish(St, Rp, n, n, n_probes, gpart, dq.nwg, d, kp, g, s));
+    hipEvent_t t0 = prof_start(h, s);
+    GP_HIP(launch_dquad(dq, d, Z, A32, B32, kp, work, gpart, s));
+    prof_stop(h, t0, h->dq_ev, s);
+    double* dpart;
+    GP_TRY(ws(h, kSlotP2, (size_t)solver_blocks(n), &dpart));
+    GP_HIP(launch_grad_finish(St, Rp, n, n, n_probes, gpart, dq.nwg, d, kp, dpart, g, s));
+    return GP_OK;
+}
+
+gp_status gp_profile(gp_handle* h, int32_t enable) {
+    GP_TRY(check_handle(h));
+    if (enable) {
+        for (hipEvent_t e : h->kmv_ev) h->pool.push_back(e);
+        for (hipEvent_t e : h->dq_ev) h->pool.push_back(e);
+        h->kmv_ev.clear();
+        h->dq_ev.clear();
+        h->solves = h->passes = 0;
+    }
+    h->prof = enable != 0;
+    return GP_OK;
+}
+
+gp_status gp_profile_read(gp_handle* h, gp_profile_stats* out) {
+    GP_TRY(check_handle(h));
+    GP_CHECK(out != nullptr, "null output");
+    auto total = [&](const std::vector<hipEvent_t>& v, double* ms) -> gp_status {
+        *ms = 0.0;
+        for (size_t k = 0; k + 1 < v.size(); k += 2) {
+            GP_HIP(hipEventSynchronize(v[k + 1]));
+            float t = 0.f;
+            GP_HIP(hipEventElapsedTime(&t, v[k], v[k + 1]));
+            *ms += t;
+        }
+        return GP_OK;
+    };
+    gp_profile_stats r{};
+    GP_TRY(total(h->kmv_ev, &r.kmv_ms));
+    GP_TRY(total(h->dq_ev, &r.dquad_ms));
+    r.kmv_launches = (int64_t)(h->kmv_ev.size() / 2);
+    r.dquad_launches = (int64_t)(h->dq_ev.size() / 2);
+    r.solves = h->solves;
+    r.kmv_passes = h->passes;
+    *out = r;
     return GP_OK;
 }
 

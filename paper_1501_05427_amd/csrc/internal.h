@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "gp_common.h"
 #include "ulisse_gp.h"
 
@@ -47,17 +49,21 @@ hipError_t launch_dkmv(const KmvShape& sh, int d, const float* Z, const float* V
 size_t dkmv_part_floats(const KmvShape& sh, int d);
 
 // Fused gradient reduction g_j = sum_ik dK_j(i,k) G(i,k), G = A B^T (A, B: n_pad x mq4,
-// ld n_pad, zero padded).  Writes per-workgroup FP64 partials for j = 0..d.
+// ld n_pad, zero padded), over the upper triangle of tiles.  Writes per-workgroup FP64
+// partials for j = 0..d at gpart[j * nwg + workgroup].  The work table lists (row tile, first column tile) per
+// workgroup; dquad_work builds it on the host.
 struct DquadShape {
     int mq4;          // padded column count of A and B (multiple of 16)
-    int rows_per_wg;
-    int split;
-    int chunk;
+    int rows_per_wg;  // rows of a row tile (64)
+    int split;        // unused
+    int chunk;        // column tiles per workgroup (L)
     int64_t n_pad;
     int nwg;
 };
 DquadShape dquad_shape(int64_t n, int d, int mcols);
+void dquad_work(const DquadShape& sh, std::vector<int2>& work);
 hipError_t launch_dquad(const DquadShape& sh, int d, const float* Z, const float* A,
-                        const float* B, const KParams* kp, double* gpart, hipStream_t s);
+                        const float* B, const KParams* kp, const int2* work, double* gpart,
+                        hipStream_t s);
 
 }  // namespace gpk

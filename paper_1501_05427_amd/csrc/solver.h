@@ -26,7 +26,7 @@ struct SysState {
     int32_t ntracks;
     int32_t l, iters, flags;
     int32_t active;    // the CG run of this system continues
-    int32_t apply;     // alpha of the current iteration is valid
+    int32_t apply;     // unused (kept for layout)
 };
 
 // Column of the series estimate of track t of system c in the output block.
@@ -39,7 +39,7 @@ struct SolverArgs {
     int32_t m;       // systems
     int32_t mp;      // padded columns of the product partials
     int32_t split;   // chunks of the product partials
-    int32_t nb;      // workgroups of the vector kernels (256 rows each)
+    int32_t nb;      // row blocks of the vector kernels (solver_blocks(n))
     int64_t ldb;
     const float* B;
     const double* S0;
@@ -52,19 +52,20 @@ struct SolverArgs {
     const KParams* kp;
     double* part;
     double* part2;
-    unsigned* counter;
     int* n_active;
-    SysState* state;
+    SysState* state;  // state read by the kernels of the current iteration
     ulisse_sysstat* stats;
     double q, rate, eps;
     int32_t eps_relative, max_iter, two_track, pad_;
     uint64_t seed, rng_stream, rng_counter;
 };
 
+int solver_blocks(int64_t n);
 hipError_t solver_init(const SolverArgs& a, int warm, hipStream_t s);
 hipError_t solver_reduce(const SolverArgs& a, hipStream_t s);
 hipError_t solver_update(const SolverArgs& a, hipStream_t s);
-hipError_t solver_direction(const SolverArgs& a, hipStream_t s);
+// Reads the state at a.state and writes the advanced state to `next`.
+hipError_t solver_direction(const SolverArgs& a, SysState* next, hipStream_t s);
 hipError_t solver_copy_s(const SolverArgs& a, double* out, hipStream_t s);
 hipError_t launch_pack_f64(const double* S0, int64_t n, int m, float* D, int64_t n_pad,
                            hipStream_t s);
@@ -75,9 +76,10 @@ hipError_t launch_philox(uint64_t k0, uint64_t k1, uint64_t first, uint64_t w1, 
 hipError_t launch_build_ab(const double* St, const float* R, int64_t ldr, int64_t n,
                            int nprobes, float* A, float* Bm, int64_t n_pad, int mq4,
                            hipStream_t s);
+// dpart: solver_blocks(n) doubles of scratch.
 hipError_t launch_grad_finish(const double* St, const float* R, int64_t ldr, int64_t n,
                               int nprobes, const double* gpart, int nwg, int d,
-                              const KParams* kp, double* g, hipStream_t s);
+                              const KParams* kp, double* dpart, double* g, hipStream_t s);
 hipError_t launch_sgld(int P, double* psi, const double* g, int prior_kind, const double* pa,
                        const double* pb, const double* L, double eps, uint64_t k0,
                        uint64_t k1, uint64_t step, hipStream_t s);

@@ -17,33 +17,6 @@
 
 namespace gpk {
 
-// Sum of the per-workgroup column partials; one thread per system, fixed order.
-__device__ inline double sum_partials(const double* __restrict__ part, int nb, int m, int c) {
-    double s = 0.0;
-    for (int b = 0; b < nb; ++b) s += part[(int64_t)b * m + c];
-    return s;
-}
-
-// Wave-level partial of every column into red[wave][c], then one barrier and the
-// per-column workgroup total written to part[blockIdx.x * m + c].
-__device__ inline void column_partials(double v, int c, double (*red)[kMaxSys]) {
-    const double w = wave_sum(v);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][c] = w;
-}
-
-__device__ inline bool last_block(unsigned* counter) {
-    __shared__ bool last;
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const unsigned prev = atomicAdd(counter, 1u);
-        last = (prev == gridDim.x - 1);
-    }
-    __syncthreads();
-    if (last) __threadfence();
-    return last;
-}
-
 __device__ inline void write_stat(const SysState& st, ulisse_sysstat* out) {
     ulisse_sysstat r;
     r.l = st.l;
@@ -56,130 +29,158 @@ __device__ inline void write_stat(const SysState& st, ulisse_sysstat* out) {
     *out = r;
 }
 
-// ---------------------------------------------------------------------------------------
-// Initialisation: e = b - K s0, d = e, s~ = s0, rho = e^T e.
-// ---------------------------------------------------------------------------------------
-__global__ __launch_bounds__(kWG) void ulisse_init_kernel(SolverArgs a, int warm) {
-    __shared__ double red[4][kMaxSys];
-    __shared__ double red2[4][kMaxSys];
-    const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
-    const bool in = i < a.n;
-    for (int c = 0; c < a.m; ++c) {
-        double e = 0.0, b = 0.0;
-        if (in) {
-            b = (double)a.B[c * a.ldb + i];
-            const double s0 = warm ? a.S0[c * a.n + i] : 0.0;
-            if (warm) {  // K s0 from the chunk partials of the product with fp32(s0) in D
-                double kq = 0.0;
-                for (int k = 0; k < a.split; ++k) kq += (double)a.kpart[((int64_t)k * a.mp + c) * a.n_pad + i];
-                kq += a.kp->lam64 * (double)a.D[c * a.n_pad + i];
-                e = b - kq;
-            } else {
-                e = b;
-            }
-            a.S[c * a.n_pad + i] = s0;
-            a.E[c * a.n_pad + i] = e;
-            a.D[c * a.n_pad + i] = (float)e;
-            const int nt = (a.two_track && c == 0) ? 2 : 1;
-            for (int t = 0; t < nt; ++t) a.St[(int64_t)sys_col(a.two_track, c, t) * a.n + i] = s0;
-        }
-        column_partials(e * e, c, red);
-        column_partials(b * b, c, red2);
+// The vector kernels run on a (row block, system) grid: blockIdx.x covers kRowsPerBlock
+// rows (kRowsPerThread per thread, strided by the workgroup size), blockIdx.y is the
+// system.  Each workgroup leaves one FP64 partial per reduction in part[bx * m + c].
+// A later kernel combines the partials of a column in every workgroup that needs the
+// total, with the same fixed order everywhere (wave 0: lane-strided sums, then an xor
+// butterfly), so all workgroups see bit-identical scalars and take the same decisions
+// without any grid-wide synchronisation.  The per-system state is double buffered: the
+// direction kernel reads `cur` and its row-block-0 workgroup writes `next`.
+constexpr int kRowsPerThread = 4;
+constexpr int kRowsPerBlock = kWG * kRowsPerThread;
+
+__device__ inline double column_total(const double* __restrict__ part, int nb, int m, int c,
+                                      double* bcast) {
+    if (threadIdx.x < 64) {
+        double s = 0.0;
+        for (int b = threadIdx.x; b < nb; b += 64) s += part[(int64_t)b * m + c];
+        s = wave_sum(s);
+        if (threadIdx.x == 0) *bcast = s;
     }
     __syncthreads();
-    if (threadIdx.x < a.m) {
-        const int c = threadIdx.x;
-        a.part[(int64_t)blockIdx.x * a.m + c] = (red[0][c] + red[1][c]) + (red[2][c] + red[3][c]);
-        a.part2[(int64_t)blockIdx.x * a.m + c] = (red2[0][c] + red2[1][c]) + (red2[2][c] + red2[3][c]);
-    }
-    if (!last_block(a.counter)) return;
-    if (threadIdx.x < a.m) {
-        const int c = threadIdx.x;
-        const double rho = sum_partials(a.part, gridDim.x, a.m, c);
-        const double bb = sum_partials(a.part2, gridDim.x, a.m, c);
-        SysState st;
-        st.rho = rho;
-        st.alpha = 0.0;
-        st.beta = 0.0;
-        st.thr_alpha = a.q * sqrt((double)a.n);
-        st.thr_eps = a.eps_relative ? a.eps * sqrt(bb) : a.eps;
-        st.res = sqrt(rho);
-        st.ntracks = (a.two_track && c == 0) ? 2 : 1;
-        for (int t = 0; t < 2; ++t) {
-            st.W[t] = t < st.ntracks ? 1.0 : 0.0;
-            st.phase[t] = t < st.ntracks ? kPre : kDone;
-            st.j[t] = 0;
-        }
-        st.l = 0;
-        st.iters = 0;
-        st.flags = 0;
-        st.active = 1;
-        st.apply = 0;
-        a.state[c] = st;
-    }
-    if (threadIdx.x == 0) {
-        *a.n_active = a.m;
-        *a.counter = 0u;
-    }
+    const double v = *bcast;
+    __syncthreads();
+    return v;
 }
 
 // ---------------------------------------------------------------------------------------
-// After the covariance product: Q = sum of chunk partials + lambda d (FP64), gamma = d^T Q,
-// alpha = rho / gamma.
+// Initialisation: e = b - K s0, d = e, s~ = s0; partials of e^T e and b^T b.
+// ---------------------------------------------------------------------------------------
+__global__ __launch_bounds__(kWG) void ulisse_init_kernel(SolverArgs a, int warm) {
+    __shared__ double scratch[4];
+    const int c = blockIdx.y;
+    const int nt = (a.two_track && c == 0) ? 2 : 1;
+    double ee = 0.0, bb = 0.0;
+#pragma unroll
+    for (int r = 0; r < kRowsPerThread; ++r) {
+        const int64_t i = (int64_t)blockIdx.x * kRowsPerBlock + r * kWG + threadIdx.x;
+        if (i >= a.n) break;
+        const double b = (double)a.B[c * a.ldb + i];
+        const double s0 = warm ? a.S0[c * a.n + i] : 0.0;
+        double e = b;
+        if (warm) {  // K s0 from the chunk partials of the product with fp32(s0) held in D
+            double kq = 0.0;
+            for (int k = 0; k < a.split; ++k) kq += (double)a.kpart[((int64_t)k * a.mp + c) * a.n_pad + i];
+            kq += a.kp->lam64 * (double)a.D[c * a.n_pad + i];
+            e = b - kq;
+        }
+        a.S[c * a.n_pad + i] = s0;
+        a.E[c * a.n_pad + i] = e;
+        a.D[c * a.n_pad + i] = (float)e;
+        for (int t = 0; t < nt; ++t) a.St[(int64_t)sys_col(a.two_track, c, t) * a.n + i] = s0;
+        ee += e * e;
+        bb += b * b;
+    }
+    ee = block_sum256(ee, scratch);
+    bb = block_sum256(bb, scratch);
+    if (threadIdx.x == 0) {
+        a.part[(int64_t)blockIdx.x * a.m + c] = ee;
+        a.part2[(int64_t)blockIdx.x * a.m + c] = bb;
+    }
+}
+
+// One workgroup per system: thresholds, rho_0 and the initial state.
+__global__ __launch_bounds__(kWG) void ulisse_init_state_kernel(SolverArgs a) {
+    __shared__ double bcast;
+    const int c = blockIdx.x;
+    const double rho = column_total(a.part, a.nb, a.m, c, &bcast);
+    const double b2 = column_total(a.part2, a.nb, a.m, c, &bcast);
+    if (threadIdx.x != 0) return;
+    SysState st;
+    st.rho = rho;
+    st.alpha = 0.0;
+    st.beta = 0.0;
+    st.thr_alpha = a.q * sqrt((double)a.n);
+    st.thr_eps = a.eps_relative ? a.eps * sqrt(b2) : a.eps;
+    st.res = sqrt(rho);
+    st.ntracks = (a.two_track && c == 0) ? 2 : 1;
+    for (int t = 0; t < 2; ++t) {
+        st.W[t] = t < st.ntracks ? 1.0 : 0.0;
+        st.phase[t] = t < st.ntracks ? kPre : kDone;
+        st.j[t] = 0;
+    }
+    st.l = 0;
+    st.iters = 0;
+    st.flags = 0;
+    st.active = 1;
+    st.apply = 0;
+    a.state[c] = st;
+    if (c == 0) *a.n_active = a.m;
+}
+
+// ---------------------------------------------------------------------------------------
+// After the covariance product: Q = sum of chunk partials + lambda d (FP64); partials of
+// gamma = d^T Q.
 // ---------------------------------------------------------------------------------------
 __global__ __launch_bounds__(kWG) void ulisse_reduce_kernel(SolverArgs a) {
     if (*a.n_active == 0) return;
-    __shared__ double red[4][kMaxSys];
-    const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
-    const bool in = i < a.n;
+    __shared__ double scratch[4];
+    const int c = blockIdx.y;
+    if (!a.state[c].active) return;  // uniform over the workgroup
     const double lam = a.kp->lam64;
-    for (int c = 0; c < a.m; ++c) {
-        if (!a.state[c].active) continue;  // uniform over the workgroup
-        double dq = 0.0;
-        if (in) {
-            double s = 0.0;
-            for (int k = 0; k < a.split; ++k) s += (double)a.kpart[((int64_t)k * a.mp + c) * a.n_pad + i];
-            const double dv = (double)a.D[c * a.n_pad + i];
-            s += lam * dv;
-            a.Q[c * a.n_pad + i] = s;
-            dq = dv * s;
-        }
-        column_partials(dq, c, red);
+    double dq = 0.0;
+#pragma unroll
+    for (int r = 0; r < kRowsPerThread; ++r) {
+        const int64_t i = (int64_t)blockIdx.x * kRowsPerBlock + r * kWG + threadIdx.x;
+        if (i >= a.n) break;
+        double s = 0.0;
+        for (int k = 0; k < a.split; ++k) s += (double)a.kpart[((int64_t)k * a.mp + c) * a.n_pad + i];
+        const double dv = (double)a.D[c * a.n_pad + i];
+        s += lam * dv;
+        a.Q[c * a.n_pad + i] = s;
+        dq += dv * s;
     }
-    __syncthreads();
-    if (threadIdx.x < a.m && a.state[threadIdx.x].active) {
-        const int c = threadIdx.x;
-        a.part[(int64_t)blockIdx.x * a.m + c] = (red[0][c] + red[1][c]) + (red[2][c] + red[3][c]);
+    dq = block_sum256(dq, scratch);
+    if (threadIdx.x == 0) a.part[(int64_t)blockIdx.x * a.m + c] = dq;
+}
+
+__device__ inline bool alpha_ok(double gamma, double alpha) { return gamma > 0.0 && isfinite(alpha); }
+
+// ---------------------------------------------------------------------------------------
+// alpha = rho / gamma; delta = alpha d;  s += delta;  e -= alpha Q;  s~_t += W_t delta;
+// partials of rho' = e^T e.  A breakdown (gamma <= 0 or alpha not finite) skips the update;
+// the direction kernel records it.
+// ---------------------------------------------------------------------------------------
+__global__ __launch_bounds__(kWG) void ulisse_update_kernel(SolverArgs a) {
+    if (*a.n_active == 0) return;
+    __shared__ double scratch[4];
+    __shared__ double bcast;
+    const int c = blockIdx.y;
+    const SysState& st0 = a.state[c];
+    if (!st0.active) return;  // uniform over the workgroup
+    const double gamma = column_total(a.part, a.nb, a.m, c, &bcast);
+    const double al = st0.rho / gamma;
+    if (!alpha_ok(gamma, al)) return;
+    const int nt = st0.ntracks;
+    const double W0 = st0.W[0], W1 = st0.W[1];
+    double* st_a = a.St + (int64_t)sys_col(a.two_track, c, 0) * a.n;
+    double* st_b = a.St + (int64_t)sys_col(a.two_track, c, 1) * a.n;
+    double ee = 0.0;
+#pragma unroll
+    for (int r = 0; r < kRowsPerThread; ++r) {
+        const int64_t i = (int64_t)blockIdx.x * kRowsPerBlock + r * kWG + threadIdx.x;
+        if (i >= a.n) break;
+        const double delta = al * (double)a.D[c * a.n_pad + i];
+        a.S[c * a.n_pad + i] += delta;
+        const double e = a.E[c * a.n_pad + i] - al * a.Q[c * a.n_pad + i];
+        a.E[c * a.n_pad + i] = e;
+        ee += e * e;
+        if (W0 != 0.0) st_a[i] += W0 * delta;
+        if (nt > 1 && W1 != 0.0) st_b[i] += W1 * delta;
     }
-    if (!last_block(a.counter)) return;
-    if (threadIdx.x < a.m) {
-        const int c = threadIdx.x;
-        SysState& st = a.state[c];
-        if (st.active) {
-            const double gamma = sum_partials(a.part, gridDim.x, a.m, c);
-            const double alpha = st.rho / gamma;
-            if (!(gamma > 0.0) || !isfinite(alpha)) {
-                st.apply = 0;
-                st.active = 0;
-                st.flags |= (int)ULISSE_BREAKDOWN;
-                for (int t = 0; t < 2; ++t) {
-                    st.phase[t] = kDone;
-                    st.W[t] = 0.0;
-                }
-                write_stat(st, a.stats + c);
-            } else {
-                st.apply = 1;
-                st.alpha = alpha;
-            }
-        }
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int cnt = 0;
-        for (int c = 0; c < a.m; ++c) cnt += a.state[c].active;
-        *a.n_active = cnt;
-        *a.counter = 0u;
-    }
+    ee = block_sum256(ee, scratch);
+    if (threadIdx.x == 0) a.part2[(int64_t)blockIdx.x * a.m + c] = ee;
 }
 
 // u_j of track t of system c: word j of Philox stream (key (seed, stream), counter
@@ -210,96 +211,83 @@ __device__ inline void tail_decide(const SolverArgs& a, SysState& st, int c, int
     if (st.phase[t] == kDone) st.W[t] = 0.0;
 }
 
-// ---------------------------------------------------------------------------------------
-// delta = alpha d;  s += delta;  e -= alpha Q;  s~_t += W_t delta;  rho' = e^T e, then the
-// per-system decisions and beta = rho' / rho.
-// ---------------------------------------------------------------------------------------
-__global__ __launch_bounds__(kWG) void ulisse_update_kernel(SolverArgs a) {
-    if (*a.n_active == 0) return;
-    __shared__ double red[4][kMaxSys];
-    const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
-    const bool in = i < a.n;
-    for (int c = 0; c < a.m; ++c) {
-        const SysState& st = a.state[c];
-        if (!st.active || !st.apply) continue;
-        double ee = 0.0;
-        if (in) {
-            const double al = st.alpha;
-            const double delta = al * (double)a.D[c * a.n_pad + i];
-            a.S[c * a.n_pad + i] += delta;
-            const double e = a.E[c * a.n_pad + i] - al * a.Q[c * a.n_pad + i];
-            a.E[c * a.n_pad + i] = e;
-            ee = e * e;
-            for (int t = 0; t < st.ntracks; ++t)
-                if (st.W[t] != 0.0) a.St[(int64_t)sys_col(a.two_track, c, t) * a.n + i] += st.W[t] * delta;
+// The per-system decisions after one CG iteration (threshold l, tail draws, convergence,
+// iteration cap, breakdown), applied to a copy of the state.
+__device__ inline void advance(const SolverArgs& a, SysState& st, int c, double gamma,
+                               double rho_new) {
+    const double al = st.rho / gamma;
+    if (!alpha_ok(gamma, al)) {
+        st.flags |= (int)ULISSE_BREAKDOWN;
+        for (int t = 0; t < 2; ++t) {
+            st.phase[t] = kDone;
+            st.W[t] = 0.0;
         }
-        column_partials(ee, c, red);
+        st.active = 0;
+        return;
     }
-    __syncthreads();
-    if (threadIdx.x < a.m) {
-        const int c = threadIdx.x;
-        if (a.state[c].active && a.state[c].apply)
-            a.part[(int64_t)blockIdx.x * a.m + c] = (red[0][c] + red[1][c]) + (red[2][c] + red[3][c]);
-    }
-    if (!last_block(a.counter)) return;
-    if (threadIdx.x < a.m) {
-        const int c = threadIdx.x;
-        SysState st = a.state[c];
-        if (st.active && st.apply) {
-            const double rho_new = sum_partials(a.part, gridDim.x, a.m, c);
-            st.res = sqrt(rho_new);
-            st.iters += 1;
-            for (int t = 0; t < st.ntracks; ++t) {
-                if (st.phase[t] == kDone) continue;
-                if (st.phase[t] == kPre) {
-                    if (st.res < st.thr_alpha || st.res < st.thr_eps) {
-                        st.l = st.iters;  // this increment was delta_l, kept with W_0 = 1
-                        st.j[t] = 0;
-                        tail_decide(a, st, c, t);
-                    } else if (st.iters >= a.max_iter) {
-                        st.phase[t] = kDone;
-                        st.W[t] = 0.0;
-                        st.flags |= (int)ULISSE_NOTCONV;
-                    }
-                } else {
-                    tail_decide(a, st, c, t);
-                }
+    st.alpha = al;
+    st.res = sqrt(rho_new);
+    st.iters += 1;
+    for (int t = 0; t < st.ntracks; ++t) {
+        if (st.phase[t] == kDone) continue;
+        if (st.phase[t] == kPre) {
+            if (st.res < st.thr_alpha || st.res < st.thr_eps) {
+                st.l = st.iters;  // this increment was delta_l, kept with W_0 = 1
+                st.j[t] = 0;
+                tail_decide(a, st, c, t);
+            } else if (st.iters >= a.max_iter) {
+                st.phase[t] = kDone;
+                st.W[t] = 0.0;
+                st.flags |= (int)ULISSE_NOTCONV;
             }
-            bool done = true;
-            for (int t = 0; t < st.ntracks; ++t) done = done && st.phase[t] == kDone;
-            if (!isfinite(rho_new)) {
-                done = true;
-                st.flags |= (int)ULISSE_BREAKDOWN;
-            }
-            st.beta = rho_new / st.rho;
-            st.rho = rho_new;
-            st.apply = 0;
-            if (done) {
-                st.active = 0;
-                write_stat(st, a.stats + c);
-            }
-            a.state[c] = st;
+        } else {
+            tail_decide(a, st, c, t);
         }
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int cnt = 0;
-        for (int c = 0; c < a.m; ++c) cnt += a.state[c].active;
-        *a.n_active = cnt;
-        *a.counter = 0u;
+    bool done = true;
+    for (int t = 0; t < st.ntracks; ++t) done = done && st.phase[t] == kDone;
+    if (!isfinite(rho_new)) {
+        done = true;
+        st.flags |= (int)ULISSE_BREAKDOWN;
     }
+    st.beta = rho_new / st.rho;
+    st.rho = rho_new;
+    if (done) st.active = 0;
 }
 
-// d = e + beta d (rounded to FP32 for the next covariance product).
-__global__ __launch_bounds__(kWG) void ulisse_direction_kernel(SolverArgs a) {
+// ---------------------------------------------------------------------------------------
+// Decisions and d = e + beta d (rounded to FP32 for the next covariance product).  Every
+// workgroup of a system derives the same new state; the one with blockIdx.x == 0 stores it
+// (and the statistics when the system stops).
+// ---------------------------------------------------------------------------------------
+__global__ __launch_bounds__(kWG) void ulisse_direction_kernel(SolverArgs a, const SysState* cur,
+                                                               SysState* next) {
     if (*a.n_active == 0) return;
-    const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
-    if (i >= a.n) return;
-    for (int c = 0; c < a.m; ++c) {
-        const SysState& st = a.state[c];
-        if (!st.active) continue;
+    __shared__ double bcast;
+    const int c = blockIdx.y;
+    SysState st = cur[c];
+    if (!st.active) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) next[c] = st;
+        return;
+    }
+    const double gamma = column_total(a.part, a.nb, a.m, c, &bcast);
+    const double rho_new = column_total(a.part2, a.nb, a.m, c, &bcast);
+    advance(a, st, c, gamma, rho_new);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        next[c] = st;
+        if (!st.active) {
+            write_stat(st, a.stats + c);
+            atomicSub(a.n_active, 1);
+        }
+    }
+    if (!st.active) return;
+    const double beta = st.beta;
+#pragma unroll
+    for (int r = 0; r < kRowsPerThread; ++r) {
+        const int64_t i = (int64_t)blockIdx.x * kRowsPerBlock + r * kWG + threadIdx.x;
+        if (i >= a.n) break;
         const int64_t o = c * a.n_pad + i;
-        a.D[o] = (float)(a.E[o] + st.beta * (double)a.D[o]);
+        a.D[o] = (float)(a.E[o] + beta * (double)a.D[o]);
     }
 }
 
@@ -389,28 +377,46 @@ __global__ void build_ab_kernel(const double* __restrict__ St, const float* __re
     }
 }
 
-// Diagonal (noise) term sum_i G_ii in FP64 from the FP64 solutions, then the final
-// fixed-order sum of the tile partials: g_0, 2 ln 2 * (g_1..g_d), lambda * diag.
-__global__ __launch_bounds__(kWG) void grad_finish_kernel(
-    const double* __restrict__ St, const float* __restrict__ R, int64_t ldr, int64_t n,
-    int nprobes, const double* __restrict__ gpart, int nwg, int d,
-    const KParams* __restrict__ kp, double* __restrict__ g) {
+// Per-workgroup partials of the diagonal (noise) term sum_i G_ii in FP64 from the FP64
+// solutions: G_ii = 1/2 s_a,i s_b,i - 1/(2 N_r) sum_c r_c,i s_c,i.
+__global__ __launch_bounds__(kWG) void grad_diag_kernel(const double* __restrict__ St,
+                                                        const float* __restrict__ R, int64_t ldr,
+                                                        int64_t n, int nprobes,
+                                                        double* __restrict__ dpart) {
     __shared__ double scratch[4];
-    double acc = 0.0;
     const double w = 1.0 / (2.0 * nprobes);
-    for (int64_t i = threadIdx.x; i < n; i += kWG) {
+    double acc = 0.0;
+#pragma unroll
+    for (int r = 0; r < kRowsPerThread; ++r) {
+        const int64_t i = (int64_t)blockIdx.x * kRowsPerBlock + r * kWG + threadIdx.x;
+        if (i >= n) break;
         double v = 0.5 * St[i] * St[n + i];
-        for (int c = 0; c < nprobes; ++c) v -= w * (double)R[c * ldr + i] * St[(int64_t)(c + 2) * n + i];
-        acc += v;
+        double t = 0.0;
+        for (int c = 0; c < nprobes; ++c) t += (double)R[c * ldr + i] * St[(int64_t)(c + 2) * n + i];
+        acc += v - w * t;
     }
-    const double diag = block_sum256(acc, scratch);
-    if (threadIdx.x <= d) {
-        const int p = threadIdx.x;
+    acc = block_sum256(acc, scratch);
+    if (threadIdx.x == 0) dpart[blockIdx.x] = acc;
+}
+
+// Final fixed-order sums: g_0, 2 ln 2 * (g_1..g_d) from the tile partials and
+// lambda * (diagonal term) from its partials.
+__global__ __launch_bounds__(kWG) void grad_finish_kernel(const double* __restrict__ gpart,
+                                                          int nwg, int d,
+                                                          const double* __restrict__ dpart,
+                                                          int ndb, const KParams* __restrict__ kp,
+                                                          double* __restrict__ g) {
+    __shared__ double scratch[4];
+    for (int p = 0; p <= d; ++p) {
         double s = 0.0;
-        for (int b = 0; b < nwg; ++b) s += gpart[(int64_t)b * (d + 1) + p];
-        g[p] = p == 0 ? s : 2.0 * M_LN2 * s;
+        for (int b = threadIdx.x; b < nwg; b += kWG) s += gpart[(int64_t)p * nwg + b];
+        s = block_sum256(s, scratch);
+        if (threadIdx.x == 0) g[p] = p == 0 ? s : 2.0 * M_LN2 * s;
     }
-    if (threadIdx.x == 0) g[d + 1] = kp->lam64 * diag;
+    double s = 0.0;
+    for (int b = threadIdx.x; b < ndb; b += kWG) s += dpart[b];
+    s = block_sum256(s, scratch);
+    if (threadIdx.x == 0) g[d + 1] = kp->lam64 * s;
 }
 
 // ---------------------------------------------------------------------------------------
@@ -460,20 +466,27 @@ static int grid_of(int64_t total) {
     return (int)std::max<int64_t>(1, std::min<int64_t>((total + kWG - 1) / kWG, 65536));
 }
 
+static dim3 vec_grid(const SolverArgs& a) { return dim3((unsigned)a.nb, (unsigned)a.m); }
+
+int solver_blocks(int64_t n) { return (int)((n + kRowsPerBlock - 1) / kRowsPerBlock); }
+
 hipError_t solver_init(const SolverArgs& a, int warm, hipStream_t s) {
-    ulisse_init_kernel<<<(unsigned)a.nb, kWG, 0, s>>>(a, warm);
+    ulisse_init_kernel<<<vec_grid(a), kWG, 0, s>>>(a, warm);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    ulisse_init_state_kernel<<<(unsigned)a.m, kWG, 0, s>>>(a);
     return hipGetLastError();
 }
 hipError_t solver_reduce(const SolverArgs& a, hipStream_t s) {
-    ulisse_reduce_kernel<<<(unsigned)a.nb, kWG, 0, s>>>(a);
+    ulisse_reduce_kernel<<<vec_grid(a), kWG, 0, s>>>(a);
     return hipGetLastError();
 }
 hipError_t solver_update(const SolverArgs& a, hipStream_t s) {
-    ulisse_update_kernel<<<(unsigned)a.nb, kWG, 0, s>>>(a);
+    ulisse_update_kernel<<<vec_grid(a), kWG, 0, s>>>(a);
     return hipGetLastError();
 }
-hipError_t solver_direction(const SolverArgs& a, hipStream_t s) {
-    ulisse_direction_kernel<<<(unsigned)a.nb, kWG, 0, s>>>(a);
+hipError_t solver_direction(const SolverArgs& a, SysState* next, hipStream_t s) {
+    ulisse_direction_kernel<<<vec_grid(a), kWG, 0, s>>>(a, a.state, next);
     return hipGetLastError();
 }
 hipError_t solver_copy_s(const SolverArgs& a, double* out, hipStream_t s) {
@@ -503,8 +516,12 @@ hipError_t launch_build_ab(const double* St, const float* R, int64_t ldr, int64_
 }
 hipError_t launch_grad_finish(const double* St, const float* R, int64_t ldr, int64_t n,
                               int nprobes, const double* gpart, int nwg, int d,
-                              const KParams* kp, double* g, hipStream_t s) {
-    grad_finish_kernel<<<1, kWG, 0, s>>>(St, R, ldr, n, nprobes, gpart, nwg, d, kp, g);
+                              const KParams* kp, double* dpart, double* g, hipStream_t s) {
+    const int ndb = solver_blocks(n);
+    grad_diag_kernel<<<ndb, kWG, 0, s>>>(St, R, ldr, n, nprobes, dpart);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    grad_finish_kernel<<<1, kWG, 0, s>>>(gpart, nwg, d, dpart, ndb, kp, g);
     return hipGetLastError();
 }
 hipError_t launch_sgld(int P, double* psi, const double* g, int prior_kind, const double* pa,

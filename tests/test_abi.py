@@ -19,7 +19,8 @@ def lib():
 def test_header_declares_the_boundary():
     names = binding.header_functions()
     for f in ["gp_create", "gp_destroy", "gp_last_error", "gp_kmv", "gp_dkmv", "ulisse_solve",
-              "gp_stoch_grad", "sgld_step", "gp_draw_probes", "gp_philox"]:
+              "gp_stoch_grad", "sgld_step", "gp_draw_probes", "gp_philox", "gp_profile",
+              "gp_profile_read"]:
         assert f in names, f
 
 
@@ -31,7 +32,8 @@ def test_every_declared_symbol_is_exported(lib):
 def test_struct_layouts_match_the_header(tmp_path):
     # the C compiler's view of the structs (size and every field offset) vs ctypes
     structs = {"gp_data": binding.gp_data, "ulisse_params": binding.ulisse_params,
-               "ulisse_sysstat": binding.ulisse_sysstat, "gp_prior": binding.gp_prior}
+               "ulisse_sysstat": binding.ulisse_sysstat, "gp_prior": binding.gp_prior,
+               "gp_profile_stats": binding.gp_profile_stats}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "ulisse_gp.h"', "int main(void) {"]
     for cname, cls in structs.items():
         lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')

@@ -183,16 +183,16 @@ def test_kmv_full_size_sampled(h, rows_seed):
 # ULISSE, draw for draw
 # ---------------------------------------------------------------------------------------
 def _safe_q(K, b, s0, target_l):
-    """q whose threshold q sqrt(n) lies midway (log scale) between two residual norms."""
+    """q whose threshold q sqrt(n) sits midway (log scale) between the running minimum of
+    the residual norms before some iteration l >= target_l and the norm at l, with a
+    clear gap, so FP32 and FP64 runs take the same l."""
     norms = []
     for i, s, e, dl in ocg.cg_iterates(lambda v: K @ v, b, s0):
         norms.append(np.linalg.norm(e))
-        if i >= target_l:
-            break
-    hi = min(norms[:target_l - 1]) if target_l >= 2 else 10 * norms[0]
-    lo = norms[target_l - 1]
-    assert hi > 1.5 * lo
-    return np.sqrt(hi * lo) / np.sqrt(len(b))
+        if i >= target_l and min(norms[:-1]) > 1.5 * norms[-1]:
+            hi, lo = min(norms[:-1]), norms[-1]
+            return np.sqrt(hi * lo) / np.sqrt(len(b))
+        assert i < 200
 
 
 @pytest.mark.parametrize("two_track,warm,m", [(0, False, 3), (1, False, 5), (1, True, 4), (0, True, 17)])
@@ -253,10 +253,17 @@ def test_ulisse_converged_series_is_the_solution(h):
 # ---------------------------------------------------------------------------------------
 # Stochastic gradient and SGLD
 # ---------------------------------------------------------------------------------------
+# Draw-for-draw comparisons need CG paths that FP32 products do not change: CG on these
+# kernel matrices turns chaotic in finite precision after some iterations (on badly
+# conditioned systems a relative perturbation of 1e-8 already changes residual norms by
+# O(1) within ten iterations), so the test systems are well conditioned (kappa < 100)
+# and stop within the first few iterations, where a CPU emulation with 1e-5 relative
+# product noise changes no residual norm by more than 1e-4.
 @pytest.mark.parametrize("given_probes", [True, False])
-@pytest.mark.parametrize("n,d,nr", [(300, 2, 4), (600, 8, 16)])
-def test_stoch_grad_draw_for_draw(h, given_probes, n, d, nr):
-    X, psi = problem(n, d, seed=n + d, lam=0.2, ell=(0.3, 1.0))
+@pytest.mark.parametrize("n,d,nr,lam,ell,seed", [(300, 2, 4, 1.0, (0.1, 0.3), 302),
+                                                 (600, 8, 16, 0.5, (0.2, 0.5), 608)])
+def test_stoch_grad_draw_for_draw(h, given_probes, n, d, nr, lam, ell, seed):
+    X, psi = problem(n, d, seed=seed, lam=lam, ell=ell)
     K = ogp.kernel_matrix(X, psi)
     y = (np.linalg.cholesky(K) @ np.random.default_rng(1).standard_normal(n)).astype(np.float32)
     stream, counter = 5, 9
@@ -274,9 +281,9 @@ def test_stoch_grad_draw_for_draw(h, given_probes, n, d, nr):
     g_ref, St, Scg, ref_stats = osg.stoch_grad(X, psi, y, R, q, rate, eps, 300, h.seed, stream,
                                                counter, eps_relative=True)
     st_gpu = pb.decode_stats(stats)
-    same = all(st_gpu[c]["l"] == ref_stats[c]["l"] and st_gpu[c]["iters"] == ref_stats[c]["iters"]
-               for c in range(nr + 1))
-    assert same, (st_gpu, ref_stats)
+    for c in range(nr + 1):
+        assert ref_stats[c]["iters"] <= 7
+        assert (st_gpu[c]["l"], st_gpu[c]["iters"]) == (ref_stats[c]["l"], ref_stats[c]["iters"]), c
     got = g.cpu().numpy()
     scale = np.abs(g_ref).max()
     np.testing.assert_allclose(got, g_ref, rtol=2e-4, atol=2e-4 * scale)
@@ -305,8 +312,9 @@ def test_stoch_grad_exact_solve_mean_matches_exact_gradient(h):
 
 
 def test_stoch_grad_full_size_consistency(h):
-    # n = 65536, d = 8, 31 probes: the fused gradient reduction agrees with covariance
-    # products of the same series estimates, through dK/dpsi_0 + dK/dpsi_{d+1} = K
+    # n = 65536, d = 8, 31 probes, in the benchmark's launch shapes: every component of the
+    # fused gradient reduction agrees with derivative products (gp_dkmv, pinned to the
+    # oracle above) of the same series estimates, assembled in FP64 on the host
     n, d, nr = 65536, 8, 31
     w = workloads.rff_gp(n=n, d=d, seed=2)
     Xd, psid, yd = dev(w["X"]), dev(w["psi"]), dev(w["y"])
@@ -319,15 +327,18 @@ def test_stoch_grad_full_size_consistency(h):
     p2 = pb.make_params(q=1.0, rate=1.0, eps=1e-6, eps_relative=1, max_iter=500,
                         two_track_first=1, rng_stream=3, rng_counter=1)
     St, stats2 = pb.ulisse_solve(h, Xd, psid, B, p2)
-    KS = pb.gp_kmv(h, Xd, psid, St.float().t().contiguous().t())
+    dKS = pb.gp_dkmv(h, Xd, psid, St.float().t().contiguous().t())   # (P, m+1, n)
     torch.cuda.synchronize()
     assert pb.decode_stats(stats) == pb.decode_stats(stats2)
-    Stn, KSn = St.cpu().numpy(), KS.cpu().numpy().astype(np.float64)
-    lhs = 0.5 * Stn[:, 0] @ KSn[:, 1] - sum(R[:, c].astype(np.float64) @ KSn[:, c + 2]
-                                            for c in range(nr)) / (2 * nr)
+    Stn = St.cpu().numpy()
+    dKSn = dKS.cpu().numpy().astype(np.float64)
+    Rn = R.astype(np.float64)
+    ref = np.array([0.5 * Stn[:, 0] @ dKSn[j, 1] - sum(Rn[:, c] @ dKSn[j, c + 2] for c in range(nr)) / (2 * nr)
+                    for j in range(d + 2)])
     gn = g.cpu().numpy()
     assert np.all(np.isfinite(gn))
-    assert abs((gn[0] + gn[-1]) - lhs) <= 1e-4 * (abs(lhs) + np.abs(gn).max())
+    scale = np.abs(ref).max()
+    np.testing.assert_allclose(gn, ref, rtol=1e-4, atol=1e-5 * scale)
     for s in pb.decode_stats(stats):
         assert s["l"] >= 1 and s["iters"] == s["l"] + max(s["J_a"], s["J_b"]) and s["flags"] == 0
 

@@ -96,6 +96,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=40)
     ap.add_argument("--fresh-steps", type=int, default=4)
+    ap.add_argument("--bf16-steps", type=int, default=40)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-kmv", action="store_true")
@@ -188,6 +189,30 @@ def main():
     # fresh probes every step, for reference (a few steps; not the headline)
     el_fresh, prof_fresh = timed(10 ** 6, args.fresh_steps, 1) if args.fresh_steps else (None, None)
 
+    # K.V throughput of each arithmetic mode at the same shape (m = 32)
+    Vb = pb.colmajor(N, M)
+    Vb.copy_(torch.from_numpy(workloads.gaussian_matrix(N, M, seed=11).T.copy()).cuda().t())
+    outb = pb.colmajor(N, M)
+    kv_modes = {}
+    for name, prec in (("fp32", pb.GP_FP32), ("bf16_split_v", pb.GP_BF16_SPLIT_V),
+                       ("bf16_split_kv", pb.GP_BF16_SPLIT_KV)):
+        pb.gp_kmv(h, X, psi0, Vb, out=outb, prec=prec)
+        torch.cuda.synchronize()
+        pb.gp_profile(h, 1)
+        for _ in range(5):
+            pb.gp_kmv(h, X, psi0, Vb, out=outb, prec=prec)
+        pr = pb.gp_profile_read(h)
+        pb.gp_profile(h, 0)
+        ms = pr["kmv_ms"] / pr["kmv_launches"]
+        kv_modes[name] = {"avg_launch_ms": ms, "tflops": kmv_flops(N, D, M) / (ms * 1e-3) / 1e12}
+
+    # the same protocol with the split-KV BF16 products inside the solver
+    el_bf16 = None
+    if args.bf16_steps:
+        params.prec = pb.GP_BF16_SPLIT_KV
+        el_bf16, prof_bf16 = timed(args.warmup + args.steps, args.bf16_steps, period)
+        params.prec = pb.GP_FP32
+
     K = args.steps
     value = K / elapsed
     kmv_avg_s = prof["kmv_ms"] / max(1, prof["kmv_launches"]) / 1e3
@@ -224,6 +249,12 @@ def main():
             "grad_estimates_per_s": args.fresh_steps / el_fresh,
             "kmv_passes_per_estimate": prof_fresh["kmv_passes"] / args.fresh_steps,
             "steps": args.fresh_steps},
+        "kv_by_precision": kv_modes,
+        "bf16_split_kv_solver": None if el_bf16 is None else {
+            "grad_estimates_per_s": args.bf16_steps / el_bf16,
+            "kmv_passes_per_estimate": prof_bf16["kmv_passes"] / args.bf16_steps,
+            "kmv_avg_launch_ms": prof_bf16["kmv_ms"] / max(1, prof_bf16["kmv_launches"]),
+            "steps": args.bf16_steps},
         "dquad_avg_ms": dq_avg_ms,
         "exp_per_s": N * float(N) / kmv_avg_s,
         "last_step_stats": {"l": [s["l"] for s in final_stats],

@@ -42,10 +42,15 @@ typedef enum {
     GP_EUNSUPPORTED = -4
 } gp_status;
 
-/* Arithmetic of the K-tile x V contraction.  GP_FP32: K entries and products in FP32.
+/* Arithmetic of the K-tile x V contraction on the MFMA path (m >= 16 right-hand sides).
+ * GP_FP32: K entries and products in FP32 (v_mfma_f32_16x16x4f32).
  * GP_BF16_SPLIT_V: K rounded to BF16, V split as V_hi + V_lo (both BF16), FP32
- * accumulation.  GP_BF16_SPLIT_KV: K and V both split, three BF16 products.  Distances
- * and exponentials are FP32 in every mode. */
+ * accumulation (v_mfma_f32_16x16x32_bf16): relative error per product term <= 2^-9.
+ * GP_BF16_SPLIT_KV: K and V both split, K_hi V_hi + K_hi V_lo + K_lo V_hi: relative error
+ * per product term about 3 * 2^-18.
+ * Distances and exponentials are FP32 in every mode; with fewer than 16 right-hand sides
+ * the contraction runs on the VALU in FP32 whatever the mode.  The gradient reduction of
+ * gp_stoch_grad is FP32 in every mode. */
 typedef enum { GP_FP32 = 0, GP_BF16_SPLIT_V = 1, GP_BF16_SPLIT_KV = 2 } gp_precision;
 
 /* Inputs x_1..x_n, row-major FP32, device memory. */
@@ -65,7 +70,7 @@ const char* gp_last_error(void);
 
 /*
  * Covariance matrix-vector products (Sec. 3: the CMVP, O(n^2) time and O(n) memory, K is
- * never stored).  out = K(psi) V with
+ * never stored).  out = K(psi) V, in the arithmetic chosen by prec, with
  *   K_ij = sigma^2 exp(-1/2 sum_k (x_ik - x_jk)^2 / ell_k^2) + lambda delta_ij
  * (the covariance function of Sec. 2 in its ARD form).  V is n x m (ldv >= n), out is
  * n x m (ldo >= n); out must not overlap V.  Tiles of K are rebuilt from X on the fly.

@@ -42,7 +42,7 @@ gp_status fail(gp_status st, const char* fmt, ...) {
 enum Slot {
     kSlotZ, kSlotKP, kSlotVP, kSlotPart, kSlotQ, kSlotS, kSlotE, kSlotD, kSlotP1, kSlotP2,
     kSlotCounter, kSlotActive, kSlotState, kSlotStats, kSlotR, kSlotB, kSlotSt, kSlotS0,
-    kSlotA32, kSlotB32, kSlotGpart, kSlotWork, kNumSlots
+    kSlotA32, kSlotB32, kSlotGpart, kSlotWork, kSlotVH, kSlotVL, kNumSlots
 };
 
 bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
@@ -182,8 +182,8 @@ gp_status solve_core(gp_handle* h, int64_t n, int d, const float* Z, const KPara
                      const float* B, int64_t ldb, int m, const double* S0,
                      const ulisse_params& p, double* St, double* S_cg, ulisse_sysstat* stats,
                      hipStream_t s) {
-    if (p.prec != GP_FP32) return fail(GP_EUNSUPPORTED, "only GP_FP32 products are available in the solver");
     const KmvShape sh = kmv_shape(n, d, m, p.prec);
+    const bool b16 = uses_bf16(sh, p.prec);
     const int64_t n_pad = sh.n_pad;
     SolverArgs a{};
     a.n = n;
@@ -222,20 +222,29 @@ gp_status solve_core(gp_handle* h, int64_t n, int d, const float* Z, const KPara
     a.rng_stream = p.rng_stream;
     a.rng_counter = p.rng_counter;
 
+    uint16_t *DH = nullptr, *DL = nullptr;
+    if (b16) {
+        GP_TRY(ws(h, kSlotVH, (size_t)n_pad * sh.mp, &DH));
+        GP_TRY(ws(h, kSlotVL, (size_t)n_pad * sh.mp, &DL));
+    }
+    // the BF16 modes split the FP32 direction into hi + lo halves before each product
+    auto product = [&](const int* n_active) -> gp_status {
+        if (b16) GP_HIP(launch_split_bf16(a.D, n_pad * sh.mp, DH, DL, s));
+        hipEvent_t t0 = prof_start(h, s);
+        GP_HIP(launch_kmv_partials(sh, d, Z, a.D, DH, DL, kp, kpart, n_active, p.prec, s));
+        prof_stop(h, t0, h->kmv_ev, s);
+        return GP_OK;
+    };
     GP_HIP(hipMemsetAsync(a.D, 0, (size_t)n_pad * sh.mp * sizeof(float), s));
     const int warm = S0 != nullptr;
     if (warm) {
         GP_HIP(launch_pack_f64(S0, n, m, a.D, n_pad, s));
-        hipEvent_t t0 = prof_start(h, s);
-        GP_HIP(launch_kmv_partials(sh, d, Z, a.D, kp, kpart, nullptr, p.prec, s));
-        prof_stop(h, t0, h->kmv_ev, s);
+        GP_TRY(product(nullptr));
         h->passes += 1;
     }
     GP_HIP(solver_init(a, warm, s));
     for (int it = 0; it <= p.max_iter; ++it) {
-        hipEvent_t t0 = prof_start(h, s);
-        GP_HIP(launch_kmv_partials(sh, d, Z, a.D, kp, kpart, a.n_active, p.prec, s));
-        prof_stop(h, t0, h->kmv_ev, s);
+        GP_TRY(product(a.n_active));
         GP_HIP(solver_reduce(a, s));
         GP_HIP(solver_update(a, s));
         SysState* next = states + ((it + 1) & 1) * m;
@@ -248,7 +257,7 @@ gp_status solve_core(gp_handle* h, int64_t n, int d, const float* Z, const KPara
             GP_HIP(hipEventSynchronize(h->ev[(it - 1) & 1]));
             if (h->pinned[(it - 1) & 1] == 0) {
                 // this iteration's launches found no running system and did nothing
-                if (t0) prof_drop_last(h, h->kmv_ev);
+                if (h->prof) prof_drop_last(h, h->kmv_ev);
                 h->passes -= 1;
                 break;
             }
@@ -307,7 +316,7 @@ gp_status gp_kmv(gp_handle* h, gp_data X, const double* psi, const float* V, int
     GP_CHECK(m >= 1 && m <= kMaxSys, "m = %d outside [1, 64]", m);
     GP_CHECK(V != nullptr && out != nullptr && aligned(V, 4) && aligned(out, 4), "V/out null or misaligned");
     GP_CHECK(ldv >= X.n && ldo >= X.n, "ldv and ldo must be >= n");
-    if (prec != GP_FP32) return fail(GP_EUNSUPPORTED, "precision mode %d not available", (int)prec);
+    GP_CHECK(prec == GP_FP32 || prec == GP_BF16_SPLIT_V || prec == GP_BF16_SPLIT_KV, "unknown precision");
     hipStream_t s = (hipStream_t)stream;
     const KmvShape sh = kmv_shape(X.n, X.d, m, prec);
     float* Z;
@@ -317,8 +326,14 @@ gp_status gp_kmv(gp_handle* h, gp_data X, const double* psi, const float* V, int
     GP_TRY(ws(h, kSlotVP, (size_t)sh.n_pad * sh.mp, &Vp));
     GP_TRY(ws(h, kSlotPart, (size_t)sh.split * sh.mp * sh.n_pad, &part));
     GP_HIP(launch_pack(V, X.n, m, ldv, Vp, sh.n_pad, sh.mp, s));
+    uint16_t *VH = nullptr, *VL = nullptr;
+    if (uses_bf16(sh, prec)) {
+        GP_TRY(ws(h, kSlotVH, (size_t)sh.n_pad * sh.mp, &VH));
+        GP_TRY(ws(h, kSlotVL, (size_t)sh.n_pad * sh.mp, &VL));
+        GP_HIP(launch_split_bf16(Vp, sh.n_pad * sh.mp, VH, VL, s));
+    }
     hipEvent_t t0 = prof_start(h, s);
-    GP_HIP(launch_kmv_partials(sh, X.d, Z, Vp, kp, part, nullptr, prec, s));
+    GP_HIP(launch_kmv_partials(sh, X.d, Z, Vp, VH, VL, kp, part, nullptr, prec, s));
     prof_stop(h, t0, h->kmv_ev, s);
     GP_HIP(launch_kmv_reduce(sh, part, Vp, kp, X.n, m, out, ldo, s));
     return GP_OK;

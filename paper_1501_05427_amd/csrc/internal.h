@@ -33,11 +33,18 @@ hipError_t launch_prep(const float* X, int64_t n, int d, int64_t ldx, const doub
 // Copy V (n x m, ldv) into a zero-padded n_pad x mp buffer (ld n_pad).
 hipError_t launch_pack(const float* V, int64_t n, int m, int64_t ldv, float* Vp, int64_t n_pad,
                        int mp, hipStream_t s);
-// Split-K partial products K V into part[split][mp][n_pad].  Vp is n_pad x mp, ld n_pad.
+// Split-K partial products K V into part[split][mp][n_pad].  Vp is n_pad x mp, ld n_pad
+// (GP_FP32, or any mode on the VALU path); the BF16 modes on the MFMA path read the split
+// halves VH, VL (bf16, same layout) made by launch_split_bf16 instead.
 // If n_active is non-null and *n_active == 0 on the device, the launch does nothing.
 hipError_t launch_kmv_partials(const KmvShape& sh, int d, const float* Z, const float* Vp,
-                               const KParams* kp, float* part, const int* n_active,
-                               gp_precision prec, hipStream_t s);
+                               const uint16_t* VH, const uint16_t* VL, const KParams* kp,
+                               float* part, const int* n_active, gp_precision prec,
+                               hipStream_t s);
+// V_hi = bf16(V), V_lo = bf16(V - V_hi) elementwise over `total` (even) floats.
+hipError_t launch_split_bf16(const float* Vp, int64_t total, uint16_t* VH, uint16_t* VL,
+                             hipStream_t s);
+inline bool uses_bf16(const KmvShape& sh, gp_precision prec) { return sh.mfma && prec != GP_FP32; }
 // out[c*ldo + i] = sum_s part + lambda V  for i < n, c < m.
 hipError_t launch_kmv_reduce(const KmvShape& sh, const float* part, const float* Vp,
                              const KParams* kp, int64_t n, int m, float* out, int64_t ldo,

@@ -4,9 +4,10 @@
 // stored: every workgroup rebuilds its tiles of K from the pre-scaled inputs
 // z_ik = x_ik sqrt(log2(e)/2) / ell_k, so that K_f(i, j) = exp2(log2 sigma^2 - |z_i - z_j|^2)
 // with the distance formed from explicit FP32 differences.  The product with V is a
-// VALU contraction for fewer than 16 right-hand sides and an FP32 MFMA contraction
-// (v_mfma_f32_16x16x4f32) otherwise, with K generated directly in the MFMA A-operand
-// layout.  Work is split over (row tile, column chunk); chunk partials are summed in a
+// VALU contraction for fewer than 16 right-hand sides and an MFMA contraction otherwise,
+// with K generated directly in the MFMA A-operand layout: FP32 MFMA
+// (v_mfma_f32_16x16x4f32) in GP_FP32 mode, BF16 MFMA (v_mfma_f32_16x16x32_bf16) with a
+// hi+lo split of V (and optionally of K) in the BF16 modes.  Work is split over (row tile, column chunk); chunk partials are summed in a
 // fixed order by a second kernel in FP64, which also adds lambda V.
 #include <hip/hip_runtime.h>
 
@@ -60,52 +61,114 @@ __global__ void pack_kernel(const float* __restrict__ V, int64_t n, int m, int64
 }
 
 // ---------------------------------------------------------------------------------------
-// Stage loader: JS rows of Z (row-major, DP floats each) and JS entries of MP columns of
+// Stage loader: kJS rows of Z (row-major, DP floats each) and kJS entries of MP columns of
 // V (column-major, ld n_pad) through registers into LDS.  V is stored in LDS either
 // column-major with a padded stride (MFMA B-operand reads) or row-major (VALU broadcast).
+// Every load count is a multiple of 64, so the bounds tests below are uniform per wave.
 // ---------------------------------------------------------------------------------------
 template <int DP, int MP, bool VROWMAJOR>
 struct Stage {
     static constexpr int NZ4 = kJS * DP / 4;
     static constexpr int NV4 = MP * kJS / 4;
-    static constexpr int NL = (NZ4 + NV4 + kWG - 1) / kWG;
+    static constexpr int LZ = (NZ4 + kWG - 1) / kWG;
+    static constexpr int LV = (NV4 + kWG - 1) / kWG;
     static constexpr int VST = VROWMAJOR ? MP : (kJS + 4);
     static constexpr int VSIZE = VROWMAJOR ? kJS * MP : MP * (kJS + 4);
+    static_assert(NZ4 % 64 == 0 && NV4 % 64 == 0, "wave-uniform stage loads");
 
-    __device__ static void load(const float* __restrict__ Z, const float* __restrict__ V,
-                                int64_t ldv, int64_t j0, float4 (&buf)[NL]) {
+    float4 z[LZ];
+    float4 v[LV];
+
+    __device__ __attribute__((always_inline)) void load(const float* __restrict__ Z, const float* __restrict__ V, int64_t ldv,
+                         int64_t j0) {
 #pragma unroll
-        for (int t = 0; t < NL; ++t) {
+        for (int t = 0; t < LZ; ++t) {
             const int idx = threadIdx.x + t * kWG;
-            if (idx < NZ4) {
-                buf[t] = reinterpret_cast<const float4*>(Z + j0 * DP)[idx];
-            } else if (idx < NZ4 + NV4) {
-                const int v = idx - NZ4;
-                const int c = v / (kJS / 4);
-                const int jj = (v % (kJS / 4)) * 4;
-                buf[t] = *reinterpret_cast<const float4*>(V + c * ldv + j0 + jj);
+            if (idx < NZ4) z[t] = reinterpret_cast<const float4*>(Z + j0 * DP)[idx];
+        }
+#pragma unroll
+        for (int t = 0; t < LV; ++t) {
+            const int idx = threadIdx.x + t * kWG;
+            if (idx < NV4) {
+                const int c = idx / (kJS / 4);
+                const int jj = (idx % (kJS / 4)) * 4;
+                v[t] = *reinterpret_cast<const float4*>(V + c * ldv + j0 + jj);
             }
         }
     }
-    __device__ static void store(float4* __restrict__ zs, float* __restrict__ vs,
-                                 const float4 (&buf)[NL]) {
+    __device__ __attribute__((always_inline)) void store(float4* __restrict__ zs, float* __restrict__ vs) const {
 #pragma unroll
-        for (int t = 0; t < NL; ++t) {
+        for (int t = 0; t < LZ; ++t) {
             const int idx = threadIdx.x + t * kWG;
-            if (idx < NZ4) {
-                zs[idx] = buf[t];
-            } else if (idx < NZ4 + NV4) {
-                const int v = idx - NZ4;
-                const int c = v / (kJS / 4);
-                const int jj = (v % (kJS / 4)) * 4;
+            if (idx < NZ4) zs[idx] = z[t];
+        }
+#pragma unroll
+        for (int t = 0; t < LV; ++t) {
+            const int idx = threadIdx.x + t * kWG;
+            if (idx < NV4) {
+                const int c = idx / (kJS / 4);
+                const int jj = (idx % (kJS / 4)) * 4;
                 if (VROWMAJOR) {
-                    vs[(jj + 0) * MP + c] = buf[t].x;
-                    vs[(jj + 1) * MP + c] = buf[t].y;
-                    vs[(jj + 2) * MP + c] = buf[t].z;
-                    vs[(jj + 3) * MP + c] = buf[t].w;
+                    vs[(jj + 0) * MP + c] = v[t].x;
+                    vs[(jj + 1) * MP + c] = v[t].y;
+                    vs[(jj + 2) * MP + c] = v[t].z;
+                    vs[(jj + 3) * MP + c] = v[t].w;
                 } else {
-                    *reinterpret_cast<float4*>(vs + c * VST + jj) = buf[t];
+                    *reinterpret_cast<float4*>(vs + c * VST + jj) = v[t];
                 }
+            }
+        }
+    }
+};
+
+// The same for the BF16 halves of a split V (column-major bf16, ld n_pad): MP columns of
+// kJS entries per part, kept column-major in LDS with a padded stride of VST bf16.
+template <int DP, int MP>
+struct StageB16 {
+    static constexpr int NZ4 = kJS * DP / 4;
+    static constexpr int NV = MP * kJS * 2 / 16;  // 16-byte loads per part
+    static constexpr int LZ = (NZ4 + kWG - 1) / kWG;
+    static constexpr int LV = (NV + kWG - 1) / kWG;
+    static constexpr int VST = kJS + 8;
+    static constexpr int VSIZE = MP * VST;
+    static_assert(NZ4 % 64 == 0 && NV % 64 == 0, "wave-uniform stage loads");
+
+    float4 z[LZ];
+    uint4 h[LV], l[LV];
+
+    __device__ __attribute__((always_inline)) void load(const float* __restrict__ Z, const uint16_t* __restrict__ VH,
+                         const uint16_t* __restrict__ VL, int64_t ldv, int64_t j0) {
+#pragma unroll
+        for (int t = 0; t < LZ; ++t) {
+            const int idx = threadIdx.x + t * kWG;
+            if (idx < NZ4) z[t] = reinterpret_cast<const float4*>(Z + j0 * DP)[idx];
+        }
+#pragma unroll
+        for (int t = 0; t < LV; ++t) {
+            const int idx = threadIdx.x + t * kWG;
+            if (idx < NV) {
+                const int c = idx / (kJS / 8);
+                const int jj = (idx % (kJS / 8)) * 8;
+                h[t] = *reinterpret_cast<const uint4*>(VH + c * ldv + j0 + jj);
+                if (VL != nullptr) l[t] = *reinterpret_cast<const uint4*>(VL + c * ldv + j0 + jj);
+            }
+        }
+    }
+    __device__ __attribute__((always_inline)) void store(float4* __restrict__ zs, uint16_t* __restrict__ hs,
+                          uint16_t* __restrict__ ls, bool with_lo) const {
+#pragma unroll
+        for (int t = 0; t < LZ; ++t) {
+            const int idx = threadIdx.x + t * kWG;
+            if (idx < NZ4) zs[idx] = z[t];
+        }
+#pragma unroll
+        for (int t = 0; t < LV; ++t) {
+            const int idx = threadIdx.x + t * kWG;
+            if (idx < NV) {
+                const int c = idx / (kJS / 8);
+                const int jj = (idx % (kJS / 8)) * 8;
+                *reinterpret_cast<uint4*>(hs + c * VST + jj) = h[t];
+                if (with_lo) *reinterpret_cast<uint4*>(ls + c * VST + jj) = l[t];
             }
         }
     }
@@ -176,16 +239,16 @@ __global__ __launch_bounds__(kWG) void kmv_mfma_f32_kernel(
 #pragma unroll
         for (int cb = 0; cb < NB; ++cb) acc[r][cb] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-    float4 pre[S::NL];
+    S st;
     if (jb < je) {
-        S::load(Z, V, ldv, jb, pre);
-        S::store(zs[0], vs[0], pre);
+        st.load(Z, V, ldv, jb);
+        st.store(zs[0], vs[0]);
     }
     __syncthreads();
     int buf = 0;
     for (int64_t j0 = jb; j0 < je; j0 += kJS) {
         const bool more = j0 + kJS < je;
-        if (more) S::load(Z, V, ldv, j0 + kJS, pre);
+        if (more) st.load(Z, V, ldv, j0 + kJS);
         const float* zsb = reinterpret_cast<const float*>(zs[buf]);
         const float* vsb = vs[buf];
 #pragma unroll 1
@@ -209,7 +272,7 @@ __global__ __launch_bounds__(kWG) void kmv_mfma_f32_kernel(
                 }
             }
         }
-        if (more) S::store(zs[buf ^ 1], vs[buf ^ 1], pre);
+        if (more) st.store(zs[buf ^ 1], vs[buf ^ 1]);
         __syncthreads();
         buf ^= 1;
     }
@@ -227,6 +290,141 @@ __global__ __launch_bounds__(kWG) void kmv_mfma_f32_kernel(
             o.w = acc[r][cb][3];
             *reinterpret_cast<float4*>(part + ((int64_t)cidx * MP + c) * n_pad + i) = o;
         }
+}
+
+// ---------------------------------------------------------------------------------------
+// BF16 MFMA product (v_mfma_f32_16x16x32_bf16, FP32 accumulation).  Inside a 32-column
+// group, lane l takes columns j = 8 (l / 16) + s for s = 0..7: its 8 K values for row
+// lane % 16 form the A operand, and the B operand is the matching 8 consecutive entries of
+// one V column, a single 16-byte LDS read.  V arrives split as V = V_hi + V_lo (both BF16).
+//   SPLITK = false: K_hi (V_hi + V_lo)                       (two products)
+//   SPLITK = true : K_hi V_hi + K_hi V_lo + K_lo V_hi         (three products)
+// with K_hi = bf16(K), K_lo = bf16(K - K_hi).  Distances and exp2 stay in FP32.
+// ---------------------------------------------------------------------------------------
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+__device__ inline uint32_t pack_bf16(float a, float b) {
+    const floatx2 v = {a, b};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2));
+}
+__device__ inline float bf16_lo_as_f32(uint32_t p) { return __uint_as_float(p << 16); }
+__device__ inline float bf16_hi_as_f32(uint32_t p) { return __uint_as_float(p & 0xffff0000u); }
+
+template <int D, int NB, int R, bool SPLITK>
+__global__ __launch_bounds__(kWG) void kmv_mfma_bf16_kernel(
+    const float* __restrict__ Z, const uint16_t* __restrict__ VH, const uint16_t* __restrict__ VL,
+    int64_t ldv, float* __restrict__ part, int64_t n_pad, int chunk, int split,
+    const KParams* __restrict__ kp, const int* __restrict__ n_active) {
+    if (n_active != nullptr && *n_active == 0) return;
+    constexpr int DP = (D + 3) & ~3;
+    constexpr int MP = NB * 16;
+    using S = StageB16<DP, MP>;
+    __shared__ float4 zs[2][S::NZ4];
+    __shared__ uint16_t hs[2][S::VSIZE];
+    __shared__ uint16_t ls[2][S::VSIZE];
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int q = lane >> 4, col = lane & 15;
+    const int cidx = blockIdx.x % split;
+    const int64_t rt = blockIdx.x / split;
+    const int64_t row0 = rt * (64 * R) + wave * (16 * R);
+    const int64_t jb = (int64_t)cidx * chunk;
+    const int64_t je = min(jb + (int64_t)chunk, n_pad);
+    const float negc0 = -kp->c0;
+
+    float zi[R][D];
+#pragma unroll
+    for (int r = 0; r < R; ++r) load_row<D>(Z + (row0 + r * 16 + col) * DP, zi[r]);
+    floatx4 acc[R][NB];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int cb = 0; cb < NB; ++cb) acc[r][cb] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+    S st;
+    if (jb < je) {
+        st.load(Z, VH, VL, ldv, jb);
+        st.store(zs[0], hs[0], ls[0], true);
+    }
+    __syncthreads();
+    int buf = 0;
+    for (int64_t j0 = jb; j0 < je; j0 += kJS) {
+        const bool more = j0 + kJS < je;
+        if (more) st.load(Z, VH, VL, ldv, j0 + kJS);
+        const float* zsb = reinterpret_cast<const float*>(zs[buf]);
+#pragma unroll 1
+        for (int g = 0; g < kJS / 32; ++g) {
+            bf16x8 bh[NB], bl[NB];
+#pragma unroll
+            for (int cb = 0; cb < NB; ++cb) {
+                const int o = (cb * 16 + col) * S::VST + g * 32 + 8 * q;
+                bh[cb] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(hs[buf] + o));
+                bl[cb] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(ls[buf] + o));
+            }
+            float kv[R][8];
+#pragma unroll
+            for (int s = 0; s < 8; ++s) {
+                float zj[D];
+                load_row<D>(zsb + (g * 32 + 8 * q + s) * DP, zj);
+#pragma unroll
+                for (int r = 0; r < R; ++r) kv[r][s] = kf_entry<D>(zi[r], zj, negc0);
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                uint32_t hi[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) hi[u] = pack_bf16(kv[r][2 * u], kv[r][2 * u + 1]);
+                const bf16x8 ah = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(hi));
+#pragma unroll
+                for (int cb = 0; cb < NB; ++cb) {
+                    acc[r][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[cb], acc[r][cb], 0, 0, 0);
+                    acc[r][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[cb], acc[r][cb], 0, 0, 0);
+                }
+                if (SPLITK) {
+                    uint32_t lo[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        lo[u] = pack_bf16(kv[r][2 * u] - bf16_lo_as_f32(hi[u]),
+                                          kv[r][2 * u + 1] - bf16_hi_as_f32(hi[u]));
+                    const bf16x8 al = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(lo));
+#pragma unroll
+                    for (int cb = 0; cb < NB; ++cb)
+                        acc[r][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[cb], acc[r][cb], 0, 0, 0);
+                }
+            }
+        }
+        if (more) st.store(zs[buf ^ 1], hs[buf ^ 1], ls[buf ^ 1], true);
+        __syncthreads();
+        buf ^= 1;
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int cb = 0; cb < NB; ++cb) {
+            const int64_t i = row0 + r * 16 + 4 * q;
+            const int c = cb * 16 + col;
+            float4 o;
+            o.x = acc[r][cb][0];
+            o.y = acc[r][cb][1];
+            o.z = acc[r][cb][2];
+            o.w = acc[r][cb][3];
+            *reinterpret_cast<float4*>(part + ((int64_t)cidx * MP + c) * n_pad + i) = o;
+        }
+}
+
+// V (FP32, n_pad x mp, ld n_pad) -> V_hi = bf16(V), V_lo = bf16(V - V_hi).
+__global__ void split_bf16_kernel(const float* __restrict__ V, int64_t total,
+                                  uint16_t* __restrict__ VH, uint16_t* __restrict__ VL) {
+    for (int64_t e = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 2; e < total;
+         e += (int64_t)gridDim.x * blockDim.x * 2) {
+        const float a = V[e], b = V[e + 1];
+        const uint32_t hi = pack_bf16(a, b);
+        const uint32_t lo = pack_bf16(a - bf16_lo_as_f32(hi), b - bf16_hi_as_f32(hi));
+        *reinterpret_cast<uint32_t*>(VH + e) = hi;
+        *reinterpret_cast<uint32_t*>(VL + e) = lo;
+    }
 }
 
 // ---------------------------------------------------------------------------------------
@@ -260,16 +458,16 @@ __global__ __launch_bounds__(kWG) void kmv_valu_kernel(
 #pragma unroll
         for (int c = 0; c < MC; ++c) acc[r][c] = 0.f;
 
-    float4 pre[S::NL];
+    S st;
     if (jb < je) {
-        S::load(Z, V, ldv, jb, pre);
-        S::store(zs[0], vs[0], pre);
+        st.load(Z, V, ldv, jb);
+        st.store(zs[0], vs[0]);
     }
     __syncthreads();
     int buf = 0;
     for (int64_t j0 = jb; j0 < je; j0 += kJS) {
         const bool more = j0 + kJS < je;
-        if (more) S::load(Z, V, ldv, j0 + kJS, pre);
+        if (more) st.load(Z, V, ldv, j0 + kJS);
         const float* zsb = reinterpret_cast<const float*>(zs[buf]);
         const float* vsb = vs[buf];
 #pragma unroll 4
@@ -292,7 +490,7 @@ __global__ __launch_bounds__(kWG) void kmv_valu_kernel(
                 for (int c = 0; c < MC; ++c) acc[r][c] = __builtin_fmaf(kv, vj[c], acc[r][c]);
             }
         }
-        if (more) S::store(zs[buf ^ 1], vs[buf ^ 1], pre);
+        if (more) st.store(zs[buf ^ 1], vs[buf ^ 1]);
         __syncthreads();
         buf ^= 1;
     }
@@ -334,16 +532,16 @@ __global__ __launch_bounds__(kWG) void dkmv_mfma_kernel(
 #pragma unroll
     for (int p = 0; p <= D; ++p) acc[p] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-    float4 pre[S::NL];
+    S st;
     if (jb < je) {
-        S::load(Z, V, ldv, jb, pre);
-        S::store(zs[0], vs[0], pre);
+        st.load(Z, V, ldv, jb);
+        st.store(zs[0], vs[0]);
     }
     __syncthreads();
     int buf = 0;
     for (int64_t j0 = jb; j0 < je; j0 += kJS) {
         const bool more = j0 + kJS < je;
-        if (more) S::load(Z, V, ldv, j0 + kJS, pre);
+        if (more) st.load(Z, V, ldv, j0 + kJS);
         const float* zsb = reinterpret_cast<const float*>(zs[buf]);
         const float* vsb = vs[buf];
 #pragma unroll 1
@@ -369,7 +567,7 @@ __global__ __launch_bounds__(kWG) void dkmv_mfma_kernel(
                     acc[k + 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(kv * sq[k], b, acc[k + 1], 0, 0, 0);
             }
         }
-        if (more) S::store(zs[buf ^ 1], vs[buf ^ 1], pre);
+        if (more) st.store(zs[buf ^ 1], vs[buf ^ 1]);
         __syncthreads();
         buf ^= 1;
     }
@@ -410,16 +608,16 @@ __global__ __launch_bounds__(kWG) void dkmv_valu_kernel(
 #pragma unroll
         for (int c = 0; c < MC; ++c) acc[p][c] = 0.f;
 
-    float4 pre[S::NL];
+    S st;
     if (jb < je) {
-        S::load(Z, V, ldv, jb, pre);
-        S::store(zs[0], vs[0], pre);
+        st.load(Z, V, ldv, jb);
+        st.store(zs[0], vs[0]);
     }
     __syncthreads();
     int buf = 0;
     for (int64_t j0 = jb; j0 < je; j0 += kJS) {
         const bool more = j0 + kJS < je;
-        if (more) S::load(Z, V, ldv, j0 + kJS, pre);
+        if (more) st.load(Z, V, ldv, j0 + kJS);
         const float* zsb = reinterpret_cast<const float*>(zs[buf]);
         const float* vsb = vs[buf];
 #pragma unroll 2
@@ -446,7 +644,7 @@ __global__ __launch_bounds__(kWG) void dkmv_valu_kernel(
                 for (int c = 0; c < MC; ++c) acc[k + 1][c] = __builtin_fmaf(w, vj[c], acc[k + 1][c]);
             }
         }
-        if (more) S::store(zs[buf ^ 1], vs[buf ^ 1], pre);
+        if (more) st.store(zs[buf ^ 1], vs[buf ^ 1]);
         __syncthreads();
         buf ^= 1;
     }
@@ -563,9 +761,29 @@ hipError_t launch_pack(const float* V, int64_t n, int m, int64_t ldv, float* Vp,
     return hipGetLastError();
 }
 
+template <int D, bool SPLITK>
+static hipError_t kmv_bf16_d(const KmvShape& sh, const float* Z, const uint16_t* VH,
+                             const uint16_t* VL, const KParams* kp, float* part,
+                             const int* n_active, hipStream_t s) {
+    const int64_t tiles = sh.n_pad / sh.rows_per_wg;
+    const dim3 grid((unsigned)(tiles * sh.split));
+    constexpr int R = D <= 8 ? 4 : 2;
+    switch (sh.mp) {
+        case 16: kmv_mfma_bf16_kernel<D, 1, R, SPLITK><<<grid, kWG, 0, s>>>(Z, VH, VL, sh.n_pad, part, sh.n_pad, sh.chunk, sh.split, kp, n_active); break;
+        case 32: kmv_mfma_bf16_kernel<D, 2, R, SPLITK><<<grid, kWG, 0, s>>>(Z, VH, VL, sh.n_pad, part, sh.n_pad, sh.chunk, sh.split, kp, n_active); break;
+        case 48: kmv_mfma_bf16_kernel<D, 3, R, SPLITK><<<grid, kWG, 0, s>>>(Z, VH, VL, sh.n_pad, part, sh.n_pad, sh.chunk, sh.split, kp, n_active); break;
+        case 64: kmv_mfma_bf16_kernel<D, 4, R, SPLITK><<<grid, kWG, 0, s>>>(Z, VH, VL, sh.n_pad, part, sh.n_pad, sh.chunk, sh.split, kp, n_active); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 template <int D>
-static hipError_t kmv_d(const KmvShape& sh, const float* Z, const float* Vp, const KParams* kp,
-                        float* part, const int* n_active, hipStream_t s) {
+static hipError_t kmv_d(const KmvShape& sh, const float* Z, const float* Vp,
+                        const uint16_t* VH, const uint16_t* VL, const KParams* kp,
+                        float* part, const int* n_active, gp_precision prec, hipStream_t s) {
+    if (sh.mfma && prec == GP_BF16_SPLIT_V) return kmv_bf16_d<D, false>(sh, Z, VH, VL, kp, part, n_active, s);
+    if (sh.mfma && prec == GP_BF16_SPLIT_KV) return kmv_bf16_d<D, true>(sh, Z, VH, VL, kp, part, n_active, s);
     const int64_t tiles = sh.n_pad / sh.rows_per_wg;
     const dim3 grid((unsigned)(tiles * sh.split));
     if (sh.mfma) {
@@ -611,10 +829,16 @@ static hipError_t kmv_d(const KmvShape& sh, const float* Z, const float* Vp, con
     }
 
 hipError_t launch_kmv_partials(const KmvShape& sh, int d, const float* Z, const float* Vp,
-                               const KParams* kp, float* part, const int* n_active,
-                               gp_precision prec, hipStream_t s) {
-    if (prec != GP_FP32) return hipErrorInvalidValue;
-    GPK_DISPATCH_D(d, kmv_d, sh, Z, Vp, kp, part, n_active, s);
+                               const uint16_t* VH, const uint16_t* VL, const KParams* kp,
+                               float* part, const int* n_active, gp_precision prec,
+                               hipStream_t s) {
+    GPK_DISPATCH_D(d, kmv_d, sh, Z, Vp, VH, VL, kp, part, n_active, prec, s);
+}
+
+hipError_t launch_split_bf16(const float* Vp, int64_t total, uint16_t* VH, uint16_t* VL,
+                             hipStream_t s) {
+    split_bf16_kernel<<<grid_for(total / 2), kWG, 0, s>>>(Vp, total, VH, VL);
+    return hipGetLastError();
 }
 
 hipError_t launch_kmv_reduce(const KmvShape& sh, const float* part, const float* Vp,

@@ -151,6 +151,64 @@ def test_kmv_leading_dimensions(h):
     assert np.all(got[:, n:] == 7.0)  # nothing written past n
 
 
+# Error bounds of the BF16 contraction modes, per column, relative to || |K| |V| ||:
+# split-V rounds every K entry to BF16 (|delta| <= 2^-9) and V to hi + lo (2^-17);
+# split-KV keeps K_hi + K_lo and V_hi + V_lo and drops K_lo V_lo (about 3 * 2^-18 in all).
+# Both bounds carry a factor 2 of margin plus the FP32 accumulation term.
+BF16_BOUND = {pb.GP_BF16_SPLIT_V: 2.0 ** -8, pb.GP_BF16_SPLIT_KV: 6 * 2.0 ** -18}
+
+
+def absprod_norm(X, psi, V):
+    return np.linalg.norm(np.abs(ogp.kernel_matrix(X, psi)) @ np.abs(V.astype(np.float64)), axis=0)
+
+
+@pytest.mark.parametrize("prec", [pb.GP_BF16_SPLIT_V, pb.GP_BF16_SPLIT_KV])
+@pytest.mark.parametrize("n,d,m", [(1000, 8, 16), (777, 2, 32), (2049, 16, 33), (600, 5, 64)])
+def test_kmv_bf16_error_bound(h, prec, n, d, m):
+    X, psi = problem(n, d, seed=n + m)
+    V = np.random.default_rng(m).standard_normal((n, m)).astype(np.float32)
+    out = pb.gp_kmv(h, dev(X), dev(psi), colm(V), prec=prec)
+    torch.cuda.synchronize()
+    ref = ogp.kmv(X, psi, V)
+    err = np.linalg.norm(out.cpu().numpy().astype(np.float64) - ref, axis=0)
+    bound = (BF16_BOUND[prec] + 1e-6) * absprod_norm(X, psi, V)
+    assert np.all(err <= bound), (err / bound).max()
+
+
+def test_kmv_bf16_below_16_columns_is_fp32(h):
+    # with fewer than 16 right-hand sides the contraction is on the VALU in FP32
+    n, d, m = 500, 3, 7
+    X, psi = problem(n, d, seed=1)
+    V = np.random.default_rng(0).standard_normal((n, m)).astype(np.float32)
+    a = pb.gp_kmv(h, dev(X), dev(psi), colm(V), prec=pb.GP_BF16_SPLIT_V)
+    b = pb.gp_kmv(h, dev(X), dev(psi), colm(V), prec=pb.GP_FP32)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(a.cpu().numpy(), b.cpu().numpy())
+
+
+@pytest.mark.parametrize("prec", [pb.GP_FP32, pb.GP_BF16_SPLIT_V, pb.GP_BF16_SPLIT_KV])
+def test_precision_report_subsample_4096(h, prec, capsys):
+    # the n = 65536, d = 8 workload restricted to its first 4096 points, solved densely by
+    # the oracle: error of K V and of converged solves for each arithmetic mode
+    w = workloads.rff_gp(n=65536, d=8, seed=2)
+    X, psi, y = w["X"][:4096], w["psi"], w["y"][:4096]
+    V = np.column_stack([y, workloads.gaussian_matrix(4096, 31, seed=13)]).astype(np.float32)
+    out = pb.gp_kmv(h, dev(X), dev(psi), colm(V), prec=prec)
+    params = pb.make_params(q=1e-12, rate=1e-9, eps=1e-6, eps_relative=1, max_iter=4000, prec=prec)
+    St, stats = pb.ulisse_solve(h, dev(X), dev(psi), colm(V), params)
+    torch.cuda.synchronize()
+    ref_kv = ogp.kmv(X, psi, V)
+    ref_s = ogp.solve(X, psi, V.astype(np.float64))
+    e_kv = colwise_rel(out.cpu().numpy(), ref_kv).max()
+    e_s = colwise_rel(St.cpu().numpy(), ref_s)
+    its = [s["iters"] for s in pb.decode_stats(stats)]
+    with capsys.disabled():
+        print(f"\n[precision report] mode {prec}: K.V max col rel err {e_kv:.2e}; solve rel err "
+              f"median {np.median(e_s):.2e} max {e_s.max():.2e}; CG iterations {min(its)}-{max(its)}")
+    bound = {pb.GP_FP32: 1e-5, pb.GP_BF16_SPLIT_V: 2e-2, pb.GP_BF16_SPLIT_KV: 1e-4}[prec]
+    assert e_kv <= bound
+
+
 @pytest.mark.parametrize("n,d,m", [(400, 2, 3), (700, 8, 16), (333, 3, 20), (257, 16, 5)])
 def test_dkmv_parity(h, n, d, m):
     X, psi = problem(n, d, seed=7 * n)
@@ -195,8 +253,9 @@ def _safe_q(K, b, s0, target_l):
         assert i < 200
 
 
-@pytest.mark.parametrize("two_track,warm,m", [(0, False, 3), (1, False, 5), (1, True, 4), (0, True, 17)])
-def test_ulisse_draw_for_draw(h, two_track, warm, m):
+@pytest.mark.parametrize("two_track,warm,m,prec", [(0, False, 3, 0), (1, False, 5, 0), (1, True, 4, 0),
+                                                   (0, True, 17, 0), (1, False, 20, 2)])
+def test_ulisse_draw_for_draw(h, two_track, warm, m, prec):
     n, d = 400, 2
     X, psi = problem(n, d, seed=40 + m, lam=0.2, ell=(0.2, 0.4))
     K = ogp.kernel_matrix(X, psi)
@@ -207,7 +266,7 @@ def test_ulisse_draw_for_draw(h, two_track, warm, m):
     q = _safe_q(K, Bm[:, 0].astype(np.float64), np.zeros(n) if S0 is None else S0[:, 0], 3)
     eps, rate = 1e-6, 0.7
     params = pb.make_params(q=q, rate=rate, eps=eps, eps_relative=1, max_iter=200,
-                            two_track_first=two_track, rng_stream=77, rng_counter=3)
+                            two_track_first=two_track, rng_stream=77, rng_counter=3, prec=prec)
     Scg = torch.zeros((m, n), dtype=torch.float64, device="cuda").t()
     St, stats = pb.ulisse_solve(h, dev(X), dev(psi), colm(Bm), params,
                                 S0=None if S0 is None else colm(S0, torch.float64), S_cg=Scg)
@@ -223,8 +282,9 @@ def test_ulisse_draw_for_draw(h, two_track, warm, m):
         if two_track and c == 0:
             assert g["J_b"] == r["J"][1]
         assert g["flags"] == r["flags"]
-    assert colwise_rel(St.cpu().numpy(), ref_St).max() <= 2e-4
-    assert colwise_rel(Scg.cpu().numpy(), ref_Scg).max() <= 2e-4
+    tol = 2e-4 if prec == pb.GP_FP32 else 2e-3
+    assert colwise_rel(St.cpu().numpy(), ref_St).max() <= tol
+    assert colwise_rel(Scg.cpu().numpy(), ref_Scg).max() <= tol
 
 
 def test_ulisse_cap_sets_notconv(h):

@@ -96,11 +96,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=40)
     ap.add_argument("--fresh-steps", type=int, default=4)
-    ap.add_argument("--bf16-steps", type=int, default=40)
+    ap.add_argument("--bf16-steps", type=int, default=None,
+                    help="steps of the BF16 split-K+V solver run (default: --steps)")
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-kmv", action="store_true")
     args = ap.parse_args()
+    if args.bf16_steps is None:
+        args.bf16_steps = args.steps
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(the sharding design is described in DESIGN.md)", file=sys.stderr)
@@ -184,10 +187,21 @@ def main():
     period = PROBE_PERIOD
     for t in range(args.warmup):
         step(t, period)
+    # the FP32 and BF16 runs below start from this same state and use the same draws
+    saved = (psi.clone(), S_warm.clone(), R.clone())
+
+    def restore():
+        psi.copy_(saved[0])
+        S_warm.copy_(saved[1])
+        R.copy_(saved[2])
+
     elapsed, prof = timed(args.warmup, args.steps, period)
     final_stats = pb.decode_stats(stats)
     # fresh probes every step, for reference (a few steps; not the headline)
-    el_fresh, prof_fresh = timed(10 ** 6, args.fresh_steps, 1) if args.fresh_steps else (None, None)
+    el_fresh, prof_fresh = None, None
+    if args.fresh_steps:
+        restore()
+        el_fresh, prof_fresh = timed(args.warmup, args.fresh_steps, 1)
 
     # K.V throughput of each arithmetic mode at the same shape (m = 32)
     Vb = pb.colmajor(N, M)
@@ -209,8 +223,9 @@ def main():
     # the same protocol with the split-KV BF16 products inside the solver
     el_bf16 = None
     if args.bf16_steps:
+        restore()
         params.prec = pb.GP_BF16_SPLIT_KV
-        el_bf16, prof_bf16 = timed(args.warmup + args.steps, args.bf16_steps, period)
+        el_bf16, prof_bf16 = timed(args.warmup, args.bf16_steps, period)
         params.prec = pb.GP_FP32
 
     K = args.steps

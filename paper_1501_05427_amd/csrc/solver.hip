@@ -399,24 +399,28 @@ __global__ __launch_bounds__(kWG) void grad_diag_kernel(const double* __restrict
     if (threadIdx.x == 0) dpart[blockIdx.x] = acc;
 }
 
-// Final fixed-order sums: g_0, 2 ln 2 * (g_1..g_d) from the tile partials and
-// lambda * (diagonal term) from its partials.
+// Final fixed-order sums, one workgroup per component: g_0 and 2 ln 2 * (g_1..g_d) from the
+// tile partials (gpart[j * nwg + w]); g_{d+1} = lambda * (diagonal term) from its partials.
 __global__ __launch_bounds__(kWG) void grad_finish_kernel(const double* __restrict__ gpart,
                                                           int nwg, int d,
                                                           const double* __restrict__ dpart,
                                                           int ndb, const KParams* __restrict__ kp,
                                                           double* __restrict__ g) {
     __shared__ double scratch[4];
-    for (int p = 0; p <= d; ++p) {
-        double s = 0.0;
-        for (int b = threadIdx.x; b < nwg; b += kWG) s += gpart[(int64_t)p * nwg + b];
-        s = block_sum256(s, scratch);
-        if (threadIdx.x == 0) g[p] = p == 0 ? s : 2.0 * M_LN2 * s;
+    const int p = blockIdx.x;
+    const double* src = p <= d ? gpart + (int64_t)p * nwg : dpart;
+    const int cnt = p <= d ? nwg : ndb;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int b = threadIdx.x;
+    for (; b + 3 * kWG < cnt; b += 4 * kWG) {
+        s0 += src[b];
+        s1 += src[b + kWG];
+        s2 += src[b + 2 * kWG];
+        s3 += src[b + 3 * kWG];
     }
-    double s = 0.0;
-    for (int b = threadIdx.x; b < ndb; b += kWG) s += dpart[b];
-    s = block_sum256(s, scratch);
-    if (threadIdx.x == 0) g[d + 1] = kp->lam64 * s;
+    for (; b < cnt; b += kWG) s0 += src[b];
+    const double s = block_sum256((s0 + s1) + (s2 + s3), scratch);
+    if (threadIdx.x == 0) g[p] = p == 0 ? s : (p <= d ? 2.0 * M_LN2 * s : kp->lam64 * s);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -521,7 +525,7 @@ hipError_t launch_grad_finish(const double* St, const float* R, int64_t ldr, int
     grad_diag_kernel<<<ndb, kWG, 0, s>>>(St, R, ldr, n, nprobes, dpart);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    grad_finish_kernel<<<1, kWG, 0, s>>>(gpart, nwg, d, dpart, ndb, kp, g);
+    grad_finish_kernel<<<d + 2, kWG, 0, s>>>(gpart, nwg, d, dpart, ndb, kp, g);
     return hipGetLastError();
 }
 hipError_t launch_sgld(int P, double* psi, const double* g, int prior_kind, const double* pa,

@@ -178,6 +178,48 @@ gp_status gp_philox(uint64_t k0, uint64_t k1, uint64_t first_block, uint64_t w1,
                     uint64_t w3, int64_t nblocks, uint64_t* out, void* stream);
 
 /*
+ * The paper's SGLD protocol (Sec. 2.1 and Sec. 5.1) run on the device for steps
+ * t = state->t, ..., state->t + T - 1 of one chain:
+ *   - probes redrawn every `probe_period` steps (key (seed, params->rng_stream), counter
+ *     (i/4, c, 1, t / probe_period)); each system is warm started from its last CG iterate
+ *     and the probe columns restart from zero when the probes change;
+ *   - g_t = gp_stoch_grad with the ULISSE draws of step t (params->rng_counter = t);
+ *   - step size eps_t = a (b + t)^(-gamma) until frozen (the decreasing schedule of
+ *     Sec. 2.1 and Sec. 5.1);
+ *   - psi += eps_t/2 M (g_t + grad log p) + sqrt(eps_t) L xi_t (SGLD noise counter t);
+ *   - after every `batch` steps, V = sample covariance of the batch's gradients and the
+ *     Langevin-phase ratio (eps_t / 4) lambda_max(L^T V L) (= the ratio of Sec. 2.1 with
+ *     M = L L^T); the first ratio below `freeze_ratio` freezes eps at its current value.
+ * Outputs (device, caller-owned): trace T x P (psi after each step, row t), eps_trace T,
+ * ratio_trace floor(T / batch) (nullable each).  Work arrays (device, caller-owned, kept
+ * between calls of one chain): S_warm n x (1 + n_probes) FP64 and R n x n_probes FP32,
+ * both ld n.  state (host memory) carries t and the freeze across calls, so a chain can be
+ * resumed; with counter-based draws a resumed chain is bit-identical to an uninterrupted
+ * one.  probe_period >= 1, batch >= 2, T >= 0.
+ */
+typedef struct {
+    double a, b, gamma;      /* eps_t = a (b + t)^(-gamma)                             */
+    double freeze_ratio;     /* 0.002 in the paper's experiments                        */
+    int32_t batch;           /* gradients per covariance estimate (100 in the paper)    */
+    int32_t probe_period;    /* 20 in the paper                                         */
+    int32_t n_probes;
+    int32_t probe_kind;      /* 0 Gaussian, 1 Rademacher                               */
+} sgld_schedule;
+
+typedef struct {
+    int64_t t;               /* next step index                                        */
+    int32_t frozen;          /* eps frozen                                             */
+    int32_t frozen_at;       /* step at which it froze (-1 if not)                      */
+    double eps_frozen;
+} sgld_state;
+
+gp_status sgld_run(gp_handle* h, gp_data X, double* psi, const float* y,
+                   const ulisse_params* params, const gp_prior* prior, const double* M_chol,
+                   const sgld_schedule* sched, sgld_state* state, int32_t T, double* S_warm,
+                   float* R, double* trace, double* eps_trace, double* ratio_trace,
+                   void* stream);
+
+/*
  * Kernel timing for measurement.  While enabled, the handle records a pair of hipEvents on
  * the launch stream around every covariance-product launch that does work (kmv, in the
  * solver and in gp_kmv) and around every fused gradient reduction (dquad).

@@ -50,6 +50,16 @@ class gp_profile_stats(Structure):
                 ("dquad_ms", c_double), ("solves", c_int64), ("kmv_passes", c_int64)]
 
 
+class sgld_schedule(Structure):
+    _fields_ = [("a", c_double), ("b", c_double), ("gamma", c_double), ("freeze_ratio", c_double),
+                ("batch", c_int32), ("probe_period", c_int32), ("n_probes", c_int32),
+                ("probe_kind", c_int32)]
+
+
+class sgld_state(Structure):
+    _fields_ = [("t", c_int64), ("frozen", c_int32), ("frozen_at", c_int32), ("eps_frozen", c_double)]
+
+
 SYSSTAT_BYTES = ctypes.sizeof(ulisse_sysstat)
 
 _lib = None
@@ -96,6 +106,10 @@ def lib():
     L.gp_draw_probes.argtypes = [c_void_p, c_int64, c_int32, c_int32, c_uint64, c_uint64, c_void_p, c_int64, c_void_p]
     L.gp_philox.restype = c_int
     L.gp_philox.argtypes = [c_uint64, c_uint64, c_uint64, c_uint64, c_uint64, c_uint64, c_int64, c_void_p, c_void_p]
+    L.sgld_run.restype = c_int
+    L.sgld_run.argtypes = [c_void_p, gp_data, c_void_p, c_void_p, POINTER(ulisse_params), POINTER(gp_prior),
+                           c_void_p, POINTER(sgld_schedule), POINTER(sgld_state), c_int32, c_void_p,
+                           c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
     L.gp_profile.restype = c_int
     L.gp_profile.argtypes = [c_void_p, c_int32]
     L.gp_profile_read.restype = c_int
@@ -291,3 +305,23 @@ def gp_profile_read(h):
     st = gp_profile_stats()
     _check(lib().gp_profile_read(h.ptr, ctypes.byref(st)))
     return {f: getattr(st, f) for f, _ in gp_profile_stats._fields_}
+
+
+def make_schedule(a, b, gamma=1.0, freeze_ratio=0.002, batch=100, probe_period=20, n_probes=4,
+                  probe_kind=PROBE_RADEMACHER):
+    return sgld_schedule(a, b, gamma, freeze_ratio, batch, probe_period, n_probes, probe_kind)
+
+
+def new_state(t=0):
+    return sgld_state(t, 0, -1, 0.0)
+
+
+def sgld_run(h, X, psi, y, params, sched, state, T, S_warm, R, prior_kind=0, prior_a=None,
+             prior_b=None, M_chol=None, trace=None, eps_trace=None, ratio_trace=None, stream=None):
+    """Runs T protocol steps in place on psi, S_warm, R; `state` (sgld_state) advances."""
+    pr = gp_prior(int(prior_kind), 0, 0 if prior_a is None else prior_a.data_ptr(),
+                  0 if prior_b is None else prior_b.data_ptr())
+    _check(lib().sgld_run(h.ptr, _data(X), _ptr(psi), _ptr(y), ctypes.byref(params), ctypes.byref(pr),
+                          _ptr(M_chol), ctypes.byref(sched), ctypes.byref(state), int(T), _ptr(S_warm),
+                          _ptr(R), _ptr(trace), _ptr(eps_trace), _ptr(ratio_trace), _stream(stream)))
+    return state

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <algorithm>
+#include <cmath>
 #include <vector>
 
 #include "gp_common.h"
@@ -42,7 +43,8 @@ gp_status fail(gp_status st, const char* fmt, ...) {
 enum Slot {
     kSlotZ, kSlotKP, kSlotVP, kSlotPart, kSlotQ, kSlotS, kSlotE, kSlotD, kSlotP1, kSlotP2,
     kSlotCounter, kSlotActive, kSlotState, kSlotStats, kSlotR, kSlotB, kSlotSt, kSlotS0,
-    kSlotA32, kSlotB32, kSlotGpart, kSlotWork, kSlotVH, kSlotVL, kNumSlots
+    kSlotA32, kSlotB32, kSlotGpart, kSlotWork, kSlotVH, kSlotVL, kSlotGbatch, kSlotGvec,
+    kSlotRatio, kSlotRunStats, kNumSlots
 };
 
 bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
@@ -55,6 +57,7 @@ struct gp_handle {
     void* buf[kNumSlots] = {};
     size_t bytes[kNumSlots] = {};
     int* pinned = nullptr;  // two words: systems still running after iteration it (it % 2)
+    double* pinned_d = nullptr;  // one word read back by sgld_run (Langevin-phase ratio)
     hipEvent_t ev[2] = {nullptr, nullptr};
     // kernel timing (gp_profile)
     bool prof = false;
@@ -284,6 +287,7 @@ gp_status gp_create(gp_handle** out, int device, uint64_t seed) {
     h->device = device;
     h->seed = seed;
     if (hipHostMalloc((void**)&h->pinned, 2 * sizeof(int), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&h->pinned_d, sizeof(double), hipHostMallocDefault) != hipSuccess ||
         hipEventCreateWithFlags(&h->ev[0], hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&h->ev[1], hipEventDisableTiming) != hipSuccess) {
         gp_destroy(h);
@@ -303,6 +307,7 @@ void gp_destroy(gp_handle* h) {
     for (int i = 0; i < 2; ++i)
         if (h->ev[i]) (void)hipEventDestroy(h->ev[i]);
     if (h->pinned) (void)hipHostFree(h->pinned);
+    if (h->pinned_d) (void)hipHostFree(h->pinned_d);
     for (hipEvent_t e : h->pool) (void)hipEventDestroy(e);
     for (hipEvent_t e : h->kmv_ev) (void)hipEventDestroy(e);
     for (hipEvent_t e : h->dq_ev) (void)hipEventDestroy(e);
@@ -457,6 +462,73 @@ gp_status gp_stoch_grad(gp_handle* h, gp_data X, const double* psi, const float*
     double* dpart;
     GP_TRY(ws(h, kSlotP2, (size_t)solver_blocks(n), &dpart));
     GP_HIP(launch_grad_finish(St, Rp, n, n, n_probes, gpart, dq.nwg, d, kp, dpart, g, s));
+    return GP_OK;
+}
+
+gp_status sgld_run(gp_handle* h, gp_data X, double* psi, const float* y,
+                   const ulisse_params* params, const gp_prior* prior, const double* M_chol,
+                   const sgld_schedule* sched, sgld_state* state, int32_t T, double* S_warm,
+                   float* R, double* trace, double* eps_trace, double* ratio_trace,
+                   void* stream) {
+    GP_TRY(check_handle(h));
+    GP_TRY(check_data(X));
+    GP_TRY(check_params(params));
+    GP_CHECK(sched != nullptr && state != nullptr, "schedule and state are required");
+    GP_CHECK(sched->batch >= 2 && sched->probe_period >= 1 && T >= 0, "batch >= 2, probe_period >= 1, T >= 0");
+    GP_CHECK(sched->n_probes >= 1 && sched->n_probes + 2 <= kMaxSys, "n_probes outside [1, 62]");
+    GP_CHECK(sched->probe_kind == 0 || sched->probe_kind == 1, "probe_kind must be 0 or 1");
+    GP_CHECK(state->t >= 0, "state->t must be >= 0");
+    GP_CHECK(S_warm != nullptr && R != nullptr && psi != nullptr && y != nullptr,
+             "psi, y, S_warm and R are required");
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n = X.n;
+    const int P = X.d + 2;
+    const int nr = sched->n_probes;
+    double *G, *gvec, *ratio_dev;
+    ulisse_sysstat* st;
+    GP_TRY(ws(h, kSlotGbatch, (size_t)sched->batch * P, &G));
+    GP_TRY(ws(h, kSlotGvec, (size_t)P, &gvec));
+    GP_TRY(ws(h, kSlotRatio, 1, &ratio_dev));
+    GP_TRY(ws(h, kSlotRunStats, (size_t)(1 + nr), &st));
+    std::vector<double> eps_h, ratio_h;
+    eps_h.reserve(T);
+    for (int32_t k = 0; k < T; ++k) {
+        const int64_t t = state->t;
+        if (t % sched->probe_period == 0) {
+            GP_HIP(launch_probes(n, nr, sched->probe_kind, h->seed, params->rng_stream,
+                                 (uint64_t)(t / sched->probe_period), R, n, s));
+            GP_HIP(hipMemsetAsync(S_warm + n, 0, (size_t)n * nr * sizeof(double), s));
+        }
+        ulisse_params p = *params;
+        p.rng_counter = (uint64_t)t;
+        GP_TRY(gp_stoch_grad(h, X, psi, y, R, nr, sched->probe_kind, &p, S_warm, gvec, st, stream));
+        GP_HIP(hipMemcpyAsync(G + (t % sched->batch) * P, gvec, P * sizeof(double),
+                              hipMemcpyDeviceToDevice, s));
+        const double eps = state->frozen ? state->eps_frozen
+                                         : sched->a * std::pow(sched->b + (double)t, -sched->gamma);
+        eps_h.push_back(eps);
+        GP_TRY(sgld_step(h, P, psi, gvec, prior, M_chol, eps, params->rng_stream, (uint64_t)t, stream));
+        if (trace) GP_HIP(hipMemcpyAsync(trace + (int64_t)k * P, psi, P * sizeof(double), hipMemcpyDeviceToDevice, s));
+        if ((t + 1) % sched->batch == 0) {
+            GP_HIP(launch_langevin_ratio(G, sched->batch, P, M_chol, eps, ratio_dev, s));
+            double r = 0.0;
+            GP_HIP(hipMemcpyAsync(h->pinned_d, ratio_dev, sizeof(double), hipMemcpyDeviceToHost, s));
+            GP_HIP(hipStreamSynchronize(s));
+            r = *h->pinned_d;
+            ratio_h.push_back(r);
+            if (!state->frozen && r < sched->freeze_ratio) {
+                state->frozen = 1;
+                state->frozen_at = (int32_t)t;
+                state->eps_frozen = eps;
+            }
+        }
+        state->t = t + 1;
+    }
+    GP_HIP(hipStreamSynchronize(s));
+    if (eps_trace && !eps_h.empty())
+        GP_HIP(hipMemcpy(eps_trace, eps_h.data(), eps_h.size() * sizeof(double), hipMemcpyHostToDevice));
+    if (ratio_trace && !ratio_h.empty())
+        GP_HIP(hipMemcpy(ratio_trace, ratio_h.data(), ratio_h.size() * sizeof(double), hipMemcpyHostToDevice));
     return GP_OK;
 }
 

@@ -84,4 +84,8 @@ hipError_t launch_sgld(int P, double* psi, const double* g, int prior_kind, cons
                        const double* pb, const double* L, double eps, uint64_t k0,
                        uint64_t k1, uint64_t step, hipStream_t s);
 
+// ratio = eps / 4 * lambda_max(L^T cov(G) L) for a batch x P row-major G.
+hipError_t launch_langevin_ratio(const double* G, int batch, int P, const double* L, double eps,
+                                 double* ratio, hipStream_t s);
+
 }  // namespace gpk

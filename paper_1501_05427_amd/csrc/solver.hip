@@ -464,6 +464,68 @@ __global__ void sgld_kernel(int P, double* __restrict__ psi, const double* __res
 }
 
 // ---------------------------------------------------------------------------------------
+// Langevin-phase monitor: ratio = eps / 4 * lambda_max(L^T V L), V the sample covariance
+// (divisor batch - 1) of the batch x P gradients G (row-major); L^T V L has the
+// eigenvalues of M^(1/2) V M^(1/2) for M = L L^T.  Cyclic Jacobi rotations on the P x P
+// symmetric matrix (one thread; P <= 18).
+// ---------------------------------------------------------------------------------------
+__global__ void langevin_ratio_kernel(const double* __restrict__ G, int batch, int P,
+                                      const double* __restrict__ L, double eps,
+                                      double* __restrict__ ratio) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double mu[kMaxP], V[kMaxP][kMaxP], B[kMaxP][kMaxP];
+    for (int i = 0; i < P; ++i) {
+        double s = 0.0;
+        for (int t = 0; t < batch; ++t) s += G[t * P + i];
+        mu[i] = s / batch;
+    }
+    for (int i = 0; i < P; ++i)
+        for (int j = 0; j < P; ++j) {
+            double s = 0.0;
+            for (int t = 0; t < batch; ++t) s += (G[t * P + i] - mu[i]) * (G[t * P + j] - mu[j]);
+            V[i][j] = s / (batch - 1);
+        }
+    // B = L^T V L (L lower triangular, column-major; identity when null)
+    for (int i = 0; i < P; ++i)
+        for (int j = 0; j < P; ++j) {
+            double s = 0.0;
+            for (int a = 0; a < P; ++a)
+                for (int b = 0; b < P; ++b) {
+                    const double lai = L ? L[a + i * P] : (a == i ? 1.0 : 0.0);
+                    const double lbj = L ? L[b + j * P] : (b == j ? 1.0 : 0.0);
+                    s += lai * V[a][b] * lbj;
+                }
+            B[i][j] = s;
+        }
+    for (int sweep = 0; sweep < 50; ++sweep) {
+        double off = 0.0, diag = 0.0;
+        for (int i = 0; i < P; ++i)
+            for (int j = 0; j < P; ++j) (i == j ? diag : off) += B[i][j] * B[i][j];
+        if (off <= 1e-30 * diag) break;
+        for (int p = 0; p < P - 1; ++p)
+            for (int q = p + 1; q < P; ++q) {
+                if (B[p][q] == 0.0) continue;
+                const double theta = (B[q][q] - B[p][p]) / (2.0 * B[p][q]);
+                const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+                const double c = 1.0 / sqrt(t * t + 1.0), sn = t * c;
+                for (int k = 0; k < P; ++k) {  // rotate columns p, q
+                    const double bkp = B[k][p], bkq = B[k][q];
+                    B[k][p] = c * bkp - sn * bkq;
+                    B[k][q] = sn * bkp + c * bkq;
+                }
+                for (int k = 0; k < P; ++k) {  // rotate rows p, q
+                    const double bpk = B[p][k], bqk = B[q][k];
+                    B[p][k] = c * bpk - sn * bqk;
+                    B[q][k] = sn * bpk + c * bqk;
+                }
+            }
+    }
+    double lmax = B[0][0];
+    for (int i = 1; i < P; ++i) lmax = fmax(lmax, B[i][i]);
+    *ratio = 0.25 * eps * lmax;
+}
+
+// ---------------------------------------------------------------------------------------
 // Host launchers
 // ---------------------------------------------------------------------------------------
 static int grid_of(int64_t total) {
@@ -535,4 +597,12 @@ hipError_t launch_sgld(int P, double* psi, const double* g, int prior_kind, cons
     return hipGetLastError();
 }
 
+}  // namespace gpk
+
+namespace gpk {
+hipError_t launch_langevin_ratio(const double* G, int batch, int P, const double* L, double eps,
+                                 double* ratio, hipStream_t s) {
+    langevin_ratio_kernel<<<1, 64, 0, s>>>(G, batch, P, L, eps, ratio);
+    return hipGetLastError();
+}
 }  // namespace gpk

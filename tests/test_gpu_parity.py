@@ -418,3 +418,65 @@ def test_sgld_step_parity(h, prior_kind):
     torch.cuda.synchronize()
     ref = osgld.step_drawn(psi, g, 1e-3, h.seed, 4, 8, L, prior_kind, a, b)
     np.testing.assert_allclose(psid.cpu().numpy(), ref, rtol=1e-13, atol=1e-14)
+
+
+@pytest.mark.parametrize("freeze_ratio", [1e-12, 1e12])
+def test_sgld_run_protocol(h, freeze_ratio):
+    # the paper's protocol on a small chain: probes redrawn every 3 steps, warm starts,
+    # decreasing step size, monitor on batches of 4 gradients, freeze rule; converged
+    # solves keep both sides on the same path, so the traces must agree
+    n, d, nr, T = 300, 2, 4, 10
+    X, psi = problem(n, d, seed=302, lam=1.0, ell=(0.1, 0.3))
+    K = ogp.kernel_matrix(X, psi)
+    y = (np.linalg.cholesky(K) @ np.random.default_rng(1).standard_normal(n)).astype(np.float32)
+    q, rate, eps_c, stream = 1e-12, 1e-9, 1e-7, 6
+    a, b = osgld.schedule_from_endpoints(2e-3, 1e-3, T)
+    L = np.diag(np.full(d + 2, n ** -0.5))
+    params = pb.make_params(q=q, rate=rate, eps=eps_c, eps_relative=1, max_iter=500, rng_stream=stream)
+    sched = pb.make_schedule(a, b, 1.0, freeze_ratio, batch=4, probe_period=3, n_probes=nr,
+                             probe_kind=pb.PROBE_RADEMACHER)
+    state = pb.new_state(0)
+    psid = dev(psi)
+    S_warm = torch.zeros((nr + 1, n), dtype=torch.float64, device="cuda").t()
+    R = pb.colmajor(n, nr)
+    trace = torch.zeros((T, d + 2), dtype=torch.float64, device="cuda")
+    eps_tr = torch.zeros(T, dtype=torch.float64, device="cuda")
+    ratio_tr = torch.zeros(T, dtype=torch.float64, device="cuda")
+    pa, pbb = np.zeros(d + 2), np.full(d + 2, 3.0)
+    Ld = dev(L.ravel(order="F"))
+    # two calls (6 + 4 steps) exercise resumption
+    pb.sgld_run(h, dev(X), psid, dev(y), params, sched, state, 6, S_warm, R, prior_kind=1,
+                prior_a=dev(pa), prior_b=dev(pbb), M_chol=Ld, trace=trace[:6], eps_trace=eps_tr[:6],
+                ratio_trace=ratio_tr[:1])
+    pb.sgld_run(h, dev(X), psid, dev(y), params, sched, state, 4, S_warm, R, prior_kind=1,
+                prior_a=dev(pa), prior_b=dev(pbb), M_chol=Ld, trace=trace[6:], eps_trace=eps_tr[6:],
+                ratio_trace=ratio_tr[1:])
+    torch.cuda.synchronize()
+    # oracle run of the same protocol
+    p_o = psi.copy()
+    Sw = np.zeros((n, nr + 1))
+    R_o = None
+    G = []
+    ratios, eps_list, tr = [], [], []
+    frozen, eps_frozen, frozen_at = False, 0.0, -1
+    for t in range(T):
+        if t % 3 == 0:
+            R_o = orng.probes(h.seed, stream, t // 3, n, nr, 1)
+            Sw[:, 1:] = 0.0
+        g, St, Scg, _ = osg.stoch_grad(X, p_o, y, R_o, q, rate, eps_c, 500, h.seed, stream, t,
+                                       S_warm=Sw, eps_relative=True)
+        Sw = Scg
+        G.append(g)
+        e = eps_frozen if frozen else osgld.eps_schedule(a, b, 1.0, t)
+        eps_list.append(e)
+        p_o = osgld.step_drawn(p_o, g, e, h.seed, stream, t, L, 1, pa, pbb)
+        tr.append(p_o.copy())
+        if (t + 1) % 4 == 0:
+            rr = osgld.langevin_ratio(np.array(G[-4:]), L, e)
+            ratios.append(rr)
+            if not frozen and rr < freeze_ratio:
+                frozen, eps_frozen, frozen_at = True, e, t
+    np.testing.assert_allclose(eps_tr.cpu().numpy(), eps_list, rtol=1e-14)
+    np.testing.assert_allclose(trace.cpu().numpy(), np.array(tr), rtol=1e-7, atol=1e-7)
+    np.testing.assert_allclose(ratio_tr.cpu().numpy()[:2], ratios, rtol=1e-3)
+    assert (state.frozen, state.frozen_at) == (int(frozen), frozen_at) and state.t == T

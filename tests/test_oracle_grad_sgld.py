@@ -173,3 +173,28 @@ def test_sgld_recovers_tiny_gp_posterior():
     se = bm.std(axis=0, ddof=1) / np.sqrt(50)
     assert np.all(np.abs(draws.mean(axis=0) - mean) < 4 * se + 0.02 * np.sqrt(np.diag(cov)))
     np.testing.assert_allclose(draws.var(axis=0), np.diag(cov), rtol=0.2)
+
+
+def test_schedule_endpoints_and_monotone():
+    a, b = sgld.schedule_from_endpoints(1e-1, 1e-4, 40000)
+    np.testing.assert_allclose(sgld.eps_schedule(a, b, 1.0, 0), 1e-1, rtol=1e-12)
+    np.testing.assert_allclose(sgld.eps_schedule(a, b, 1.0, 39999), 1e-4, rtol=1e-12)
+    e = sgld.eps_schedule(a, b, 1.0, np.arange(40000))
+    assert np.all(np.diff(e) < 0)
+    # the conditions of Sec. 2.1: sum eps_t diverges (harmonic), sum eps_t^2 converges
+    np.testing.assert_allclose(a, 4.0039, rtol=1e-4)
+
+
+def test_langevin_ratio_matches_symmetric_square_root_form():
+    import scipy.linalg as sla
+    r = np.random.default_rng(3)
+    G = r.standard_normal((100, 5)) @ r.standard_normal((5, 5))
+    A = r.standard_normal((5, 5))
+    M = A @ A.T + 5 * np.eye(5)
+    L = np.linalg.cholesky(M)
+    Mh = np.real(sla.sqrtm(M))
+    V = np.cov(G.T)
+    ref = 0.25 * 0.01 * np.max(np.linalg.eigvalsh(Mh @ V @ Mh))
+    np.testing.assert_allclose(sgld.langevin_ratio(G, L, 0.01), ref, rtol=1e-10)
+    np.testing.assert_allclose(sgld.langevin_ratio(G, None, 0.01),
+                               0.25 * 0.01 * np.linalg.eigvalsh(V)[-1], rtol=1e-12)

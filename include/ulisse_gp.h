@@ -102,6 +102,21 @@ typedef struct {
     gp_precision prec;      /* arithmetic of the products K d                               */
 } ulisse_params;
 
+/* Preconditioner for the CG iterations under ULISSE (the preconditioned variant of
+ * Sec. 3.3 with a fixed preconditioner; the series of Sec. 4 stays unbiased for any CG
+ * variant):  P^-1 v = tau_inv v + U (h o (U^T v)), i.e. P = U diag(d) U^T + tau (I - U U^T)
+ * with h_kappa = 1/d_kappa - tau_inv for orthonormal U.  U: n x k FP32 device, column-major
+ * with ld ldu >= n, k in {16, 32, 64}.  coef: k + 1 FP64 device values, h_0..h_{k-1}
+ * then tau_inv.  P must be SPD (d_kappa > 0, tau_inv > 0).  The residual norms that set l
+ * and the convergence test stay unpreconditioned (||b - K s||_2). */
+typedef struct {
+    const float* U;
+    int64_t ldu;
+    int32_t k;
+    int32_t reserved;
+    const double* coef;
+} gp_precond;
+
 /* Per-system outcome, written by the device.  J_b = -1 for a single-track system. */
 typedef struct {
     int32_t l;       /* first iteration with ||e|| below alpha (0: never reached)           */
@@ -131,6 +146,12 @@ gp_status ulisse_solve(gp_handle* h, gp_data X, const double* psi, const float* 
                        int32_t m, int64_t ldb, const double* S0, const ulisse_params* params,
                        double* S_tilde, double* S_cg, ulisse_sysstat* stats, void* stream);
 
+/* ulisse_solve over preconditioned CG (pc non-null; same conventions otherwise). */
+gp_status ulisse_solve_pc(gp_handle* h, gp_data X, const double* psi, const float* B,
+                          int32_t m, int64_t ldb, const double* S0, const ulisse_params* params,
+                          const gp_precond* pc, double* S_tilde, double* S_cg,
+                          ulisse_sysstat* stats, void* stream);
+
 /*
  * One unbiased estimate of the gradient of log p(y | psi, X) with respect to psi
  * (eq. gradient:unbiased with the two-estimate quadratic term of Sec. 4.1):
@@ -146,6 +167,12 @@ gp_status gp_stoch_grad(gp_handle* h, gp_data X, const double* psi, const float*
                         const float* R, int32_t n_probes, int32_t probe_kind,
                         const ulisse_params* params, double* S_warm, double* g,
                         ulisse_sysstat* stats, void* stream);
+
+/* gp_stoch_grad with its solves over preconditioned CG (pc non-null). */
+gp_status gp_stoch_grad_pc(gp_handle* h, gp_data X, const double* psi, const float* y,
+                           const float* R, int32_t n_probes, int32_t probe_kind,
+                           const ulisse_params* params, const gp_precond* pc, double* S_warm,
+                           double* g, ulisse_sysstat* stats, void* stream);
 
 /* Prior on psi: kind 0 flat; kind 1 psi_j ~ N(a_j, b_j^2); kind 2 exp(psi_j) ~ Gamma(shape
  * a_j, rate b_j) with the Jacobian of the log transform.  a, b: P FP64 device (NULL for

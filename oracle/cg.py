@@ -47,3 +47,40 @@ def cg(matvec, b, s0, eps, max_iter):
             return s, i, True, r
         if i >= max_iter:
             return s, i, False, r
+
+
+def pcg_iterates(matvec, apply_pinv, b, s0):
+    """Preconditioned CG (the variant named in Sec. 3.3, with a preconditioner applied as
+    z = P^-1 e): yields (i, s_i, e_i, delta_i) like cg_iterates.
+
+    e is the unpreconditioned residual b - K s (recursively updated); the step lengths use
+    rho = e^T z.  With P = I this is Alg. 1.
+    """
+    b = np.asarray(b, dtype=np.float64)
+    s = np.array(s0, dtype=np.float64, copy=True)
+    e = b - matvec(s)
+    z = apply_pinv(e)
+    d = z.copy()
+    rho = e @ z
+    i = 0
+    while True:
+        q = matvec(d)
+        alpha = rho / (d @ q)
+        delta = alpha * d
+        s = s + delta
+        e = e - alpha * q
+        i += 1
+        yield i, s, e, delta
+        z = apply_pinv(e)
+        rho_next = e @ z
+        beta = rho_next / rho
+        d = z + beta * d
+        rho = rho_next
+
+
+def lowrank_pinv(U, h, tau_inv):
+    """v -> tau_inv v + U (h * (U^T v)): inverse of the rank-k-plus-identity preconditioner
+    P = U diag(dk) U^T + tau (I - U U^T) for orthonormal U, with h_k = 1/dk - 1/tau."""
+    U = np.asarray(U, dtype=np.float64)
+    h = np.asarray(h, dtype=np.float64)
+    return lambda v: tau_inv * v + U @ (h * (U.T @ v))

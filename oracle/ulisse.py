@@ -42,8 +42,11 @@ def expected_tail_terms(rate, jmax=100000):
 class _LazyCG:
     """One CG run whose increments are produced on demand and shared by all tracks."""
 
-    def __init__(self, matvec, b, s0):
-        self.it = _cg.cg_iterates(matvec, b, s0)
+    def __init__(self, matvec, b, s0, apply_pinv=None):
+        if apply_pinv is None:
+            self.it = _cg.cg_iterates(matvec, b, s0)
+        else:
+            self.it = _cg.pcg_iterates(matvec, apply_pinv, b, s0)
         self.deltas = [None]     # 1-based: deltas[i] = delta_i
         self.norms = [None]
         self.last_s = np.array(s0, dtype=np.float64, copy=True)
@@ -57,8 +60,9 @@ class _LazyCG:
         return self.deltas[i], self.norms[i]
 
 
-def solve(matvec, b, s0, alpha, eps, max_iter, rate, uniform, ntracks=1):
-    """One ULISSE solve of K s = b.
+def solve(matvec, b, s0, alpha, eps, max_iter, rate, uniform, ntracks=1, apply_pinv=None):
+    """One ULISSE solve of K s = b (over preconditioned CG when apply_pinv is given: the
+    series argument of Sec. 4 holds for any CG variant, as the paper notes).
 
     uniform(track, j) returns u_j for that track.  Returns a dict with
       s_tilde  list of ntracks FP64 vectors (the unbiased estimates)
@@ -68,7 +72,7 @@ def solve(matvec, b, s0, alpha, eps, max_iter, rate, uniform, ntracks=1):
       flags    NOTCONV if the cap was hit before the series ended
     """
     b = np.asarray(b, dtype=np.float64)
-    cgrun = _LazyCG(matvec, b, s0)
+    cgrun = _LazyCG(matvec, b, s0, apply_pinv)
     base = np.array(s0, dtype=np.float64, copy=True)
     flags = 0
     i = 0
@@ -114,7 +118,7 @@ def solve(matvec, b, s0, alpha, eps, max_iter, rate, uniform, ntracks=1):
 
 
 def solve_systems(matvec, B, S0, q, rate, eps, max_iter, seed, stream, step,
-                  two_track_first=False, eps_relative=False):
+                  two_track_first=False, eps_relative=False, apply_pinv=None):
     """ULISSE on every column of B with the library's counter layout for the u_j.
 
     Column c is system c; with two_track_first, column 0 carries tracks 0 and 1.
@@ -133,7 +137,7 @@ def solve_systems(matvec, B, S0, q, rate, eps, max_iter, seed, stream, step,
         def uniform(t, j, c=c):
             return _rng.ulisse_uniform(seed, stream, step, c, t, j)
 
-        res = solve(matvec, b, s0, alpha, thr, max_iter, rate, uniform, nt)
+        res = solve(matvec, b, s0, alpha, thr, max_iter, rate, uniform, nt, apply_pinv)
         out_cols.extend(res["s_tilde"])
         scg[:, c] = res["s_cg"]
         stats.append(dict(l=res["l"], J=res["J"], iters=res["iters"], flags=res["flags"]))

@@ -50,6 +50,11 @@ class gp_profile_stats(Structure):
                 ("dquad_ms", c_double), ("solves", c_int64), ("kmv_passes", c_int64)]
 
 
+class gp_precond(Structure):
+    _fields_ = [("U", c_void_p), ("ldu", c_int64), ("k", c_int32), ("reserved", c_int32),
+                ("coef", c_void_p)]
+
+
 class sgld_schedule(Structure):
     _fields_ = [("a", c_double), ("b", c_double), ("gamma", c_double), ("freeze_ratio", c_double),
                 ("batch", c_int32), ("probe_period", c_int32), ("n_probes", c_int32),
@@ -106,6 +111,14 @@ def lib():
     L.gp_draw_probes.argtypes = [c_void_p, c_int64, c_int32, c_int32, c_uint64, c_uint64, c_void_p, c_int64, c_void_p]
     L.gp_philox.restype = c_int
     L.gp_philox.argtypes = [c_uint64, c_uint64, c_uint64, c_uint64, c_uint64, c_uint64, c_int64, c_void_p, c_void_p]
+    L.ulisse_solve_pc.restype = c_int
+    L.ulisse_solve_pc.argtypes = [c_void_p, gp_data, c_void_p, c_void_p, c_int32, c_int64, c_void_p,
+                                  POINTER(ulisse_params), POINTER(gp_precond), c_void_p, c_void_p,
+                                  c_void_p, c_void_p]
+    L.gp_stoch_grad_pc.restype = c_int
+    L.gp_stoch_grad_pc.argtypes = [c_void_p, gp_data, c_void_p, c_void_p, c_void_p, c_int32, c_int32,
+                                   POINTER(ulisse_params), POINTER(gp_precond), c_void_p, c_void_p,
+                                   c_void_p, c_void_p]
     L.sgld_run.restype = c_int
     L.sgld_run.argtypes = [c_void_p, gp_data, c_void_p, c_void_p, POINTER(ulisse_params), POINTER(gp_prior),
                            c_void_p, POINTER(sgld_schedule), POINTER(sgld_state), c_int32, c_void_p,
@@ -325,3 +338,47 @@ def sgld_run(h, X, psi, y, params, sched, state, T, S_warm, R, prior_kind=0, pri
                           _ptr(M_chol), ctypes.byref(sched), ctypes.byref(state), int(T), _ptr(S_warm),
                           _ptr(R), _ptr(trace), _ptr(eps_trace), _ptr(ratio_trace), _stream(stream)))
     return state
+
+
+class Precond:
+    """A gp_precond plus references to its device tensors (they must outlive every call
+    that uses the descriptor).  U: (n, k) column-major FP32; coef: k + 1 FP64 (h, tau_inv)."""
+
+    def __init__(self, U, coef):
+        self.U, self.coef = U, coef
+        self.c = gp_precond(U.data_ptr(), _ld(U, U.shape[0]), U.shape[1], 0, coef.data_ptr())
+
+
+def make_precond(U, coef):
+    return Precond(U, coef)
+
+
+def ulisse_solve_pc(h, X, psi, B, params, pc, S0=None, S_tilde=None, S_cg=None, stats=None, stream=None):
+    import torch
+    n = X.shape[0]
+    m = _cols(B)
+    mt = m + (1 if params.two_track_first else 0)
+    if S_tilde is None:
+        S_tilde = torch.zeros((mt, n), dtype=torch.float64, device=B.device).t()
+    if stats is None:
+        stats = stats_tensor(m, B.device)
+    _check(lib().ulisse_solve_pc(h.ptr, _data(X), _ptr(psi), _ptr(B), m, _ld(B, n), _ptr(S0),
+                                 ctypes.byref(params), ctypes.byref(pc.c), _ptr(S_tilde), _ptr(S_cg),
+                                 _ptr(stats), _stream(stream)))
+    return S_tilde, stats
+
+
+def gp_stoch_grad_pc(h, X, psi, y, params, pc, R=None, n_probes=None, probe_kind=PROBE_GAUSSIAN,
+                     S_warm=None, g=None, stats=None, stream=None):
+    import torch
+    d = X.shape[1]
+    if R is not None:
+        n_probes = _cols(R)
+    if g is None:
+        g = torch.zeros(d + 2, dtype=torch.float64, device=y.device)
+    if stats is None:
+        stats = stats_tensor(1 + n_probes, y.device)
+    _check(lib().gp_stoch_grad_pc(h.ptr, _data(X), _ptr(psi), _ptr(y), _ptr(R), int(n_probes),
+                                  int(probe_kind), ctypes.byref(params), ctypes.byref(pc.c), _ptr(S_warm),
+                                  _ptr(g), _ptr(stats), _stream(stream)))
+    return g, stats

@@ -44,7 +44,7 @@ enum Slot {
     kSlotZ, kSlotKP, kSlotVP, kSlotPart, kSlotQ, kSlotS, kSlotE, kSlotD, kSlotP1, kSlotP2,
     kSlotCounter, kSlotActive, kSlotState, kSlotStats, kSlotR, kSlotB, kSlotSt, kSlotS0,
     kSlotA32, kSlotB32, kSlotGpart, kSlotWork, kSlotVH, kSlotVL, kSlotGbatch, kSlotGvec,
-    kSlotRatio, kSlotRunStats, kNumSlots
+    kSlotRatio, kSlotRunStats, kSlotZp, kSlotUtv, kSlotHW, kSlotP3, kNumSlots
 };
 
 bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
@@ -181,10 +181,18 @@ gp_status prep(gp_handle* h, const gp_data& X, const double* psi, int64_t n_pad,
 
 // The ULISSE iterations for m systems whose right-hand sides are B (ld ldb); Z and kp
 // already prepared.
+gp_status check_precond(const gp_precond* pc, int64_t n) {
+    if (pc == nullptr) return GP_OK;
+    GP_CHECK(pc->U != nullptr && aligned(pc->U, 4) && pc->ldu >= n, "preconditioner U null, misaligned or ldu < n");
+    GP_CHECK(pc->k == 16 || pc->k == 32 || pc->k == 64, "preconditioner rank must be 16, 32 or 64");
+    GP_CHECK(pc->coef != nullptr && aligned(pc->coef, 8), "preconditioner coef null or misaligned");
+    return GP_OK;
+}
+
 gp_status solve_core(gp_handle* h, int64_t n, int d, const float* Z, const KParams* kp,
                      const float* B, int64_t ldb, int m, const double* S0,
                      const ulisse_params& p, double* St, double* S_cg, ulisse_sysstat* stats,
-                     hipStream_t s) {
+                     hipStream_t s, const gp_precond* pc = nullptr) {
     const KmvShape sh = kmv_shape(n, d, m, p.prec);
     const bool b16 = uses_bf16(sh, p.prec);
     const int64_t n_pad = sh.n_pad;
@@ -224,6 +232,17 @@ gp_status solve_core(gp_handle* h, int64_t n, int d, const float* Z, const KPara
     a.seed = h->seed;
     a.rng_stream = p.rng_stream;
     a.rng_counter = p.rng_counter;
+    if (pc != nullptr) {
+        a.U = pc->U;
+        a.ldu = pc->ldu;
+        a.pk = pc->k;
+        a.coef = pc->coef;
+        a.nb256 = pc_chunks(n);
+        GP_TRY(ws(h, kSlotZp, (size_t)n_pad * m, &a.Zp));
+        GP_TRY(ws(h, kSlotUtv, (size_t)a.nb256 * pc->k * m, &a.utv_part));
+        GP_TRY(ws(h, kSlotHW, (size_t)pc->k * m, &a.HW));
+        GP_TRY(ws(h, kSlotP3, (size_t)a.nb256 * m, &a.part3));
+    }
 
     uint16_t *DH = nullptr, *DL = nullptr;
     if (b16) {
@@ -246,10 +265,13 @@ gp_status solve_core(gp_handle* h, int64_t n, int d, const float* Z, const KPara
         h->passes += 1;
     }
     GP_HIP(solver_init(a, warm, s));
+    if (pc != nullptr) GP_HIP(launch_pc_step(a, 1, s));
+    GP_HIP(solver_init_state(a, s));
     for (int it = 0; it <= p.max_iter; ++it) {
         GP_TRY(product(a.n_active));
         GP_HIP(solver_reduce(a, s));
         GP_HIP(solver_update(a, s));
+        if (pc != nullptr) GP_HIP(launch_pc_step(a, 0, s));
         SysState* next = states + ((it + 1) & 1) * m;
         GP_HIP(solver_direction(a, next, s));
         a.state = next;
@@ -371,6 +393,13 @@ gp_status gp_dkmv(gp_handle* h, gp_data X, const double* psi, const float* V, in
 gp_status ulisse_solve(gp_handle* h, gp_data X, const double* psi, const float* B,
                        int32_t m, int64_t ldb, const double* S0, const ulisse_params* params,
                        double* S_tilde, double* S_cg, ulisse_sysstat* stats, void* stream) {
+    return ulisse_solve_pc(h, X, psi, B, m, ldb, S0, params, nullptr, S_tilde, S_cg, stats, stream);
+}
+
+gp_status ulisse_solve_pc(gp_handle* h, gp_data X, const double* psi, const float* B,
+                          int32_t m, int64_t ldb, const double* S0, const ulisse_params* params,
+                          const gp_precond* pc, double* S_tilde, double* S_cg,
+                          ulisse_sysstat* stats, void* stream) {
     GP_TRY(check_handle(h));
     GP_TRY(check_data(X));
     GP_TRY(check_params(params));
@@ -379,18 +408,27 @@ gp_status ulisse_solve(gp_handle* h, gp_data X, const double* psi, const float* 
     GP_CHECK(S_tilde != nullptr && aligned(S_tilde, 8), "S_tilde null or misaligned");
     GP_CHECK(S0 == nullptr || aligned(S0, 8), "S0 misaligned");
     GP_CHECK(S_cg == nullptr || aligned(S_cg, 8), "S_cg misaligned");
+    GP_TRY(check_precond(pc, X.n));
     hipStream_t s = (hipStream_t)stream;
     const int64_t n_pad = round_up(X.n, kRowPad);
     float* Z;
     KParams* kp;
     GP_TRY(prep(h, X, psi, n_pad, &Z, &kp, s));
-    return solve_core(h, X.n, X.d, Z, kp, B, ldb, m, S0, *params, S_tilde, S_cg, stats, s);
+    return solve_core(h, X.n, X.d, Z, kp, B, ldb, m, S0, *params, S_tilde, S_cg, stats, s, pc);
 }
 
 gp_status gp_stoch_grad(gp_handle* h, gp_data X, const double* psi, const float* y,
                         const float* R, int32_t n_probes, int32_t probe_kind,
                         const ulisse_params* params, double* S_warm, double* g,
                         ulisse_sysstat* stats, void* stream) {
+    return gp_stoch_grad_pc(h, X, psi, y, R, n_probes, probe_kind, params, nullptr, S_warm, g,
+                            stats, stream);
+}
+
+gp_status gp_stoch_grad_pc(gp_handle* h, gp_data X, const double* psi, const float* y,
+                           const float* R, int32_t n_probes, int32_t probe_kind,
+                           const ulisse_params* params, const gp_precond* pc, double* S_warm,
+                           double* g, ulisse_sysstat* stats, void* stream) {
     GP_TRY(check_handle(h));
     GP_TRY(check_data(X));
     GP_TRY(check_params(params));
@@ -400,6 +438,7 @@ gp_status gp_stoch_grad(gp_handle* h, gp_data X, const double* psi, const float*
     GP_CHECK(R == nullptr || aligned(R, 4), "R misaligned");
     GP_CHECK(g != nullptr && aligned(g, 8), "g null or misaligned");
     GP_CHECK(S_warm == nullptr || aligned(S_warm, 8), "S_warm misaligned");
+    GP_TRY(check_precond(pc, X.n));
     hipStream_t s = (hipStream_t)stream;
     const int64_t n = X.n;
     const int d = X.d;
@@ -436,7 +475,7 @@ gp_status gp_stoch_grad(gp_handle* h, gp_data X, const double* psi, const float*
     GP_TRY(ws(h, kSlotSt, (size_t)n * (m + 1), &St));
     ulisse_params p = *params;
     p.two_track_first = 1;
-    GP_TRY(solve_core(h, n, d, Z, kp, Bm, n, m, S0, p, St, S_warm, stats, s));
+    GP_TRY(solve_core(h, n, d, Z, kp, Bm, n, m, S0, p, St, S_warm, stats, s, pc));
 
     const DquadShape dq = dquad_shape(n, d, m);
     float *A32, *B32;

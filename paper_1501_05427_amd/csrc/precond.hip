@@ -1,0 +1,147 @@
+// Rank-k plus scaled-identity preconditioner inside the ULISSE/CG iterations.
+//
+//   P^-1 v = tau_inv v + U (h o (U^T v)),   U: n x k orthonormal columns (FP32),
+//   h_kappa = 1/d_kappa - tau_inv, the inverse of P = U diag(d) U^T + tau (I - U U^T).
+// Preconditioned CG (the variant of Sec. 3.3 with a fixed preconditioner) keeps the
+// estimator of Sec. 4 unbiased: the series is still a telescoping sum of CG increments
+// that converges to K^-1 b.
+//
+// Per iteration: U^T E for all systems (a k x n by n x m product, split over 256-row chunks
+// with FP32 partials), a fixed-order FP64 sum of the chunks scaled by h, then z for every
+// row and system with the partial sums of e^T z.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "gp_common.h"
+#include "internal.h"
+#include "solver.h"
+
+namespace gpk {
+
+constexpr int kChunk = 256;  // rows per workgroup of the U^T E partials and of the apply
+constexpr int kSub = 64;     // rows staged in LDS at a time
+
+// part[chunk][kappa][c] = sum over the chunk's rows of U[kappa][i] * E[c][i], in FP64: once
+// the residual lies mostly in span(U), e^T z = tau_inv ||e||^2 + sum h (u^T e)^2 cancels
+// (h ~ -tau_inv), and FP32 partial sums can make it negative.
+// With `first` (the initial residual, before the per-system state exists) every system is
+// processed and the "no system running" early exit is off.
+template <int KB>
+__global__ __launch_bounds__(kWG) void pc_utv_partial_kernel(SolverArgs a, int first) {
+    if (!first && *a.n_active == 0) return;
+    __shared__ float us[KB][kSub + 1];
+    __shared__ double es[kMaxSys][kSub + 1];
+    const int m = a.m;
+    const int nout = KB * m;
+    double acc[KB * kMaxSys / kWG];
+#pragma unroll
+    for (int r = 0; r < KB * kMaxSys / kWG; ++r) acc[r] = 0.0;
+    const int64_t base = (int64_t)blockIdx.x * kChunk;
+    for (int sub = 0; sub < kChunk / kSub; ++sub) {
+        const int64_t r0 = base + sub * kSub;
+        for (int e = threadIdx.x; e < KB * kSub; e += kWG) {
+            const int kappa = e / kSub, rr = e % kSub;
+            const int64_t i = r0 + rr;
+            us[kappa][rr] = i < a.n ? a.U[kappa * a.ldu + i] : 0.f;
+        }
+        for (int e = threadIdx.x; e < m * kSub; e += kWG) {
+            const int c = e / kSub, rr = e % kSub;
+            const int64_t i = r0 + rr;
+            es[c][rr] = i < a.n ? a.E[c * a.n_pad + i] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < KB * kMaxSys / kWG; ++r) {
+            const int o = threadIdx.x + r * kWG;
+            if (o < nout) {
+                const int kappa = o / m, c = o % m;
+                double s = acc[r];
+                for (int rr = 0; rr < kSub; ++rr) s = fma((double)us[kappa][rr], es[c][rr], s);
+                acc[r] = s;
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int r = 0; r < KB * kMaxSys / kWG; ++r) {
+        const int o = threadIdx.x + r * kWG;
+        if (o < nout) a.utv_part[(int64_t)blockIdx.x * nout + o] = acc[r];
+    }
+}
+
+// HW[kappa][c] = h_kappa * sum over chunks (fixed order, FP64)
+__global__ void pc_reduce_kernel(SolverArgs a, int nchunk, int first) {
+    if (!first && *a.n_active == 0) return;
+    const int nout = a.pk * a.m;
+    const int o = blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= nout) return;
+    double s = 0.0;
+    for (int b = 0; b < nchunk; ++b) s += a.utv_part[(int64_t)b * nout + o];
+    a.HW[o] = a.coef[o / a.m] * s;
+}
+
+// z = tau_inv e + U HW[:, c] for every active system; partial sums of e^T z per workgroup;
+// with `first`, also the initial direction d = fp32(z).
+template <int KB>
+__global__ __launch_bounds__(kWG) void pc_apply_kernel(SolverArgs a, int first) {
+    if (!first && *a.n_active == 0) return;
+    __shared__ double hw[KB][kMaxSys];
+    __shared__ double red[4][kMaxSys];
+    const int m = a.m;
+    for (int e = threadIdx.x; e < KB * m; e += kWG) hw[e / m][e % m] = a.HW[e];
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * kChunk + threadIdx.x;
+    const bool in = i < a.n;
+    float u[KB];
+#pragma unroll
+    for (int kappa = 0; kappa < KB; ++kappa) u[kappa] = in ? a.U[kappa * a.ldu + i] : 0.f;
+    const double tau_inv = a.coef[a.pk];
+    for (int c = 0; c < m; ++c) {
+        if (!first && !a.state[c].active) continue;  // uniform over the workgroup
+        double ez = 0.0;
+        if (in) {
+            double z = 0.0;
+#pragma unroll
+            for (int kappa = 0; kappa < KB; ++kappa) z += (double)u[kappa] * hw[kappa][c];
+            const double e = a.E[c * a.n_pad + i];
+            z += tau_inv * e;
+            a.Zp[c * a.n_pad + i] = z;
+            if (first) a.D[c * a.n_pad + i] = (float)z;
+            ez = e * z;
+        }
+        const double w = wave_sum(ez);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][c] = w;
+    }
+    __syncthreads();
+    if (threadIdx.x < m && (first || a.state[threadIdx.x].active)) {
+        const int c = threadIdx.x;
+        a.part3[(int64_t)blockIdx.x * m + c] = (red[0][c] + red[1][c]) + (red[2][c] + red[3][c]);
+    }
+}
+
+int pc_chunks(int64_t n) { return (int)((n + kChunk - 1) / kChunk); }
+
+template <int KB>
+static hipError_t pc_step_k(const SolverArgs& a, int first, hipStream_t s) {
+    const int nchunk = pc_chunks(a.n);
+    pc_utv_partial_kernel<KB><<<nchunk, kWG, 0, s>>>(a, first);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    pc_reduce_kernel<<<(KB * a.m + kWG - 1) / kWG, kWG, 0, s>>>(a, nchunk, first);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    pc_apply_kernel<KB><<<nchunk, kWG, 0, s>>>(a, first);
+    return hipGetLastError();
+}
+
+hipError_t launch_pc_step(const SolverArgs& a, int first, hipStream_t s) {
+    switch (a.pk) {
+        case 16: return pc_step_k<16>(a, first, s);
+        case 32: return pc_step_k<32>(a, first, s);
+        case 64: return pc_step_k<64>(a, first, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace gpk

@@ -58,6 +58,16 @@ struct SolverArgs {
     double q, rate, eps;
     int32_t eps_relative, max_iter, two_track, pad_;
     uint64_t seed, rng_stream, rng_counter;
+    // preconditioner P^-1 v = tau_inv v + U (h o U^T v); U == nullptr: plain CG
+    const float* U;        // n x pk, ld ldu (FP32)
+    int64_t ldu;
+    int32_t pk;            // 16, 32 or 64
+    int32_t nb256;         // workgroups of the preconditioner kernels (pc_chunks(n))
+    const double* coef;    // h[0..pk-1], tau_inv at [pk]
+    double* Zp;            // z = P^-1 e, ld n_pad
+    double* utv_part;      // nb256 x pk x m
+    double* HW;            // pk x m
+    double* part3;         // nb256 x m partial sums of e^T z
 };
 
 int solver_blocks(int64_t n);
@@ -83,6 +93,12 @@ hipError_t launch_grad_finish(const double* St, const float* R, int64_t ldr, int
 hipError_t launch_sgld(int P, double* psi, const double* g, int prior_kind, const double* pa,
                        const double* pb, const double* L, double eps, uint64_t k0,
                        uint64_t k1, uint64_t step, hipStream_t s);
+
+// z = P^-1 e for every active system and the partials of e^T z; `first` also sets d = z.
+int pc_chunks(int64_t n);
+hipError_t launch_pc_step(const SolverArgs& a, int first, hipStream_t s);
+// Initial state once the initial residual (and z for PCG) are in place.
+hipError_t solver_init_state(const SolverArgs& a, hipStream_t s);
 
 // ratio = eps / 4 * lambda_max(L^T cov(G) L) for a batch x P row-major G.
 hipError_t launch_langevin_ratio(const double* G, int batch, int P, const double* L, double eps,

@@ -94,8 +94,9 @@ __global__ __launch_bounds__(kWG) void ulisse_init_kernel(SolverArgs a, int warm
 __global__ __launch_bounds__(kWG) void ulisse_init_state_kernel(SolverArgs a) {
     __shared__ double bcast;
     const int c = blockIdx.x;
-    const double rho = column_total(a.part, a.nb, a.m, c, &bcast);
+    const double ee = column_total(a.part, a.nb, a.m, c, &bcast);
     const double b2 = column_total(a.part2, a.nb, a.m, c, &bcast);
+    const double rho = a.U != nullptr ? column_total(a.part3, a.nb256, a.m, c, &bcast) : ee;
     if (threadIdx.x != 0) return;
     SysState st;
     st.rho = rho;
@@ -103,7 +104,7 @@ __global__ __launch_bounds__(kWG) void ulisse_init_state_kernel(SolverArgs a) {
     st.beta = 0.0;
     st.thr_alpha = a.q * sqrt((double)a.n);
     st.thr_eps = a.eps_relative ? a.eps * sqrt(b2) : a.eps;
-    st.res = sqrt(rho);
+    st.res = sqrt(ee);
     st.ntracks = (a.two_track && c == 0) ? 2 : 1;
     for (int t = 0; t < 2; ++t) {
         st.W[t] = t < st.ntracks ? 1.0 : 0.0;
@@ -214,7 +215,7 @@ __device__ inline void tail_decide(const SolverArgs& a, SysState& st, int c, int
 // The per-system decisions after one CG iteration (threshold l, tail draws, convergence,
 // iteration cap, breakdown), applied to a copy of the state.
 __device__ inline void advance(const SolverArgs& a, SysState& st, int c, double gamma,
-                               double rho_new) {
+                               double rho_new, double ee) {
     const double al = st.rho / gamma;
     if (!alpha_ok(gamma, al)) {
         st.flags |= (int)ULISSE_BREAKDOWN;
@@ -226,7 +227,7 @@ __device__ inline void advance(const SolverArgs& a, SysState& st, int c, double 
         return;
     }
     st.alpha = al;
-    st.res = sqrt(rho_new);
+    st.res = sqrt(ee);
     st.iters += 1;
     for (int t = 0; t < st.ntracks; ++t) {
         if (st.phase[t] == kDone) continue;
@@ -246,7 +247,7 @@ __device__ inline void advance(const SolverArgs& a, SysState& st, int c, double 
     }
     bool done = true;
     for (int t = 0; t < st.ntracks; ++t) done = done && st.phase[t] == kDone;
-    if (!isfinite(rho_new)) {
+    if (!isfinite(rho_new) || !isfinite(ee)) {
         done = true;
         st.flags |= (int)ULISSE_BREAKDOWN;
     }
@@ -271,8 +272,9 @@ __global__ __launch_bounds__(kWG) void ulisse_direction_kernel(SolverArgs a, con
         return;
     }
     const double gamma = column_total(a.part, a.nb, a.m, c, &bcast);
-    const double rho_new = column_total(a.part2, a.nb, a.m, c, &bcast);
-    advance(a, st, c, gamma, rho_new);
+    const double ee = column_total(a.part2, a.nb, a.m, c, &bcast);
+    const double rho_new = a.U != nullptr ? column_total(a.part3, a.nb256, a.m, c, &bcast) : ee;
+    advance(a, st, c, gamma, rho_new, ee);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         next[c] = st;
         if (!st.active) {
@@ -287,7 +289,8 @@ __global__ __launch_bounds__(kWG) void ulisse_direction_kernel(SolverArgs a, con
         const int64_t i = (int64_t)blockIdx.x * kRowsPerBlock + r * kWG + threadIdx.x;
         if (i >= a.n) break;
         const int64_t o = c * a.n_pad + i;
-        a.D[o] = (float)(a.E[o] + beta * (double)a.D[o]);
+        const double zv = a.U != nullptr ? a.Zp[o] : a.E[o];
+        a.D[o] = (float)(zv + beta * (double)a.D[o]);
     }
 }
 
@@ -538,8 +541,9 @@ int solver_blocks(int64_t n) { return (int)((n + kRowsPerBlock - 1) / kRowsPerBl
 
 hipError_t solver_init(const SolverArgs& a, int warm, hipStream_t s) {
     ulisse_init_kernel<<<vec_grid(a), kWG, 0, s>>>(a, warm);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    return hipGetLastError();
+}
+hipError_t solver_init_state(const SolverArgs& a, hipStream_t s) {
     ulisse_init_state_kernel<<<(unsigned)a.m, kWG, 0, s>>>(a);
     return hipGetLastError();
 }

@@ -480,3 +480,62 @@ def test_sgld_run_protocol(h, freeze_ratio):
     np.testing.assert_allclose(trace.cpu().numpy(), np.array(tr), rtol=1e-7, atol=1e-7)
     np.testing.assert_allclose(ratio_tr.cpu().numpy()[:2], ratios, rtol=1e-3)
     assert (state.frozen, state.frozen_at) == (int(frozen), frozen_at) and state.t == T
+
+
+def _deflation(K, k):
+    """Top-k eigenvectors of K and the matching h, tau_inv (test-side construction)."""
+    w, Q = np.linalg.eigh(K)
+    U, dk = Q[:, -k:], w[-k:]
+    tau = np.mean(w[:-k])
+    h_ = 1.0 / dk - 1.0 / tau
+    return U, h_, 1.0 / tau
+
+
+@pytest.mark.parametrize("k,m,two_track", [(16, 3, 0), (32, 17, 1), (64, 5, 1)])
+def test_ulisse_pcg_draw_for_draw(h, k, m, two_track):
+    n, d = 400, 2
+    X, psi = problem(n, d, seed=40 + m, lam=0.2, ell=(0.2, 0.4))
+    K = ogp.kernel_matrix(X, psi)
+    U, hh, tinv = _deflation(K, k)
+    pinv = ocg.lowrank_pinv(U, hh, tinv)
+    Bm = np.random.default_rng(m).standard_normal((n, m)).astype(np.float32)
+    # threshold between two residual norms of the preconditioned run of system 0
+    norms = []
+    for i, s_, e, dl in ocg.pcg_iterates(lambda v: K @ v, pinv, Bm[:, 0].astype(np.float64), np.zeros(n)):
+        norms.append(np.linalg.norm(e))
+        if i >= 2 and min(norms[:-1]) > 1.5 * norms[-1]:
+            break
+    q = np.sqrt(min(norms[:-1]) * norms[-1]) / np.sqrt(n)
+    rate, eps = 0.7, 1e-6
+    params = pb.make_params(q=q, rate=rate, eps=eps, eps_relative=1, max_iter=200,
+                            two_track_first=two_track, rng_stream=5, rng_counter=2)
+    Ud = colm(U.astype(np.float32))
+    coef = dev(np.concatenate([hh, [tinv]]))
+    pc = pb.make_precond(Ud, coef)
+    St, stats = pb.ulisse_solve_pc(h, dev(X), dev(psi), colm(Bm), params, pc)
+    torch.cuda.synchronize()
+    U32 = U.astype(np.float32).astype(np.float64)
+    ref_St, _, ref_stats = oul.solve_systems(lambda v: K @ v, Bm.astype(np.float64), None, q, rate, eps,
+                                             200, h.seed, 5, 2, two_track_first=bool(two_track),
+                                             eps_relative=True, apply_pinv=ocg.lowrank_pinv(U32, hh, tinv))
+    for c, (g_, r) in enumerate(zip(pb.decode_stats(stats), ref_stats)):
+        assert (g_["l"], g_["iters"], g_["J_a"], g_["flags"]) == (r["l"], r["iters"], r["J"][0], r["flags"]), c
+    assert colwise_rel(St.cpu().numpy(), ref_St).max() <= 2e-4
+
+
+def test_pcg_converged_solution_and_fewer_iterations(h):
+    n, d, m, k = 1000, 2, 4, 64
+    X, psi = problem(n, d, seed=3, lam=0.02, ell=(0.2, 0.3))
+    K = ogp.kernel_matrix(X, psi)
+    U, hh, tinv = _deflation(K, k)
+    Bm = np.random.default_rng(0).standard_normal((n, m)).astype(np.float32)
+    params = pb.make_params(q=1e-12, rate=1e-9, eps=1e-6, eps_relative=1, max_iter=3000)
+    pc = pb.make_precond(colm(U.astype(np.float32)), dev(np.concatenate([hh, [tinv]])))
+    St_pc, st_pc = pb.ulisse_solve_pc(h, dev(X), dev(psi), colm(Bm), params, pc)
+    St, st = pb.ulisse_solve(h, dev(X), dev(psi), colm(Bm), params)
+    torch.cuda.synchronize()
+    ref = ogp.solve(X, psi, Bm.astype(np.float64))
+    assert colwise_rel(St_pc.cpu().numpy(), ref).max() <= 1e-4, (pb.decode_stats(st_pc), pb.decode_stats(st))
+    it_pc = max(s["iters"] for s in pb.decode_stats(st_pc))
+    it = max(s["iters"] for s in pb.decode_stats(st))
+    assert it_pc < 0.7 * it, (it_pc, it)

@@ -117,3 +117,38 @@ def test_probe_matrix_columns_are_independent_streams():
     np.testing.assert_array_equal(R[:, 1], rng.gaussians(1, 2, 1, rng.PROBE, 3, 100))
     Rr = rng.probes(1, 2, 3, 100, 2, kind=1)
     assert set(np.unique(Rr)) == {-1.0, 1.0}
+
+
+def test_pcg_with_exact_preconditioner_converges_in_one_step():
+    K, b = _spd(30, seed=7)
+    Kinv = np.linalg.inv(K)
+    it = cg.pcg_iterates(lambda v: K @ v, lambda v: Kinv @ v, b, np.zeros(30))
+    i, s, e, _ = next(it)
+    np.testing.assert_allclose(s, sla.cho_solve(sla.cho_factor(K), b), rtol=1e-9, atol=1e-10)
+    assert np.linalg.norm(e) < 1e-9 * np.linalg.norm(b)
+
+
+def test_pcg_identity_is_cg_and_lowrank_preconditioner_helps():
+    K, b = _spd(60, lam=1e-2, seed=8)
+    for (i1, s1, e1, _), (i2, s2, e2, _) in zip(cg.cg_iterates(lambda v: K @ v, b, np.zeros(60)),
+                                              cg.pcg_iterates(lambda v: K @ v, lambda v: v, b, np.zeros(60))):
+        np.testing.assert_allclose(s1, s2, rtol=1e-12, atol=1e-12)
+        if i1 == 8:
+            break
+    # deflating the top 10 eigenvectors: P^-1 = (1/tau) I + U (1/d - 1/tau) U^T
+    w, Q = np.linalg.eigh(K)
+    U, dk = Q[:, -10:], w[-10:]
+    tau = np.mean(w[:-10])
+    pinv = cg.lowrank_pinv(U, 1 / dk - 1 / tau, 1 / tau)
+    P = U @ np.diag(dk) @ U.T + tau * (np.eye(60) - U @ U.T)
+    np.testing.assert_allclose(pinv(b), np.linalg.solve(P, b), rtol=1e-9, atol=1e-12)
+
+    def run(gen, tol):
+        for i, s, e, _ in gen:
+            if np.linalg.norm(e) < tol * np.linalg.norm(b) or i >= 500:
+                return i, s
+    n_cg, _ = run(cg.cg_iterates(lambda v: K @ v, b, np.zeros(60)), 1e-8)
+    n_pcg, _ = run(cg.pcg_iterates(lambda v: K @ v, pinv, b, np.zeros(60)), 1e-8)
+    assert n_pcg < n_cg < 500
+    _, s = run(cg.pcg_iterates(lambda v: K @ v, pinv, b, np.zeros(60)), 1e-10)
+    np.testing.assert_allclose(s, sla.cho_solve(sla.cho_factor(K), b), rtol=1e-8, atol=1e-9)

@@ -182,3 +182,35 @@ def test_s_cg_is_the_last_cg_iterate():
         if i == it:
             np.testing.assert_allclose(res["s_cg"], s, rtol=1e-13, atol=1e-13)
             break
+
+
+def test_exact_mean_over_preconditioned_cg_path():
+    # unbiasedness does not depend on the CG variant: enumerate J over a PCG path
+    K, b = _system(40, lam=0.05, seed=6)
+    w, Q = np.linalg.eigh(K)
+    U, dk = Q[:, -6:], w[-6:]
+    tau = np.mean(w[:-6])
+    pinv = cg.lowrank_pinv(U, 1 / dk - 1 / tau, 1 / tau)
+    rate, eps = 0.5, 1e-11
+    deltas, norms = [None], [None]
+    for i, s, e, dl in cg.pcg_iterates(lambda v: K @ v, pinv, b, np.zeros(40)):
+        deltas.append(dl)
+        norms.append(np.linalg.norm(e))
+        if norms[-1] < eps:
+            break
+    T = len(deltas) - 1
+    alpha = 0.5 * (norms[T - 3] + norms[T - 4]) if norms[T - 3] < norms[T - 4] else norms[T - 3] * 1.0001
+    mean = np.zeros(40)
+    total = 0.0
+    for Jt in range(8):
+        res = ulisse.solve(lambda v: K @ v, b, np.zeros(40), alpha, eps, 1000, rate, _forced(Jt),
+                           apply_pinv=pinv)
+        l = res["l"]
+        tail = T - l
+        if Jt > tail:
+            break
+        p = ulisse.survival(rate, Jt) - (ulisse.survival(rate, Jt + 1) if Jt < tail else 0.0)
+        mean += p * res["s_tilde"][0]
+        total += p
+    np.testing.assert_allclose(total, 1.0, rtol=1e-12)
+    np.testing.assert_allclose(mean, sla.cho_solve(sla.cho_factor(K), b), rtol=1e-7, atol=1e-8)

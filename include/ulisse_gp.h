@@ -247,6 +247,59 @@ gp_status sgld_run(gp_handle* h, gp_data X, double* psi, const float* y,
                    void* stream);
 
 /*
+ * Learned warm start and preconditioner.  A fixed orthonormal basis U (n x k) and a small
+ * network psi -> (c, log d, log tau) give, for every psi of the chain,
+ *   s0 = U c  (warm start of the y system) and  P^-1 = tau^-1 I + U diag(1/d - 1/tau) U^T
+ * (the preconditioned variant of Sec. 3.3 with a fixed P; the series of Sec. 4 stays
+ * unbiased for any SPD P, so the network changes only the cost of the solves).
+ *
+ * precond_build_basis: randomized range finder of K(psi_ref) with one power step
+ *   (Omega from Philox purpose 4), CholeskyQR2 in FP64, Rayleigh-Ritz rotation; writes U
+ *   (n x k FP32, ld ldu >= n) and the Ritz values (k FP64, decreasing).  k in {16, 32, 64}.
+ * precond_targets: for N log-parameter vectors psis (N x P FP64 row-major, device) the
+ *   Galerkin targets (N x (2k + 1) FP32 row-major): c = T^-1 U^T y, log diag T and
+ *   log tau, tau = (tr K - tr T) / (n - k), with T = U^T K(psi) U.
+ * MLP in -> hidden (tanh) -> hidden (tanh) -> out, FP32 parameters in one buffer of
+ *   precond_mlp_size(in, hidden, out) floats (weights, biases, then input/target
+ *   standardisation constants); hidden <= 1024.
+ * precond_mlp_init: standardisation constants from (psis, targets), Xavier-normal weights
+ *   (Philox purpose 5, key (seed, 0)), zero biases.
+ * precond_mlp_train: `steps` full-batch Adam steps (beta 0.9 / 0.999, eps 1e-8, learning
+ *   rate lr) on the mean squared error of the standardised targets; adam: 2 x trainable
+ *   floats (moments, zero at the first step); first_step = number of steps already taken;
+ *   loss_trace (nullable) receives the loss before each step.
+ * precond_mlp_forward: outputs (B x out, standardised) for B inputs, FP32 or, with bf16,
+ *   BF16 operands and FP32 accumulation.
+ * precond_mlp_grad: loss and gradient of the trainable parameters (for checks).
+ * precond_from_mlp: BF16 forward at one psi (device, P) -> coef (k + 1 FP64: h, tau_inv;
+ *   d is floored at tau so P stays SPD) and, if non-null, c (k FP64).
+ * precond_warm_start: s0 = U c (n FP64).
+ */
+gp_status precond_build_basis(gp_handle* h, gp_data X, const double* psi_ref, int32_t k,
+                              float* U, int64_t ldu, double* ritz, void* stream);
+gp_status precond_targets(gp_handle* h, gp_data X, const float* y, const float* U, int64_t ldu,
+                          int32_t k, const double* psis, int32_t N, float* targets, void* stream);
+int64_t precond_mlp_size(int32_t in, int32_t hidden, int32_t out);
+gp_status precond_mlp_init(gp_handle* h, float* params, int32_t in, int32_t hidden, int32_t out,
+                           const double* psis, const float* targets, int32_t N, uint64_t seed,
+                           void* stream);
+gp_status precond_mlp_train(gp_handle* h, float* params, float* adam, int32_t in, int32_t hidden,
+                            int32_t out, const double* psis, const float* targets, int32_t N,
+                            int32_t steps, int32_t first_step, float lr, float* loss_trace,
+                            void* stream);
+gp_status precond_mlp_forward(gp_handle* h, const float* params, int32_t in, int32_t hidden,
+                              int32_t out, const double* psis, int32_t B, float* Y, int32_t bf16,
+                              void* stream);
+gp_status precond_mlp_grad(gp_handle* h, const float* params, int32_t in, int32_t hidden,
+                           int32_t out, const double* psis, const float* targets, int32_t N,
+                           float* grad, float* loss, void* stream);
+gp_status precond_from_mlp(gp_handle* h, const float* params, int32_t in, int32_t hidden,
+                           int32_t out, const double* psi, int32_t k, double* coef, double* c,
+                           void* stream);
+gp_status precond_warm_start(gp_handle* h, const float* U, int64_t ldu, int32_t k, int64_t n,
+                             const double* c, double* s0, void* stream);
+
+/*
  * Kernel timing for measurement.  While enabled, the handle records a pair of hipEvents on
  * the launch stream around every covariance-product launch that does work (kmv, in the
  * solver and in gp_kmv) and around every fused gradient reduction (dquad).

@@ -13,10 +13,11 @@ Modules
   ulisse      randomly truncated CG series (Sec. 4) and its exact moments
   rng         Philox4x64-10 counter layout and the uniform / normal / sign mappings
   stoch_grad  the unbiased stochastic gradient (Sec. 2.1 and Sec. 4.1)
-  sgld        the preconditioned SGLD update and the priors (Sec. 2.1)
+  sgld        the preconditioned SGLD update, step-size schedule, Langevin monitor, priors
+  precond     Galerkin targets, MLP forward/backward and Adam for the learned preconditioner
 
 Parity status: every function listed above is pinned by a CPU test against a library
 routine, a closed form, a published test vector or brute force; no function here is
 "parity unpinned".
 """
-from . import gp, cg, ulisse, rng, stoch_grad, sgld  # noqa: F401
+from . import gp, cg, ulisse, rng, stoch_grad, sgld, precond  # noqa: F401

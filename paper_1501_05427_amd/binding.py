@@ -119,6 +119,30 @@ def lib():
     L.gp_stoch_grad_pc.argtypes = [c_void_p, gp_data, c_void_p, c_void_p, c_void_p, c_int32, c_int32,
                                    POINTER(ulisse_params), POINTER(gp_precond), c_void_p, c_void_p,
                                    c_void_p, c_void_p]
+    L.precond_build_basis.restype = c_int
+    L.precond_build_basis.argtypes = [c_void_p, gp_data, c_void_p, c_int32, c_void_p, c_int64, c_void_p, c_void_p]
+    L.precond_targets.restype = c_int
+    L.precond_targets.argtypes = [c_void_p, gp_data, c_void_p, c_void_p, c_int64, c_int32, c_void_p, c_int32,
+                                  c_void_p, c_void_p]
+    L.precond_mlp_size.restype = c_int64
+    L.precond_mlp_size.argtypes = [c_int32, c_int32, c_int32]
+    L.precond_mlp_init.restype = c_int
+    L.precond_mlp_init.argtypes = [c_void_p, c_void_p, c_int32, c_int32, c_int32, c_void_p, c_void_p, c_int32,
+                                   c_uint64, c_void_p]
+    L.precond_mlp_train.restype = c_int
+    L.precond_mlp_train.argtypes = [c_void_p, c_void_p, c_void_p, c_int32, c_int32, c_int32, c_void_p, c_void_p,
+                                    c_int32, c_int32, c_int32, ctypes.c_float, c_void_p, c_void_p]
+    L.precond_mlp_forward.restype = c_int
+    L.precond_mlp_forward.argtypes = [c_void_p, c_void_p, c_int32, c_int32, c_int32, c_void_p, c_int32, c_void_p,
+                                      c_int32, c_void_p]
+    L.precond_mlp_grad.restype = c_int
+    L.precond_mlp_grad.argtypes = [c_void_p, c_void_p, c_int32, c_int32, c_int32, c_void_p, c_void_p, c_int32,
+                                   c_void_p, c_void_p, c_void_p]
+    L.precond_from_mlp.restype = c_int
+    L.precond_from_mlp.argtypes = [c_void_p, c_void_p, c_int32, c_int32, c_int32, c_void_p, c_int32, c_void_p,
+                                   c_void_p, c_void_p]
+    L.precond_warm_start.restype = c_int
+    L.precond_warm_start.argtypes = [c_void_p, c_void_p, c_int64, c_int32, c_int64, c_void_p, c_void_p, c_void_p]
     L.sgld_run.restype = c_int
     L.sgld_run.argtypes = [c_void_p, gp_data, c_void_p, c_void_p, POINTER(ulisse_params), POINTER(gp_prior),
                            c_void_p, POINTER(sgld_schedule), POINTER(sgld_state), c_int32, c_void_p,
@@ -382,3 +406,99 @@ def gp_stoch_grad_pc(h, X, psi, y, params, pc, R=None, n_probes=None, probe_kind
                                   int(probe_kind), ctypes.byref(params), ctypes.byref(pc.c), _ptr(S_warm),
                                   _ptr(g), _ptr(stats), _stream(stream)))
     return g, stats
+
+
+# ---------------------------------------------------------------------------------------
+# Learned warm start and preconditioner
+# ---------------------------------------------------------------------------------------
+def mlp_layout(n_in, hidden, n_out):
+    """Float offsets of the parameter buffer (the library's layout)."""
+    o = {}
+    o["W1"] = 0
+    o["b1"] = o["W1"] + n_in * hidden
+    o["W2"] = o["b1"] + hidden
+    o["b2"] = o["W2"] + hidden * hidden
+    o["W3"] = o["b2"] + hidden
+    o["b3"] = o["W3"] + hidden * n_out
+    o["trainable"] = o["b3"] + n_out
+    o["in_mu"] = o["trainable"]
+    o["in_sd"] = o["in_mu"] + n_in
+    o["out_mu"] = o["in_sd"] + n_in
+    o["out_sd"] = o["out_mu"] + n_out
+    o["total"] = o["out_sd"] + n_out
+    return o
+
+
+def precond_mlp_size(n_in, hidden, n_out):
+    return int(lib().precond_mlp_size(n_in, hidden, n_out))
+
+
+def precond_build_basis(h, X, psi_ref, k, U=None, ritz=None, stream=None):
+    import torch
+    n = X.shape[0]
+    if U is None:
+        U = colmajor(n, k)
+    if ritz is None:
+        ritz = torch.zeros(k, dtype=torch.float64, device=X.device)
+    _check(lib().precond_build_basis(h.ptr, _data(X), _ptr(psi_ref), int(k), _ptr(U), _ld(U, n), _ptr(ritz),
+                                     _stream(stream)))
+    return U, ritz
+
+
+def precond_targets(h, X, y, U, psis, targets=None, stream=None):
+    import torch
+    n, k = U.shape
+    N = psis.shape[0]
+    if targets is None:
+        targets = torch.zeros((N, 2 * k + 1), dtype=torch.float32, device=X.device)
+    _check(lib().precond_targets(h.ptr, _data(X), _ptr(y), _ptr(U), _ld(U, n), int(k), _ptr(psis), int(N),
+                                 _ptr(targets), _stream(stream)))
+    return targets
+
+
+def precond_mlp_init(h, params, n_in, hidden, n_out, psis, targets, seed=0, stream=None):
+    _check(lib().precond_mlp_init(h.ptr, _ptr(params), n_in, hidden, n_out, _ptr(psis), _ptr(targets),
+                                  psis.shape[0], int(seed), _stream(stream)))
+
+
+def precond_mlp_train(h, params, adam, n_in, hidden, n_out, psis, targets, steps, first_step=0, lr=1e-3,
+                      loss_trace=None, stream=None):
+    _check(lib().precond_mlp_train(h.ptr, _ptr(params), _ptr(adam), n_in, hidden, n_out, _ptr(psis),
+                                   _ptr(targets), psis.shape[0], int(steps), int(first_step), float(lr),
+                                   _ptr(loss_trace), _stream(stream)))
+
+
+def precond_mlp_forward(h, params, n_in, hidden, n_out, psis, bf16=False, Y=None, stream=None):
+    import torch
+    B = psis.shape[0]
+    if Y is None:
+        Y = torch.zeros((B, n_out), dtype=torch.float32, device=psis.device)
+    _check(lib().precond_mlp_forward(h.ptr, _ptr(params), n_in, hidden, n_out, _ptr(psis), B, _ptr(Y),
+                                     int(bool(bf16)), _stream(stream)))
+    return Y
+
+
+def precond_mlp_grad(h, params, n_in, hidden, n_out, psis, targets, stream=None):
+    import torch
+    lay = mlp_layout(n_in, hidden, n_out)
+    grad = torch.zeros(lay["trainable"], dtype=torch.float32, device=psis.device)
+    loss = torch.zeros(1, dtype=torch.float32, device=psis.device)
+    _check(lib().precond_mlp_grad(h.ptr, _ptr(params), n_in, hidden, n_out, _ptr(psis), _ptr(targets),
+                                  psis.shape[0], _ptr(grad), _ptr(loss), _stream(stream)))
+    return loss, grad
+
+
+def precond_from_mlp(h, params, n_in, hidden, n_out, psi, k, coef=None, c=None, stream=None):
+    import torch
+    if coef is None:
+        coef = torch.zeros(k + 1, dtype=torch.float64, device=psi.device)
+    _check(lib().precond_from_mlp(h.ptr, _ptr(params), n_in, hidden, n_out, _ptr(psi), int(k), _ptr(coef),
+                                  _ptr(c), _stream(stream)))
+    return coef
+
+
+def precond_warm_start(h, U, c, s0, stream=None):
+    n, k = U.shape
+    _check(lib().precond_warm_start(h.ptr, _ptr(U), _ld(U, n), int(k), int(n), _ptr(c), _ptr(s0),
+                                    _stream(stream)))
+    return s0

@@ -12,6 +12,7 @@
 
 #include "gp_common.h"
 #include "internal.h"
+#include "learned.h"
 #include "solver.h"
 #include "ulisse_gp.h"
 
@@ -44,7 +45,8 @@ enum Slot {
     kSlotZ, kSlotKP, kSlotVP, kSlotPart, kSlotQ, kSlotS, kSlotE, kSlotD, kSlotP1, kSlotP2,
     kSlotCounter, kSlotActive, kSlotState, kSlotStats, kSlotR, kSlotB, kSlotSt, kSlotS0,
     kSlotA32, kSlotB32, kSlotGpart, kSlotWork, kSlotVH, kSlotVL, kSlotGbatch, kSlotGvec,
-    kSlotRatio, kSlotRunStats, kSlotZp, kSlotUtv, kSlotHW, kSlotP3, kNumSlots
+    kSlotRatio, kSlotRunStats, kSlotZp, kSlotUtv, kSlotHW, kSlotP3, kSlotY0, kSlotY1,
+    kSlotY2, kSlotGram, kSlotGpart2, kSlotSmall, kSlotMlp, kNumSlots
 };
 
 bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
@@ -568,6 +570,242 @@ gp_status sgld_run(gp_handle* h, gp_data X, double* psi, const float* y,
         GP_HIP(hipMemcpy(eps_trace, eps_h.data(), eps_h.size() * sizeof(double), hipMemcpyHostToDevice));
     if (ratio_trace && !ratio_h.empty())
         GP_HIP(hipMemcpy(ratio_trace, ratio_h.data(), ratio_h.size() * sizeof(double), hipMemcpyHostToDevice));
+    return GP_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// One FP32 covariance product of a padded n_pad x mp block (ld n_pad) into out (ld ldo).
+gp_status product_padded(gp_handle* h, const KmvShape& sh, int d, const float* Z, const KParams* kp,
+                         const float* Vp, int m, float* out, int64_t ldo, int64_t n, hipStream_t s) {
+    float* part;
+    GP_TRY(ws(h, kSlotPart, (size_t)sh.split * sh.mp * sh.n_pad, &part));
+    GP_HIP(launch_kmv_partials(sh, d, Z, Vp, nullptr, nullptr, kp, part, nullptr, GP_FP32, s));
+    GP_HIP(launch_kmv_reduce(sh, part, Vp, kp, n, m, out, ldo, s));
+    return GP_OK;
+}
+
+gp_status check_k(int32_t k) {
+    GP_CHECK(k == 16 || k == 32 || k == 64, "k must be 16, 32 or 64");
+    return GP_OK;
+}
+
+gp_status check_mlp(int32_t in, int32_t hidden, int32_t out) {
+    GP_CHECK(in >= 1 && in <= kMaxP && hidden >= 1 && hidden <= 1024 && out >= 1 && out <= 1024,
+             "MLP sizes outside the supported range");
+    return GP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gp_status precond_build_basis(gp_handle* h, gp_data X, const double* psi_ref, int32_t k,
+                              float* U, int64_t ldu, double* ritz, void* stream) {
+    GP_TRY(check_handle(h));
+    GP_TRY(check_data(X));
+    GP_TRY(check_k(k));
+    GP_CHECK(X.n > k, "n must exceed k");
+    GP_CHECK(U != nullptr && aligned(U, 4) && ldu >= X.n, "U null, misaligned or ldu < n");
+    GP_CHECK(ritz != nullptr && aligned(ritz, 8), "ritz null or misaligned");
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n = X.n;
+    const KmvShape sh = kmv_shape(n, X.d, k, GP_FP32);
+    const int64_t np = sh.n_pad;
+    float *Z, *Y0, *Y1, *Y2;
+    KParams* kp;
+    GP_TRY(prep(h, X, psi_ref, np, &Z, &kp, s));
+    GP_TRY(ws(h, kSlotY0, (size_t)np * k, &Y0));
+    GP_TRY(ws(h, kSlotY1, (size_t)np * k, &Y1));
+    GP_TRY(ws(h, kSlotY2, (size_t)np * k, &Y2));
+    double *gpart, *small;
+    int* status;
+    GP_TRY(ws(h, kSlotGpart2, (size_t)ts_blocks(n) * k * k, &gpart));
+    GP_TRY(ws(h, kSlotSmall, (size_t)4 * k * k + 64, &small));
+    double* G = small;
+    double* M = small + k * k;
+    double* Q = small + 2 * k * k;
+    status = reinterpret_cast<int*>(small + 4 * k * k);
+    for (float* b : {Y0, Y1, Y2}) GP_HIP(hipMemsetAsync(b, 0, (size_t)np * k * sizeof(float), s));
+    GP_HIP(hipMemsetAsync(status, 0, sizeof(int), s));
+    // orthonormal columns of src into dst (tmp as scratch): a shifted CholeskyQR pass, then
+    // an unshifted one
+    auto orth = [&](const float* src, float* tmp, float* dst) -> gp_status {
+        GP_HIP(launch_gram(src, np, k, src, np, k, n, gpart, G, s));
+        GP_HIP(launch_chol_inv(G, k, 1e-5, M, status, s));
+        GP_HIP(launch_right_mul(src, np, tmp, np, k, n, M, s));
+        GP_HIP(launch_gram(tmp, np, k, tmp, np, k, n, gpart, G, s));
+        GP_HIP(launch_chol_inv(G, k, 0.0, M, status, s));
+        GP_HIP(launch_right_mul(tmp, np, dst, np, k, n, M, s));
+        return GP_OK;
+    };
+    // subspace iteration from a Gaussian block: two products, orthonormalised after each
+    GP_HIP(launch_omega(n, k, np, h->seed, 0, Y0, s));
+    GP_TRY(product_padded(h, sh, X.d, Z, kp, Y0, k, Y1, np, n, s));
+    GP_TRY(orth(Y1, Y0, Y2));
+    GP_TRY(product_padded(h, sh, X.d, Z, kp, Y2, k, Y1, np, n, s));
+    GP_TRY(orth(Y1, Y0, Y2));
+    // Rayleigh-Ritz: T = U^T K U, U <- U Q
+    GP_TRY(product_padded(h, sh, X.d, Z, kp, Y2, k, Y0, np, n, s));
+    GP_HIP(launch_gram(Y2, np, k, Y0, np, k, n, gpart, G, s));
+    GP_HIP(launch_jacobi_eig(G, k, Q, ritz, s));
+    GP_HIP(launch_right_mul(Y2, np, U, ldu, k, n, Q, s));
+    int st = 0;
+    GP_HIP(hipMemcpyAsync(&st, status, sizeof(int), hipMemcpyDeviceToHost, s));
+    GP_HIP(hipStreamSynchronize(s));
+    GP_CHECK(st == 0, "the range-finder block was rank deficient (Cholesky of its Gram matrix failed)");
+    return GP_OK;
+}
+
+gp_status precond_targets(gp_handle* h, gp_data X, const float* y, const float* U, int64_t ldu,
+                          int32_t k, const double* psis, int32_t N, float* targets, void* stream) {
+    GP_TRY(check_handle(h));
+    GP_TRY(check_data(X));
+    GP_TRY(check_k(k));
+    GP_CHECK(y && U && psis && targets && N >= 1 && ldu >= X.n && X.n > k, "bad arguments");
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n = X.n;
+    const int P = X.d + 2;
+    const KmvShape sh = kmv_shape(n, X.d, k, GP_FP32);
+    const int64_t np = sh.n_pad;
+    float *Up, *KU;
+    double *gpart, *small;
+    GP_TRY(ws(h, kSlotY1, (size_t)np * k, &Up));
+    GP_TRY(ws(h, kSlotY2, (size_t)np * k, &KU));
+    GP_TRY(ws(h, kSlotGpart2, (size_t)ts_blocks(n) * k * k, &gpart));
+    GP_TRY(ws(h, kSlotSmall, (size_t)4 * k * k + 64, &small));
+    GP_HIP(launch_pack(U, n, k, ldu, Up, np, k, s));
+    double* T = small;
+    double* w = small + k * k;
+    for (int i = 0; i < N; ++i) {
+        float* Z;
+        KParams* kp;
+        GP_TRY(prep(h, X, psis + (int64_t)i * P, np, &Z, &kp, s));
+        GP_TRY(product_padded(h, sh, X.d, Z, kp, Up, k, KU, np, n, s));
+        GP_HIP(launch_gram(Up, np, k, KU, np, k, n, gpart, T, s));
+        GP_HIP(launch_gram(Up, np, k, y, n, 1, n, gpart, w, s));
+        GP_HIP(launch_targets(T, w, k, n, kp, targets + (int64_t)i * (2 * k + 1), s));
+    }
+    return GP_OK;
+}
+
+int64_t precond_mlp_size(int32_t in, int32_t hidden, int32_t out) {
+    return mlp_layout(in, hidden, out).total;
+}
+
+gp_status precond_mlp_init(gp_handle* h, float* params, int32_t in, int32_t hidden, int32_t out,
+                           const double* psis, const float* targets, int32_t N, uint64_t seed,
+                           void* stream) {
+    GP_TRY(check_handle(h));
+    GP_TRY(check_mlp(in, hidden, out));
+    GP_CHECK(params && psis && targets && N >= 1, "bad arguments");
+    GP_HIP(launch_mlp_init(params, mlp_layout(in, hidden, out), psis, targets, N, seed, 0,
+                           (hipStream_t)stream));
+    return GP_OK;
+}
+
+namespace {
+struct MlpWork {
+    float *xs, *a1, *a2, *y, *dy, *d2, *d1, *grad;
+    double* lpart;
+};
+gp_status mlp_work(gp_handle* h, const MlpLayout& L, int B, MlpWork* w) {
+    const size_t nb = (size_t)(((int64_t)B * L.O + kWG - 1) / kWG);
+    const size_t fl = (size_t)B * L.in + 4 * (size_t)B * L.H + 2 * (size_t)B * L.O + L.trainable + 2 * nb + 64;
+    float* base;
+    GP_TRY(ws(h, kSlotMlp, fl, &base));
+    w->xs = base;
+    w->a1 = w->xs + (size_t)B * L.in;
+    w->a2 = w->a1 + (size_t)B * L.H;
+    w->d2 = w->a2 + (size_t)B * L.H;
+    w->d1 = w->d2 + (size_t)B * L.H;
+    w->y = w->d1 + (size_t)B * L.H;
+    w->dy = w->y + (size_t)B * L.O;
+    w->grad = w->dy + (size_t)B * L.O;
+    float* tail = w->grad + L.trainable;
+    tail += (8 - ((uintptr_t)tail / sizeof(float)) % 8) % 8;  // 32-byte alignment for doubles
+    w->lpart = reinterpret_cast<double*>(tail);
+    return GP_OK;
+}
+}  // namespace
+
+gp_status precond_mlp_train(gp_handle* h, float* params, float* adam, int32_t in, int32_t hidden,
+                            int32_t out, const double* psis, const float* targets, int32_t N,
+                            int32_t steps, int32_t first_step, float lr, float* loss_trace,
+                            void* stream) {
+    GP_TRY(check_handle(h));
+    GP_TRY(check_mlp(in, hidden, out));
+    GP_CHECK(params && adam && psis && targets && N >= 1 && steps >= 0 && first_step >= 0, "bad arguments");
+    hipStream_t s = (hipStream_t)stream;
+    const MlpLayout L = mlp_layout(in, hidden, out);
+    MlpWork w;
+    GP_TRY(mlp_work(h, L, N, &w));
+    float* loss_scratch;
+    GP_TRY(ws(h, kSlotRatio, 1, &loss_scratch));
+    for (int t = 0; t < steps; ++t) {
+        GP_HIP(launch_mlp_forward(params, L, psis, N, w.xs, w.a1, w.a2, w.y, 0, s));
+        GP_HIP(launch_mlp_backward(params, L, targets, N, w.xs, w.a1, w.a2, w.y, w.dy, w.d2, w.d1,
+                                   w.grad, w.lpart, loss_trace ? loss_trace + t : loss_scratch, s));
+        GP_HIP(launch_adam(params, w.grad, adam, adam + L.trainable, L.trainable, lr, first_step + t + 1, s));
+    }
+    return GP_OK;
+}
+
+gp_status precond_mlp_forward(gp_handle* h, const float* params, int32_t in, int32_t hidden,
+                              int32_t out, const double* psis, int32_t B, float* Y, int32_t bf16,
+                              void* stream) {
+    GP_TRY(check_handle(h));
+    GP_TRY(check_mlp(in, hidden, out));
+    GP_CHECK(params && psis && Y && B >= 1, "bad arguments");
+    hipStream_t s = (hipStream_t)stream;
+    const MlpLayout L = mlp_layout(in, hidden, out);
+    MlpWork w;
+    GP_TRY(mlp_work(h, L, B, &w));
+    GP_HIP(launch_mlp_forward(params, L, psis, B, w.xs, w.a1, w.a2, Y, bf16 ? 1 : 0, s));
+    return GP_OK;
+}
+
+gp_status precond_mlp_grad(gp_handle* h, const float* params, int32_t in, int32_t hidden,
+                           int32_t out, const double* psis, const float* targets, int32_t N,
+                           float* grad, float* loss, void* stream) {
+    GP_TRY(check_handle(h));
+    GP_TRY(check_mlp(in, hidden, out));
+    GP_CHECK(params && psis && targets && grad && loss && N >= 1, "bad arguments");
+    hipStream_t s = (hipStream_t)stream;
+    const MlpLayout L = mlp_layout(in, hidden, out);
+    MlpWork w;
+    GP_TRY(mlp_work(h, L, N, &w));
+    GP_HIP(launch_mlp_forward(params, L, psis, N, w.xs, w.a1, w.a2, w.y, 0, s));
+    GP_HIP(launch_mlp_backward(params, L, targets, N, w.xs, w.a1, w.a2, w.y, w.dy, w.d2, w.d1, grad,
+                               w.lpart, loss, s));
+    return GP_OK;
+}
+
+gp_status precond_from_mlp(gp_handle* h, const float* params, int32_t in, int32_t hidden,
+                           int32_t out, const double* psi, int32_t k, double* coef, double* c,
+                           void* stream) {
+    GP_TRY(check_handle(h));
+    GP_TRY(check_mlp(in, hidden, out));
+    GP_TRY(check_k(k));
+    GP_CHECK(out == 2 * k + 1, "the network must have 2k + 1 outputs");
+    GP_CHECK(params && psi && coef, "bad arguments");
+    hipStream_t s = (hipStream_t)stream;
+    const MlpLayout L = mlp_layout(in, hidden, out);
+    MlpWork w;
+    GP_TRY(mlp_work(h, L, 1, &w));
+    GP_HIP(launch_mlp_forward(params, L, psi, 1, w.xs, w.a1, w.a2, w.y, 1, s));
+    GP_HIP(launch_mlp_to_precond(w.y, L, k, params, coef, c, s));
+    return GP_OK;
+}
+
+gp_status precond_warm_start(gp_handle* h, const float* U, int64_t ldu, int32_t k, int64_t n,
+                             const double* c, double* s0, void* stream) {
+    GP_TRY(check_handle(h));
+    GP_TRY(check_k(k));
+    GP_CHECK(U && c && s0 && ldu >= n && n >= 1, "bad arguments");
+    GP_HIP(launch_warm_from_c(U, ldu, k, n, c, s0, (hipStream_t)stream));
     return GP_OK;
 }
 

@@ -539,3 +539,151 @@ def test_pcg_converged_solution_and_fewer_iterations(h):
     it_pc = max(s["iters"] for s in pb.decode_stats(st_pc))
     it = max(s["iters"] for s in pb.decode_stats(st))
     assert it_pc < 0.7 * it, (it_pc, it)
+
+
+# ---------------------------------------------------------------------------------------
+# Learned warm start and preconditioner
+# ---------------------------------------------------------------------------------------
+def _host_params(rng, I, H, O):
+    return {"W1": rng.standard_normal((I, H)) * (2 / (I + H)) ** 0.5, "b1": rng.standard_normal(H) * 0.1,
+            "W2": rng.standard_normal((H, H)) * (2 / (2 * H)) ** 0.5, "b2": rng.standard_normal(H) * 0.1,
+            "W3": rng.standard_normal((H, O)) * (2 / (H + O)) ** 0.5, "b3": rng.standard_normal(O) * 0.1,
+            "in_mu": rng.standard_normal(I), "in_sd": rng.uniform(0.5, 2, I),
+            "out_mu": rng.standard_normal(O), "out_sd": rng.uniform(0.5, 2, O)}
+
+
+def _pack(p, I, H, O):
+    lay = pb.mlp_layout(I, H, O)
+    buf = np.zeros(lay["total"], np.float32)
+    for name in ["W1", "b1", "W2", "b2", "W3", "b3", "in_mu", "in_sd", "out_mu", "out_sd"]:
+        v = np.asarray(p[name], np.float32).ravel()
+        buf[lay[name]:lay[name] + v.size] = v
+    return buf
+
+
+def _f32(p):
+    return {k: np.asarray(v, np.float32).astype(np.float64) for k, v in p.items()}
+
+
+def test_mlp_forward_grad_adam_vs_oracle(h):
+    from oracle import precond as opc
+    I, H, O, B = 10, 256, 129, 64
+    r = np.random.default_rng(0)
+    p = _host_params(r, I, H, O)
+    buf = dev(_pack(p, I, H, O))
+    assert pb.precond_mlp_size(I, H, O) == buf.numel()
+    psis = r.standard_normal((B, I))
+    T = r.standard_normal((B, O)).astype(np.float32)
+    Y = pb.precond_mlp_forward(h, buf, I, H, O, dev(psis))
+    Yb = pb.precond_mlp_forward(h, buf, I, H, O, dev(psis), bf16=True)
+    loss, grad = pb.precond_mlp_grad(h, buf, I, H, O, dev(psis), dev(T))
+    torch.cuda.synchronize()
+    pf = _f32(p)
+    y_ref, _ = opc.mlp_forward(pf, psis)
+    np.testing.assert_allclose(Y.cpu().numpy(), y_ref, rtol=1e-4, atol=1e-4)
+    # BF16 operands: each product term carries about 2^-8 relative error
+    assert np.abs(Yb.cpu().numpy() - y_ref).max() < 0.05 * np.abs(y_ref).max()
+    l_ref, g_ref = opc.mlp_grad(pf, psis, T.astype(np.float64))
+    np.testing.assert_allclose(loss.item(), l_ref, rtol=1e-4)
+    lay = pb.mlp_layout(I, H, O)
+    gn = grad.cpu().numpy()
+    for name in ["W1", "b1", "W2", "b2", "W3", "b3"]:
+        got = gn[lay[name]:lay[name] + g_ref[name].size].reshape(g_ref[name].shape)
+        np.testing.assert_allclose(got, g_ref[name], rtol=2e-3, atol=2e-4 * np.abs(g_ref[name]).max())
+    # one Adam step from zero moments
+    adam = torch.zeros(2 * lay["trainable"], dtype=torch.float32, device="cuda")
+    pb.precond_mlp_train(h, buf, adam, I, H, O, dev(psis), dev(T), 1, 0, 1e-3)
+    torch.cuda.synchronize()
+    after = buf.cpu().numpy()
+    for name in ["W3", "b1"]:
+        new, _, _ = opc.adam_step(pf[name], g_ref[name], 0 * g_ref[name], 0 * g_ref[name], 1, 1e-3)
+        got = after[lay[name]:lay[name] + new.size].reshape(new.shape)
+        np.testing.assert_allclose(got, new, rtol=1e-4, atol=2e-6)
+
+
+def test_mlp_init_constants_and_training_reduces_loss(h):
+    I, H, O, N = 4, 64, 9, 256
+    r = np.random.default_rng(1)
+    psis = r.standard_normal((N, I)) * [1, 2, 3, 4] + [0, 1, 2, 3]
+    T = np.column_stack([np.sin(psis @ r.standard_normal(I)) for _ in range(O)]).astype(np.float32)
+    buf = torch.zeros(pb.precond_mlp_size(I, H, O), dtype=torch.float32, device="cuda")
+    pb.precond_mlp_init(h, buf, I, H, O, dev(psis), dev(T), seed=3)
+    torch.cuda.synchronize()
+    lay = pb.mlp_layout(I, H, O)
+    got = buf.cpu().numpy()
+    np.testing.assert_allclose(got[lay["in_mu"]:lay["in_mu"] + I], psis.mean(0), rtol=1e-5, atol=1e-5)
+    np.testing.assert_allclose(got[lay["in_sd"]:lay["in_sd"] + I], psis.std(0), rtol=1e-4)
+    np.testing.assert_allclose(got[lay["out_mu"]:lay["out_mu"] + O], T.mean(0), rtol=1e-4, atol=1e-5)
+    w2 = got[lay["W2"]:lay["W2"] + H * H]
+    assert abs(w2.std() - (1.0 / H) ** 0.5) < 0.1 * (1.0 / H) ** 0.5
+    adam = torch.zeros(2 * lay["trainable"], dtype=torch.float32, device="cuda")
+    trace = torch.zeros(400, dtype=torch.float32, device="cuda")
+    pb.precond_mlp_train(h, buf, adam, I, H, O, dev(psis), dev(T), 400, 0, 3e-3, loss_trace=trace)
+    torch.cuda.synchronize()
+    tr = trace.cpu().numpy()
+    assert tr[-1] < 0.3 * tr[0] and np.all(np.isfinite(tr))
+
+
+def test_basis_orthonormal_and_ritz_values_interlace(h):
+    n, d, k = 1500, 2, 32
+    X, psi = problem(n, d, seed=11, lam=0.05, ell=(0.2, 0.3))
+    U, ritz = pb.precond_build_basis(h, dev(X), dev(psi), k)
+    torch.cuda.synchronize()
+    Un = U.cpu().numpy().astype(np.float64)
+    np.testing.assert_allclose(Un.T @ Un, np.eye(k), atol=1e-4)
+    lam = np.linalg.eigvalsh(ogp.kernel_matrix(X, psi))[::-1]
+    rz = ritz.cpu().numpy()
+    # Cauchy interlacing: the j-th Ritz value lies below the j-th eigenvalue
+    assert np.all(rz <= lam[:k] * (1 + 1e-5))
+    np.testing.assert_allclose(rz[:4], lam[:4], rtol=1e-3)
+    assert np.all(np.diff(rz) <= 1e-9 * rz[0])
+
+
+def test_galerkin_targets_vs_oracle(h):
+    from oracle import precond as opc
+    n, d, k = 700, 3, 16
+    X, psi0 = problem(n, d, seed=5, lam=0.1)
+    y = np.random.default_rng(2).standard_normal(n).astype(np.float32)
+    U, _ = np.linalg.qr(np.random.default_rng(3).standard_normal((n, k)))
+    U32 = U.astype(np.float32)
+    psis = np.stack([psi0 + 0.1 * np.random.default_rng(i).standard_normal(d + 2) for i in range(3)])
+    T = pb.precond_targets(h, dev(X), dev(y), colm(U32), dev(psis))
+    torch.cuda.synchronize()
+    got = T.cpu().numpy()
+    for i in range(3):
+        ref = opc.galerkin_targets(X, psis[i], y, U32.astype(np.float64))
+        np.testing.assert_allclose(got[i], ref, rtol=2e-4, atol=2e-4 * np.abs(ref[:k]).max())
+
+
+def test_learned_preconditioner_gains_and_keeps_the_gradient(h):
+    # a small end-to-end run: basis at the reference psi, targets for psi's around it, a
+    # trained network; at new psi's the preconditioned solves need fewer iterations and the
+    # converged gradient is the same as without preconditioning
+    n, d, k, nr = 4096, 2, 64, 8
+    X, psi0 = problem(n, d, seed=21, lam=0.01, ell=(0.15, 0.25))
+    y = workloads.gaussian_matrix(n, 1, seed=4)[:, 0]
+    Xd, yd = dev(X), dev(y)
+    U, ritz = pb.precond_build_basis(h, Xd, dev(psi0), k)
+    r = np.random.default_rng(7)
+    psis = psi0 + 0.05 * r.standard_normal((48, d + 2))
+    T = pb.precond_targets(h, Xd, yd, U, dev(psis))
+    I, H, O = d + 2, 128, 2 * k + 1
+    prm = torch.zeros(pb.precond_mlp_size(I, H, O), dtype=torch.float32, device="cuda")
+    pb.precond_mlp_init(h, prm, I, H, O, dev(psis), T, seed=1)
+    adam = torch.zeros(2 * pb.mlp_layout(I, H, O)["trainable"], dtype=torch.float32, device="cuda")
+    pb.precond_mlp_train(h, prm, adam, I, H, O, dev(psis), T, 600, 0, 2e-3)
+    R = workloads.gaussian_matrix(n, nr, seed=9)
+    params = pb.make_params(q=1e-12, rate=1e-9, eps=1e-6, eps_relative=1, max_iter=5000)
+    its_plain, its_pc = [], []
+    for j in range(3):
+        psi_t = dev(psi0 + 0.05 * np.random.default_rng(100 + j).standard_normal(d + 2))
+        coef = pb.precond_from_mlp(h, prm, I, H, O, psi_t, k)
+        pc = pb.make_precond(U, coef)
+        g0, s0 = pb.gp_stoch_grad(h, Xd, psi_t, yd, params, R=colm(R))
+        g1, s1 = pb.gp_stoch_grad_pc(h, Xd, psi_t, yd, params, pc, R=colm(R))
+        torch.cuda.synchronize()
+        its_plain.append(max(s["iters"] for s in pb.decode_stats(s0)))
+        its_pc.append(max(s["iters"] for s in pb.decode_stats(s1)))
+        a, b = g0.cpu().numpy(), g1.cpu().numpy()
+        np.testing.assert_allclose(b, a, rtol=1e-3, atol=1e-4 * np.abs(a).max())
+    assert max(its_pc) < 0.6 * min(its_plain), (its_pc, its_plain)

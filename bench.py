@@ -26,6 +26,7 @@ sys.path.insert(0, ROOT)
 
 N, D, NPROBES = 65536, 8, 31
 PROBE_PERIOD = 20
+LEARN_JITTER = 0.03   # spread of the training log-parameters around the reference
 M = 1 + NPROBES
 WORKLOAD = "rff_n65536_d8_m32"
 VALU_FP32_PEAK_TFLOPS = 157.3   # 256 CU x 2.4 GHz x 256 flop/CU/clk (datasheet FP32 vector)
@@ -96,6 +97,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=40)
     ap.add_argument("--fresh-steps", type=int, default=4)
+    ap.add_argument("--learned-steps", type=int, default=None,
+                    help="steps of the learned-preconditioner + BF16 run (default: --steps; 0 skips)")
+    ap.add_argument("--learn-pairs", type=int, default=256)
+    ap.add_argument("--learn-epochs", type=int, default=1500)
     ap.add_argument("--bf16-steps", type=int, default=None,
                     help="steps of the BF16 split-K+V solver run (default: --steps)")
     ap.add_argument("--warmup", type=int, default=5)
@@ -104,6 +109,8 @@ def main():
     args = ap.parse_args()
     if args.bf16_steps is None:
         args.bf16_steps = args.steps
+    if args.learned_steps is None:
+        args.learned_steps = args.steps
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(the sharding design is described in DESIGN.md)", file=sys.stderr)
@@ -197,6 +204,7 @@ def main():
 
     elapsed, prof = timed(args.warmup, args.steps, period)
     final_stats = pb.decode_stats(stats)
+    value_plain = args.steps / elapsed
     # fresh probes every step, for reference (a few steps; not the headline)
     el_fresh, prof_fresh = None, None
     if args.fresh_steps:
@@ -227,6 +235,81 @@ def main():
         params.prec = pb.GP_BF16_SPLIT_KV
         el_bf16, prof_bf16 = timed(args.warmup, args.bf16_steps, period)
         params.prec = pb.GP_FP32
+
+    # learned warm start / preconditioner + BF16 split-KV products (setup untimed)
+    learned = None
+    if args.learned_steps:
+        t_setup = time.perf_counter()
+        k, H = 64, 256
+        U, ritz = pb.precond_build_basis(h, X, psi0, k)
+        rng = np.random.default_rng(17)
+        psis = torch.from_numpy(w["psi"] + LEARN_JITTER * rng.standard_normal((args.learn_pairs, D + 2))).cuda()
+        T = pb.precond_targets(h, X, y, U, psis)
+        I_, O_ = D + 2, 2 * k + 1
+        prm = torch.zeros(pb.precond_mlp_size(I_, H, O_), dtype=torch.float32, device="cuda")
+        pb.precond_mlp_init(h, prm, I_, H, O_, psis, T, seed=5)
+        adam = torch.zeros(2 * pb.mlp_layout(I_, H, O_)["trainable"], dtype=torch.float32, device="cuda")
+        ltr = torch.zeros(args.learn_epochs, dtype=torch.float32, device="cuda")
+        pb.precond_mlp_train(h, prm, adam, I_, H, O_, psis, T, args.learn_epochs, 0, 2e-3, loss_trace=ltr)
+        torch.cuda.synchronize()
+        t_setup = time.perf_counter() - t_setup
+        coef = torch.zeros(k + 1, dtype=torch.float64, device="cuda")
+        pc = pb.make_precond(U, coef)
+
+        def step_learned(t):
+            params.rng_counter = t
+            if t % period == 0:
+                pb.gp_draw_probes(h, N, NPROBES, pb.PROBE_GAUSSIAN, 7, t // period, R=R)
+                S_warm[:, 1:].zero_()
+            pb.precond_from_mlp(h, prm, I_, H, O_, psi, k, coef=coef)
+            pb.gp_stoch_grad_pc(h, X, psi, y, params, pc, R=R, S_warm=S_warm, g=g, stats=stats)
+            pb.sgld_step(h, psi, g, eps_t, rng_stream=1, rng_counter=t, prior_kind=1,
+                         prior_a=prior_a, prior_b=prior_b, M_chol=M_chol)
+            flagged.add_(stats.view(M, -1)[:, 24:28].view(torch.int32).ne(0).any().to(torch.int64))
+
+        def timed_learned(first, count, fresh):
+            torch.cuda.synchronize()
+            pb.gp_profile(h, 1)
+            t0 = time.perf_counter()
+            for t in range(first, first + count):
+                if fresh:
+                    S_warm[:, 1:].zero_()
+                    pb.gp_draw_probes(h, N, NPROBES, pb.PROBE_GAUSSIAN, 9, t, R=R)
+                    params.rng_counter = t
+                    pb.precond_from_mlp(h, prm, I_, H, O_, psi, k, coef=coef)
+                    pb.gp_stoch_grad_pc(h, X, psi, y, params, pc, R=R, S_warm=S_warm, g=g, stats=stats)
+                    pb.sgld_step(h, psi, g, eps_t, rng_stream=1, rng_counter=t, prior_kind=1,
+                                 prior_a=prior_a, prior_b=prior_b, M_chol=M_chol)
+                else:
+                    step_learned(t)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            pr = pb.gp_profile_read(h)
+            pb.gp_profile(h, 0)
+            return el, pr
+
+        params.prec = pb.GP_BF16_SPLIT_KV
+        restore()
+        el_l, pr_l = timed_learned(args.warmup, args.learned_steps, False)
+        el_lf, pr_lf = None, None
+        if args.fresh_steps:
+            restore()
+            el_lf, pr_lf = timed_learned(args.warmup, args.fresh_steps, True)
+        params.prec = pb.GP_FP32
+        learned = {
+            "grad_estimates_per_s": args.learned_steps / el_l,
+            "kmv_passes_per_estimate": pr_l["kmv_passes"] / args.learned_steps,
+            "kmv_avg_launch_ms": pr_l["kmv_ms"] / max(1, pr_l["kmv_launches"]),
+            "steps": args.learned_steps,
+            "vs_plain_fp32": (args.learned_steps / el_l) / value_plain,
+            "fresh_probes_every_step": None if el_lf is None else {
+                "grad_estimates_per_s": args.fresh_steps / el_lf,
+                "kmv_passes_per_estimate": pr_lf["kmv_passes"] / args.fresh_steps},
+            "setup_s": t_setup, "rank": k, "hidden": H, "train_pairs": args.learn_pairs,
+            "train_epochs": args.learn_epochs, "train_loss_first_last": [float(ltr[0]), float(ltr[-1])],
+            "ritz_top_bottom": [float(ritz[0]), float(ritz[-1])],
+            "precision": "bf16_split_kv",
+        }
 
     K = args.steps
     value = K / elapsed
@@ -270,6 +353,7 @@ def main():
             "kmv_passes_per_estimate": prof_bf16["kmv_passes"] / args.bf16_steps,
             "kmv_avg_launch_ms": prof_bf16["kmv_ms"] / max(1, prof_bf16["kmv_launches"]),
             "steps": args.bf16_steps},
+        "learned_bf16": learned,
         "dquad_avg_ms": dq_avg_ms,
         "exp_per_s": N * float(N) / kmv_avg_s,
         "last_step_stats": {"l": [s["l"] for s in final_stats],

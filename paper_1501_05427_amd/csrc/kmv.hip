@@ -65,7 +65,11 @@ __global__ void pack_kernel(const float* __restrict__ V, int64_t n, int m, int64
 // V (column-major, ld n_pad) through registers into LDS.  V is stored in LDS either
 // column-major with a padded stride (MFMA B-operand reads) or row-major (VALU broadcast).
 // Every load count is a multiple of 64, so the bounds tests below are uniform per wave.
+// The staged values are native vector types: copies of HIP's float4/uint4 structs lower
+// to memcpy, which keeps the stage in private (scratch) memory instead of registers.
 // ---------------------------------------------------------------------------------------
+typedef unsigned int uintx4 __attribute__((ext_vector_type(4)));
+
 template <int DP, int MP, bool VROWMAJOR>
 struct Stage {
     static constexpr int NZ4 = kJS * DP / 4;
@@ -76,15 +80,15 @@ struct Stage {
     static constexpr int VSIZE = VROWMAJOR ? kJS * MP : MP * (kJS + 4);
     static_assert(NZ4 % 64 == 0 && NV4 % 64 == 0, "wave-uniform stage loads");
 
-    float4 z[LZ];
-    float4 v[LV];
+    floatx4 z[LZ];
+    floatx4 v[LV];
 
     __device__ __attribute__((always_inline)) void load(const float* __restrict__ Z, const float* __restrict__ V, int64_t ldv,
                          int64_t j0) {
 #pragma unroll
         for (int t = 0; t < LZ; ++t) {
             const int idx = threadIdx.x + t * kWG;
-            if (idx < NZ4) z[t] = reinterpret_cast<const float4*>(Z + j0 * DP)[idx];
+            if (idx < NZ4) z[t] = reinterpret_cast<const floatx4*>(Z + j0 * DP)[idx];
         }
 #pragma unroll
         for (int t = 0; t < LV; ++t) {
@@ -92,7 +96,7 @@ struct Stage {
             if (idx < NV4) {
                 const int c = idx / (kJS / 4);
                 const int jj = (idx % (kJS / 4)) * 4;
-                v[t] = *reinterpret_cast<const float4*>(V + c * ldv + j0 + jj);
+                v[t] = *reinterpret_cast<const floatx4*>(V + c * ldv + j0 + jj);
             }
         }
     }
@@ -100,7 +104,7 @@ struct Stage {
 #pragma unroll
         for (int t = 0; t < LZ; ++t) {
             const int idx = threadIdx.x + t * kWG;
-            if (idx < NZ4) zs[idx] = z[t];
+            if (idx < NZ4) reinterpret_cast<floatx4*>(zs)[idx] = z[t];
         }
 #pragma unroll
         for (int t = 0; t < LV; ++t) {
@@ -114,7 +118,7 @@ struct Stage {
                     vs[(jj + 2) * MP + c] = v[t].z;
                     vs[(jj + 3) * MP + c] = v[t].w;
                 } else {
-                    *reinterpret_cast<float4*>(vs + c * VST + jj) = v[t];
+                    *reinterpret_cast<floatx4*>(vs + c * VST + jj) = v[t];
                 }
             }
         }
@@ -133,15 +137,15 @@ struct StageB16 {
     static constexpr int VSIZE = MP * VST;
     static_assert(NZ4 % 64 == 0 && NV % 64 == 0, "wave-uniform stage loads");
 
-    float4 z[LZ];
-    uint4 h[LV], l[LV];
+    floatx4 z[LZ];
+    uintx4 h[LV], l[LV];
 
     __device__ __attribute__((always_inline)) void load(const float* __restrict__ Z, const uint16_t* __restrict__ VH,
                          const uint16_t* __restrict__ VL, int64_t ldv, int64_t j0) {
 #pragma unroll
         for (int t = 0; t < LZ; ++t) {
             const int idx = threadIdx.x + t * kWG;
-            if (idx < NZ4) z[t] = reinterpret_cast<const float4*>(Z + j0 * DP)[idx];
+            if (idx < NZ4) z[t] = reinterpret_cast<const floatx4*>(Z + j0 * DP)[idx];
         }
 #pragma unroll
         for (int t = 0; t < LV; ++t) {
@@ -149,8 +153,8 @@ struct StageB16 {
             if (idx < NV) {
                 const int c = idx / (kJS / 8);
                 const int jj = (idx % (kJS / 8)) * 8;
-                h[t] = *reinterpret_cast<const uint4*>(VH + c * ldv + j0 + jj);
-                if (VL != nullptr) l[t] = *reinterpret_cast<const uint4*>(VL + c * ldv + j0 + jj);
+                h[t] = *reinterpret_cast<const uintx4*>(VH + c * ldv + j0 + jj);
+                if (VL != nullptr) l[t] = *reinterpret_cast<const uintx4*>(VL + c * ldv + j0 + jj);
             }
         }
     }
@@ -159,7 +163,7 @@ struct StageB16 {
 #pragma unroll
         for (int t = 0; t < LZ; ++t) {
             const int idx = threadIdx.x + t * kWG;
-            if (idx < NZ4) zs[idx] = z[t];
+            if (idx < NZ4) reinterpret_cast<floatx4*>(zs)[idx] = z[t];
         }
 #pragma unroll
         for (int t = 0; t < LV; ++t) {
@@ -167,8 +171,8 @@ struct StageB16 {
             if (idx < NV) {
                 const int c = idx / (kJS / 8);
                 const int jj = (idx % (kJS / 8)) * 8;
-                *reinterpret_cast<uint4*>(hs + c * VST + jj) = h[t];
-                if (with_lo) *reinterpret_cast<uint4*>(ls + c * VST + jj) = l[t];
+                *reinterpret_cast<uintx4*>(hs + c * VST + jj) = h[t];
+                if (with_lo) *reinterpret_cast<uintx4*>(ls + c * VST + jj) = l[t];
             }
         }
     }

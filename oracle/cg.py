@@ -84,3 +84,28 @@ def lowrank_pinv(U, h, tau_inv):
     U = np.asarray(U, dtype=np.float64)
     h = np.asarray(h, dtype=np.float64)
     return lambda v: tau_inv * v + U @ (h * (U.T @ v))
+
+
+def shifted_inner_pinv(matvec, delta, eps_inner, max_inner):
+    """v -> approximate (K + delta I)^-1 v by an inner run of Alg. 1 from zero: the PCG
+    variant of Sec. 3.3 whose preconditioner J = K + delta I (delta > 0) is itself applied
+    by CG.
+
+    The inner run stops at the first iterate with ||r|| < eps_inner ||v|| or after
+    `max_inner` products, whichever comes first (eps_inner = 0: exactly max_inner
+    iterations).  Because CG is not linear in its right-hand side, the preconditioner
+    changes from one outer iteration to the next unless the inner solves converge.
+    """
+    def shifted(v):
+        return matvec(v) + delta * v
+
+    def apply(v):
+        v = np.asarray(v, dtype=np.float64)
+        nv = np.linalg.norm(v)
+        if nv == 0.0:
+            return np.zeros_like(v)
+        for i, s, r, _ in cg_iterates(shifted, v, np.zeros_like(v)):
+            if np.linalg.norm(r) < eps_inner * nv or i >= max_inner:
+                return s
+
+    return apply

@@ -152,3 +152,57 @@ def test_pcg_identity_is_cg_and_lowrank_preconditioner_helps():
     assert n_pcg < n_cg < 500
     _, s = run(cg.pcg_iterates(lambda v: K @ v, pinv, b, np.zeros(60)), 1e-10)
     np.testing.assert_allclose(s, sla.cho_solve(sla.cho_factor(K), b), rtol=1e-8, atol=1e-9)
+
+
+# ---- PCG with J = K + delta I applied by an inner CG (Sec. 3.3) ----------------------------
+
+def test_shifted_inner_solve_is_the_shifted_system_solution():
+    K, b = _spd(40, seed=11)
+    for delta in (1e-3, 0.1, 2.0):
+        z = cg.shifted_inner_pinv(lambda v: K @ v, delta, 1e-13, 400)(b)
+        ref = sla.cho_solve(sla.cho_factor(K + delta * np.eye(40)), b)
+        np.testing.assert_allclose(z, ref, rtol=1e-9, atol=1e-11)
+    assert not np.any(cg.shifted_inner_pinv(lambda v: K @ v, 0.1, 0.0, 5)(np.zeros(40)))
+
+
+def test_shifted_inner_solve_fixed_count_is_that_many_cg_steps():
+    # eps_inner = 0: exactly max_inner products; the result is the max_inner-th Krylov iterate
+    # of (K + delta I), which minimises the energy error over that Krylov space
+    K, b = _spd(40, seed=12)
+    delta, k = 0.05, 4
+    A = K + delta * np.eye(40)
+    calls = []
+    z = cg.shifted_inner_pinv(lambda v: (calls.append(1), K @ v)[1], delta, 0.0, k)(b)
+    assert len(calls) == k + 1  # k steps plus the initial residual b - K 0
+    Kr = np.column_stack([np.linalg.matrix_power(A, j) @ b for j in range(k)])
+    Q, _ = np.linalg.qr(Kr)
+    c = np.linalg.solve(Q.T @ A @ Q, Q.T @ b)
+    np.testing.assert_allclose(z, Q @ c, rtol=1e-8, atol=1e-10)
+
+
+def test_pcg_shifted_large_delta_is_cg_and_zero_delta_one_step():
+    K, b = _spd(50, lam=1e-2, seed=13)
+    mv = lambda v: K @ v
+    # delta >> ||K||: J^-1 ~ I / delta, a scalar preconditioner, which leaves CG's iterates
+    # unchanged (up to O(||K|| / delta))
+    pinv = cg.shifted_inner_pinv(mv, 1e9, 1e-14, 200)
+    for (i1, s1, _, _), (i2, s2, _, _) in zip(cg.cg_iterates(mv, b, np.zeros(50)),
+                                              cg.pcg_iterates(mv, pinv, b, np.zeros(50))):
+        np.testing.assert_allclose(s2, s1, rtol=1e-6, atol=1e-8)
+        if i1 == 6:
+            break
+    # delta -> 0 with converged inner solves: J = K, one outer step reaches K^-1 b
+    pinv0 = cg.shifted_inner_pinv(mv, 1e-12, 1e-14, 2000)
+    _, s, e, _ = next(cg.pcg_iterates(mv, pinv0, b, np.zeros(50)))
+    np.testing.assert_allclose(s, sla.cho_solve(sla.cho_factor(K), b), rtol=1e-6, atol=1e-8)
+
+
+def test_pcg_shifted_converges_to_the_solution_with_inexact_inner_solves():
+    K, b = _spd(60, lam=1e-2, seed=14)
+    mv = lambda v: K @ v
+    pinv = cg.shifted_inner_pinv(mv, 0.1, 0.0, 6)
+    for i, s, e, _ in cg.pcg_iterates(mv, pinv, b, np.zeros(60)):
+        if np.linalg.norm(e) < 1e-10 * np.linalg.norm(b) or i >= 300:
+            break
+    assert i < 300
+    np.testing.assert_allclose(s, sla.cho_solve(sla.cho_factor(K), b), rtol=1e-7, atol=1e-8)

@@ -184,13 +184,18 @@ def test_s_cg_is_the_last_cg_iterate():
             break
 
 
-def test_exact_mean_over_preconditioned_cg_path():
-    # unbiasedness does not depend on the CG variant: enumerate J over a PCG path
+@pytest.mark.parametrize("kind", ["lowrank", "shifted_inner"])
+def test_exact_mean_over_preconditioned_cg_path(kind):
+    # unbiasedness does not depend on the CG variant: enumerate J over a PCG path, with the
+    # rank-k preconditioner or with J = K + delta I applied by 5 inner CG steps (Sec. 3.3)
     K, b = _system(40, lam=0.05, seed=6)
-    w, Q = np.linalg.eigh(K)
-    U, dk = Q[:, -6:], w[-6:]
-    tau = np.mean(w[:-6])
-    pinv = cg.lowrank_pinv(U, 1 / dk - 1 / tau, 1 / tau)
+    if kind == "lowrank":
+        w, Q = np.linalg.eigh(K)
+        U, dk = Q[:, -6:], w[-6:]
+        tau = np.mean(w[:-6])
+        pinv = cg.lowrank_pinv(U, 1 / dk - 1 / tau, 1 / tau)
+    else:
+        pinv = cg.shifted_inner_pinv(lambda v: K @ v, 0.05, 0.0, 5)
     rate, eps = 0.5, 1e-11
     deltas, norms = [None], [None]
     for i, s, e, dl in cg.pcg_iterates(lambda v: K @ v, pinv, b, np.zeros(40)):

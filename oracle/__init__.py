@@ -15,9 +15,10 @@ Modules
   stoch_grad  the unbiased stochastic gradient (Sec. 2.1 and Sec. 4.1)
   sgld        the preconditioned SGLD update, step-size schedule, Langevin monitor, priors
   precond     Galerkin targets, MLP forward/backward and Adam for the learned preconditioner
+  diagnostics PSRF, effective sample size, subset MAP and the SGLD preconditioner M
 
 Parity status: every function listed above is pinned by a CPU test against a library
 routine, a closed form, a published test vector or brute force; no function here is
 "parity unpinned".
 """
-from . import gp, cg, ulisse, rng, stoch_grad, sgld, precond  # noqa: F401
+from . import gp, cg, ulisse, rng, stoch_grad, sgld, precond, diagnostics  # noqa: F401

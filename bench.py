@@ -92,6 +92,207 @@ def cpu_baseline(X, psi, passes_per_estimate, budget_rows=(768, 256)):
                 kmv_s_full=t_kmv, assembly_s_full=t_asm)
 
 
+def setup_learned(pb, h, X, y, w, pairs, epochs, k=64, H=256):
+    """Basis, Galerkin targets and the trained MLP of the learned warm start/preconditioner.
+
+    Training pairs are psi's jittered around the workload's psi (N(0, LEARN_JITTER^2) per
+    component); everything runs in the library's kernels.
+    """
+    import numpy as np
+    import torch
+    U, ritz = pb.precond_build_basis(h, X, torch.from_numpy(w["psi"]).cuda(), k)
+    rng = np.random.default_rng(17)
+    psis = torch.from_numpy(w["psi"] + LEARN_JITTER * rng.standard_normal((pairs, D + 2))).cuda()
+    T = pb.precond_targets(h, X, y, U, psis)
+    I_, O_ = D + 2, 2 * k + 1
+    prm = torch.zeros(pb.precond_mlp_size(I_, H, O_), dtype=torch.float32, device="cuda")
+    pb.precond_mlp_init(h, prm, I_, H, O_, psis, T, seed=5)
+    adam = torch.zeros(2 * pb.mlp_layout(I_, H, O_)["trainable"], dtype=torch.float32, device="cuda")
+    ltr = torch.zeros(epochs, dtype=torch.float32, device="cuda")
+    pb.precond_mlp_train(h, prm, adam, I_, H, O_, psis, T, epochs, 0, 2e-3, loss_trace=ltr)
+    coef = torch.zeros(k + 1, dtype=torch.float64, device="cuda")
+    pc = pb.make_precond(U, coef)
+    torch.cuda.synchronize()
+    return {"prm": prm, "pc": pc, "coef": coef, "U": U, "I": I_, "H": H, "O": O_, "k": k,
+            "loss_trace": ltr, "ritz": ritz}
+
+
+def error_sweep(args, pb, h, X, y, w, psi0):
+    """Gradient error against estimates/s, plain FP32 against learned + BF16 split-K+V.
+
+    Error of one estimate: log10 ||g~ - g_ref||^2 / ||g_ref||^2, averaged over `reps`
+    independent estimates at the workload's psi (the paper's measure of gradient accuracy,
+    Sec. 4.2).  g_ref: the plain FP32 estimator with converged solves (q = 0, so the series
+    never truncates; CG to 1e-6 relative) averaged over `ref_probes` Gaussian probes; its
+    standard error is reported.  Each estimate draws fresh probes; the y system keeps its
+    warm start from the previous estimate as it would along a chain.
+    """
+    import numpy as np
+    import torch
+    P = D + 2
+    g = torch.zeros(P, dtype=torch.float64, device="cuda")
+    R = pb.colmajor(N, NPROBES)
+    stats = pb.stats_tensor(M)
+    S_warm = torch.zeros((M, N), dtype=torch.float64, device="cuda").t()
+
+    # reference gradient
+    t0 = time.perf_counter()
+    ref = pb.make_params(q=0.0, rate=1.0, eps=1e-6, eps_relative=1, max_iter=5000, rng_stream=3)
+    batches = max(1, args.ref_probes // NPROBES)
+    gs = []
+    for b in range(batches):
+        pb.gp_draw_probes(h, N, NPROBES, pb.PROBE_GAUSSIAN, 21, b, R=R)
+        S_warm[:, 1:].zero_()
+        ref.rng_counter = b
+        pb.gp_stoch_grad(h, X, psi0, y, ref, R=R, S_warm=S_warm, g=g, stats=stats)
+        gs.append(g.cpu().numpy().copy())
+        if b % 8 == 7:
+            print(f"reference: {b + 1}/{batches} probe batches, {time.perf_counter() - t0:.1f} s",
+                  file=sys.stderr, flush=True)
+        fl = [s_["flags"] for s_ in pb.decode_stats(stats)]
+        assert not any(fl), f"reference solve flagged: {fl}"
+    gs = np.array(gs)
+    g_ref = gs.mean(0)
+    g_ref_se = gs.std(0, ddof=1) / np.sqrt(len(gs))
+    t_ref = time.perf_counter() - t0
+
+    L = setup_learned(pb, h, X, y, w, args.learn_pairs, args.learn_epochs)
+    psi = psi0.clone()
+
+    def run(method, q):
+        params = pb.make_params(q=q, rate=1.0, eps=1e-6, eps_relative=1, max_iter=1000, rng_stream=5)
+        if method == "learned_bf16":
+            params.prec = pb.GP_BF16_SPLIT_KV
+            pb.precond_from_mlp(h, L["prm"], L["I"], L["H"], L["O"], psi, L["k"], coef=L["coef"])
+        S_warm.zero_()
+        errs, passes = [], 0.0
+        elapsed = 0.0
+        for r in range(args.sweep_reps + 1):  # rep 0 warms the y system up, untimed
+            torch.cuda.synchronize()
+            pb.gp_profile(h, 1)
+            t0 = time.perf_counter()
+            pb.gp_draw_probes(h, N, NPROBES, pb.PROBE_GAUSSIAN, 23, r, R=R)
+            S_warm[:, 1:].zero_()
+            params.rng_counter = r
+            if method == "learned_bf16":
+                pb.precond_from_mlp(h, L["prm"], L["I"], L["H"], L["O"], psi, L["k"], coef=L["coef"])
+                pb.gp_stoch_grad_pc(h, X, psi, y, params, L["pc"], R=R, S_warm=S_warm, g=g, stats=stats)
+            else:
+                pb.gp_stoch_grad(h, X, psi, y, params, R=R, S_warm=S_warm, g=g, stats=stats)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            pr = pb.gp_profile_read(h)
+            pb.gp_profile(h, 0)
+            if r == 0:
+                continue
+            elapsed += dt
+            passes += pr["kmv_passes"]
+            e = g.cpu().numpy() - g_ref
+            errs.append(float(np.sum(e * e) / np.sum(g_ref * g_ref)))
+        errs = np.array(errs)
+        return {"method": method, "q": q, "reps": len(errs),
+                "mean_log10_rel_sq_err": float(np.mean(np.log10(errs))),
+                "se_mean_log10": float(np.std(np.log10(errs), ddof=1) / np.sqrt(len(errs))),
+                "rel_mse": float(np.mean(errs)),
+                "grad_estimates_per_s": len(errs) / elapsed,
+                "kmv_passes_per_estimate": passes / len(errs),
+                "var_normalised_throughput": len(errs) / elapsed / float(np.mean(errs))}
+
+    rows = []
+    for method in ("plain_fp32", "learned_bf16"):
+        for q in args.sweep_q:
+            rows.append(run(method, q))
+            print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+    out = {"error_sweep": rows, "g_ref": g_ref.tolist(), "g_ref_se": g_ref_se.tolist(),
+           "ref_probes": batches * NPROBES, "ref_seconds": t_ref,
+           "workload": WORKLOAD, "probes": NPROBES, "fresh_probes_every_estimate": True}
+    print(json.dumps(out), flush=True)
+
+
+def solver_study(args, pb, h):
+    """The solver study of Sec. 3.2 and Sec. 4.2 on synthetic data, against the condition
+    number: CG iterations to convergence; ULISSE products per solve and the per-element
+    standard deviation of its estimates (Fig. 3's measure); log10 relative squared error of
+    the gradient (Fig. 4's measure) for q in {0.1, 1} and rate c in {1, 0.01}.
+
+    Inputs: the n = 16384, d = 8 random-Fourier-feature workload with lambda varied to set
+    kappa = (lambda_max(K_f) + lambda) / lambda.  The ULISSE draws for one kappa share one CG
+    path: the right-hand side y is repeated in 32 columns, whose uniforms are independent.
+    """
+    import numpy as np
+    import torch
+    import workloads
+    n, d, m = 16384, 8, 32
+    w = workloads.rff_gp(n=n, d=d, seed=1)
+    X = torch.from_numpy(w["X"]).cuda()
+    y = torch.from_numpy(w["y"]).cuda()
+    Y = pb.colmajor(n, m)
+    Y.copy_(y[:, None].expand(n, m))
+    R = pb.colmajor(n, NPROBES)
+    g = torch.zeros(d + 2, dtype=torch.float64, device="cuda")
+    # (q, rate); q = 0 is plain CG run to convergence (the "CG" line of Figs. 3 and 4)
+    settings = [(0.0, 1.0), (0.1, 1.0), (1.0, 1.0), (0.1, 0.01), (1.0, 0.01)]
+    rows = []
+    for lam in args.study_lambdas:
+        psi_np = w["psi"].copy()
+        psi_np[-1] = np.log(lam)
+        psi = torch.from_numpy(psi_np).cuda()
+        # lambda_max of K by power iteration
+        v = pb.colmajor(n, 1)
+        v.copy_(torch.from_numpy(workloads.gaussian_matrix(n, 1, seed=5)).cuda())
+        for _ in range(40):
+            kv = pb.gp_kmv(h, X, psi, v)
+            v.copy_(kv / torch.linalg.vector_norm(kv))
+        lmax = float(torch.dot(v[:, 0], pb.gp_kmv(h, X, psi, v)[:, 0]))
+        kappa = lmax / lam
+        t0 = time.perf_counter()
+        conv = pb.make_params(q=0.0, rate=1.0, eps=1e-6, eps_relative=1, max_iter=args.study_max_iter)
+        St, st = pb.ulisse_solve(h, X, psi, Y[:, :1], conv)
+        cg_stats = pb.decode_stats(st)[0]
+        s_ref = St[:, 0].clone()
+        row = {"lambda": lam, "kappa": kappa, "cg_iters": cg_stats["iters"],
+               "cg_flags": cg_stats["flags"], "solution_rms": float(torch.sqrt(torch.mean(s_ref ** 2))),
+               "settings": []}
+        # reference gradient: converged solves, averaged over batches of NPROBES probes
+        gs = []
+        for b in range(args.study_ref_batches):
+            conv.rng_counter = 1000 + b
+            pb.gp_stoch_grad(h, X, psi, y, conv, n_probes=NPROBES, g=g)
+            gs.append(g.cpu().numpy().copy())
+        g_ref = np.mean(gs, 0)
+        row["g_ref_rel_se"] = float(np.linalg.norm(np.std(gs, 0, ddof=1) / np.sqrt(len(gs)))
+                                    / np.linalg.norm(g_ref))
+        for q, c in settings:
+            par = pb.make_params(q=q, rate=c, eps=1e-6, eps_relative=1, max_iter=args.study_max_iter,
+                                 rng_stream=11)
+            St, st = pb.ulisse_solve(h, X, psi, Y, par)
+            ss = pb.decode_stats(st)
+            Sn = St.cpu().numpy()
+            per_elem_std = float(np.mean(np.std(Sn, axis=1, ddof=1)))
+            errs = []
+            for r in range(args.study_reps):
+                par.rng_counter = 5000 + r
+                pb.gp_stoch_grad(h, X, psi, y, par, n_probes=args.study_probes, g=g)
+                e = g.cpu().numpy() - g_ref
+                errs.append(float(np.sum(e * e) / np.sum(g_ref * g_ref)))
+            print(f"kappa {kappa:.3g}: q={q} rate={c} done, {time.perf_counter() - t0:.1f} s",
+                  file=sys.stderr, flush=True)
+            row["settings"].append({
+                "q": q, "rate": c,
+                "products_mean": float(np.mean([s_["iters"] for s_ in ss])),
+                "l_mean": float(np.mean([s_["l"] for s_ in ss])),
+                "J_mean": float(np.mean([s_["J_a"] for s_ in ss])),
+                "flagged": int(sum(1 for s_ in ss if s_["flags"])),
+                "per_element_std": per_elem_std,
+                "grad_mean_log10_err": float(np.mean(np.log10(errs))),
+                "grad_reps": len(errs)})
+        row["seconds"] = time.perf_counter() - t0
+        rows.append(row)
+        print(json.dumps(row), flush=True)
+    print(json.dumps({"solver_study": rows, "workload": "rff_n16384_d8", "probes": args.study_probes,
+                      "ref_probes": args.study_ref_batches * NPROBES, "draws_per_path": m}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -106,6 +307,19 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-kmv", action="store_true")
+    ap.add_argument("--error-sweep", action="store_true",
+                    help="gradient error vs estimates/s, plain FP32 vs learned + BF16 (separate report)")
+    ap.add_argument("--sweep-reps", type=int, default=100)
+    ap.add_argument("--sweep-q", type=lambda t: [float(v) for v in t.split(",")], default=[0.3, 1.0, 3.0])
+    ap.add_argument("--ref-probes", type=int, default=1024)
+    ap.add_argument("--solver-study", action="store_true",
+                    help="CG/ULISSE iterations, spread and gradient error against kappa (separate report)")
+    ap.add_argument("--study-lambdas", type=lambda t: [float(v) for v in t.split(",")],
+                    default=[1.0, 0.1, 0.01, 1e-3, 1e-4])
+    ap.add_argument("--study-reps", type=int, default=30)
+    ap.add_argument("--study-probes", type=int, default=1, help="probes per gradient estimate (Fig. 4: 1)")
+    ap.add_argument("--study-ref-batches", type=int, default=8)
+    ap.add_argument("--study-max-iter", type=int, default=20000)
     args = ap.parse_args()
     if args.bf16_steps is None:
         args.bf16_steps = args.steps
@@ -131,6 +345,13 @@ def main():
     psi0 = torch.from_numpy(w["psi"]).cuda()
     y = torch.from_numpy(w["y"]).cuda()
     h = pb.Handle(0, seed=2015)
+
+    if args.error_sweep:
+        error_sweep(args, pb, h, X, y, w, psi0)
+        return
+    if args.solver_study:
+        solver_study(args, pb, h)
+        return
 
     if args.profile_kmv:
         V = pb.colmajor(N, M)
@@ -240,21 +461,10 @@ def main():
     learned = None
     if args.learned_steps:
         t_setup = time.perf_counter()
-        k, H = 64, 256
-        U, ritz = pb.precond_build_basis(h, X, psi0, k)
-        rng = np.random.default_rng(17)
-        psis = torch.from_numpy(w["psi"] + LEARN_JITTER * rng.standard_normal((args.learn_pairs, D + 2))).cuda()
-        T = pb.precond_targets(h, X, y, U, psis)
-        I_, O_ = D + 2, 2 * k + 1
-        prm = torch.zeros(pb.precond_mlp_size(I_, H, O_), dtype=torch.float32, device="cuda")
-        pb.precond_mlp_init(h, prm, I_, H, O_, psis, T, seed=5)
-        adam = torch.zeros(2 * pb.mlp_layout(I_, H, O_)["trainable"], dtype=torch.float32, device="cuda")
-        ltr = torch.zeros(args.learn_epochs, dtype=torch.float32, device="cuda")
-        pb.precond_mlp_train(h, prm, adam, I_, H, O_, psis, T, args.learn_epochs, 0, 2e-3, loss_trace=ltr)
-        torch.cuda.synchronize()
+        L = setup_learned(pb, h, X, y, w, args.learn_pairs, args.learn_epochs)
         t_setup = time.perf_counter() - t_setup
-        coef = torch.zeros(k + 1, dtype=torch.float64, device="cuda")
-        pc = pb.make_precond(U, coef)
+        prm, pc, coef, I_, H, O_, k = L["prm"], L["pc"], L["coef"], L["I"], L["H"], L["O"], L["k"]
+        ltr, ritz = L["loss_trace"], L["ritz"]
 
         def step_learned(t):
             params.rng_counter = t
@@ -321,7 +531,7 @@ def main():
     traffic = traffic_from_profile()
 
     rec = {
-        "metric": "unbiased grad estimates/s and K.V TFLOP/s at n=65536 (plain FP32 path)",
+        "metric": "unbiased grad estimates/s and K\u00b7V TFLOP/s at n=65536, learned+BF16 vs plain",
         "value": value,
         "unit": "grad_estimates/s",
         "n_gpus": 1,
@@ -336,7 +546,8 @@ def main():
         "config": {"workload": WORKLOAD, "n": N, "d": D, "rhs": M, "probes": NPROBES,
                    "probe_kind": "gaussian", "probe_period": period, "q": 1.0, "rate": 1.0,
                    "eps_rel": 1e-6, "warm_start": "last CG iterate, every system",
-                   "sgld_eps": eps_t, "sgld_M": "I/n", "precision": "fp32"},
+                   "sgld_eps": eps_t, "sgld_M": "I/n", "precision": "fp32",
+                   "value_is": "plain FP32 path; learned+BF16 in learned_bf16, K.V in roofline"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_FP32_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / VALU_FP32_PEAK_TFLOPS,
                      "traffic": traffic, "kernel": "kmv_mfma_f32 (K.V, m=32)",

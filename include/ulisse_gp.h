@@ -152,6 +152,29 @@ gp_status ulisse_solve_pc(gp_handle* h, gp_data X, const double* psi, const floa
                           const gp_precond* pc, double* S_tilde, double* S_cg,
                           ulisse_sysstat* stats, void* stream);
 
+/* The PCG variant of Sec. 3.3 whose preconditioner is J = K + delta I (delta > 0), applied
+ * to each residual by an inner run of Alg. 1 on (K + delta I) z = e from z = 0.  The inner
+ * run stops at ||r|| < eps_inner ||e|| (relative; eps_inner = 0 never stops early) or after
+ * max_inner products, whichever comes first; it takes no ULISSE truncation, its products use
+ * prec_inner, and its right-hand side is e rounded to FP32.  Since CG is not linear in its
+ * right-hand side, an inner run that stops early applies a slightly different operator at
+ * every outer iteration; the outer series stays unbiased either way (it only needs the
+ * iterates to converge).  Each outer iteration waits on the host for the inner run.  The
+ * outer iteration count (stats.iters) excludes the inner products. */
+typedef struct {
+    double delta;         /* shift of J = K + delta I, > 0                                 */
+    double eps_inner;     /* inner relative tolerance, >= 0                                 */
+    int32_t max_inner;    /* inner products per application, >= 1                           */
+    gp_precision prec_inner;
+} gp_shift_precond;
+
+/* ulisse_solve over PCG with J = K + delta I (sp non-null; same conventions otherwise). */
+gp_status ulisse_solve_shift_pc(gp_handle* h, gp_data X, const double* psi, const float* B,
+                                int32_t m, int64_t ldb, const double* S0,
+                                const ulisse_params* params, const gp_shift_precond* sp,
+                                double* S_tilde, double* S_cg, ulisse_sysstat* stats,
+                                void* stream);
+
 /*
  * One unbiased estimate of the gradient of log p(y | psi, X) with respect to psi
  * (eq. gradient:unbiased with the two-estimate quadratic term of Sec. 4.1):
@@ -173,6 +196,13 @@ gp_status gp_stoch_grad_pc(gp_handle* h, gp_data X, const double* psi, const flo
                            const float* R, int32_t n_probes, int32_t probe_kind,
                            const ulisse_params* params, const gp_precond* pc, double* S_warm,
                            double* g, ulisse_sysstat* stats, void* stream);
+
+/* gp_stoch_grad with its solves over PCG with J = K + delta I (sp non-null). */
+gp_status gp_stoch_grad_shift_pc(gp_handle* h, gp_data X, const double* psi, const float* y,
+                                 const float* R, int32_t n_probes, int32_t probe_kind,
+                                 const ulisse_params* params, const gp_shift_precond* sp,
+                                 double* S_warm, double* g, ulisse_sysstat* stats,
+                                 void* stream);
 
 /* Prior on psi: kind 0 flat; kind 1 psi_j ~ N(a_j, b_j^2); kind 2 exp(psi_j) ~ Gamma(shape
  * a_j, rate b_j) with the Jacobian of the log transform.  a, b: P FP64 device (NULL for

@@ -55,6 +55,11 @@ class gp_precond(Structure):
                 ("coef", c_void_p)]
 
 
+class gp_shift_precond(Structure):
+    _fields_ = [("delta", c_double), ("eps_inner", c_double), ("max_inner", c_int32),
+                ("prec_inner", c_int)]
+
+
 class sgld_schedule(Structure):
     _fields_ = [("a", c_double), ("b", c_double), ("gamma", c_double), ("freeze_ratio", c_double),
                 ("batch", c_int32), ("probe_period", c_int32), ("n_probes", c_int32),
@@ -119,6 +124,14 @@ def lib():
     L.gp_stoch_grad_pc.argtypes = [c_void_p, gp_data, c_void_p, c_void_p, c_void_p, c_int32, c_int32,
                                    POINTER(ulisse_params), POINTER(gp_precond), c_void_p, c_void_p,
                                    c_void_p, c_void_p]
+    L.ulisse_solve_shift_pc.restype = c_int
+    L.ulisse_solve_shift_pc.argtypes = [c_void_p, gp_data, c_void_p, c_void_p, c_int32, c_int64, c_void_p,
+                                        POINTER(ulisse_params), POINTER(gp_shift_precond), c_void_p,
+                                        c_void_p, c_void_p, c_void_p]
+    L.gp_stoch_grad_shift_pc.restype = c_int
+    L.gp_stoch_grad_shift_pc.argtypes = [c_void_p, gp_data, c_void_p, c_void_p, c_void_p, c_int32, c_int32,
+                                         POINTER(ulisse_params), POINTER(gp_shift_precond), c_void_p,
+                                         c_void_p, c_void_p, c_void_p]
     L.precond_build_basis.restype = c_int
     L.precond_build_basis.argtypes = [c_void_p, gp_data, c_void_p, c_int32, c_void_p, c_int64, c_void_p, c_void_p]
     L.precond_targets.restype = c_int
@@ -405,6 +418,43 @@ def gp_stoch_grad_pc(h, X, psi, y, params, pc, R=None, n_probes=None, probe_kind
     _check(lib().gp_stoch_grad_pc(h.ptr, _data(X), _ptr(psi), _ptr(y), _ptr(R), int(n_probes),
                                   int(probe_kind), ctypes.byref(params), ctypes.byref(pc.c), _ptr(S_warm),
                                   _ptr(g), _ptr(stats), _stream(stream)))
+    return g, stats
+
+
+def make_shift_precond(delta, eps_inner=0.0, max_inner=10, prec_inner=GP_FP32):
+    """J = K + delta I applied by an inner CG (eps_inner relative, at most max_inner steps)."""
+    return gp_shift_precond(float(delta), float(eps_inner), int(max_inner), int(prec_inner))
+
+
+def ulisse_solve_shift_pc(h, X, psi, B, params, sp, S0=None, S_tilde=None, S_cg=None, stats=None,
+                          stream=None):
+    import torch
+    n = X.shape[0]
+    m = _cols(B)
+    mt = m + (1 if params.two_track_first else 0)
+    if S_tilde is None:
+        S_tilde = torch.zeros((mt, n), dtype=torch.float64, device=B.device).t()
+    if stats is None:
+        stats = stats_tensor(m, B.device)
+    _check(lib().ulisse_solve_shift_pc(h.ptr, _data(X), _ptr(psi), _ptr(B), m, _ld(B, n), _ptr(S0),
+                                       ctypes.byref(params), ctypes.byref(sp), _ptr(S_tilde), _ptr(S_cg),
+                                       _ptr(stats), _stream(stream)))
+    return S_tilde, stats
+
+
+def gp_stoch_grad_shift_pc(h, X, psi, y, params, sp, R=None, n_probes=None, probe_kind=PROBE_GAUSSIAN,
+                           S_warm=None, g=None, stats=None, stream=None):
+    import torch
+    d = X.shape[1]
+    if R is not None:
+        n_probes = _cols(R)
+    if g is None:
+        g = torch.zeros(d + 2, dtype=torch.float64, device=y.device)
+    if stats is None:
+        stats = stats_tensor(1 + n_probes, y.device)
+    _check(lib().gp_stoch_grad_shift_pc(h.ptr, _data(X), _ptr(psi), _ptr(y), _ptr(R), int(n_probes),
+                                        int(probe_kind), ctypes.byref(params), ctypes.byref(sp),
+                                        _ptr(S_warm), _ptr(g), _ptr(stats), _stream(stream)))
     return g, stats
 
 

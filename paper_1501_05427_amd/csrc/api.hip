@@ -46,8 +46,12 @@ enum Slot {
     kSlotCounter, kSlotActive, kSlotState, kSlotStats, kSlotR, kSlotB, kSlotSt, kSlotS0,
     kSlotA32, kSlotB32, kSlotGpart, kSlotWork, kSlotVH, kSlotVL, kSlotGbatch, kSlotGvec,
     kSlotRatio, kSlotRunStats, kSlotZp, kSlotUtv, kSlotHW, kSlotP3, kSlotY0, kSlotY1,
-    kSlotY2, kSlotGram, kSlotGpart2, kSlotSmall, kSlotMlp, kNumSlots
+    kSlotY2, kSlotGram, kSlotGpart2, kSlotSmall, kSlotMlp, kSlotIcgB, kSlotIcgZ, kSlotIcgSt,
+    kSlotIcgKP, kNumSlots
 };
+// Solves nest one level (the inner CG of the shifted preconditioner): the inner solve's
+// buffers live in a second set of slots, offset by kNumSlots.
+constexpr int kLevels = 2;
 
 bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
@@ -56,11 +60,12 @@ bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
 struct gp_handle {
     int device = 0;
     uint64_t seed = 0;
-    void* buf[kNumSlots] = {};
-    size_t bytes[kNumSlots] = {};
-    int* pinned = nullptr;  // two words: systems still running after iteration it (it % 2)
+    void* buf[kLevels * kNumSlots] = {};
+    size_t bytes[kLevels * kNumSlots] = {};
+    // two words per solve level: systems still running after iteration it (it % 2)
+    int* pinned = nullptr;
     double* pinned_d = nullptr;  // one word read back by sgld_run (Langevin-phase ratio)
-    hipEvent_t ev[2] = {nullptr, nullptr};
+    hipEvent_t ev[2 * kLevels] = {};
     // kernel timing (gp_profile)
     bool prof = false;
     std::vector<hipEvent_t> pool;
@@ -191,10 +196,25 @@ gp_status check_precond(const gp_precond* pc, int64_t n) {
     return GP_OK;
 }
 
+gp_status check_shift(const gp_shift_precond* sp) {
+    if (sp == nullptr) return GP_OK;
+    GP_CHECK(std::isfinite(sp->delta) && sp->delta > 0.0, "shift delta must be finite and > 0");
+    GP_CHECK(std::isfinite(sp->eps_inner) && sp->eps_inner >= 0.0, "eps_inner must be >= 0");
+    GP_CHECK(sp->max_inner >= 1, "max_inner must be >= 1");
+    GP_CHECK(sp->prec_inner == GP_FP32 || sp->prec_inner == GP_BF16_SPLIT_V ||
+                 sp->prec_inner == GP_BF16_SPLIT_KV,
+             "unknown inner precision");
+    return GP_OK;
+}
+
 gp_status solve_core(gp_handle* h, int64_t n, int d, const float* Z, const KParams* kp,
                      const float* B, int64_t ldb, int m, const double* S0,
                      const ulisse_params& p, double* St, double* S_cg, ulisse_sysstat* stats,
-                     hipStream_t s, const gp_precond* pc = nullptr) {
+                     hipStream_t s, const gp_precond* pc = nullptr,
+                     const gp_shift_precond* sp = nullptr, int level = 0) {
+    if (level >= kLevels || (sp != nullptr && level + 1 >= kLevels))
+        return fail(GP_EUNSUPPORTED, "solves nest at most %d levels", kLevels);
+    const int so = level * kNumSlots;  // this level's workspace slots
     const KmvShape sh = kmv_shape(n, d, m, p.prec);
     const bool b16 = uses_bf16(sh, p.prec);
     const int64_t n_pad = sh.n_pad;
@@ -209,18 +229,18 @@ gp_status solve_core(gp_handle* h, int64_t n, int d, const float* Z, const KPara
     a.B = B;
     a.S0 = S0;
     float* kpart = nullptr;
-    GP_TRY(ws(h, kSlotPart, (size_t)sh.split * sh.mp * n_pad, &kpart));
-    GP_TRY(ws(h, kSlotQ, (size_t)n_pad * m, &a.Q));
-    GP_TRY(ws(h, kSlotS, (size_t)n_pad * m, &a.S));
-    GP_TRY(ws(h, kSlotE, (size_t)n_pad * m, &a.E));
-    GP_TRY(ws(h, kSlotD, (size_t)n_pad * sh.mp, &a.D));
-    GP_TRY(ws(h, kSlotP1, (size_t)a.nb * m, &a.part));
-    GP_TRY(ws(h, kSlotP2, (size_t)a.nb * m, &a.part2));
-    GP_TRY(ws(h, kSlotActive, 1, &a.n_active));
+    GP_TRY(ws(h, kSlotPart + so, (size_t)sh.split * sh.mp * n_pad, &kpart));
+    GP_TRY(ws(h, kSlotQ + so, (size_t)n_pad * m, &a.Q));
+    GP_TRY(ws(h, kSlotS + so, (size_t)n_pad * m, &a.S));
+    GP_TRY(ws(h, kSlotE + so, (size_t)n_pad * m, &a.E));
+    GP_TRY(ws(h, kSlotD + so, (size_t)n_pad * sh.mp, &a.D));
+    GP_TRY(ws(h, kSlotP1 + so, (size_t)a.nb * m, &a.part));
+    GP_TRY(ws(h, kSlotP2 + so, (size_t)a.nb * m, &a.part2));
+    GP_TRY(ws(h, kSlotActive + so, 1, &a.n_active));
     SysState* states;
-    GP_TRY(ws(h, kSlotState, (size_t)2 * m, &states));
+    GP_TRY(ws(h, kSlotState + so, (size_t)2 * m, &states));
     a.state = states;
-    if (stats == nullptr) GP_TRY(ws(h, kSlotStats, (size_t)m, &stats));
+    if (stats == nullptr) GP_TRY(ws(h, kSlotStats + so, (size_t)m, &stats));
     a.St = St;
     a.kpart = kpart;
     a.kp = kp;
@@ -235,21 +255,44 @@ gp_status solve_core(gp_handle* h, int64_t n, int d, const float* Z, const KPara
     a.rng_stream = p.rng_stream;
     a.rng_counter = p.rng_counter;
     if (pc != nullptr) {
+        a.pcm = 1;
         a.U = pc->U;
         a.ldu = pc->ldu;
         a.pk = pc->k;
         a.coef = pc->coef;
         a.nb256 = pc_chunks(n);
-        GP_TRY(ws(h, kSlotZp, (size_t)n_pad * m, &a.Zp));
-        GP_TRY(ws(h, kSlotUtv, (size_t)a.nb256 * pc->k * m, &a.utv_part));
-        GP_TRY(ws(h, kSlotHW, (size_t)pc->k * m, &a.HW));
-        GP_TRY(ws(h, kSlotP3, (size_t)a.nb256 * m, &a.part3));
+        GP_TRY(ws(h, kSlotZp + so, (size_t)n_pad * m, &a.Zp));
+        GP_TRY(ws(h, kSlotUtv + so, (size_t)a.nb256 * pc->k * m, &a.utv_part));
+        GP_TRY(ws(h, kSlotHW + so, (size_t)pc->k * m, &a.HW));
+        GP_TRY(ws(h, kSlotP3 + so, (size_t)a.nb256 * m, &a.part3));
+    }
+    // J = K + delta I: inner solves on the shifted covariance, one level down
+    float* Bin = nullptr;
+    double *Zin = nullptr, *Stin = nullptr;
+    KParams* kp_in = nullptr;
+    ulisse_params ip{};
+    if (sp != nullptr) {
+        a.pcm = 2;
+        a.nb256 = pc_chunks(n);
+        GP_TRY(ws(h, kSlotZp + so, (size_t)n_pad * m, &a.Zp));
+        GP_TRY(ws(h, kSlotP3 + so, (size_t)a.nb256 * m, &a.part3));
+        GP_TRY(ws(h, kSlotIcgB + so, (size_t)n_pad * m, &Bin));
+        GP_TRY(ws(h, kSlotIcgZ + so, (size_t)n * m, &Zin));
+        GP_TRY(ws(h, kSlotIcgSt + so, (size_t)n * m, &Stin));
+        GP_TRY(ws(h, kSlotIcgKP + so, 1, &kp_in));
+        GP_HIP(launch_shift_kp(kp, sp->delta, kp_in, s));
+        ip.q = 0.0;  // no truncation: the inner run is plain CG
+        ip.rate = 1.0;
+        ip.eps = sp->eps_inner;
+        ip.eps_relative = 1;
+        ip.max_iter = sp->max_inner;
+        ip.prec = sp->prec_inner;
     }
 
     uint16_t *DH = nullptr, *DL = nullptr;
     if (b16) {
-        GP_TRY(ws(h, kSlotVH, (size_t)n_pad * sh.mp, &DH));
-        GP_TRY(ws(h, kSlotVL, (size_t)n_pad * sh.mp, &DL));
+        GP_TRY(ws(h, kSlotVH + so, (size_t)n_pad * sh.mp, &DH));
+        GP_TRY(ws(h, kSlotVL + so, (size_t)n_pad * sh.mp, &DL));
     }
     // the BF16 modes split the FP32 direction into hi + lo halves before each product
     auto product = [&](const int* n_active) -> gp_status {
@@ -266,23 +309,39 @@ gp_status solve_core(gp_handle* h, int64_t n, int d, const float* Z, const KPara
         GP_TRY(product(nullptr));
         h->passes += 1;
     }
+    // z = J^-1 e by the inner run (its last CG iterate), then Zp, e^T z and (first) d = z
+    auto inner_step = [&](int first) -> gp_status {
+        GP_HIP(launch_icg_rhs(a, Bin, first, s));
+        GP_TRY(solve_core(h, n, d, Z, kp_in, Bin, n_pad, m, nullptr, ip, Stin, Zin, nullptr, s,
+                          nullptr, nullptr, level + 1));
+        GP_HIP(launch_icg_finish(a, Zin, first, s));
+        return GP_OK;
+    };
     GP_HIP(solver_init(a, warm, s));
     if (pc != nullptr) GP_HIP(launch_pc_step(a, 1, s));
+    if (sp != nullptr) GP_TRY(inner_step(1));
     GP_HIP(solver_init_state(a, s));
+    int* pinned = h->pinned + 2 * level;
+    hipEvent_t* ev = h->ev + 2 * level;
     for (int it = 0; it <= p.max_iter; ++it) {
         GP_TRY(product(a.n_active));
         GP_HIP(solver_reduce(a, s));
         GP_HIP(solver_update(a, s));
         if (pc != nullptr) GP_HIP(launch_pc_step(a, 0, s));
+        if (sp != nullptr) GP_TRY(inner_step(0));
         SysState* next = states + ((it + 1) & 1) * m;
         GP_HIP(solver_direction(a, next, s));
         a.state = next;
-        GP_HIP(hipMemcpyAsync(h->pinned + (it & 1), a.n_active, sizeof(int), hipMemcpyDeviceToHost, s));
-        GP_HIP(hipEventRecord(h->ev[it & 1], s));
+        GP_HIP(hipMemcpyAsync(pinned + (it & 1), a.n_active, sizeof(int), hipMemcpyDeviceToHost, s));
+        GP_HIP(hipEventRecord(ev[it & 1], s));
         h->passes += 1;
-        if (it >= 1) {
-            GP_HIP(hipEventSynchronize(h->ev[(it - 1) & 1]));
-            if (h->pinned[(it - 1) & 1] == 0) {
+        if (sp != nullptr) {
+            // the inner runs synchronise anyway: stop before launching another one
+            GP_HIP(hipEventSynchronize(ev[it & 1]));
+            if (pinned[it & 1] == 0) break;
+        } else if (it >= 1) {
+            GP_HIP(hipEventSynchronize(ev[(it - 1) & 1]));
+            if (pinned[(it - 1) & 1] == 0) {
                 // this iteration's launches found no running system and did nothing
                 if (h->prof) prof_drop_last(h, h->kmv_ev);
                 h->passes -= 1;
@@ -290,10 +349,21 @@ gp_status solve_core(gp_handle* h, int64_t n, int d, const float* Z, const KPara
             }
         }
     }
-    h->solves += 1;
+    if (level == 0) h->solves += 1;
     if (S_cg != nullptr) GP_HIP(solver_copy_s(a, S_cg, s));
     return GP_OK;
 }
+
+// Bodies of the solve and gradient entry points, shared by their preconditioned forms.
+gp_status solve_entry(gp_handle* h, gp_data X, const double* psi, const float* B, int32_t m,
+                      int64_t ldb, const double* S0, const ulisse_params* params,
+                      const gp_precond* pc, const gp_shift_precond* sp, double* S_tilde,
+                      double* S_cg, ulisse_sysstat* stats, void* stream);
+gp_status grad_entry(gp_handle* h, gp_data X, const double* psi, const float* y,
+                     const float* R, int32_t n_probes, int32_t probe_kind,
+                     const ulisse_params* params, const gp_precond* pc,
+                     const gp_shift_precond* sp, double* S_warm, double* g,
+                     ulisse_sysstat* stats, void* stream);
 
 }  // namespace
 
@@ -310,14 +380,15 @@ gp_status gp_create(gp_handle** out, int device, uint64_t seed) {
     gp_handle* h = new gp_handle();
     h->device = device;
     h->seed = seed;
-    if (hipHostMalloc((void**)&h->pinned, 2 * sizeof(int), hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void**)&h->pinned_d, sizeof(double), hipHostMallocDefault) != hipSuccess ||
-        hipEventCreateWithFlags(&h->ev[0], hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&h->ev[1], hipEventDisableTiming) != hipSuccess) {
+    bool ok = hipHostMalloc((void**)&h->pinned, 2 * kLevels * sizeof(int), hipHostMallocDefault) == hipSuccess &&
+              hipHostMalloc((void**)&h->pinned_d, sizeof(double), hipHostMallocDefault) == hipSuccess;
+    for (int i = 0; ok && i < 2 * kLevels; ++i)
+        ok = hipEventCreateWithFlags(&h->ev[i], hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
         gp_destroy(h);
         return fail(GP_EDEVICE, "handle setup failed: %s", hipGetErrorString(hipGetLastError()));
     }
-    h->pinned[0] = h->pinned[1] = 1;
+    for (int i = 0; i < 2 * kLevels; ++i) h->pinned[i] = 1;
     *out = h;
     return GP_OK;
 }
@@ -326,9 +397,9 @@ void gp_destroy(gp_handle* h) {
     if (!h) return;
     (void)hipSetDevice(h->device);
     (void)hipDeviceSynchronize();
-    for (int i = 0; i < kNumSlots; ++i)
+    for (int i = 0; i < kLevels * kNumSlots; ++i)
         if (h->buf[i]) (void)hipFree(h->buf[i]);
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < 2 * kLevels; ++i)
         if (h->ev[i]) (void)hipEventDestroy(h->ev[i]);
     if (h->pinned) (void)hipHostFree(h->pinned);
     if (h->pinned_d) (void)hipHostFree(h->pinned_d);
@@ -402,21 +473,16 @@ gp_status ulisse_solve_pc(gp_handle* h, gp_data X, const double* psi, const floa
                           int32_t m, int64_t ldb, const double* S0, const ulisse_params* params,
                           const gp_precond* pc, double* S_tilde, double* S_cg,
                           ulisse_sysstat* stats, void* stream) {
-    GP_TRY(check_handle(h));
-    GP_TRY(check_data(X));
-    GP_TRY(check_params(params));
-    GP_CHECK(m >= 1 && m + (params->two_track_first ? 1 : 0) <= kMaxSys, "too many systems");
-    GP_CHECK(B != nullptr && aligned(B, 4) && ldb >= X.n, "B null, misaligned or ldb < n");
-    GP_CHECK(S_tilde != nullptr && aligned(S_tilde, 8), "S_tilde null or misaligned");
-    GP_CHECK(S0 == nullptr || aligned(S0, 8), "S0 misaligned");
-    GP_CHECK(S_cg == nullptr || aligned(S_cg, 8), "S_cg misaligned");
-    GP_TRY(check_precond(pc, X.n));
-    hipStream_t s = (hipStream_t)stream;
-    const int64_t n_pad = round_up(X.n, kRowPad);
-    float* Z;
-    KParams* kp;
-    GP_TRY(prep(h, X, psi, n_pad, &Z, &kp, s));
-    return solve_core(h, X.n, X.d, Z, kp, B, ldb, m, S0, *params, S_tilde, S_cg, stats, s, pc);
+    return solve_entry(h, X, psi, B, m, ldb, S0, params, pc, nullptr, S_tilde, S_cg, stats, stream);
+}
+
+gp_status ulisse_solve_shift_pc(gp_handle* h, gp_data X, const double* psi, const float* B,
+                                int32_t m, int64_t ldb, const double* S0,
+                                const ulisse_params* params, const gp_shift_precond* sp,
+                                double* S_tilde, double* S_cg, ulisse_sysstat* stats,
+                                void* stream) {
+    if (sp == nullptr) return fail(GP_EINVAL, "shift preconditioner is null");
+    return solve_entry(h, X, psi, B, m, ldb, S0, params, nullptr, sp, S_tilde, S_cg, stats, stream);
 }
 
 gp_status gp_stoch_grad(gp_handle* h, gp_data X, const double* psi, const float* y,
@@ -431,6 +497,51 @@ gp_status gp_stoch_grad_pc(gp_handle* h, gp_data X, const double* psi, const flo
                            const float* R, int32_t n_probes, int32_t probe_kind,
                            const ulisse_params* params, const gp_precond* pc, double* S_warm,
                            double* g, ulisse_sysstat* stats, void* stream) {
+    return grad_entry(h, X, psi, y, R, n_probes, probe_kind, params, pc, nullptr, S_warm, g,
+                      stats, stream);
+}
+
+gp_status gp_stoch_grad_shift_pc(gp_handle* h, gp_data X, const double* psi, const float* y,
+                                 const float* R, int32_t n_probes, int32_t probe_kind,
+                                 const ulisse_params* params, const gp_shift_precond* sp,
+                                 double* S_warm, double* g, ulisse_sysstat* stats,
+                                 void* stream) {
+    if (sp == nullptr) return fail(GP_EINVAL, "shift preconditioner is null");
+    return grad_entry(h, X, psi, y, R, n_probes, probe_kind, params, nullptr, sp, S_warm, g,
+                      stats, stream);
+}
+
+}  // extern "C"
+
+namespace {
+
+gp_status solve_entry(gp_handle* h, gp_data X, const double* psi, const float* B, int32_t m,
+                      int64_t ldb, const double* S0, const ulisse_params* params,
+                      const gp_precond* pc, const gp_shift_precond* sp, double* S_tilde,
+                      double* S_cg, ulisse_sysstat* stats, void* stream) {
+    GP_TRY(check_handle(h));
+    GP_TRY(check_data(X));
+    GP_TRY(check_params(params));
+    GP_CHECK(m >= 1 && m + (params->two_track_first ? 1 : 0) <= kMaxSys, "too many systems");
+    GP_CHECK(B != nullptr && aligned(B, 4) && ldb >= X.n, "B null, misaligned or ldb < n");
+    GP_CHECK(S_tilde != nullptr && aligned(S_tilde, 8), "S_tilde null or misaligned");
+    GP_CHECK(S0 == nullptr || aligned(S0, 8), "S0 misaligned");
+    GP_CHECK(S_cg == nullptr || aligned(S_cg, 8), "S_cg misaligned");
+    GP_TRY(check_precond(pc, X.n));
+    GP_TRY(check_shift(sp));
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n_pad = round_up(X.n, kRowPad);
+    float* Z;
+    KParams* kp;
+    GP_TRY(prep(h, X, psi, n_pad, &Z, &kp, s));
+    return solve_core(h, X.n, X.d, Z, kp, B, ldb, m, S0, *params, S_tilde, S_cg, stats, s, pc, sp);
+}
+
+gp_status grad_entry(gp_handle* h, gp_data X, const double* psi, const float* y,
+                     const float* R, int32_t n_probes, int32_t probe_kind,
+                     const ulisse_params* params, const gp_precond* pc,
+                     const gp_shift_precond* sp, double* S_warm, double* g,
+                     ulisse_sysstat* stats, void* stream) {
     GP_TRY(check_handle(h));
     GP_TRY(check_data(X));
     GP_TRY(check_params(params));
@@ -441,6 +552,7 @@ gp_status gp_stoch_grad_pc(gp_handle* h, gp_data X, const double* psi, const flo
     GP_CHECK(g != nullptr && aligned(g, 8), "g null or misaligned");
     GP_CHECK(S_warm == nullptr || aligned(S_warm, 8), "S_warm misaligned");
     GP_TRY(check_precond(pc, X.n));
+    GP_TRY(check_shift(sp));
     hipStream_t s = (hipStream_t)stream;
     const int64_t n = X.n;
     const int d = X.d;
@@ -477,7 +589,7 @@ gp_status gp_stoch_grad_pc(gp_handle* h, gp_data X, const double* psi, const flo
     GP_TRY(ws(h, kSlotSt, (size_t)n * (m + 1), &St));
     ulisse_params p = *params;
     p.two_track_first = 1;
-    GP_TRY(solve_core(h, n, d, Z, kp, Bm, n, m, S0, p, St, S_warm, stats, s, pc));
+    GP_TRY(solve_core(h, n, d, Z, kp, Bm, n, m, S0, p, St, S_warm, stats, s, pc, sp));
 
     const DquadShape dq = dquad_shape(n, d, m);
     float *A32, *B32;
@@ -505,6 +617,10 @@ gp_status gp_stoch_grad_pc(gp_handle* h, gp_data X, const double* psi, const flo
     GP_HIP(launch_grad_finish(St, Rp, n, n, n_probes, gpart, dq.nwg, d, kp, dpart, g, s));
     return GP_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 gp_status sgld_run(gp_handle* h, gp_data X, double* psi, const float* y,
                    const ulisse_params* params, const gp_prior* prior, const double* M_chol,

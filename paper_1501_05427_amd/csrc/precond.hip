@@ -144,4 +144,68 @@ hipError_t launch_pc_step(const SolverArgs& a, int first, hipStream_t s) {
     }
 }
 
+// ---------------------------------------------------------------------------------------
+// J = K + delta I applied by an inner CG (the PCG variant of Sec. 3.3).  The inner run is
+// an ordinary solve on the shifted covariance; these kernels hand the outer residuals to
+// it and take its result back into the outer iteration.
+// ---------------------------------------------------------------------------------------
+__global__ void icg_rhs_kernel(SolverArgs a, float* __restrict__ Bin, int first) {
+    if (!first && *a.n_active == 0) return;
+    const int64_t total = a.n_pad * a.m;
+    for (int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; o < total;
+         o += (int64_t)gridDim.x * blockDim.x)
+        Bin[o] = (float)a.E[o];
+}
+
+__global__ __launch_bounds__(kWG) void icg_finish_kernel(SolverArgs a, const double* __restrict__ Zin,
+                                                         int first) {
+    if (!first && *a.n_active == 0) return;
+    __shared__ double red[4][kMaxSys];
+    const int m = a.m;
+    const int64_t i = (int64_t)blockIdx.x * kChunk + threadIdx.x;
+    const bool in = i < a.n;
+    for (int c = 0; c < m; ++c) {
+        if (!first && !a.state[c].active) continue;  // uniform over the workgroup
+        double ez = 0.0;
+        if (in) {
+            const double z = Zin[c * a.n + i];
+            a.Zp[c * a.n_pad + i] = z;
+            if (first) a.D[c * a.n_pad + i] = (float)z;
+            ez = a.E[c * a.n_pad + i] * z;
+        }
+        const double w = wave_sum(ez);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][c] = w;
+    }
+    __syncthreads();
+    if (threadIdx.x < m && (first || a.state[threadIdx.x].active)) {
+        const int c = threadIdx.x;
+        a.part3[(int64_t)blockIdx.x * m + c] = (red[0][c] + red[1][c]) + (red[2][c] + red[3][c]);
+    }
+}
+
+__global__ void shift_kp_kernel(const KParams* in, double delta, KParams* out) {
+    if (threadIdx.x != 0) return;
+    KParams p = *in;
+    p.lam64 = in->lam64 + delta;
+    p.lam = (float)p.lam64;
+    *out = p;
+}
+
+hipError_t launch_icg_rhs(const SolverArgs& a, float* Bin, int first, hipStream_t s) {
+    const int64_t total = a.n_pad * a.m;
+    const int blocks = (int)std::min<int64_t>((total + kWG - 1) / kWG, 4096);
+    icg_rhs_kernel<<<blocks, kWG, 0, s>>>(a, Bin, first);
+    return hipGetLastError();
+}
+
+hipError_t launch_icg_finish(const SolverArgs& a, const double* Zin, int first, hipStream_t s) {
+    icg_finish_kernel<<<pc_chunks(a.n), kWG, 0, s>>>(a, Zin, first);
+    return hipGetLastError();
+}
+
+hipError_t launch_shift_kp(const KParams* in, double delta, KParams* out, hipStream_t s) {
+    shift_kp_kernel<<<1, 64, 0, s>>>(in, delta, out);
+    return hipGetLastError();
+}
+
 }  // namespace gpk

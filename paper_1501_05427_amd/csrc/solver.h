@@ -58,7 +58,9 @@ struct SolverArgs {
     double q, rate, eps;
     int32_t eps_relative, max_iter, two_track, pad_;
     uint64_t seed, rng_stream, rng_counter;
-    // preconditioner P^-1 v = tau_inv v + U (h o U^T v); U == nullptr: plain CG
+    // pcm: 0 plain CG; 1 P^-1 v = tau_inv v + U (h o U^T v); 2 z from an inner CG on
+    // (K + delta I) z = e.  For 1 and 2 the step lengths use rho = e^T z (partials in part3).
+    int32_t pcm, pad2_;
     const float* U;        // n x pk, ld ldu (FP32)
     int64_t ldu;
     int32_t pk;            // 16, 32 or 64
@@ -97,6 +99,13 @@ hipError_t launch_sgld(int P, double* psi, const double* g, int prior_kind, cons
 // z = P^-1 e for every active system and the partials of e^T z; `first` also sets d = z.
 int pc_chunks(int64_t n);
 hipError_t launch_pc_step(const SolverArgs& a, int first, hipStream_t s);
+// Inner-CG preconditioner (pcm 2): the outer residuals rounded to FP32 as the inner
+// right-hand sides (n_pad x m, ld n_pad), and, once the inner run has left z in Zin
+// (n x m FP64, ld n), Zp = z, the partials of e^T z and, with `first`, d = z.
+hipError_t launch_icg_rhs(const SolverArgs& a, float* Bin, int first, hipStream_t s);
+hipError_t launch_icg_finish(const SolverArgs& a, const double* Zin, int first, hipStream_t s);
+// out = in with lambda replaced by lambda + delta (the covariance of J = K + delta I).
+hipError_t launch_shift_kp(const KParams* in, double delta, KParams* out, hipStream_t s);
 // Initial state once the initial residual (and z for PCG) are in place.
 hipError_t solver_init_state(const SolverArgs& a, hipStream_t s);
 

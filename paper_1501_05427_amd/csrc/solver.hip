@@ -96,7 +96,7 @@ __global__ __launch_bounds__(kWG) void ulisse_init_state_kernel(SolverArgs a) {
     const int c = blockIdx.x;
     const double ee = column_total(a.part, a.nb, a.m, c, &bcast);
     const double b2 = column_total(a.part2, a.nb, a.m, c, &bcast);
-    const double rho = a.U != nullptr ? column_total(a.part3, a.nb256, a.m, c, &bcast) : ee;
+    const double rho = a.pcm != 0 ? column_total(a.part3, a.nb256, a.m, c, &bcast) : ee;
     if (threadIdx.x != 0) return;
     SysState st;
     st.rho = rho;
@@ -273,7 +273,7 @@ __global__ __launch_bounds__(kWG) void ulisse_direction_kernel(SolverArgs a, con
     }
     const double gamma = column_total(a.part, a.nb, a.m, c, &bcast);
     const double ee = column_total(a.part2, a.nb, a.m, c, &bcast);
-    const double rho_new = a.U != nullptr ? column_total(a.part3, a.nb256, a.m, c, &bcast) : ee;
+    const double rho_new = a.pcm != 0 ? column_total(a.part3, a.nb256, a.m, c, &bcast) : ee;
     advance(a, st, c, gamma, rho_new, ee);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         next[c] = st;
@@ -289,7 +289,7 @@ __global__ __launch_bounds__(kWG) void ulisse_direction_kernel(SolverArgs a, con
         const int64_t i = (int64_t)blockIdx.x * kRowsPerBlock + r * kWG + threadIdx.x;
         if (i >= a.n) break;
         const int64_t o = c * a.n_pad + i;
-        const double zv = a.U != nullptr ? a.Zp[o] : a.E[o];
+        const double zv = a.pcm != 0 ? a.Zp[o] : a.E[o];
         a.D[o] = (float)(zv + beta * (double)a.D[o]);
     }
 }

@@ -542,6 +542,85 @@ def test_pcg_converged_solution_and_fewer_iterations(h):
 
 
 # ---------------------------------------------------------------------------------------
+# PCG with J = K + delta I applied by an inner CG (Sec. 3.3)
+# ---------------------------------------------------------------------------------------
+def _pcg_q(K, b, pinv, target_l=1):
+    """q between two residual norms of a PCG run (same rule as _safe_q)."""
+    norms = []
+    for i, s_, e, dl in ocg.pcg_iterates(lambda v: K @ v, pinv, b, np.zeros(len(b))):
+        norms.append(np.linalg.norm(e))
+        if i >= target_l + 1 and min(norms[:-1]) > 1.5 * norms[-1]:
+            return np.sqrt(min(norms[:-1]) * norms[-1]) / np.sqrt(len(b))
+        assert i < 100
+
+
+@pytest.mark.parametrize("m,two_track,delta,max_inner", [(3, 0, 0.5, 4), (17, 1, 0.2, 3), (5, 1, 1.0, 6)])
+def test_ulisse_shift_pcg_draw_for_draw(h, m, two_track, delta, max_inner):
+    # a fixed inner count (eps_inner = 0) leaves no inner decision to rounding
+    n, d = 400, 2
+    X, psi = problem(n, d, seed=40 + m, lam=0.2, ell=(0.2, 0.4))
+    K = ogp.kernel_matrix(X, psi)
+    Bm = np.random.default_rng(m).standard_normal((n, m)).astype(np.float32)
+    pinv = ocg.shifted_inner_pinv(lambda v: K @ v, delta, 0.0, max_inner)
+    q = _pcg_q(K, Bm[:, 0].astype(np.float64), pinv)
+    rate, eps = 0.7, 1e-6
+    params = pb.make_params(q=q, rate=rate, eps=eps, eps_relative=1, max_iter=200,
+                            two_track_first=two_track, rng_stream=5, rng_counter=2)
+    sp = pb.make_shift_precond(delta, 0.0, max_inner)
+    St, stats = pb.ulisse_solve_shift_pc(h, dev(X), dev(psi), colm(Bm), params, sp)
+    torch.cuda.synchronize()
+    ref_St, _, ref_stats = oul.solve_systems(lambda v: K @ v, Bm.astype(np.float64), None, q, rate, eps,
+                                             200, h.seed, 5, 2, two_track_first=bool(two_track),
+                                             eps_relative=True, apply_pinv=pinv)
+    for c, (g_, r) in enumerate(zip(pb.decode_stats(stats), ref_stats)):
+        assert (g_["l"], g_["iters"], g_["J_a"], g_["flags"]) == (r["l"], r["iters"], r["J"][0], r["flags"]), c
+    assert colwise_rel(St.cpu().numpy(), ref_St).max() <= 2e-4
+
+
+def test_shift_pcg_converged_solution_and_outer_iterations(h):
+    n, d, m = 1000, 2, 4
+    X, psi = problem(n, d, seed=3, lam=0.02, ell=(0.2, 0.3))
+    Bm = np.random.default_rng(0).standard_normal((n, m)).astype(np.float32)
+    params = pb.make_params(q=0.0, rate=1.0, eps=1e-6, eps_relative=1, max_iter=3000)
+    sp = pb.make_shift_precond(0.05, 1e-4, 200)
+    St_sp, st_sp = pb.ulisse_solve_shift_pc(h, dev(X), dev(psi), colm(Bm), params, sp)
+    St, st = pb.ulisse_solve(h, dev(X), dev(psi), colm(Bm), params)
+    torch.cuda.synchronize()
+    ref = ogp.solve(X, psi, Bm.astype(np.float64))
+    ss, sc = pb.decode_stats(st_sp), pb.decode_stats(st)
+    assert not any(s_["flags"] for s_ in ss), ss
+    assert colwise_rel(St_sp.cpu().numpy(), ref).max() <= 1e-4
+    assert colwise_rel(St.cpu().numpy(), ref).max() <= 1e-4
+    # nearly exact inner solves of a close J: far fewer outer iterations than plain CG
+    assert max(s_["iters"] for s_ in ss) < 0.5 * max(s_["iters"] for s_ in sc), (ss, sc)
+
+
+def test_stoch_grad_shift_pcg_draw_for_draw(h):
+    n, d, nr, lam, ell, seed = 300, 2, 4, 1.0, (0.1, 0.3), 302
+    X, psi = problem(n, d, seed=seed, lam=lam, ell=ell)
+    K = ogp.kernel_matrix(X, psi)
+    y = (np.linalg.cholesky(K) @ np.random.default_rng(1).standard_normal(n)).astype(np.float32)
+    R = workloads.gaussian_matrix(n, nr, seed=3)
+    delta, max_inner = 0.5, 3
+    pinv = ocg.shifted_inner_pinv(lambda v: K @ v, delta, 0.0, max_inner)
+    q = _pcg_q(K, y.astype(np.float64), pinv)
+    stream, counter, eps, rate = 5, 9, 1e-6, 1.0
+    params = pb.make_params(q=q, rate=rate, eps=eps, eps_relative=1, max_iter=300,
+                            rng_stream=stream, rng_counter=counter)
+    sp = pb.make_shift_precond(delta, 0.0, max_inner)
+    g, stats = pb.gp_stoch_grad_shift_pc(h, dev(X), dev(psi), dev(y), params, sp, R=colm(R))
+    torch.cuda.synchronize()
+    g_ref, St, Scg, ref_stats = osg.stoch_grad(X, psi, y, R, q, rate, eps, 300, h.seed, stream, counter,
+                                               eps_relative=True, apply_pinv=pinv)
+    st_gpu = pb.decode_stats(stats)
+    for c in range(nr + 1):
+        assert ref_stats[c]["iters"] <= 7
+        assert (st_gpu[c]["l"], st_gpu[c]["iters"]) == (ref_stats[c]["l"], ref_stats[c]["iters"]), c
+    scale = np.abs(g_ref).max()
+    np.testing.assert_allclose(g.cpu().numpy(), g_ref, rtol=2e-4, atol=2e-4 * scale)
+
+
+# ---------------------------------------------------------------------------------------
 # Learned warm start and preconditioner
 # ---------------------------------------------------------------------------------------
 def _host_params(rng, I, H, O):
@@ -687,3 +766,34 @@ def test_learned_preconditioner_gains_and_keeps_the_gradient(h):
         a, b = g0.cpu().numpy(), g1.cpu().numpy()
         np.testing.assert_allclose(b, a, rtol=1e-3, atol=1e-4 * np.abs(a).max())
     assert max(its_pc) < 0.6 * min(its_plain), (its_pc, its_plain)
+
+
+# ---------------------------------------------------------------------------------------
+# SGLD protocol: exact subset gradient, MAP and preconditioner M (Sec. 5)
+# ---------------------------------------------------------------------------------------
+def test_protocol_exact_gradient_vs_oracle(h):
+    from paper_1501_05427_amd import protocol
+    n, d = 300, 2
+    X, psi = problem(n, d, seed=77, lam=0.1, ell=(0.2, 0.5))
+    K = ogp.kernel_matrix(X, psi)
+    y = (np.linalg.cholesky(K) @ np.random.default_rng(7).standard_normal(n)).astype(np.float32)
+    g = protocol.exact_gradient(h, dev(X), dev(y), psi)
+    ref = ogp.exact_gradient(X, psi, y.astype(np.float64))
+    np.testing.assert_allclose(g, ref, rtol=1e-4, atol=1e-4 * np.abs(ref).max())
+
+
+def test_protocol_subset_map_and_preconditioner_vs_oracle(h):
+    from oracle import diagnostics as od
+    from paper_1501_05427_amd import protocol
+    n, d = 400, 2
+    X, psi = problem(n, d, seed=78, lam=0.1, ell=(0.2, 0.5))
+    K = ogp.kernel_matrix(X, psi)
+    y = (np.linalg.cholesky(K) @ np.random.default_rng(8).standard_normal(n)).astype(np.float32)
+    prior = {"kind": 1, "a": np.zeros(d + 2), "b": np.full(d + 2, 3.0)}
+    psi_map, M, L = protocol.sgld_preconditioner(h, X, y, psi + 0.1, prior, n_sub=200, seed=5)
+    idx = np.sort(np.random.default_rng(5).choice(n, size=200, replace=False))
+    ref_map, ref_A = od.subset_map(X[idx], y[idx].astype(np.float64), psi + 0.1, 1, prior["a"], prior["b"])
+    np.testing.assert_allclose(psi_map, ref_map, atol=2e-3)
+    ref_M = np.linalg.inv(ref_A)
+    np.testing.assert_allclose(M, ref_M, rtol=2e-2, atol=2e-2 * np.abs(ref_M).max())
+    np.testing.assert_allclose(L @ L.T, M, rtol=1e-12, atol=1e-14)

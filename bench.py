@@ -293,6 +293,92 @@ def solver_study(args, pb, h):
                       "ref_probes": args.study_ref_batches * NPROBES, "draws_per_path": m}), flush=True)
 
 
+def batched_bench(args, pb):
+    """64 independent SGLD chains over 64 GPs (n uniform in [2048, 32768], d in {2, 4, 8, 16},
+    the random-Fourier-feature generator with a sub-seed per GP, y + 16 probes each),
+    stepped together through gp_batch_* (captured graphs, autotuned product shapes), against
+    the same chains stepped one after another through gp_stoch_grad + sgld_step.
+    Protocol of the main bench: probes redrawn every 20 steps with warm starts, q = 1,
+    M = I / n, eps = 1e-3, N(0, 3^2) prior on psi."""
+    import numpy as np
+    import torch
+    import workloads
+    B, nr = args.batch_chains, 16
+    r = np.random.default_rng(3)
+    ns = r.integers(2048, 32768, endpoint=True, size=B)
+    ds = r.choice([2, 4, 8, 16], size=B)
+    seeds = r.integers(0, 2**31, size=B)
+    probs = []
+    for i in range(B):
+        n, d = int(ns[i]), int(ds[i])
+        w = workloads.rff_gp(n=n, d=d, seed=int(seeds[i]))
+        probs.append({"X": torch.from_numpy(w["X"]).cuda(), "y": torch.from_numpy(w["y"]).cuda(),
+                      "psi": torch.from_numpy(w["psi"]).cuda(),
+                      "M_chol": torch.diag(torch.full((d + 2,), n ** -0.5, dtype=torch.float64)).cuda(),
+                      "prior": (1, torch.zeros(d + 2, dtype=torch.float64, device="cuda"),
+                                torch.full((d + 2,), 3.0, dtype=torch.float64, device="cuda"))})
+    pairs = float(np.sum(ns.astype(np.float64) ** 2))
+    params = pb.make_params(q=1.0, rate=1.0, eps=1e-6, eps_relative=1, max_iter=1000, rng_stream=1)
+    eps_t = 1e-3
+    psi0 = [p["psi"].clone() for p in probs]
+    out = {"workload": f"batch{B}_rff_n2048-32768_d2-16_m17", "chains": B, "pairs_per_product_sweep": pairs}
+    # unbatched: the same chains one after another (own handle per chain, eager calls)
+    hs = [pb.Handle(0, seed=7000 + i) for i in range(B)]
+    st = []
+    for i, p in enumerate(probs):
+        n, d = p["X"].shape
+        st.append({"S_warm": torch.zeros((1 + nr, n), dtype=torch.float64, device="cuda").t(),
+                   "R": pb.colmajor(n, nr), "g": torch.zeros(d + 2, dtype=torch.float64, device="cuda")})
+
+    def unbatched_step(t):
+        for i, p in enumerate(probs):
+            s_ = st[i]
+            n = p["X"].shape[0]
+            if t % PROBE_PERIOD == 0:
+                pb.gp_draw_probes(hs[i], n, nr, pb.PROBE_GAUSSIAN, params.rng_stream, t // PROBE_PERIOD, R=s_["R"])
+                s_["S_warm"][:, 1:].zero_()
+            params.rng_counter = t
+            pb.gp_stoch_grad(hs[i], p["X"], p["psi"], p["y"], params, R=s_["R"], S_warm=s_["S_warm"], g=s_["g"])
+            kind, a, b = p["prior"]
+            pb.sgld_step(hs[i], p["psi"], s_["g"], eps_t, rng_stream=params.rng_stream, rng_counter=t,
+                         prior_kind=kind, prior_a=a, prior_b=b, M_chol=p["M_chol"])
+
+    for t in range(args.warmup):
+        unbatched_step(t)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for t in range(args.warmup, args.warmup + args.batch_steps):
+        unbatched_step(t)
+    torch.cuda.synchronize()
+    el_u = time.perf_counter() - t0
+    out["unbatched"] = {"grad_estimates_per_s": B * args.batch_steps / el_u,
+                        "ms_per_step": 1e3 * el_u / args.batch_steps}
+    print(json.dumps({"unbatched_done": out["unbatched"]}), file=sys.stderr, flush=True)
+    del hs
+    for mode, tune in (("batched_graphs", False), ("batched_graphs_autotuned", True)):
+        for i, p in enumerate(probs):
+            p["psi"].copy_(psi0[i])
+        batch = pb.Batch(probs, nr, params, seed=7000, probe_period=PROBE_PERIOD, iters_per_graph=8,
+                         autotune=tune, streams=8)
+        for t in range(args.warmup):
+            batch.step(t, eps_t)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for t in range(args.warmup, args.warmup + args.batch_steps):
+            batch.step(t, eps_t)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out[mode] = {"grad_estimates_per_s": B * args.batch_steps / el, "ms_per_step": 1e3 * el / args.batch_steps,
+                     "stats": batch.stats(),
+                     "psi_finite": bool(all(torch.isfinite(p["psi"]).all().item() for p in probs))}
+        batch.close()
+        print(json.dumps({mode: out[mode]}), file=sys.stderr, flush=True)
+    out["steps"] = args.batch_steps
+    out["speedup_batched_vs_unbatched"] = out["batched_graphs_autotuned"]["grad_estimates_per_s"] / \
+        out["unbatched"]["grad_estimates_per_s"]
+    print(json.dumps({"batched": out}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -312,6 +398,10 @@ def main():
     ap.add_argument("--sweep-reps", type=int, default=100)
     ap.add_argument("--sweep-q", type=lambda t: [float(v) for v in t.split(",")], default=[0.3, 1.0, 3.0])
     ap.add_argument("--ref-probes", type=int, default=1024)
+    ap.add_argument("--batched", action="store_true",
+                    help="64 chains over 64 GPs: batched graphs vs unbatched calls (separate report)")
+    ap.add_argument("--batch-chains", type=int, default=64)
+    ap.add_argument("--batch-steps", type=int, default=20)
     ap.add_argument("--solver-study", action="store_true",
                     help="CG/ULISSE iterations, spread and gradient error against kappa (separate report)")
     ap.add_argument("--study-lambdas", type=lambda t: [float(v) for v in t.split(",")],
@@ -351,6 +441,9 @@ def main():
         return
     if args.solver_study:
         solver_study(args, pb, h)
+        return
+    if args.batched:
+        batched_bench(args, pb)
         return
 
     if args.profile_kmv:

@@ -330,6 +330,74 @@ gp_status precond_warm_start(gp_handle* h, const float* U, int64_t ldu, int32_t 
                              const double* c, double* s0, void* stream);
 
 /*
+ * Batched SGLD: B independent chains, each over its own GP (own X, n, d, y), advanced one
+ * SGLD step per gp_batch_step call with the protocol of sgld_run (probes redrawn every
+ * probe_period steps with warm starts from the last CG iterates; Sec. 5).  Chain b draws
+ * with Philox key (seed + b, rng_stream): its probes, uniforms and SGLD noise are those of
+ * gp_draw_probes (counter t / probe_period), gp_stoch_grad (counter t) and sgld_step
+ * (counter t) on a handle created with seed + b, so a batched step reproduces the unbatched
+ * calls exactly.
+ *
+ * The first step runs eagerly (sizing every workspace and, with autotune, timing the
+ * product shapes); later steps replay graphs captured once: set-up (probes, right-hand
+ * sides, initial residuals), a chunk of iters_per_graph solver iterations for every chain
+ * (replayed until no system of any chain is running; the device count is read back after
+ * each chunk), then the gradient reduction and the SGLD update of every chain.  The chains
+ * are spread over `streams` side streams, so the small ones run alongside the large ones.
+ * The step index and step size are read by the kernels from device memory, so the graphs
+ * never change.
+ *
+ * Every pointer of every problem is device memory owned by the caller and must stay valid,
+ * at the same address, for the batch's lifetime: X (n x d, ld ldx), y (n), psi (d + 2,
+ * in/out), S_warm (n x (1 + n_probes) FP64, ld n, zero at the start), R (n x n_probes FP32,
+ * ld n; the batch writes it), g (d + 2, out), stats (1 + n_probes entries, nullable),
+ * M_chol (nullable = I), prior as for sgld_step.  iters_per_graph: even, >= 2.  The shifted
+ * and learned preconditioners are not available in a batch.
+ */
+typedef struct {
+    gp_data X;
+    const float* y;
+    double* psi;
+    double* S_warm;
+    float* R;
+    double* g;
+    ulisse_sysstat* stats;
+    const double* M_chol;
+    gp_prior prior;
+} gp_batch_problem;
+
+typedef struct gp_batch gp_batch;
+
+typedef struct {
+    int64_t eager_steps;       /* steps run without graphs                              */
+    int64_t graph_steps;       /* steps run by graph replays                            */
+    int64_t iteration_graphs;  /* replays of the solver-iteration graph                 */
+    int64_t captures;          /* graphs captured                                       */
+} gp_batch_stats;
+
+gp_status gp_batch_create(gp_batch** b, int device, uint64_t seed, int32_t B,
+                          const gp_batch_problem* problems, int32_t n_probes, int32_t probe_kind,
+                          int32_t probe_period, const ulisse_params* params,
+                          int32_t iters_per_graph, int32_t autotune, int32_t streams);
+/* One SGLD step (step index t, step size eps_t) of every chain, ordered after prior work on
+ * `stream`; returns when the step is complete. */
+gp_status gp_batch_step(gp_batch* b, uint64_t t, double eps_t, void* stream);
+gp_status gp_batch_read_stats(const gp_batch* b, gp_batch_stats* out);
+void gp_batch_destroy(gp_batch* b);
+
+/*
+ * Autotuner of the covariance products.  With gp_autotune(h, 1), the first product of each
+ * shape (n rounded up to 256, d, padded column count, precision) on this handle times the
+ * split-K candidates (the number of column chunks, for 256 to 8192 workgroups, at most 64
+ * chunks) on the stream and keeps the fastest for every later product of that shape; that
+ * first call synchronises the stream.  Off by default (a fixed rule then targets 2048
+ * workgroups).  gp_autotune_split reports the split products of a shape use now.
+ */
+gp_status gp_autotune(gp_handle* h, int32_t enable);
+gp_status gp_autotune_split(gp_handle* h, int64_t n, int32_t d, int32_t m, gp_precision prec,
+                            int32_t* split);
+
+/*
  * Kernel timing for measurement.  While enabled, the handle records a pair of hipEvents on
  * the launch stream around every covariance-product launch that does work (kmv, in the
  * solver and in gp_kmv) and around every fused gradient reduction (dquad).

@@ -70,6 +70,16 @@ class sgld_state(Structure):
     _fields_ = [("t", c_int64), ("frozen", c_int32), ("frozen_at", c_int32), ("eps_frozen", c_double)]
 
 
+class gp_batch_problem(Structure):
+    _fields_ = [("X", gp_data), ("y", c_void_p), ("psi", c_void_p), ("S_warm", c_void_p), ("R", c_void_p),
+                ("g", c_void_p), ("stats", c_void_p), ("M_chol", c_void_p), ("prior", gp_prior)]
+
+
+class gp_batch_stats(Structure):
+    _fields_ = [("eager_steps", c_int64), ("graph_steps", c_int64), ("iteration_graphs", c_int64),
+                ("captures", c_int64)]
+
+
 SYSSTAT_BYTES = ctypes.sizeof(ulisse_sysstat)
 
 _lib = None
@@ -162,6 +172,19 @@ def lib():
                            c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
     L.gp_profile.restype = c_int
     L.gp_profile.argtypes = [c_void_p, c_int32]
+    L.gp_autotune.restype = c_int
+    L.gp_autotune.argtypes = [c_void_p, c_int32]
+    L.gp_autotune_split.restype = c_int
+    L.gp_autotune_split.argtypes = [c_void_p, c_int64, c_int32, c_int32, c_int, POINTER(c_int32)]
+    L.gp_batch_create.restype = c_int
+    L.gp_batch_create.argtypes = [POINTER(c_void_p), c_int, c_uint64, c_int32, POINTER(gp_batch_problem),
+                                  c_int32, c_int32, c_int32, POINTER(ulisse_params), c_int32, c_int32, c_int32]
+    L.gp_batch_step.restype = c_int
+    L.gp_batch_step.argtypes = [c_void_p, c_uint64, c_double, c_void_p]
+    L.gp_batch_read_stats.restype = c_int
+    L.gp_batch_read_stats.argtypes = [c_void_p, POINTER(gp_batch_stats)]
+    L.gp_batch_destroy.restype = None
+    L.gp_batch_destroy.argtypes = [c_void_p]
     L.gp_profile_read.restype = c_int
     L.gp_profile_read.argtypes = [c_void_p, POINTER(gp_profile_stats)]
     _lib = L
@@ -552,3 +575,72 @@ def precond_warm_start(h, U, c, s0, stream=None):
     _check(lib().precond_warm_start(h.ptr, _ptr(U), _ld(U, n), int(k), int(n), _ptr(c), _ptr(s0),
                                     _stream(stream)))
     return s0
+
+
+# ---------------------------------------------------------------------------------------
+# Autotuner and batched SGLD
+# ---------------------------------------------------------------------------------------
+def gp_autotune(h, enable):
+    _check(lib().gp_autotune(h.ptr, int(enable)))
+
+
+def gp_autotune_split(h, n, d, m, prec=GP_FP32):
+    out = c_int32(0)
+    _check(lib().gp_autotune_split(h.ptr, int(n), int(d), int(m), int(prec), ctypes.byref(out)))
+    return out.value
+
+
+class Batch:
+    """B independent SGLD chains over their own GPs, stepped together (gp_batch_*).
+
+    problems: list of dicts with device tensors X (n, d) FP32, y (n,) FP32, psi (d + 2) FP64;
+    optional M_chol ((d + 2) x (d + 2) FP64, column-major), prior (kind, a, b).  The batch
+    allocates S_warm, R, g and stats per chain and keeps every tensor alive.
+    """
+
+    def __init__(self, problems, n_probes, params, seed=0, probe_kind=PROBE_GAUSSIAN, probe_period=20,
+                 iters_per_graph=8, autotune=True, streams=8, device=0):
+        import torch
+        self.keep = []
+        descs = (gp_batch_problem * len(problems))()
+        self.chains = []
+        for i, pr in enumerate(problems):
+            X, y, psi = pr["X"], pr["y"], pr["psi"]
+            n, d = X.shape
+            S_warm = torch.zeros((1 + n_probes, n), dtype=torch.float64, device=X.device).t()
+            R = colmajor(n, n_probes, device=X.device)
+            g = torch.zeros(d + 2, dtype=torch.float64, device=X.device)
+            st = stats_tensor(1 + n_probes, X.device)
+            kind, a, b = pr.get("prior", (0, None, None))
+            M = pr.get("M_chol")
+            chain = {"X": X, "y": y, "psi": psi, "S_warm": S_warm, "R": R, "g": g, "stats": st,
+                     "M_chol": M, "a": a, "b": b}
+            self.chains.append(chain)
+            addr = lambda t: 0 if t is None else t.data_ptr()
+            descs[i] = gp_batch_problem(_data(X), addr(y), addr(psi), addr(S_warm), addr(R), addr(g),
+                                        addr(st), addr(M), gp_prior(int(kind), 0, addr(a), addr(b)))
+        self.params = params
+        ptr = c_void_p()
+        _check(lib().gp_batch_create(ctypes.byref(ptr), device, seed, len(problems), descs, n_probes,
+                                     probe_kind, probe_period, ctypes.byref(params), iters_per_graph,
+                                     int(bool(autotune)), streams))
+        self.ptr = ptr.value
+
+    def step(self, t, eps_t, stream=None):
+        _check(lib().gp_batch_step(self.ptr, int(t), float(eps_t), _stream(stream)))
+
+    def stats(self):
+        out = gp_batch_stats()
+        _check(lib().gp_batch_read_stats(self.ptr, ctypes.byref(out)))
+        return {k: getattr(out, k) for k, _ in gp_batch_stats._fields_}
+
+    def close(self):
+        if getattr(self, "ptr", None):
+            lib().gp_batch_destroy(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

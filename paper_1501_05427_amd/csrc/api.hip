@@ -7,7 +7,9 @@
 #include <cstdio>
 #include <cstring>
 #include <algorithm>
+#include <array>
 #include <cmath>
+#include <map>
 #include <vector>
 
 #include "gp_common.h"
@@ -47,7 +49,7 @@ enum Slot {
     kSlotA32, kSlotB32, kSlotGpart, kSlotWork, kSlotVH, kSlotVL, kSlotGbatch, kSlotGvec,
     kSlotRatio, kSlotRunStats, kSlotZp, kSlotUtv, kSlotHW, kSlotP3, kSlotY0, kSlotY1,
     kSlotY2, kSlotGram, kSlotGpart2, kSlotSmall, kSlotMlp, kSlotIcgB, kSlotIcgZ, kSlotIcgSt,
-    kSlotIcgKP, kNumSlots
+    kSlotIcgKP, kSlotTuneV, kSlotTunePart, kSlotTuneVH, kSlotTuneVL, kNumSlots
 };
 // Solves nest one level (the inner CG of the shifted preconditioner): the inner solve's
 // buffers live in a second set of slots, offset by kNumSlots.
@@ -71,6 +73,13 @@ struct gp_handle {
     std::vector<hipEvent_t> pool;
     std::vector<hipEvent_t> kmv_ev, dq_ev;  // start/stop pairs
     int64_t solves = 0, passes = 0;
+    // set only by the batched driver: step word and step size read from device memory
+    const uint64_t* dyn_step = nullptr;
+    const uint64_t* dyn_probe_step = nullptr;
+    const double* dyn_eps = nullptr;
+    // autotuner: (n_pad, d, mp, prec) -> workgroup target of the covariance product
+    bool autotune = false;
+    std::map<std::array<int64_t, 4>, int> tuned;
     // work table of the gradient reduction currently in the workspace
     int64_t work_npad = -1;
     int work_L = -1;
@@ -196,6 +205,75 @@ gp_status check_precond(const gp_precond* pc, int64_t n) {
     return GP_OK;
 }
 
+// Split-K candidates of the autotuner (workgroup targets; duplicates after rounding are
+// skipped) and the timing of one candidate: a warm-up launch, then kTuneReps launches.
+constexpr int kTuneTargets[] = {256, 512, 1024, 2048, 4096, 8192};
+constexpr int kTuneReps = 3;
+constexpr int kTuneMaxSplit = 64;
+
+// The shape of the covariance products for (n, d, m, prec): the default, or with the
+// autotuner on, the fastest of the candidate splits, timed once per shape on this handle
+// with the prepared Z and kp (the timing synchronises the stream).
+gp_status shape_for(gp_handle* h, int64_t n, int d, int m, gp_precision prec, const float* Z,
+                    const KParams* kp, hipStream_t s, KmvShape* out) {
+    const KmvShape base = kmv_shape(n, d, m, prec);
+    if (!h->autotune) {
+        *out = base;
+        return GP_OK;
+    }
+    const std::array<int64_t, 4> key{base.n_pad, d, base.mp, (int64_t)prec};
+    auto it = h->tuned.find(key);
+    if (it != h->tuned.end()) {
+        *out = kmv_shape_target(n, d, m, prec, it->second);
+        return GP_OK;
+    }
+    const bool b16 = uses_bf16(base, prec);
+    float *V, *part;
+    uint16_t *VH = nullptr, *VL = nullptr;
+    GP_TRY(ws(h, kSlotTuneV, (size_t)base.n_pad * base.mp, &V));
+    GP_TRY(ws(h, kSlotTunePart, (size_t)kTuneMaxSplit * base.mp * base.n_pad, &part));
+    if (b16) {
+        GP_TRY(ws(h, kSlotTuneVH, (size_t)base.n_pad * base.mp, &VH));
+        GP_TRY(ws(h, kSlotTuneVL, (size_t)base.n_pad * base.mp, &VL));
+    }
+    hipEvent_t e0, e1;
+    GP_HIP(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(GP_EDEVICE, "event creation failed");
+    }
+    int best_target = 2048, last_split = -1;
+    float best_ms = 1e30f;
+    gp_status st = GP_OK;
+    for (int target : kTuneTargets) {
+        const KmvShape sh = kmv_shape_target(n, d, m, prec, target);
+        if (sh.split == last_split || sh.split > kTuneMaxSplit) continue;
+        last_split = sh.split;
+        hipError_t e = launch_kmv_partials(sh, d, Z, V, VH, VL, kp, part, nullptr, prec, s);
+        if (e == hipSuccess) e = hipEventRecord(e0, s);
+        for (int r = 0; r < kTuneReps && e == hipSuccess; ++r)
+            e = launch_kmv_partials(sh, d, Z, V, VH, VL, kp, part, nullptr, prec, s);
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) {
+            st = fail(GP_EDEVICE, "autotuner launch failed: %s", hipGetErrorString(e));
+            break;
+        }
+        if (ms < best_ms) {
+            best_ms = ms;
+            best_target = target;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != GP_OK) return st;
+    h->tuned[key] = best_target;
+    *out = kmv_shape_target(n, d, m, prec, best_target);
+    return GP_OK;
+}
+
 gp_status check_shift(const gp_shift_precond* sp) {
     if (sp == nullptr) return GP_OK;
     GP_CHECK(std::isfinite(sp->delta) && sp->delta > 0.0, "shift delta must be finite and > 0");
@@ -207,152 +285,325 @@ gp_status check_shift(const gp_shift_precond* sp) {
     return GP_OK;
 }
 
-gp_status solve_core(gp_handle* h, int64_t n, int d, const float* Z, const KParams* kp,
-                     const float* B, int64_t ldb, int m, const double* S0,
-                     const ulisse_params& p, double* St, double* S_cg, ulisse_sysstat* stats,
-                     hipStream_t s, const gp_precond* pc = nullptr,
-                     const gp_shift_precond* sp = nullptr, int level = 0) {
-    if (level >= kLevels || (sp != nullptr && level + 1 >= kLevels))
-        return fail(GP_EUNSUPPORTED, "solves nest at most %d levels", kLevels);
-    const int so = level * kNumSlots;  // this level's workspace slots
-    const KmvShape sh = kmv_shape(n, d, m, p.prec);
-    const bool b16 = uses_bf16(sh, p.prec);
-    const int64_t n_pad = sh.n_pad;
+// One ULISSE solve in three phases, so that the batched driver can capture each phase in a
+// graph: begin() sets up buffers, the initial residual and state; step() launches one
+// iteration of every running system (its kernels do nothing once none runs); end() copies
+// the last CG iterates out.  run() is the eager loop: it polls the device's count of running
+// systems one iteration behind the launches.
+struct Solve {
+    gp_handle* h = nullptr;
+    int level = 0, so = 0;
+    int64_t n = 0;
+    int d = 0, m = 0;
+    const float* Z = nullptr;
+    const KParams* kp = nullptr;
+    ulisse_params p{};
+    const gp_precond* pc = nullptr;
+    const gp_shift_precond* sp = nullptr;
+    hipStream_t s = nullptr;
+    KmvShape sh{};
+    bool b16 = false;
     SolverArgs a{};
-    a.n = n;
-    a.n_pad = n_pad;
-    a.m = m;
-    a.mp = sh.mp;
-    a.split = sh.split;
-    a.nb = solver_blocks(n);
-    a.ldb = ldb;
-    a.B = B;
-    a.S0 = S0;
+    SysState* states = nullptr;
+    uint16_t *DH = nullptr, *DL = nullptr;
     float* kpart = nullptr;
-    GP_TRY(ws(h, kSlotPart + so, (size_t)sh.split * sh.mp * n_pad, &kpart));
-    GP_TRY(ws(h, kSlotQ + so, (size_t)n_pad * m, &a.Q));
-    GP_TRY(ws(h, kSlotS + so, (size_t)n_pad * m, &a.S));
-    GP_TRY(ws(h, kSlotE + so, (size_t)n_pad * m, &a.E));
-    GP_TRY(ws(h, kSlotD + so, (size_t)n_pad * sh.mp, &a.D));
-    GP_TRY(ws(h, kSlotP1 + so, (size_t)a.nb * m, &a.part));
-    GP_TRY(ws(h, kSlotP2 + so, (size_t)a.nb * m, &a.part2));
-    GP_TRY(ws(h, kSlotActive + so, 1, &a.n_active));
-    SysState* states;
-    GP_TRY(ws(h, kSlotState + so, (size_t)2 * m, &states));
-    a.state = states;
-    if (stats == nullptr) GP_TRY(ws(h, kSlotStats + so, (size_t)m, &stats));
-    a.St = St;
-    a.kpart = kpart;
-    a.kp = kp;
-    a.stats = stats;
-    a.q = p.q;
-    a.rate = p.rate;
-    a.eps = p.eps;
-    a.eps_relative = p.eps_relative;
-    a.max_iter = p.max_iter;
-    a.two_track = p.two_track_first ? 1 : 0;
-    a.seed = h->seed;
-    a.rng_stream = p.rng_stream;
-    a.rng_counter = p.rng_counter;
-    if (pc != nullptr) {
-        a.pcm = 1;
-        a.U = pc->U;
-        a.ldu = pc->ldu;
-        a.pk = pc->k;
-        a.coef = pc->coef;
-        a.nb256 = pc_chunks(n);
-        GP_TRY(ws(h, kSlotZp + so, (size_t)n_pad * m, &a.Zp));
-        GP_TRY(ws(h, kSlotUtv + so, (size_t)a.nb256 * pc->k * m, &a.utv_part));
-        GP_TRY(ws(h, kSlotHW + so, (size_t)pc->k * m, &a.HW));
-        GP_TRY(ws(h, kSlotP3 + so, (size_t)a.nb256 * m, &a.part3));
-    }
-    // J = K + delta I: inner solves on the shifted covariance, one level down
     float* Bin = nullptr;
     double *Zin = nullptr, *Stin = nullptr;
     KParams* kp_in = nullptr;
     ulisse_params ip{};
-    if (sp != nullptr) {
-        a.pcm = 2;
-        a.nb256 = pc_chunks(n);
-        GP_TRY(ws(h, kSlotZp + so, (size_t)n_pad * m, &a.Zp));
-        GP_TRY(ws(h, kSlotP3 + so, (size_t)a.nb256 * m, &a.part3));
-        GP_TRY(ws(h, kSlotIcgB + so, (size_t)n_pad * m, &Bin));
-        GP_TRY(ws(h, kSlotIcgZ + so, (size_t)n * m, &Zin));
-        GP_TRY(ws(h, kSlotIcgSt + so, (size_t)n * m, &Stin));
-        GP_TRY(ws(h, kSlotIcgKP + so, 1, &kp_in));
-        GP_HIP(launch_shift_kp(kp, sp->delta, kp_in, s));
-        ip.q = 0.0;  // no truncation: the inner run is plain CG
-        ip.rate = 1.0;
-        ip.eps = sp->eps_inner;
-        ip.eps_relative = 1;
-        ip.max_iter = sp->max_inner;
-        ip.prec = sp->prec_inner;
-    }
+    int it = 0;  // iterations launched
 
-    uint16_t *DH = nullptr, *DL = nullptr;
-    if (b16) {
-        GP_TRY(ws(h, kSlotVH + so, (size_t)n_pad * sh.mp, &DH));
-        GP_TRY(ws(h, kSlotVL + so, (size_t)n_pad * sh.mp, &DL));
-    }
-    // the BF16 modes split the FP32 direction into hi + lo halves before each product
-    auto product = [&](const int* n_active) -> gp_status {
-        if (b16) GP_HIP(launch_split_bf16(a.D, n_pad * sh.mp, DH, DL, s));
+    gp_status product(const int* n_active) {
+        // the BF16 modes split the FP32 direction into hi + lo halves before each product
+        if (b16) GP_HIP(launch_split_bf16(a.D, sh.n_pad * sh.mp, DH, DL, s));
         hipEvent_t t0 = prof_start(h, s);
         GP_HIP(launch_kmv_partials(sh, d, Z, a.D, DH, DL, kp, kpart, n_active, p.prec, s));
         prof_stop(h, t0, h->kmv_ev, s);
         return GP_OK;
-    };
-    GP_HIP(hipMemsetAsync(a.D, 0, (size_t)n_pad * sh.mp * sizeof(float), s));
-    const int warm = S0 != nullptr;
-    if (warm) {
-        GP_HIP(launch_pack_f64(S0, n, m, a.D, n_pad, s));
-        GP_TRY(product(nullptr));
-        h->passes += 1;
     }
-    // z = J^-1 e by the inner run (its last CG iterate), then Zp, e^T z and (first) d = z
-    auto inner_step = [&](int first) -> gp_status {
-        GP_HIP(launch_icg_rhs(a, Bin, first, s));
-        GP_TRY(solve_core(h, n, d, Z, kp_in, Bin, n_pad, m, nullptr, ip, Stin, Zin, nullptr, s,
-                          nullptr, nullptr, level + 1));
-        GP_HIP(launch_icg_finish(a, Zin, first, s));
+
+    gp_status run_inner(int first);
+
+    gp_status begin(const float* B, int64_t ldb, const double* S0, double* St, ulisse_sysstat* stats) {
+        if (level >= kLevels || (sp != nullptr && level + 1 >= kLevels))
+            return fail(GP_EUNSUPPORTED, "solves nest at most %d levels", kLevels);
+        so = level * kNumSlots;  // this level's workspace slots
+        GP_TRY(shape_for(h, n, d, m, p.prec, Z, kp, s, &sh));
+        b16 = uses_bf16(sh, p.prec);
+        const int64_t n_pad = sh.n_pad;
+        a = SolverArgs{};
+        a.n = n;
+        a.n_pad = n_pad;
+        a.m = m;
+        a.mp = sh.mp;
+        a.split = sh.split;
+        a.nb = solver_blocks(n);
+        a.ldb = ldb;
+        a.B = B;
+        a.S0 = S0;
+        GP_TRY(ws(h, kSlotPart + so, (size_t)sh.split * sh.mp * n_pad, &kpart));
+        GP_TRY(ws(h, kSlotQ + so, (size_t)n_pad * m, &a.Q));
+        GP_TRY(ws(h, kSlotS + so, (size_t)n_pad * m, &a.S));
+        GP_TRY(ws(h, kSlotE + so, (size_t)n_pad * m, &a.E));
+        GP_TRY(ws(h, kSlotD + so, (size_t)n_pad * sh.mp, &a.D));
+        GP_TRY(ws(h, kSlotP1 + so, (size_t)a.nb * m, &a.part));
+        GP_TRY(ws(h, kSlotP2 + so, (size_t)a.nb * m, &a.part2));
+        GP_TRY(ws(h, kSlotActive + so, 1, &a.n_active));
+        GP_TRY(ws(h, kSlotState + so, (size_t)2 * m, &states));
+        a.state = states;
+        if (stats == nullptr) GP_TRY(ws(h, kSlotStats + so, (size_t)m, &stats));
+        a.St = St;
+        a.kpart = kpart;
+        a.kp = kp;
+        a.stats = stats;
+        a.q = p.q;
+        a.rate = p.rate;
+        a.eps = p.eps;
+        a.eps_relative = p.eps_relative;
+        a.max_iter = p.max_iter;
+        a.two_track = p.two_track_first ? 1 : 0;
+        a.seed = h->seed;
+        a.rng_stream = p.rng_stream;
+        a.rng_counter = p.rng_counter;
+        a.counter_dev = level == 0 ? h->dyn_step : nullptr;
+        if (pc != nullptr) {
+            a.pcm = 1;
+            a.U = pc->U;
+            a.ldu = pc->ldu;
+            a.pk = pc->k;
+            a.coef = pc->coef;
+            a.nb256 = pc_chunks(n);
+            GP_TRY(ws(h, kSlotZp + so, (size_t)n_pad * m, &a.Zp));
+            GP_TRY(ws(h, kSlotUtv + so, (size_t)a.nb256 * pc->k * m, &a.utv_part));
+            GP_TRY(ws(h, kSlotHW + so, (size_t)pc->k * m, &a.HW));
+            GP_TRY(ws(h, kSlotP3 + so, (size_t)a.nb256 * m, &a.part3));
+        }
+        // J = K + delta I: inner solves on the shifted covariance, one level down
+        if (sp != nullptr) {
+            a.pcm = 2;
+            a.nb256 = pc_chunks(n);
+            GP_TRY(ws(h, kSlotZp + so, (size_t)n_pad * m, &a.Zp));
+            GP_TRY(ws(h, kSlotP3 + so, (size_t)a.nb256 * m, &a.part3));
+            GP_TRY(ws(h, kSlotIcgB + so, (size_t)n_pad * m, &Bin));
+            GP_TRY(ws(h, kSlotIcgZ + so, (size_t)n * m, &Zin));
+            GP_TRY(ws(h, kSlotIcgSt + so, (size_t)n * m, &Stin));
+            GP_TRY(ws(h, kSlotIcgKP + so, 1, &kp_in));
+            GP_HIP(launch_shift_kp(kp, sp->delta, kp_in, s));
+            ip = ulisse_params{};
+            ip.q = 0.0;  // no truncation: the inner run is plain CG
+            ip.rate = 1.0;
+            ip.eps = sp->eps_inner;
+            ip.eps_relative = 1;
+            ip.max_iter = sp->max_inner;
+            ip.prec = sp->prec_inner;
+        }
+        if (b16) {
+            GP_TRY(ws(h, kSlotVH + so, (size_t)n_pad * sh.mp, &DH));
+            GP_TRY(ws(h, kSlotVL + so, (size_t)n_pad * sh.mp, &DL));
+        }
+        GP_HIP(launch_zero(a.D, (size_t)n_pad * sh.mp * sizeof(float), s));
+        const int warm = S0 != nullptr;
+        if (warm) {
+            GP_HIP(launch_pack_f64(S0, n, m, a.D, n_pad, s));
+            GP_TRY(product(nullptr));
+            h->passes += 1;
+        }
+        GP_HIP(solver_init(a, warm, s));
+        if (pc != nullptr) GP_HIP(launch_pc_step(a, 1, s));
+        if (sp != nullptr) GP_TRY(run_inner(1));
+        GP_HIP(solver_init_state(a, s));
+        it = 0;
         return GP_OK;
-    };
-    GP_HIP(solver_init(a, warm, s));
-    if (pc != nullptr) GP_HIP(launch_pc_step(a, 1, s));
-    if (sp != nullptr) GP_TRY(inner_step(1));
-    GP_HIP(solver_init_state(a, s));
-    int* pinned = h->pinned + 2 * level;
-    hipEvent_t* ev = h->ev + 2 * level;
-    for (int it = 0; it <= p.max_iter; ++it) {
+    }
+
+    gp_status step() {
         GP_TRY(product(a.n_active));
         GP_HIP(solver_reduce(a, s));
         GP_HIP(solver_update(a, s));
         if (pc != nullptr) GP_HIP(launch_pc_step(a, 0, s));
-        if (sp != nullptr) GP_TRY(inner_step(0));
+        if (sp != nullptr) GP_TRY(run_inner(0));
         SysState* next = states + ((it + 1) & 1) * m;
         GP_HIP(solver_direction(a, next, s));
         a.state = next;
-        GP_HIP(hipMemcpyAsync(pinned + (it & 1), a.n_active, sizeof(int), hipMemcpyDeviceToHost, s));
-        GP_HIP(hipEventRecord(ev[it & 1], s));
-        h->passes += 1;
-        if (sp != nullptr) {
-            // the inner runs synchronise anyway: stop before launching another one
-            GP_HIP(hipEventSynchronize(ev[it & 1]));
-            if (pinned[it & 1] == 0) break;
-        } else if (it >= 1) {
-            GP_HIP(hipEventSynchronize(ev[(it - 1) & 1]));
-            if (pinned[(it - 1) & 1] == 0) {
-                // this iteration's launches found no running system and did nothing
-                if (h->prof) prof_drop_last(h, h->kmv_ev);
-                h->passes -= 1;
-                break;
+        ++it;
+        return GP_OK;
+    }
+
+    gp_status run() {
+        int* pinned = h->pinned + 2 * level;
+        hipEvent_t* ev = h->ev + 2 * level;
+        for (int k = 0; k <= p.max_iter; ++k) {
+            GP_TRY(step());
+            GP_HIP(hipMemcpyAsync(pinned + (k & 1), a.n_active, sizeof(int), hipMemcpyDeviceToHost, s));
+            GP_HIP(hipEventRecord(ev[k & 1], s));
+            h->passes += 1;
+            if (sp != nullptr) {
+                // the inner runs synchronise anyway: stop before launching another one
+                GP_HIP(hipEventSynchronize(ev[k & 1]));
+                if (pinned[k & 1] == 0) break;
+            } else if (k >= 1) {
+                GP_HIP(hipEventSynchronize(ev[(k - 1) & 1]));
+                if (pinned[(k - 1) & 1] == 0) {
+                    // this iteration's launches found no running system and did nothing
+                    if (h->prof) prof_drop_last(h, h->kmv_ev);
+                    h->passes -= 1;
+                    break;
+                }
             }
         }
+        return GP_OK;
     }
-    if (level == 0) h->solves += 1;
-    if (S_cg != nullptr) GP_HIP(solver_copy_s(a, S_cg, s));
+
+    gp_status end(double* S_cg) {
+        if (level == 0) h->solves += 1;
+        if (S_cg != nullptr) GP_HIP(solver_copy_s(a, S_cg, s));
+        return GP_OK;
+    }
+};
+
+// z = J^-1 e by the inner run (its last CG iterate), then Zp, e^T z and (first) d = z
+gp_status Solve::run_inner(int first) {
+    GP_HIP(launch_icg_rhs(a, Bin, first, s));
+    Solve in;
+    in.h = h;
+    in.level = level + 1;
+    in.n = n;
+    in.d = d;
+    in.m = m;
+    in.Z = Z;
+    in.kp = kp_in;
+    in.p = ip;
+    in.s = s;
+    GP_TRY(in.begin(Bin, sh.n_pad, nullptr, Stin, nullptr));
+    GP_TRY(in.run());
+    GP_TRY(in.end(Zin));
+    GP_HIP(launch_icg_finish(a, Zin, first, s));
     return GP_OK;
 }
+
+gp_status solve_core(gp_handle* h, int64_t n, int d, const float* Z, const KParams* kp,
+                     const float* B, int64_t ldb, int m, const double* S0,
+                     const ulisse_params& p, double* St, double* S_cg, ulisse_sysstat* stats,
+                     hipStream_t s, const gp_precond* pc = nullptr,
+                     const gp_shift_precond* sp = nullptr) {
+    Solve sv;
+    sv.h = h;
+    sv.n = n;
+    sv.d = d;
+    sv.m = m;
+    sv.Z = Z;
+    sv.kp = kp;
+    sv.p = p;
+    sv.pc = pc;
+    sv.sp = sp;
+    sv.s = s;
+    GP_TRY(sv.begin(B, ldb, S0, St, stats));
+    GP_TRY(sv.run());
+    return sv.end(S_cg);
+}
+
+// One stochastic gradient estimate in phases around its solve: begin() prepares Z, the
+// right-hand sides (y and the probes) and the warm starts and begins the solve; end() takes
+// the last CG iterates out and runs the fused gradient reduction.
+struct Grad {
+    gp_handle* h = nullptr;
+    gp_data X{};
+    const double* psi = nullptr;
+    const float* y = nullptr;
+    const float* R = nullptr;
+    int nr = 0, kind = 0;
+    ulisse_params p{};
+    double* S_warm = nullptr;
+    double* g = nullptr;
+    ulisse_sysstat* stats = nullptr;
+    hipStream_t s = nullptr;
+    float* Z = nullptr;
+    KParams* kp = nullptr;
+    float* Bm = nullptr;
+    double* St = nullptr;
+    Solve sv;
+
+    gp_status begin(const gp_precond* pc, const gp_shift_precond* sp) {
+        const int64_t n = X.n;
+        const int m = 1 + nr;
+        GP_TRY(prep(h, X, psi, round_up(n, kRowPad), &Z, &kp, s));
+        GP_TRY(ws(h, kSlotB, (size_t)n * m, &Bm));
+        GP_HIP(hipMemcpyAsync(Bm, y, n * sizeof(float), hipMemcpyDeviceToDevice, s));
+        if (R == nullptr) {
+            GP_HIP(launch_probes(n, nr, kind, h->seed, p.rng_stream, p.rng_counter, Bm + n, n, s,
+                                 h->dyn_step));
+        } else {
+            GP_HIP(hipMemcpyAsync(Bm + n, R, (size_t)n * nr * sizeof(float), hipMemcpyDeviceToDevice, s));
+        }
+        const double* S0 = nullptr;
+        if (S_warm != nullptr) {
+            if (R == nullptr) {
+                double* S0b;
+                GP_TRY(ws(h, kSlotS0, (size_t)n * m, &S0b));
+                GP_HIP(launch_zero(S0b, (size_t)n * m * sizeof(double), s));
+                GP_HIP(hipMemcpyAsync(S0b, S_warm, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+                S0 = S0b;
+            } else {
+                S0 = S_warm;
+            }
+        }
+        GP_TRY(ws(h, kSlotSt, (size_t)n * (m + 1), &St));
+        ulisse_params ps = p;
+        ps.two_track_first = 1;
+        sv = Solve{};
+        sv.h = h;
+        sv.n = n;
+        sv.d = X.d;
+        sv.m = m;
+        sv.Z = Z;
+        sv.kp = kp;
+        sv.p = ps;
+        sv.pc = pc;
+        sv.sp = sp;
+        sv.s = s;
+        return sv.begin(Bm, n, S0, St, stats);
+    }
+
+    // The fused reduction's work table, uploaded when the shape changes (this synchronises:
+    // done before any graph capture).
+    gp_status work_table(const DquadShape& dq, int2** work) {
+        GP_TRY(ws(h, kSlotWork, (size_t)dq.nwg, work));
+        if (h->work_npad != dq.n_pad || h->work_L != dq.chunk || h->work_ptr != (void*)*work) {
+            std::vector<int2> tab;
+            dquad_work(dq, tab);
+            GP_HIP(hipStreamSynchronize(s));
+            GP_HIP(hipMemcpy(*work, tab.data(), tab.size() * sizeof(int2), hipMemcpyHostToDevice));
+            h->work_npad = dq.n_pad;
+            h->work_L = dq.chunk;
+            h->work_ptr = *work;
+        }
+        return GP_OK;
+    }
+
+    gp_status end() {
+        const int64_t n = X.n;
+        const int d = X.d;
+        const int m = 1 + nr;
+        GP_TRY(sv.end(S_warm));
+        const float* Rp = Bm + n;
+        const DquadShape dq = dquad_shape(n, d, m);
+        float *A32, *B32;
+        double* gpart;
+        GP_TRY(ws(h, kSlotA32, (size_t)dq.n_pad * dq.mq4, &A32));
+        GP_TRY(ws(h, kSlotB32, (size_t)dq.n_pad * dq.mq4, &B32));
+        GP_TRY(ws(h, kSlotGpart, (size_t)dq.nwg * (d + 1), &gpart));
+        int2* work;
+        GP_TRY(work_table(dq, &work));
+        GP_HIP(launch_build_ab(St, Rp, n, n, nr, A32, B32, dq.n_pad, dq.mq4, s));
+        hipEvent_t t0 = prof_start(h, s);
+        GP_HIP(launch_dquad(dq, d, Z, A32, B32, kp, work, gpart, s));
+        prof_stop(h, t0, h->dq_ev, s);
+        double* dpart;
+        GP_TRY(ws(h, kSlotP2, (size_t)solver_blocks(n), &dpart));
+        GP_HIP(launch_grad_finish(St, Rp, n, n, nr, gpart, dq.nwg, d, kp, dpart, g, s));
+        return GP_OK;
+    }
+};
 
 // Bodies of the solve and gradient entry points, shared by their preconditioned forms.
 gp_status solve_entry(gp_handle* h, gp_data X, const double* psi, const float* B, int32_t m,
@@ -418,10 +669,11 @@ gp_status gp_kmv(gp_handle* h, gp_data X, const double* psi, const float* V, int
     GP_CHECK(ldv >= X.n && ldo >= X.n, "ldv and ldo must be >= n");
     GP_CHECK(prec == GP_FP32 || prec == GP_BF16_SPLIT_V || prec == GP_BF16_SPLIT_KV, "unknown precision");
     hipStream_t s = (hipStream_t)stream;
-    const KmvShape sh = kmv_shape(X.n, X.d, m, prec);
     float* Z;
     KParams* kp;
-    GP_TRY(prep(h, X, psi, sh.n_pad, &Z, &kp, s));
+    GP_TRY(prep(h, X, psi, round_up(X.n, kRowPad), &Z, &kp, s));
+    KmvShape sh;
+    GP_TRY(shape_for(h, X.n, X.d, m, prec, Z, kp, s, &sh));
     float *Vp, *part;
     GP_TRY(ws(h, kSlotVP, (size_t)sh.n_pad * sh.mp, &Vp));
     GP_TRY(ws(h, kSlotPart, (size_t)sh.split * sh.mp * sh.n_pad, &part));
@@ -553,69 +805,22 @@ gp_status grad_entry(gp_handle* h, gp_data X, const double* psi, const float* y,
     GP_CHECK(S_warm == nullptr || aligned(S_warm, 8), "S_warm misaligned");
     GP_TRY(check_precond(pc, X.n));
     GP_TRY(check_shift(sp));
-    hipStream_t s = (hipStream_t)stream;
-    const int64_t n = X.n;
-    const int d = X.d;
-    const int m = 1 + n_probes;
-    const int64_t n_pad = round_up(n, kRowPad);
-    float* Z;
-    KParams* kp;
-    GP_TRY(prep(h, X, psi, n_pad, &Z, &kp, s));
-
-    float* Bm;
-    GP_TRY(ws(h, kSlotB, (size_t)n * m, &Bm));
-    GP_HIP(hipMemcpyAsync(Bm, y, n * sizeof(float), hipMemcpyDeviceToDevice, s));
-    if (R == nullptr) {
-        GP_HIP(launch_probes(n, n_probes, probe_kind, h->seed, params->rng_stream,
-                             params->rng_counter, Bm + n, n, s));
-    } else {
-        GP_HIP(hipMemcpyAsync(Bm + n, R, (size_t)n * n_probes * sizeof(float), hipMemcpyDeviceToDevice, s));
-    }
-    const float* Rp = Bm + n;
-
-    const double* S0 = nullptr;
-    if (S_warm != nullptr) {
-        if (R == nullptr) {
-            double* S0b;
-            GP_TRY(ws(h, kSlotS0, (size_t)n * m, &S0b));
-            GP_HIP(hipMemsetAsync(S0b, 0, (size_t)n * m * sizeof(double), s));
-            GP_HIP(hipMemcpyAsync(S0b, S_warm, n * sizeof(double), hipMemcpyDeviceToDevice, s));
-            S0 = S0b;
-        } else {
-            S0 = S_warm;
-        }
-    }
-    double* St;
-    GP_TRY(ws(h, kSlotSt, (size_t)n * (m + 1), &St));
-    ulisse_params p = *params;
-    p.two_track_first = 1;
-    GP_TRY(solve_core(h, n, d, Z, kp, Bm, n, m, S0, p, St, S_warm, stats, s, pc, sp));
-
-    const DquadShape dq = dquad_shape(n, d, m);
-    float *A32, *B32;
-    double* gpart;
-    GP_TRY(ws(h, kSlotA32, (size_t)dq.n_pad * dq.mq4, &A32));
-    GP_TRY(ws(h, kSlotB32, (size_t)dq.n_pad * dq.mq4, &B32));
-    GP_TRY(ws(h, kSlotGpart, (size_t)dq.nwg * (d + 1), &gpart));
-    int2* work;
-    GP_TRY(ws(h, kSlotWork, (size_t)dq.nwg, &work));
-    if (h->work_npad != dq.n_pad || h->work_L != dq.chunk || h->work_ptr != (void*)work) {
-        std::vector<int2> tab;
-        dquad_work(dq, tab);
-        GP_HIP(hipStreamSynchronize(s));
-        GP_HIP(hipMemcpy(work, tab.data(), tab.size() * sizeof(int2), hipMemcpyHostToDevice));
-        h->work_npad = dq.n_pad;
-        h->work_L = dq.chunk;
-        h->work_ptr = work;
-    }
-    GP_HIP(launch_build_ab(St, Rp, n, n, n_probes, A32, B32, dq.n_pad, dq.mq4, s));
-    hipEvent_t t0 = prof_start(h, s);
-    GP_HIP(launch_dquad(dq, d, Z, A32, B32, kp, work, gpart, s));
-    prof_stop(h, t0, h->dq_ev, s);
-    double* dpart;
-    GP_TRY(ws(h, kSlotP2, (size_t)solver_blocks(n), &dpart));
-    GP_HIP(launch_grad_finish(St, Rp, n, n, n_probes, gpart, dq.nwg, d, kp, dpart, g, s));
-    return GP_OK;
+    Grad gr;
+    gr.h = h;
+    gr.X = X;
+    gr.psi = psi;
+    gr.y = y;
+    gr.R = R;
+    gr.nr = n_probes;
+    gr.kind = probe_kind;
+    gr.p = *params;
+    gr.S_warm = S_warm;
+    gr.g = g;
+    gr.stats = stats;
+    gr.s = (hipStream_t)stream;
+    GP_TRY(gr.begin(pc, sp));
+    GP_TRY(gr.sv.run());
+    return gr.end();
 }
 
 }  // namespace
@@ -925,6 +1130,23 @@ gp_status precond_warm_start(gp_handle* h, const float* U, int64_t ldu, int32_t 
     return GP_OK;
 }
 
+gp_status gp_autotune(gp_handle* h, int32_t enable) {
+    GP_TRY(check_handle(h));
+    h->autotune = enable != 0;
+    return GP_OK;
+}
+
+gp_status gp_autotune_split(gp_handle* h, int64_t n, int32_t d, int32_t m, gp_precision prec,
+                            int32_t* split) {
+    GP_TRY(check_handle(h));
+    GP_CHECK(split != nullptr && n >= 1 && d >= 1 && d <= kMaxD && m >= 1 && m <= kMaxSys,
+             "bad arguments");
+    const KmvShape base = kmv_shape(n, d, m, prec);
+    auto it = h->tuned.find(std::array<int64_t, 4>{base.n_pad, d, base.mp, (int64_t)prec});
+    *split = it == h->tuned.end() ? base.split : kmv_shape_target(n, d, m, prec, it->second).split;
+    return GP_OK;
+}
+
 gp_status gp_profile(gp_handle* h, int32_t enable) {
     GP_TRY(check_handle(h));
     if (enable) {
@@ -997,6 +1219,278 @@ gp_status gp_philox(uint64_t k0, uint64_t k1, uint64_t first_block, uint64_t w1,
     GP_CHECK(out != nullptr && aligned(out, 8), "out null or misaligned");
     if (nblocks == 0) return GP_OK;
     GP_HIP(launch_philox(k0, k1, first_block, w1, w2, w3, nblocks, out, (hipStream_t)stream));
+    return GP_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------------------
+// Batched SGLD over independent GPs with captured graphs.
+// ---------------------------------------------------------------------------------------
+struct gp_batch {
+    int device = 0;
+    int B = 0, nr = 0, kind = 0, period = 1, iters = 8;
+    ulisse_params params{};
+    std::vector<gp_handle*> hs;
+    std::vector<gp_batch_problem> probs;
+    std::vector<Grad> grads;
+    std::vector<hipStream_t> side;
+    std::vector<hipEvent_t> side_ev;
+    hipStream_t cap = nullptr;      // capture stream
+    hipEvent_t fork_ev = nullptr;
+    uint64_t* dyn = nullptr;        // device: step, probe step, eps (as bits)
+    uint64_t* dyn_host = nullptr;   // pinned host copy
+    int* active = nullptr;          // device: running systems over all chains
+    int* active_host = nullptr;     // pinned
+    const int** counts = nullptr;   // device array of the chains' running-system counters
+    hipGraphExec_t pre[2] = {nullptr, nullptr};  // [0] probes kept, [1] probes redrawn
+    hipGraphExec_t iter = nullptr, post = nullptr;
+    bool counts_ready = false;
+    gp_batch_stats st{};
+};
+
+namespace {
+
+hipStream_t chain_stream(gp_batch* b, int i) { return b->side[i % (int)b->side.size()]; }
+
+// Probes (when redrawn) and the start of the gradient of chain i, on its stream.
+gp_status batch_pre(gp_batch* b, int i, bool redraw) {
+    const gp_batch_problem& pr = b->probs[i];
+    Grad& gr = b->grads[i];
+    gp_handle* h = b->hs[i];
+    const int64_t n = pr.X.n;
+    hipStream_t s = chain_stream(b, i);
+    if (redraw) {
+        GP_HIP(launch_probes(n, b->nr, b->kind, h->seed, b->params.rng_stream, 0, pr.R, n, s,
+                             h->dyn_probe_step));
+        GP_HIP(launch_zero(pr.S_warm + n, (size_t)n * b->nr * sizeof(double), s));
+    }
+    gr = Grad{};
+    gr.h = h;
+    gr.X = pr.X;
+    gr.psi = pr.psi;
+    gr.y = pr.y;
+    gr.R = pr.R;
+    gr.nr = b->nr;
+    gr.kind = b->kind;
+    gr.p = b->params;
+    gr.S_warm = pr.S_warm;
+    gr.g = pr.g;
+    gr.stats = pr.stats;
+    gr.s = s;
+    return gr.begin(nullptr, nullptr);
+}
+
+// Gradient reduction and SGLD update of chain i.
+gp_status batch_post(gp_batch* b, int i) {
+    const gp_batch_problem& pr = b->probs[i];
+    gp_handle* h = b->hs[i];
+    GP_TRY(b->grads[i].end());
+    GP_HIP(launch_sgld(pr.X.d + 2, pr.psi, pr.g, pr.prior.kind, pr.prior.a, pr.prior.b, pr.M_chol,
+                       0.0, h->seed, b->params.rng_stream, 0, chain_stream(b, i), h->dyn_step,
+                       reinterpret_cast<const double*>(h->dyn_eps)));
+    return GP_OK;
+}
+
+gp_status fork(gp_batch* b, hipStream_t from) {
+    GP_HIP(hipEventRecord(b->fork_ev, from));
+    for (hipStream_t s : b->side) GP_HIP(hipStreamWaitEvent(s, b->fork_ev, 0));
+    return GP_OK;
+}
+
+gp_status join(gp_batch* b, hipStream_t into) {
+    for (size_t k = 0; k < b->side.size(); ++k) {
+        GP_HIP(hipEventRecord(b->side_ev[k], b->side[k]));
+        GP_HIP(hipStreamWaitEvent(into, b->side_ev[k], 0));
+    }
+    return GP_OK;
+}
+
+// Capture `body` (work issued on the side streams between a fork and a join) as a graph.
+template <typename F>
+gp_status capture(gp_batch* b, hipGraphExec_t* out, F body) {
+    GP_HIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+    gp_status st = fork(b, b->cap);
+    if (st == GP_OK) st = body();
+    if (st == GP_OK) st = join(b, b->cap);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(b->cap, &g);
+    if (st != GP_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    if (e != hipSuccess) return fail(GP_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
+    const hipError_t e2 = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e2 != hipSuccess) return fail(GP_EDEVICE, "graph instantiation failed: %s", hipGetErrorString(e2));
+    b->st.captures += 1;
+    return GP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void gp_batch_destroy(gp_batch* b) {
+    if (!b) return;
+    (void)hipSetDevice(b->device);
+    (void)hipDeviceSynchronize();
+    for (hipGraphExec_t g : {b->pre[0], b->pre[1], b->iter, b->post})
+        if (g) (void)hipGraphExecDestroy(g);
+    for (hipStream_t s : b->side) (void)hipStreamDestroy(s);
+    for (hipEvent_t e : b->side_ev) (void)hipEventDestroy(e);
+    if (b->fork_ev) (void)hipEventDestroy(b->fork_ev);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    if (b->dyn) (void)hipFree(b->dyn);
+    if (b->active) (void)hipFree(b->active);
+    if (b->counts) (void)hipFree(b->counts);
+    if (b->dyn_host) (void)hipHostFree(b->dyn_host);
+    if (b->active_host) (void)hipHostFree(b->active_host);
+    for (gp_handle* h : b->hs) gp_destroy(h);
+    delete b;
+}
+
+gp_status gp_batch_create(gp_batch** out, int device, uint64_t seed, int32_t B,
+                          const gp_batch_problem* problems, int32_t n_probes, int32_t probe_kind,
+                          int32_t probe_period, const ulisse_params* params,
+                          int32_t iters_per_graph, int32_t autotune, int32_t streams) {
+    GP_CHECK(out != nullptr && problems != nullptr && B >= 1, "null output, no problems or B < 1");
+    GP_TRY(check_params(params));
+    GP_CHECK(n_probes >= 1 && n_probes + 2 <= kMaxSys, "n_probes = %d outside [1, 62]", n_probes);
+    GP_CHECK(probe_kind == 0 || probe_kind == 1, "probe_kind must be 0 or 1");
+    GP_CHECK(probe_period >= 1, "probe_period must be >= 1");
+    GP_CHECK(iters_per_graph >= 2 && iters_per_graph % 2 == 0, "iters_per_graph must be even and >= 2");
+    GP_CHECK(streams >= 1 && streams <= 64, "streams must be in [1, 64]");
+    for (int i = 0; i < B; ++i) {
+        const gp_batch_problem& pr = problems[i];
+        GP_TRY(check_data(pr.X));
+        GP_CHECK(pr.y && pr.psi && pr.S_warm && pr.R && pr.g, "problem %d: y, psi, S_warm, R and g are required", i);
+        GP_CHECK(aligned(pr.y, 4) && aligned(pr.R, 4) && aligned(pr.psi, 8) && aligned(pr.S_warm, 8) &&
+                     aligned(pr.g, 8) && (pr.M_chol == nullptr || aligned(pr.M_chol, 8)),
+                 "problem %d: misaligned pointer", i);
+        GP_CHECK(pr.prior.kind >= 0 && pr.prior.kind <= 2 &&
+                     (pr.prior.kind == 0 || (pr.prior.a != nullptr && pr.prior.b != nullptr)),
+                 "problem %d: bad prior", i);
+    }
+    GP_HIP(hipSetDevice(device));
+    gp_batch* b = new gp_batch();
+    b->device = device;
+    b->B = B;
+    b->nr = n_probes;
+    b->kind = probe_kind;
+    b->period = probe_period;
+    b->iters = iters_per_graph;
+    b->params = *params;
+    b->probs.assign(problems, problems + B);
+    b->grads.resize(B);
+    auto bail = [&](gp_status st) {
+        gp_batch_destroy(b);
+        return st;
+    };
+    if (hipMalloc((void**)&b->dyn, 3 * sizeof(uint64_t)) != hipSuccess ||
+        hipMalloc((void**)&b->active, sizeof(int)) != hipSuccess ||
+        hipMalloc((void**)&b->counts, (size_t)B * sizeof(int*)) != hipSuccess ||
+        hipHostMalloc((void**)&b->dyn_host, 3 * sizeof(uint64_t), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&b->active_host, sizeof(int), hipHostMallocDefault) != hipSuccess ||
+        hipStreamCreate(&b->cap) != hipSuccess || hipEventCreateWithFlags(&b->fork_ev, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        return bail(fail(GP_ENOMEM, "batch set-up failed"));
+    }
+    const int ns = std::min(streams, B);
+    for (int k = 0; k < ns; ++k) {
+        hipStream_t s = nullptr;
+        hipEvent_t e = nullptr;
+        if (hipStreamCreate(&s) != hipSuccess || hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+            (void)hipGetLastError();
+            if (s) (void)hipStreamDestroy(s);
+            return bail(fail(GP_EDEVICE, "stream creation failed"));
+        }
+        b->side.push_back(s);
+        b->side_ev.push_back(e);
+    }
+    for (int i = 0; i < B; ++i) {
+        gp_handle* h = nullptr;
+        const gp_status st = gp_create(&h, device, seed + (uint64_t)i);
+        if (st != GP_OK) return bail(st);
+        h->autotune = autotune != 0;
+        h->dyn_step = b->dyn;
+        h->dyn_probe_step = b->dyn + 1;
+        h->dyn_eps = reinterpret_cast<const double*>(b->dyn + 2);
+        b->hs.push_back(h);
+    }
+    *out = b;
+    return GP_OK;
+}
+
+gp_status gp_batch_step(gp_batch* b, uint64_t t, double eps_t, void* stream) {
+    GP_CHECK(b != nullptr, "null batch");
+    GP_HIP(hipSetDevice(b->device));
+    hipStream_t s = (hipStream_t)stream;
+    const bool redraw = t % (uint64_t)b->period == 0;
+    // the step words: written to pinned memory, copied in stream order (the previous step
+    // has completed: this call returns only then)
+    b->dyn_host[0] = t;
+    b->dyn_host[1] = t / (uint64_t)b->period;
+    std::memcpy(&b->dyn_host[2], &eps_t, sizeof(double));
+    GP_HIP(hipMemcpyAsync(b->dyn, b->dyn_host, 3 * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+    const bool graphs = b->counts_ready;
+    if (!graphs) {
+        // eager step: sizes every workspace, tunes the shapes, uploads the work tables
+        GP_TRY(fork(b, s));
+        for (int i = 0; i < b->B; ++i) GP_TRY(batch_pre(b, i, redraw));
+        for (int i = 0; i < b->B; ++i) GP_TRY(b->grads[i].sv.run());
+        for (int i = 0; i < b->B; ++i) GP_TRY(batch_post(b, i));
+        GP_TRY(join(b, s));
+        GP_HIP(hipStreamSynchronize(s));
+        std::vector<const int*> cnt(b->B);
+        for (int i = 0; i < b->B; ++i) cnt[i] = b->grads[i].sv.a.n_active;
+        GP_HIP(hipMemcpy(b->counts, cnt.data(), (size_t)b->B * sizeof(int*), hipMemcpyHostToDevice));
+        b->counts_ready = true;
+        b->st.eager_steps += 1;
+        return GP_OK;
+    }
+    hipGraphExec_t& pre = b->pre[redraw ? 1 : 0];
+    if (pre == nullptr) {
+        GP_TRY(capture(b, &pre, [&]() -> gp_status {
+            for (int i = 0; i < b->B; ++i) GP_TRY(batch_pre(b, i, redraw));
+            return GP_OK;
+        }));
+    }
+    if (b->iter == nullptr) {
+        // the chains' solver objects as left by the set-up capture (their buffers do not
+        // change between steps); an even count returns each to its first state buffer
+        GP_TRY(capture(b, &b->iter, [&]() -> gp_status {
+            for (int k = 0; k < b->iters; ++k)
+                for (int i = 0; i < b->B; ++i) GP_TRY(b->grads[i].sv.step());
+            return GP_OK;
+        }));
+        for (int i = 0; i < b->B; ++i) b->grads[i].sv.it = 0;
+    }
+    if (b->post == nullptr) {
+        GP_TRY(capture(b, &b->post, [&]() -> gp_status {
+            for (int i = 0; i < b->B; ++i) GP_TRY(batch_post(b, i));
+            return GP_OK;
+        }));
+    }
+    GP_HIP(hipGraphLaunch(pre, s));
+    const int max_chunks = b->params.max_iter / b->iters + 2;
+    for (int c = 0; c < max_chunks; ++c) {
+        GP_HIP(hipGraphLaunch(b->iter, s));
+        GP_HIP(launch_sum_active(b->counts, b->B, b->active, s));
+        GP_HIP(hipMemcpyAsync(b->active_host, b->active, sizeof(int), hipMemcpyDeviceToHost, s));
+        GP_HIP(hipStreamSynchronize(s));
+        b->st.iteration_graphs += 1;
+        if (*b->active_host == 0) break;
+    }
+    GP_HIP(hipGraphLaunch(b->post, s));
+    GP_HIP(hipStreamSynchronize(s));
+    b->st.graph_steps += 1;
+    return GP_OK;
+}
+
+gp_status gp_batch_read_stats(const gp_batch* b, gp_batch_stats* out) {
+    GP_CHECK(b != nullptr && out != nullptr, "null argument");
+    *out = b->st;
     return GP_OK;
 }
 

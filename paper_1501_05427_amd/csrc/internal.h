@@ -25,6 +25,9 @@ struct KmvShape {
 };
 
 KmvShape kmv_shape(int64_t n, int d, int m, gp_precision prec);
+// The same with the split-K factor chosen for about target_wg workgroups (the default
+// targets 2048; the autotuner times several targets per shape).
+KmvShape kmv_shape_target(int64_t n, int d, int m, gp_precision prec, int target_wg);
 KmvShape dkmv_shape(int64_t n, int d, int m);
 
 // psi -> KParams and the scaled, padded inputs Z (n_pad x dpad(d), zero rows past n).

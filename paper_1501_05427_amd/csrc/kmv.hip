@@ -722,6 +722,10 @@ static void pick_split(KmvShape& sh, int target_wg) {
 }
 
 KmvShape kmv_shape(int64_t n, int d, int m, gp_precision prec) {
+    return kmv_shape_target(n, d, m, prec, 2048);
+}
+
+KmvShape kmv_shape_target(int64_t n, int d, int m, gp_precision prec, int target_wg) {
     (void)prec;
     KmvShape sh;
     sh.n_pad = round_up(std::max<int64_t>(n, 1), kRowPad);
@@ -734,7 +738,7 @@ KmvShape kmv_shape(int64_t n, int d, int m, gp_precision prec) {
         sh.mp = (int)round_up(m, 4);
         sh.rows_per_wg = kWG;
     }
-    pick_split(sh, 2048);
+    pick_split(sh, target_wg);
     return sh;
 }
 

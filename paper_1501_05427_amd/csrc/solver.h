@@ -58,6 +58,7 @@ struct SolverArgs {
     double q, rate, eps;
     int32_t eps_relative, max_iter, two_track, pad_;
     uint64_t seed, rng_stream, rng_counter;
+    const uint64_t* counter_dev;  // non-null: the step word of the counter is read here
     // pcm: 0 plain CG; 1 P^-1 v = tau_inv v + U (h o U^T v); 2 z from an inner CG on
     // (K + delta I) z = e.  For 1 and 2 the step lengths use rho = e^T z (partials in part3).
     int32_t pcm, pad2_;
@@ -81,8 +82,11 @@ hipError_t solver_direction(const SolverArgs& a, SysState* next, hipStream_t s);
 hipError_t solver_copy_s(const SolverArgs& a, double* out, hipStream_t s);
 hipError_t launch_pack_f64(const double* S0, int64_t n, int m, float* D, int64_t n_pad,
                            hipStream_t s);
+// step_dev / eps_dev (nullable): read the step word (and the step size) from device memory,
+// so that a captured graph can be replayed for a new step.
 hipError_t launch_probes(int64_t n, int nprobes, int kind, uint64_t k0, uint64_t k1,
-                         uint64_t step, float* R, int64_t ldr, hipStream_t s);
+                         uint64_t step, float* R, int64_t ldr, hipStream_t s,
+                         const uint64_t* step_dev = nullptr);
 hipError_t launch_philox(uint64_t k0, uint64_t k1, uint64_t first, uint64_t w1, uint64_t w2,
                          uint64_t w3, int64_t nblocks, uint64_t* out, hipStream_t s);
 hipError_t launch_build_ab(const double* St, const float* R, int64_t ldr, int64_t n,
@@ -94,7 +98,11 @@ hipError_t launch_grad_finish(const double* St, const float* R, int64_t ldr, int
                               const KParams* kp, double* dpart, double* g, hipStream_t s);
 hipError_t launch_sgld(int P, double* psi, const double* g, int prior_kind, const double* pa,
                        const double* pb, const double* L, double eps, uint64_t k0,
-                       uint64_t k1, uint64_t step, hipStream_t s);
+                       uint64_t k1, uint64_t step, hipStream_t s,
+                       const uint64_t* step_dev = nullptr, const double* eps_dev = nullptr);
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
+// out = sum of *counts[b], b < B (counts: device array of B device pointers).
+hipError_t launch_sum_active(const int* const* counts, int B, int* out, hipStream_t s);
 
 // z = P^-1 e for every active system and the partials of e^T z; `first` also sets d = z.
 int pc_chunks(int64_t n);

@@ -187,8 +187,9 @@ __global__ __launch_bounds__(kWG) void ulisse_update_kernel(SolverArgs a) {
 // u_j of track t of system c: word j of Philox stream (key (seed, stream), counter
 // (j/4, 2c + t, 2, step)), mapped to [0, 1).
 __device__ inline double ulisse_u(const SolverArgs& a, int c, int t, int j) {
+    const uint64_t step = a.counter_dev != nullptr ? *a.counter_dev : a.rng_counter;
     const u64x4 w = philox4x64_10((uint64_t)(j >> 2), (uint64_t)(2 * c + t), kPurposeUlisse,
-                                  a.rng_counter, a.seed, a.rng_stream);
+                                  step, a.seed, a.rng_stream);
     return u01_co(w.v[j & 3]);
 }
 
@@ -321,7 +322,9 @@ __global__ void pack_f64_kernel(const double* __restrict__ S0, int64_t n, int m,
 // Draws
 // ---------------------------------------------------------------------------------------
 __global__ void probes_kernel(int64_t n, int nprobes, int kind, uint64_t k0, uint64_t k1,
-                              uint64_t step, float* __restrict__ R, int64_t ldr) {
+                              uint64_t step_arg, const uint64_t* __restrict__ step_dev,
+                              float* __restrict__ R, int64_t ldr) {
+    const uint64_t step = step_dev != nullptr ? *step_dev : step_arg;
     const int64_t nblk = (n + 3) / 4;
     const int64_t total = nblk * nprobes;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
@@ -432,8 +435,11 @@ __global__ __launch_bounds__(kWG) void grad_finish_kernel(const double* __restri
 __global__ void sgld_kernel(int P, double* __restrict__ psi, const double* __restrict__ g,
                             int prior_kind, const double* __restrict__ pa,
                             const double* __restrict__ pb, const double* __restrict__ L,
-                            double eps, uint64_t k0, uint64_t k1, uint64_t step) {
+                            double eps_arg, uint64_t k0, uint64_t k1, uint64_t step_arg,
+                            const uint64_t* __restrict__ step_dev, const double* __restrict__ eps_dev) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const uint64_t step = step_dev != nullptr ? *step_dev : step_arg;
+    const double eps = eps_dev != nullptr ? *eps_dev : eps_arg;
     double v[kMaxP], xi[kMaxP + 3], t[kMaxP];
     for (int i = 0; i < P; ++i) {
         double pg = 0.0;
@@ -569,8 +575,10 @@ hipError_t launch_pack_f64(const double* S0, int64_t n, int m, float* D, int64_t
     return hipGetLastError();
 }
 hipError_t launch_probes(int64_t n, int nprobes, int kind, uint64_t k0, uint64_t k1,
-                         uint64_t step, float* R, int64_t ldr, hipStream_t s) {
-    probes_kernel<<<grid_of((n + 3) / 4 * nprobes), kWG, 0, s>>>(n, nprobes, kind, k0, k1, step, R, ldr);
+                         uint64_t step, float* R, int64_t ldr, hipStream_t s,
+                         const uint64_t* step_dev) {
+    probes_kernel<<<grid_of((n + 3) / 4 * nprobes), kWG, 0, s>>>(n, nprobes, kind, k0, k1, step, step_dev,
+                                                                   R, ldr);
     return hipGetLastError();
 }
 hipError_t launch_philox(uint64_t k0, uint64_t k1, uint64_t first, uint64_t w1, uint64_t w2,
@@ -596,8 +604,9 @@ hipError_t launch_grad_finish(const double* St, const float* R, int64_t ldr, int
 }
 hipError_t launch_sgld(int P, double* psi, const double* g, int prior_kind, const double* pa,
                        const double* pb, const double* L, double eps, uint64_t k0,
-                       uint64_t k1, uint64_t step, hipStream_t s) {
-    sgld_kernel<<<1, 64, 0, s>>>(P, psi, g, prior_kind, pa, pb, L, eps, k0, k1, step);
+                       uint64_t k1, uint64_t step, hipStream_t s, const uint64_t* step_dev,
+                       const double* eps_dev) {
+    sgld_kernel<<<1, 64, 0, s>>>(P, psi, g, prior_kind, pa, pb, L, eps, k0, k1, step, step_dev, eps_dev);
     return hipGetLastError();
 }
 
@@ -609,4 +618,35 @@ hipError_t launch_langevin_ratio(const double* G, int batch, int P, const double
     langevin_ratio_kernel<<<1, 64, 0, s>>>(G, batch, P, L, eps, ratio);
     return hipGetLastError();
 }
+}  // namespace gpk
+
+namespace gpk {
+
+// Zero fill by a kernel (a memset node recorded into a captured graph is avoided).
+__global__ void zero_kernel(uint32_t* __restrict__ p, int64_t words) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < words;
+         e += (int64_t)gridDim.x * blockDim.x)
+        p[e] = 0u;
+}
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
+    const int64_t words = (int64_t)(bytes / 4);
+    if (words == 0) return hipSuccess;
+    zero_kernel<<<grid_of(words), kWG, 0, s>>>(static_cast<uint32_t*>(p), words);
+    return hipGetLastError();
+}
+
+// out = sum over b of *counts[b] (one wave).
+__global__ void sum_active_kernel(const int* const* __restrict__ counts, int B, int* __restrict__ out) {
+    int t = 0;
+    for (int b = threadIdx.x; b < B; b += 64) t += *counts[b];
+    for (int o = 32; o >= 1; o >>= 1) t += __shfl_xor(t, o);
+    if (threadIdx.x == 0) *out = t;
+}
+
+hipError_t launch_sum_active(const int* const* counts, int B, int* out, hipStream_t s) {
+    sum_active_kernel<<<1, 64, 0, s>>>(counts, B, out);
+    return hipGetLastError();
+}
+
 }  // namespace gpk

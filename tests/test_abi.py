@@ -35,7 +35,8 @@ def test_struct_layouts_match_the_header(tmp_path):
                "ulisse_sysstat": binding.ulisse_sysstat, "gp_prior": binding.gp_prior,
                "gp_profile_stats": binding.gp_profile_stats, "gp_precond": binding.gp_precond,
                "gp_shift_precond": binding.gp_shift_precond, "sgld_schedule": binding.sgld_schedule,
-               "sgld_state": binding.sgld_state}
+               "sgld_state": binding.sgld_state, "gp_batch_problem": binding.gp_batch_problem,
+               "gp_batch_stats": binding.gp_batch_stats}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "ulisse_gp.h"', "int main(void) {"]
     for cname, cls in structs.items():
         lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')

@@ -797,3 +797,69 @@ def test_protocol_subset_map_and_preconditioner_vs_oracle(h):
     ref_M = np.linalg.inv(ref_A)
     np.testing.assert_allclose(M, ref_M, rtol=2e-2, atol=2e-2 * np.abs(ref_M).max())
     np.testing.assert_allclose(L @ L.T, M, rtol=1e-12, atol=1e-14)
+
+
+# ---------------------------------------------------------------------------------------
+# Batched SGLD (captured graphs) and the autotuner
+# ---------------------------------------------------------------------------------------
+def _batch_problems(specs, nr):
+    out = []
+    for i, (n, d) in enumerate(specs):
+        w = workloads.rff_gp(n=n, d=d, seed=100 + i, n_features=256)
+        out.append({"X": dev(w["X"]), "y": dev(w["y"]), "psi": dev(w["psi"]),
+                    "M_chol": dev(np.eye(d + 2) / np.sqrt(n)),
+                    "prior": (1, dev(np.zeros(d + 2)), dev(np.full(d + 2, 3.0)))})
+    return out
+
+
+def test_batch_reproduces_unbatched_calls():
+    # each chain of the batch must follow exactly the trajectory of the unbatched calls with
+    # the same Philox keys and counters (autotune off: identical product shapes)
+    specs = [(300, 2), (700, 4), (1500, 8), (2049, 16), (4000, 3)]
+    nr, T, period, eps = 16, 5, 2, 1e-3
+    probs = _batch_problems(specs, nr)
+    params = pb.make_params(q=1.0, rate=1.0, eps=1e-6, eps_relative=1, max_iter=2000, rng_stream=3)
+    ref = [{k: (v.clone() if torch.is_tensor(v) else v) for k, v in p.items()} for p in probs]
+    batch = pb.Batch(probs, nr, params, seed=900, probe_period=period, iters_per_graph=4,
+                     autotune=False, streams=3)
+    for t in range(T):
+        batch.step(t, eps)
+    torch.cuda.synchronize()
+    st = batch.stats()
+    assert st["eager_steps"] == 1 and st["graph_steps"] == T - 1 and st["captures"] == 4, st
+    for i, ((n, d), p) in enumerate(zip(specs, ref)):
+        hi = pb.Handle(0, seed=900 + i)
+        S_warm = torch.zeros((1 + nr, n), dtype=torch.float64, device="cuda").t()
+        R = pb.colmajor(n, nr)
+        g = torch.zeros(d + 2, dtype=torch.float64, device="cuda")
+        kind, a, b = p["prior"]
+        for t in range(T):
+            if t % period == 0:
+                pb.gp_draw_probes(hi, n, nr, pb.PROBE_GAUSSIAN, params.rng_stream, t // period, R=R)
+                S_warm[:, 1:].zero_()
+            params.rng_counter = t
+            pb.gp_stoch_grad(hi, p["X"], p["psi"], p["y"], params, R=R, S_warm=S_warm, g=g)
+            pb.sgld_step(hi, p["psi"], g, eps, rng_stream=params.rng_stream, rng_counter=t, prior_kind=kind,
+                         prior_a=a, prior_b=b, M_chol=p["M_chol"])
+        torch.cuda.synchronize()
+        ch = batch.chains[i]
+        np.testing.assert_array_equal(ch["psi"].cpu().numpy(), p["psi"].cpu().numpy(), err_msg=f"chain {i}")
+        np.testing.assert_array_equal(ch["g"].cpu().numpy(), g.cpu().numpy(), err_msg=f"chain {i}")
+        np.testing.assert_array_equal(ch["R"].cpu().numpy(), R.cpu().numpy(), err_msg=f"chain {i}")
+    batch.close()
+
+
+def test_autotuned_products_match_oracle():
+    h2 = pb.Handle(0, seed=5)
+    pb.gp_autotune(h2, 1)
+    for n, d, m in [(3000, 8, 32), (2049, 16, 17), (5000, 2, 5)]:
+        X, psi = problem(n, d, seed=n + d)
+        V = np.random.default_rng(m).standard_normal((n, m)).astype(np.float32)
+        out = pb.gp_kmv(h2, dev(X), dev(psi), colm(V))
+        out2 = pb.gp_kmv(h2, dev(X), dev(psi), colm(V))  # the cached shape
+        torch.cuda.synchronize()
+        ref = ogp.kmv(X, psi, V)
+        assert colwise_rel(out.cpu().numpy(), ref).max() <= 1e-5
+        assert colwise_rel(out2.cpu().numpy(), ref).max() <= 1e-5
+        split = pb.gp_autotune_split(h2, n, d, m)
+        assert 1 <= split <= 64

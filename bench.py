@@ -355,9 +355,11 @@ def batched_bench(args, pb):
                         "ms_per_step": 1e3 * el_u / args.batch_steps}
     print(json.dumps({"unbatched_done": out["unbatched"]}), file=sys.stderr, flush=True)
     del hs
-    for mode, tune in (("batched_graphs", False), ("batched_graphs_autotuned", True)):
+    for mode, tune, prec in (("batched_graphs", False, pb.GP_FP32), ("batched_graphs_autotuned", True, pb.GP_FP32),
+                             ("batched_graphs_autotuned_bf16_split_kv", True, pb.GP_BF16_SPLIT_KV)):
         for i, p in enumerate(probs):
             p["psi"].copy_(psi0[i])
+        params.prec = prec
         batch = pb.Batch(probs, nr, params, seed=7000, probe_period=PROBE_PERIOD, iters_per_graph=8,
                          autotune=tune, streams=8)
         for t in range(args.warmup):
@@ -374,8 +376,49 @@ def batched_bench(args, pb):
         batch.close()
         print(json.dumps({mode: out[mode]}), file=sys.stderr, flush=True)
     out["steps"] = args.batch_steps
-    out["speedup_batched_vs_unbatched"] = out["batched_graphs_autotuned"]["grad_estimates_per_s"] / \
-        out["unbatched"]["grad_estimates_per_s"]
+    # learned preconditioner per GP (basis at the chain's start, 128 Galerkin pairs, 1000 Adam
+    # steps, all in the library's kernels; set-up untimed) + BF16 split-K+V products
+    t_setup = time.perf_counter()
+    hs_setup = pb.Handle(0, seed=11)
+    k, H = 64, 256
+    for i, p in enumerate(probs):
+        p["psi"].copy_(psi0[i])
+        d = p["X"].shape[1]
+        U, _ = pb.precond_build_basis(hs_setup, p["X"], p["psi"], k)
+        rr = np.random.default_rng(1000 + i)
+        psis = torch.from_numpy(psi0[i].cpu().numpy() + LEARN_JITTER * rr.standard_normal((128, d + 2))).cuda()
+        Tg = pb.precond_targets(hs_setup, p["X"], p["y"], U, psis)
+        I_, O_ = d + 2, 2 * k + 1
+        prm = torch.zeros(pb.precond_mlp_size(I_, H, O_), dtype=torch.float32, device="cuda")
+        pb.precond_mlp_init(hs_setup, prm, I_, H, O_, psis, Tg, seed=5)
+        adam = torch.zeros(2 * pb.mlp_layout(I_, H, O_)["trainable"], dtype=torch.float32, device="cuda")
+        pb.precond_mlp_train(hs_setup, prm, adam, I_, H, O_, psis, Tg, 1000, 0, 2e-3)
+        p["learned"] = {"mlp": prm, "hidden": H, "U": U,
+                        "coef": torch.zeros(k + 1, dtype=torch.float64, device="cuda")}
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t_setup
+    mode = "batched_graphs_autotuned_learned_bf16_split_kv"
+    params.prec = pb.GP_BF16_SPLIT_KV
+    batch = pb.Batch(probs, nr, params, seed=7000, probe_period=PROBE_PERIOD, iters_per_graph=8,
+                     autotune=True, streams=8)
+    for t in range(args.warmup):
+        batch.step(t, eps_t)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for t in range(args.warmup, args.warmup + args.batch_steps):
+        batch.step(t, eps_t)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    out[mode] = {"grad_estimates_per_s": B * args.batch_steps / el, "ms_per_step": 1e3 * el / args.batch_steps,
+                 "stats": batch.stats(), "setup_s": t_setup, "rank": k, "hidden": H,
+                 "psi_finite": bool(all(torch.isfinite(p["psi"]).all().item() for p in probs))}
+    batch.close()
+    print(json.dumps({mode: out[mode]}), file=sys.stderr, flush=True)
+    params.prec = pb.GP_FP32
+    u = out["unbatched"]["grad_estimates_per_s"]
+    out["speedup_vs_unbatched"] = {m_: out[m_]["grad_estimates_per_s"] / u for m_ in
+                                   ("batched_graphs", "batched_graphs_autotuned",
+                                    "batched_graphs_autotuned_bf16_split_kv", mode)}
     print(json.dumps({"batched": out}), flush=True)
 
 
@@ -416,8 +459,8 @@ def main():
     if args.learned_steps is None:
         args.learned_steps = args.steps
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(its kernels run one GPU's share of the work; the rows would shard across GPUs)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -351,8 +351,9 @@ gp_status precond_warm_start(gp_handle* h, const float* U, int64_t ldu, int32_t 
  * at the same address, for the batch's lifetime: X (n x d, ld ldx), y (n), psi (d + 2,
  * in/out), S_warm (n x (1 + n_probes) FP64, ld n, zero at the start), R (n x n_probes FP32,
  * ld n; the batch writes it), g (d + 2, out), stats (1 + n_probes entries, nullable),
- * M_chol (nullable = I), prior as for sgld_step.  iters_per_graph: even, >= 2.  The shifted
- * and learned preconditioners are not available in a batch.
+ * M_chol (nullable = I), prior as for sgld_step.  iters_per_graph: even, >= 2.  With mlp
+ * set, the chain's solves run over the learned preconditioner (gp_stoch_grad_pc); the
+ * shifted preconditioner is not available in a batch.
  */
 typedef struct {
     gp_data X;
@@ -364,6 +365,16 @@ typedef struct {
     ulisse_sysstat* stats;
     const double* M_chol;
     gp_prior prior;
+    /* Learned preconditioner (optional, mlp = NULL for none): a network trained by
+     * precond_mlp_train for this GP (in = d + 2, hidden, out = 2k + 1), the basis U of
+     * precond_build_basis (n x k, ld ldu) and coef (k + 1 FP64, written by the batch every
+     * step from the network at the chain's psi, as precond_from_mlp does). */
+    const float* mlp;
+    int32_t mlp_hidden;
+    int32_t k;
+    const float* U;
+    int64_t ldu;
+    double* coef;
 } gp_batch_problem;
 
 typedef struct gp_batch gp_batch;

@@ -72,7 +72,9 @@ class sgld_state(Structure):
 
 class gp_batch_problem(Structure):
     _fields_ = [("X", gp_data), ("y", c_void_p), ("psi", c_void_p), ("S_warm", c_void_p), ("R", c_void_p),
-                ("g", c_void_p), ("stats", c_void_p), ("M_chol", c_void_p), ("prior", gp_prior)]
+                ("g", c_void_p), ("stats", c_void_p), ("M_chol", c_void_p), ("prior", gp_prior),
+                ("mlp", c_void_p), ("mlp_hidden", c_int32), ("k", c_int32), ("U", c_void_p), ("ldu", c_int64),
+                ("coef", c_void_p)]
 
 
 class gp_batch_stats(Structure):
@@ -617,8 +619,18 @@ class Batch:
                      "M_chol": M, "a": a, "b": b}
             self.chains.append(chain)
             addr = lambda t: 0 if t is None else t.data_ptr()
-            descs[i] = gp_batch_problem(_data(X), addr(y), addr(psi), addr(S_warm), addr(R), addr(g),
-                                        addr(st), addr(M), gp_prior(int(kind), 0, addr(a), addr(b)))
+            lr = pr.get("learned")
+            if lr is not None:
+                # keys: mlp (trained parameters), hidden, U (basis, n x k column-major), coef
+                # (k + 1 FP64, rewritten every step)
+                chain["learned"] = lr
+                descs[i] = gp_batch_problem(_data(X), addr(y), addr(psi), addr(S_warm), addr(R), addr(g),
+                                            addr(st), addr(M), gp_prior(int(kind), 0, addr(a), addr(b)),
+                                            addr(lr["mlp"]), int(lr["hidden"]), lr["U"].shape[1],
+                                            addr(lr["U"]), _ld(lr["U"], n), addr(lr["coef"]))
+            else:
+                descs[i] = gp_batch_problem(_data(X), addr(y), addr(psi), addr(S_warm), addr(R), addr(g),
+                                            addr(st), addr(M), gp_prior(int(kind), 0, addr(a), addr(b)))
         self.params = params
         ptr = c_void_p()
         _check(lib().gp_batch_create(ctypes.byref(ptr), device, seed, len(problems), descs, n_probes,

@@ -1234,6 +1234,7 @@ struct gp_batch {
     std::vector<gp_handle*> hs;
     std::vector<gp_batch_problem> probs;
     std::vector<Grad> grads;
+    std::vector<gp_precond> pcs;  // learned preconditioner of each chain (k = 0: none)
     std::vector<hipStream_t> side;
     std::vector<hipEvent_t> side_ev;
     hipStream_t cap = nullptr;      // capture stream
@@ -1278,7 +1279,17 @@ gp_status batch_pre(gp_batch* b, int i, bool redraw) {
     gr.g = pr.g;
     gr.stats = pr.stats;
     gr.s = s;
-    return gr.begin(nullptr, nullptr);
+    const gp_precond* pc = nullptr;
+    if (pr.mlp != nullptr) {
+        // the network at the chain's psi -> the preconditioner's coefficients
+        const MlpLayout L = mlp_layout(pr.X.d + 2, pr.mlp_hidden, 2 * pr.k + 1);
+        MlpWork w;
+        GP_TRY(mlp_work(h, L, 1, &w));
+        GP_HIP(launch_mlp_forward(pr.mlp, L, pr.psi, 1, w.xs, w.a1, w.a2, w.y, 1, s));
+        GP_HIP(launch_mlp_to_precond(w.y, L, pr.k, pr.mlp, pr.coef, nullptr, s));
+        pc = &b->pcs[i];
+    }
+    return gr.begin(pc, nullptr);
 }
 
 // Gradient reduction and SGLD update of chain i.
@@ -1371,6 +1382,13 @@ gp_status gp_batch_create(gp_batch** out, int device, uint64_t seed, int32_t B,
         GP_CHECK(pr.prior.kind >= 0 && pr.prior.kind <= 2 &&
                      (pr.prior.kind == 0 || (pr.prior.a != nullptr && pr.prior.b != nullptr)),
                  "problem %d: bad prior", i);
+        if (pr.mlp != nullptr) {
+            GP_TRY(check_k(pr.k));
+            GP_TRY(check_mlp(pr.X.d + 2, pr.mlp_hidden, 2 * pr.k + 1));
+            GP_CHECK(pr.U != nullptr && aligned(pr.U, 4) && pr.ldu >= pr.X.n && pr.coef != nullptr &&
+                         aligned(pr.coef, 8) && aligned(pr.mlp, 4),
+                     "problem %d: learned preconditioner needs U (ld >= n) and coef", i);
+        }
     }
     GP_HIP(hipSetDevice(device));
     gp_batch* b = new gp_batch();
@@ -1383,6 +1401,10 @@ gp_status gp_batch_create(gp_batch** out, int device, uint64_t seed, int32_t B,
     b->params = *params;
     b->probs.assign(problems, problems + B);
     b->grads.resize(B);
+    b->pcs.resize(B);
+    for (int i = 0; i < B; ++i)
+        if (problems[i].mlp != nullptr)
+            b->pcs[i] = gp_precond{problems[i].U, problems[i].ldu, problems[i].k, 0, problems[i].coef};
     auto bail = [&](gp_status st) {
         gp_batch_destroy(b);
         return st;

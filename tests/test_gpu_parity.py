@@ -863,3 +863,57 @@ def test_autotuned_products_match_oracle():
         assert colwise_rel(out2.cpu().numpy(), ref).max() <= 1e-5
         split = pb.gp_autotune_split(h2, n, d, m)
         assert 1 <= split <= 64
+
+
+def test_batch_learned_bf16_reproduces_unbatched_calls():
+    # chains with their own basis and trained network, BF16 split-K+V products: the batch
+    # evaluates the network at each chain's psi inside its captured set-up graph
+    specs = [(1500, 2), (2500, 4), (3000, 8)]
+    nr, T, period, eps, k, H = 16, 4, 2, 1e-3, 16, 64
+    probs = _batch_problems(specs, nr)
+    hs = pb.Handle(0, seed=1)
+    for i, p in enumerate(probs):
+        d = p["X"].shape[1]
+        U, _ = pb.precond_build_basis(hs, p["X"], p["psi"], k)
+        psis = p["psi"][None, :] + 0.03 * torch.from_numpy(
+            np.random.default_rng(i).standard_normal((32, d + 2))).cuda()
+        Tg = pb.precond_targets(hs, p["X"], p["y"], U, psis)
+        I, O = d + 2, 2 * k + 1
+        prm = torch.zeros(pb.precond_mlp_size(I, H, O), dtype=torch.float32, device="cuda")
+        pb.precond_mlp_init(hs, prm, I, H, O, psis, Tg, seed=3)
+        adam = torch.zeros(2 * pb.mlp_layout(I, H, O)["trainable"], dtype=torch.float32, device="cuda")
+        pb.precond_mlp_train(hs, prm, adam, I, H, O, psis, Tg, 200, 0, 2e-3)
+        p["learned"] = {"mlp": prm, "hidden": H, "U": U,
+                        "coef": torch.zeros(k + 1, dtype=torch.float64, device="cuda")}
+    torch.cuda.synchronize()
+    params = pb.make_params(q=1.0, rate=1.0, eps=1e-6, eps_relative=1, max_iter=2000, rng_stream=3)
+    params.prec = pb.GP_BF16_SPLIT_KV
+    psi0 = [p["psi"].clone() for p in probs]
+    batch = pb.Batch(probs, nr, params, seed=900, probe_period=period, iters_per_graph=4,
+                     autotune=False, streams=2)
+    for t in range(T):
+        batch.step(t, eps)
+    torch.cuda.synchronize()
+    for i, ((n, d), p) in enumerate(zip(specs, probs)):
+        hi = pb.Handle(0, seed=900 + i)
+        psi = psi0[i]
+        S_warm = torch.zeros((1 + nr, n), dtype=torch.float64, device="cuda").t()
+        R = pb.colmajor(n, nr)
+        g = torch.zeros(d + 2, dtype=torch.float64, device="cuda")
+        coef = torch.zeros(k + 1, dtype=torch.float64, device="cuda")
+        pc = pb.make_precond(p["learned"]["U"], coef)
+        kind, a, b = p["prior"]
+        for t in range(T):
+            if t % period == 0:
+                pb.gp_draw_probes(hi, n, nr, pb.PROBE_GAUSSIAN, params.rng_stream, t // period, R=R)
+                S_warm[:, 1:].zero_()
+            params.rng_counter = t
+            pb.precond_from_mlp(hi, p["learned"]["mlp"], d + 2, H, 2 * k + 1, psi, k, coef=coef)
+            pb.gp_stoch_grad_pc(hi, p["X"], psi, p["y"], params, pc, R=R, S_warm=S_warm, g=g)
+            pb.sgld_step(hi, psi, g, eps, rng_stream=params.rng_stream, rng_counter=t, prior_kind=kind,
+                         prior_a=a, prior_b=b, M_chol=p["M_chol"])
+        torch.cuda.synchronize()
+        ch = batch.chains[i]
+        np.testing.assert_array_equal(ch["psi"].cpu().numpy(), psi.cpu().numpy(), err_msg=f"chain {i}")
+        np.testing.assert_array_equal(ch["g"].cpu().numpy(), g.cpu().numpy(), err_msg=f"chain {i}")
+    batch.close()

@@ -252,7 +252,22 @@ def solver_study(args, pb, h):
         s_ref = St[:, 0].clone()
         row = {"lambda": lam, "kappa": kappa, "cg_iters": cg_stats["iters"],
                "cg_flags": cg_stats["flags"], "solution_rms": float(torch.sqrt(torch.mean(s_ref ** 2))),
-               "settings": []}
+               "settings": [], "shifted_pcg": []}
+        # PCG with J = K + delta I (Sec. 3.3): outer iterations and all products (outer and
+        # inner) to the same convergence as CG, for a few shifts and inner tolerances
+        for rel_delta in (1.0, 10.0, 100.0):
+            for eps_in in (1e-1, 1e-2):
+                sp = pb.make_shift_precond(rel_delta * lam, eps_in, 5000)
+                pb.gp_profile(h, 1)
+                Ssp, stsp = pb.ulisse_solve_shift_pc(h, X, psi, Y[:, :1], conv, sp)
+                prs = pb.gp_profile_read(h)
+                pb.gp_profile(h, 0)
+                ss_ = pb.decode_stats(stsp)[0]
+                row["shifted_pcg"].append({"delta_over_lambda": rel_delta, "eps_inner": eps_in,
+                                           "outer_iters": ss_["iters"], "flags": ss_["flags"],
+                                           "total_products": prs["kmv_passes"],
+                                           "rel_diff_to_cg": float(torch.linalg.vector_norm(Ssp[:, 0] - s_ref)
+                                                                   / torch.linalg.vector_norm(s_ref))})
         # reference gradient: converged solves, averaged over batches of NPROBES probes
         gs = []
         for b in range(args.study_ref_batches):
@@ -646,6 +661,7 @@ def main():
             "grad_estimates_per_s": args.learned_steps / el_l,
             "kmv_passes_per_estimate": pr_l["kmv_passes"] / args.learned_steps,
             "kmv_avg_launch_ms": pr_l["kmv_ms"] / max(1, pr_l["kmv_launches"]),
+            "dquad_avg_ms": pr_l["dquad_ms"] / max(1, pr_l["dquad_launches"]),
             "steps": args.learned_steps,
             "vs_plain_fp32": (args.learned_steps / el_l) / value_plain,
             "fresh_probes_every_step": None if el_lf is None else {
@@ -699,6 +715,7 @@ def main():
             "grad_estimates_per_s": args.bf16_steps / el_bf16,
             "kmv_passes_per_estimate": prof_bf16["kmv_passes"] / args.bf16_steps,
             "kmv_avg_launch_ms": prof_bf16["kmv_ms"] / max(1, prof_bf16["kmv_launches"]),
+            "dquad_avg_ms": prof_bf16["dquad_ms"] / max(1, prof_bf16["dquad_launches"]),
             "steps": args.bf16_steps},
         "learned_bf16": learned,
         "dquad_avg_ms": dq_avg_ms,

@@ -99,7 +99,9 @@ typedef struct {
     int32_t reserved;
     uint64_t rng_stream;    /* second Philox key word                                       */
     uint64_t rng_counter;   /* step word of the Philox counter                              */
-    gp_precision prec;      /* arithmetic of the products K d                               */
+    gp_precision prec;      /* arithmetic of the products K d; in the BF16 modes the G tiles
+                               of the gradient reduction (gp_stoch_grad*) also come from
+                               split BF16 (hi + lo) operands                               */
 } ulisse_params;
 
 /* Preconditioner for the CG iterations under ULISSE (the preconditioned variant of

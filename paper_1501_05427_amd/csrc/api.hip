@@ -49,7 +49,8 @@ enum Slot {
     kSlotA32, kSlotB32, kSlotGpart, kSlotWork, kSlotVH, kSlotVL, kSlotGbatch, kSlotGvec,
     kSlotRatio, kSlotRunStats, kSlotZp, kSlotUtv, kSlotHW, kSlotP3, kSlotY0, kSlotY1,
     kSlotY2, kSlotGram, kSlotGpart2, kSlotSmall, kSlotMlp, kSlotIcgB, kSlotIcgZ, kSlotIcgSt,
-    kSlotIcgKP, kSlotTuneV, kSlotTunePart, kSlotTuneVH, kSlotTuneVL, kNumSlots
+    kSlotIcgKP, kSlotTuneV, kSlotTunePart, kSlotTuneVH, kSlotTuneVL, kSlotAH, kSlotAL, kSlotBH,
+    kSlotBL, kNumSlots
 };
 // Solves nest one level (the inner CG of the shifted preconditioner): the inner solve's
 // buffers live in a second set of slots, offset by kNumSlots.
@@ -587,17 +588,30 @@ struct Grad {
         GP_TRY(sv.end(S_warm));
         const float* Rp = Bm + n;
         const DquadShape dq = dquad_shape(n, d, m);
-        float *A32, *B32;
         double* gpart;
-        GP_TRY(ws(h, kSlotA32, (size_t)dq.n_pad * dq.mq4, &A32));
-        GP_TRY(ws(h, kSlotB32, (size_t)dq.n_pad * dq.mq4, &B32));
         GP_TRY(ws(h, kSlotGpart, (size_t)dq.nwg * (d + 1), &gpart));
         int2* work;
         GP_TRY(work_table(dq, &work));
-        GP_HIP(launch_build_ab(St, Rp, n, n, nr, A32, B32, dq.n_pad, dq.mq4, s));
-        hipEvent_t t0 = prof_start(h, s);
-        GP_HIP(launch_dquad(dq, d, Z, A32, B32, kp, work, gpart, s));
-        prof_stop(h, t0, h->dq_ev, s);
+        if (sv.b16) {
+            // BF16 product modes: the G tiles from split BF16 operands as well
+            uint16_t *AH, *AL, *BH, *BL;
+            GP_TRY(ws(h, kSlotAH, (size_t)dq.n_pad * dq.mqb, &AH));
+            GP_TRY(ws(h, kSlotAL, (size_t)dq.n_pad * dq.mqb, &AL));
+            GP_TRY(ws(h, kSlotBH, (size_t)dq.n_pad * dq.mqb, &BH));
+            GP_TRY(ws(h, kSlotBL, (size_t)dq.n_pad * dq.mqb, &BL));
+            GP_HIP(launch_build_ab_bf16(St, Rp, n, n, nr, AH, AL, BH, BL, dq.n_pad, dq.mqb, s));
+            hipEvent_t t0 = prof_start(h, s);
+            GP_HIP(launch_dquad_bf16(dq, d, Z, AH, AL, BH, BL, kp, work, gpart, s));
+            prof_stop(h, t0, h->dq_ev, s);
+        } else {
+            float *A32, *B32;
+            GP_TRY(ws(h, kSlotA32, (size_t)dq.n_pad * dq.mq4, &A32));
+            GP_TRY(ws(h, kSlotB32, (size_t)dq.n_pad * dq.mq4, &B32));
+            GP_HIP(launch_build_ab(St, Rp, n, n, nr, A32, B32, dq.n_pad, dq.mq4, s));
+            hipEvent_t t0 = prof_start(h, s);
+            GP_HIP(launch_dquad(dq, d, Z, A32, B32, kp, work, gpart, s));
+            prof_stop(h, t0, h->dq_ev, s);
+        }
         double* dpart;
         GP_TRY(ws(h, kSlotP2, (size_t)solver_blocks(n), &dpart));
         GP_HIP(launch_grad_finish(St, Rp, n, n, nr, gpart, dq.nwg, d, kp, dpart, g, s));

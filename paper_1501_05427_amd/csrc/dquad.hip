@@ -155,17 +155,26 @@ __global__ __launch_bounds__(kWG) void dquad_sym_kernel(
             const int jr = jt * 16 + col;  // this lane's column of the G tile
             float bJ[MQ];
             load_op<MQ>(bs[buf] + jr * ST + q * MQ, bJ);
-            floatx4 G = {0.f, 0.f, 0.f, 0.f};
+            // two independent accumulator chains per product (even and odd steps), so that
+            // consecutive MFMAs do not wait on each other's results
+            floatx4 G = {0.f, 0.f, 0.f, 0.f}, G1 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int t = 0; t < MQ; ++t) G = __builtin_amdgcn_mfma_f32_16x16x4f32(aI[t], bJ[t], G, 0, 0, 0);
+            for (int t = 0; t < MQ; t += 2) {
+                G = __builtin_amdgcn_mfma_f32_16x16x4f32(aI[t], bJ[t], G, 0, 0, 0);
+                G1 = __builtin_amdgcn_mfma_f32_16x16x4f32(aI[t + 1], bJ[t + 1], G1, 0, 0, 0);
+            }
             if (J > I) {
                 float aJ[MQ];
                 load_op<MQ>(as[buf] + jr * ST + q * MQ, aJ);
-                floatx4 H = {0.f, 0.f, 0.f, 0.f};
+                floatx4 H = {0.f, 0.f, 0.f, 0.f}, H1 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-                for (int t = 0; t < MQ; ++t) H = __builtin_amdgcn_mfma_f32_16x16x4f32(bI[t], aJ[t], H, 0, 0, 0);
-                G += H;
+                for (int t = 0; t < MQ; t += 2) {
+                    H = __builtin_amdgcn_mfma_f32_16x16x4f32(bI[t], aJ[t], H, 0, 0, 0);
+                    H1 = __builtin_amdgcn_mfma_f32_16x16x4f32(bI[t + 1], aJ[t + 1], H1, 0, 0, 0);
+                }
+                G1 += H + H1;
             }
+            G += G1;
             float zj[D];
             load_row_q<D>(zsb + jr * DP, zj);
 #pragma unroll
@@ -206,11 +215,176 @@ __global__ __launch_bounds__(kWG) void dquad_sym_kernel(
     }
 }
 
+
+// ---------------------------------------------------------------------------------------
+// BF16 form (the BF16 product modes): the G tiles come from operands split into BF16
+// halves, G = A_hi B_hi^T + A_hi B_lo^T + A_lo B_hi^T (the lo x lo term, about 2^-18 of
+// |A||B|, is dropped), by v_mfma_f32_16x16x32_bf16 with FP32 accumulation.  A lane's
+// operand is 8 consecutive columns of one row, so the operands are row-major (stride
+// MB = 32 KB bf16).  Kernel entries, squared differences and accumulation are those of
+// dquad_sym_kernel.
+// ---------------------------------------------------------------------------------------
+typedef __bf16 dq_bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned int dq_uintx4 __attribute__((ext_vector_type(4)));
+
+template <int D, int KB>
+__global__ __launch_bounds__(kWG) void dquad_sym_bf16_kernel(
+    const float* __restrict__ Z, const uint16_t* __restrict__ AH, const uint16_t* __restrict__ AL,
+    const uint16_t* __restrict__ BH, const uint16_t* __restrict__ BL, double* __restrict__ gpart,
+    int64_t n_pad, const int2* __restrict__ work, int L, const KParams* __restrict__ kp) {
+    constexpr int DP = (D + 3) & ~3;
+    constexpr int MB = 32 * KB;           // operand columns
+    constexpr int SB = MB + 8;            // LDS row stride (bf16), 16-byte multiple
+    constexpr int NZ4 = kTile * DP / 4;   // 16-byte loads of the Z tile
+    constexpr int NO = kTile * MB / 8;    // 16-byte loads of one operand tile
+    constexpr int NL = (NZ4 + 4 * NO + kWG - 1) / kWG;
+    __shared__ dq_uintx4 zs[2][NZ4];
+    __shared__ __attribute__((aligned(16))) uint16_t ops[2][4][kTile * SB];  // AH, AL, BH, BL
+    __shared__ double red[4][D + 1];
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int q = lane >> 4, col = lane & 15;
+    const int2 wk = work[blockIdx.x];
+    const int64_t tiles = n_pad / kTile;
+    const int64_t row0 = (int64_t)wk.x * kTile + wave * 16;
+    const int64_t I = row0 / 16;
+    const int64_t jb = (int64_t)wk.y * kTile;
+    const int64_t je = min((int64_t)(wk.y + L), tiles) * kTile;
+    const float negc0 = -kp->c0;
+
+    dq_bf16x8 aIh[KB], aIl[KB], bIh[KB], bIl[KB];
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) {
+        const int64_t o = (row0 + col) * MB + 32 * kb + 8 * q;
+        aIh[kb] = __builtin_bit_cast(dq_bf16x8, *reinterpret_cast<const dq_uintx4*>(AH + o));
+        aIl[kb] = __builtin_bit_cast(dq_bf16x8, *reinterpret_cast<const dq_uintx4*>(AL + o));
+        bIh[kb] = __builtin_bit_cast(dq_bf16x8, *reinterpret_cast<const dq_uintx4*>(BH + o));
+        bIl[kb] = __builtin_bit_cast(dq_bf16x8, *reinterpret_cast<const dq_uintx4*>(BL + o));
+    }
+    float zi[4][D];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) load_row_q<D>(Z + (row0 + 4 * q + u) * DP, zi[u]);
+
+    float gacc[D + 1];
+    double gsum[D + 1];
+#pragma unroll
+    for (int p = 0; p <= D; ++p) {
+        gacc[p] = 0.f;
+        gsum[p] = 0.0;
+    }
+
+    auto load = [&](int64_t j0, dq_uintx4(&buf)[NL]) {
+#pragma unroll
+        for (int t = 0; t < NL; ++t) {
+            const int idx = threadIdx.x + t * kWG;
+            if (idx < NZ4) {
+                buf[t] = reinterpret_cast<const dq_uintx4*>(Z + j0 * DP)[idx];
+            } else if (idx < NZ4 + 4 * NO) {
+                const int o = idx - NZ4;
+                const int a = o / NO, v = o % NO;
+                const int row = v / (MB / 8), c8 = (v % (MB / 8)) * 8;
+                const uint16_t* src = a == 0 ? AH : a == 1 ? AL : a == 2 ? BH : BL;
+                buf[t] = *reinterpret_cast<const dq_uintx4*>(src + (j0 + row) * MB + c8);
+            }
+        }
+    };
+    auto store = [&](int b, const dq_uintx4(&buf)[NL]) {
+#pragma unroll
+        for (int t = 0; t < NL; ++t) {
+            const int idx = threadIdx.x + t * kWG;
+            if (idx < NZ4) {
+                zs[b][idx] = buf[t];
+            } else if (idx < NZ4 + 4 * NO) {
+                const int o = idx - NZ4;
+                const int a = o / NO, v = o % NO;
+                const int row = v / (MB / 8), c8 = (v % (MB / 8)) * 8;
+                *reinterpret_cast<dq_uintx4*>(&ops[b][a][row * SB + c8]) = buf[t];
+            }
+        }
+    };
+
+    dq_uintx4 pre[NL];
+    load(jb, pre);
+    store(0, pre);
+    __syncthreads();
+    int buf = 0;
+    for (int64_t j0 = jb; j0 < je; j0 += kTile) {
+        const bool more = j0 + kTile < je;
+        if (more) load(j0 + kTile, pre);
+        const float* zsb = reinterpret_cast<const float*>(zs[buf]);
+#pragma unroll 1
+        for (int jt = 0; jt < kTile / 16; ++jt) {
+            const int64_t J = j0 / 16 + jt;
+            if (J < I) continue;  // lower triangle: covered by the transposed tile
+            const int jr = jt * 16 + col;
+            floatx4 G = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kb = 0; kb < KB; ++kb) {
+                const int o = jr * SB + 32 * kb + 8 * q;
+                const dq_bf16x8 bh = __builtin_bit_cast(dq_bf16x8, *reinterpret_cast<const dq_uintx4*>(&ops[buf][2][o]));
+                const dq_bf16x8 bl = __builtin_bit_cast(dq_bf16x8, *reinterpret_cast<const dq_uintx4*>(&ops[buf][3][o]));
+                G = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aIh[kb], bh, G, 0, 0, 0);
+                G = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aIh[kb], bl, G, 0, 0, 0);
+                G = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aIl[kb], bh, G, 0, 0, 0);
+            }
+            if (J > I) {
+                floatx4 H = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int kb = 0; kb < KB; ++kb) {
+                    const int o = jr * SB + 32 * kb + 8 * q;
+                    const dq_bf16x8 ah = __builtin_bit_cast(dq_bf16x8, *reinterpret_cast<const dq_uintx4*>(&ops[buf][0][o]));
+                    const dq_bf16x8 al = __builtin_bit_cast(dq_bf16x8, *reinterpret_cast<const dq_uintx4*>(&ops[buf][1][o]));
+                    H = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bIh[kb], ah, H, 0, 0, 0);
+                    H = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bIh[kb], al, H, 0, 0, 0);
+                    H = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bIl[kb], ah, H, 0, 0, 0);
+                }
+                G += H;
+            }
+            float zj[D];
+            load_row_q<D>(zsb + jr * DP, zj);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                float sq[D];
+                float a = negc0;
+#pragma unroll
+                for (int k = 0; k < D; ++k) {
+                    const float t = zi[u][k] - zj[k];
+                    sq[k] = t * t;
+                    a += sq[k];
+                }
+                const float w = __builtin_amdgcn_exp2f(-a) * G[u];
+                gacc[0] += w;
+#pragma unroll
+                for (int k = 0; k < D; ++k) gacc[k + 1] = __builtin_fmaf(w, sq[k], gacc[k + 1]);
+            }
+        }
+#pragma unroll
+        for (int p = 0; p <= D; ++p) {
+            gsum[p] += (double)gacc[p];
+            gacc[p] = 0.f;
+        }
+        if (more) store(buf ^ 1, pre);
+        __syncthreads();
+        buf ^= 1;
+    }
+#pragma unroll
+    for (int p = 0; p <= D; ++p) {
+        const double v = wave_sum(gsum[p]);
+        if (lane == 0) red[wave][p] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x <= D) {
+        const int p = threadIdx.x;
+        gpart[(int64_t)p * gridDim.x + blockIdx.x] = (red[0][p] + red[1][p]) + (red[2][p] + red[3][p]);
+    }
+}
+
 DquadShape dquad_shape(int64_t n, int d, int mcols) {
     (void)d;
     DquadShape sh;
     sh.n_pad = round_up(std::max<int64_t>(n, 1), kRowPad);
     sh.mq4 = (int)round_up(std::max(mcols, 1), 16);
+    sh.mqb = (int)round_up(std::max(mcols, 1), 32);
     sh.rows_per_wg = kTile;
     const int64_t T = sh.n_pad / kTile;
     // columns tiles per workgroup: about 16 for large n, fewer when n is small so that
@@ -268,6 +442,43 @@ hipError_t launch_dquad(const DquadShape& sh, int d, const float* Z, const float
         case 14: return dquad_d<14>(sh, Z, A, B, kp, work, gpart, s);
         case 15: return dquad_d<15>(sh, Z, A, B, kp, work, gpart, s);
         case 16: return dquad_d<16>(sh, Z, A, B, kp, work, gpart, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int D>
+static hipError_t dquad_bf16_d(const DquadShape& sh, const float* Z, const uint16_t* AH,
+                               const uint16_t* AL, const uint16_t* BH, const uint16_t* BL,
+                               const KParams* kp, const int2* work, double* gpart, hipStream_t s) {
+    const dim3 grid((unsigned)sh.nwg);
+    switch (sh.mqb) {
+        case 32: dquad_sym_bf16_kernel<D, 1><<<grid, kWG, 0, s>>>(Z, AH, AL, BH, BL, gpart, sh.n_pad, work, sh.chunk, kp); break;
+        case 64: dquad_sym_bf16_kernel<D, 2><<<grid, kWG, 0, s>>>(Z, AH, AL, BH, BL, gpart, sh.n_pad, work, sh.chunk, kp); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_dquad_bf16(const DquadShape& sh, int d, const float* Z, const uint16_t* AH,
+                             const uint16_t* AL, const uint16_t* BH, const uint16_t* BL,
+                             const KParams* kp, const int2* work, double* gpart, hipStream_t s) {
+    switch (d) {
+        case 1: return dquad_bf16_d<1>(sh, Z, AH, AL, BH, BL, kp, work, gpart, s);
+        case 2: return dquad_bf16_d<2>(sh, Z, AH, AL, BH, BL, kp, work, gpart, s);
+        case 3: return dquad_bf16_d<3>(sh, Z, AH, AL, BH, BL, kp, work, gpart, s);
+        case 4: return dquad_bf16_d<4>(sh, Z, AH, AL, BH, BL, kp, work, gpart, s);
+        case 5: return dquad_bf16_d<5>(sh, Z, AH, AL, BH, BL, kp, work, gpart, s);
+        case 6: return dquad_bf16_d<6>(sh, Z, AH, AL, BH, BL, kp, work, gpart, s);
+        case 7: return dquad_bf16_d<7>(sh, Z, AH, AL, BH, BL, kp, work, gpart, s);
+        case 8: return dquad_bf16_d<8>(sh, Z, AH, AL, BH, BL, kp, work, gpart, s);
+        case 9: return dquad_bf16_d<9>(sh, Z, AH, AL, BH, BL, kp, work, gpart, s);
+        case 10: return dquad_bf16_d<10>(sh, Z, AH, AL, BH, BL, kp, work, gpart, s);
+        case 11: return dquad_bf16_d<11>(sh, Z, AH, AL, BH, BL, kp, work, gpart, s);
+        case 12: return dquad_bf16_d<12>(sh, Z, AH, AL, BH, BL, kp, work, gpart, s);
+        case 13: return dquad_bf16_d<13>(sh, Z, AH, AL, BH, BL, kp, work, gpart, s);
+        case 14: return dquad_bf16_d<14>(sh, Z, AH, AL, BH, BL, kp, work, gpart, s);
+        case 15: return dquad_bf16_d<15>(sh, Z, AH, AL, BH, BL, kp, work, gpart, s);
+        case 16: return dquad_bf16_d<16>(sh, Z, AH, AL, BH, BL, kp, work, gpart, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -64,6 +64,7 @@ size_t dkmv_part_floats(const KmvShape& sh, int d);
 // workgroup; dquad_work builds it on the host.
 struct DquadShape {
     int mq4;          // padded column count of A and B (multiple of 16)
+    int mqb;          // padded column count of the BF16 operands (multiple of 32)
     int rows_per_wg;  // rows of a row tile (64)
     int split;        // unused
     int chunk;        // column tiles per workgroup (L)
@@ -72,6 +73,10 @@ struct DquadShape {
 };
 DquadShape dquad_shape(int64_t n, int d, int mcols);
 void dquad_work(const DquadShape& sh, std::vector<int2>& work);
+// BF16 form: operands split into hi + lo halves, row-major with row stride sh.mqb.
+hipError_t launch_dquad_bf16(const DquadShape& sh, int d, const float* Z, const uint16_t* AH,
+                             const uint16_t* AL, const uint16_t* BH, const uint16_t* BL,
+                             const KParams* kp, const int2* work, double* gpart, hipStream_t s);
 hipError_t launch_dquad(const DquadShape& sh, int d, const float* Z, const float* A,
                         const float* B, const KParams* kp, const int2* work, double* gpart,
                         hipStream_t s);

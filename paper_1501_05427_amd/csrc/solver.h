@@ -92,6 +92,11 @@ hipError_t launch_philox(uint64_t k0, uint64_t k1, uint64_t first, uint64_t w1, 
 hipError_t launch_build_ab(const double* St, const float* R, int64_t ldr, int64_t n,
                            int nprobes, float* A, float* Bm, int64_t n_pad, int mq4,
                            hipStream_t s);
+// The same operands split into BF16 halves (hi + lo), row-major with row stride mqb (a
+// multiple of 32), for the BF16 form of the gradient reduction.
+hipError_t launch_build_ab_bf16(const double* St, const float* R, int64_t ldr, int64_t n,
+                                int nprobes, uint16_t* AH, uint16_t* AL, uint16_t* BH,
+                                uint16_t* BL, int64_t n_pad, int mqb, hipStream_t s);
 // dpart: solver_blocks(n) doubles of scratch.
 hipError_t launch_grad_finish(const double* St, const float* R, int64_t ldr, int64_t n,
                               int nprobes, const double* gpart, int nwg, int d,

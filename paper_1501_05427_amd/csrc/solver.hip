@@ -650,3 +650,60 @@ hipError_t launch_sum_active(const int* const* counts, int B, int* out, hipStrea
 }
 
 }  // namespace gpk
+
+namespace gpk {
+
+// The operands of the gradient reduction split into BF16 halves (v = hi + lo, both BF16),
+// row-major with row stride mqb (a multiple of 32): AH[i * mqb + c] etc.  Column c of A / B
+// as in build_ab_kernel.
+__device__ inline uint32_t pack2_bf16(float a, float b) {
+    typedef float f2 __attribute__((ext_vector_type(2)));
+    typedef __bf16 b2 __attribute__((ext_vector_type(2)));
+    const f2 v = {a, b};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, b2));
+}
+
+__global__ void build_ab_bf16_kernel(const double* __restrict__ St, const float* __restrict__ R,
+                                     int64_t ldr, int64_t n, int nprobes,
+                                     uint32_t* __restrict__ AH, uint32_t* __restrict__ AL,
+                                     uint32_t* __restrict__ BH, uint32_t* __restrict__ BL,
+                                     int64_t n_pad, int mqb) {
+    const int half = mqb / 2;  // column pairs per row
+    const int64_t total = n_pad * half;
+    const double w = -1.0 / (2.0 * nprobes);
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e / half;
+        const int c0 = (int)(e % half) * 2;
+        float av[2] = {0.f, 0.f}, bv[2] = {0.f, 0.f};
+        for (int u = 0; u < 2; ++u) {
+            const int c = c0 + u;
+            if (i < n && c <= nprobes) {
+                if (c == 0) {
+                    av[u] = (float)(0.5 * St[i]);
+                    bv[u] = (float)St[n + i];
+                } else {
+                    av[u] = (float)(w * (double)R[(c - 1) * ldr + i]);
+                    bv[u] = (float)St[(int64_t)(c + 1) * n + i];
+                }
+            }
+        }
+        const uint32_t ah = pack2_bf16(av[0], av[1]);
+        const uint32_t bh = pack2_bf16(bv[0], bv[1]);
+        AH[e] = ah;
+        BH[e] = bh;
+        AL[e] = pack2_bf16(av[0] - __uint_as_float(ah << 16), av[1] - __uint_as_float(ah & 0xffff0000u));
+        BL[e] = pack2_bf16(bv[0] - __uint_as_float(bh << 16), bv[1] - __uint_as_float(bh & 0xffff0000u));
+    }
+}
+
+hipError_t launch_build_ab_bf16(const double* St, const float* R, int64_t ldr, int64_t n,
+                                int nprobes, uint16_t* AH, uint16_t* AL, uint16_t* BH,
+                                uint16_t* BL, int64_t n_pad, int mqb, hipStream_t s) {
+    build_ab_bf16_kernel<<<grid_of(n_pad * (mqb / 2)), kWG, 0, s>>>(
+        St, R, ldr, n, nprobes, reinterpret_cast<uint32_t*>(AH), reinterpret_cast<uint32_t*>(AL),
+        reinterpret_cast<uint32_t*>(BH), reinterpret_cast<uint32_t*>(BL), n_pad, mqb);
+    return hipGetLastError();
+}
+
+}  // namespace gpk

@@ -917,3 +917,22 @@ def test_batch_learned_bf16_reproduces_unbatched_calls():
         np.testing.assert_array_equal(ch["psi"].cpu().numpy(), psi.cpu().numpy(), err_msg=f"chain {i}")
         np.testing.assert_array_equal(ch["g"].cpu().numpy(), g.cpu().numpy(), err_msg=f"chain {i}")
     batch.close()
+
+
+@pytest.mark.parametrize("prec", [pb.GP_BF16_SPLIT_KV])
+def test_bf16_gradient_reduction_matches_fp32(h, prec):
+    # the BF16 modes also take the gradient's G tiles from split BF16 operands; with
+    # converged solves the estimate must agree with the FP32 path to the solve accuracy of
+    # the mode (split K+V: ~3e-5 on the 4096-point report) plus the G rounding (~2^-17)
+    n, d, nr = 3000, 4, 31
+    X, psi = problem(n, d, seed=31, lam=0.1, ell=(0.2, 0.5))
+    y = workloads.gaussian_matrix(n, 1, seed=2)[:, 0]
+    R = workloads.gaussian_matrix(n, nr, seed=3)
+    params = pb.make_params(q=1e-12, rate=1e-9, eps=1e-6, eps_relative=1, max_iter=3000)
+    g32, st32 = pb.gp_stoch_grad(h, dev(X), dev(psi), dev(y), params, R=colm(R))
+    params.prec = prec
+    g16, st16 = pb.gp_stoch_grad(h, dev(X), dev(psi), dev(y), params, R=colm(R))
+    torch.cuda.synchronize()
+    assert not any(s["flags"] for s in pb.decode_stats(st16))
+    a, b = g32.cpu().numpy(), g16.cpu().numpy()
+    np.testing.assert_allclose(b, a, rtol=1e-3, atol=1e-3 * np.abs(a).max())

@@ -451,6 +451,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-kmv", action="store_true")
+    ap.add_argument("--profile-util", action="store_true",
+                    help="a few launches of each hot kernel, for rocprofv3 counter passes")
     ap.add_argument("--error-sweep", action="store_true",
                     help="gradient error vs estimates/s, plain FP32 vs learned + BF16 (separate report)")
     ap.add_argument("--sweep-reps", type=int, default=100)
@@ -502,6 +504,26 @@ def main():
         return
     if args.batched:
         batched_bench(args, pb)
+        return
+
+    if args.profile_util:
+        # the hot kernels of both paths, a few launches each, for counter passes
+        V = pb.colmajor(N, M)
+        V.copy_(torch.from_numpy(workloads.gaussian_matrix(N, M, seed=11)).cuda())
+        out = pb.colmajor(N, M)
+        for prec in (pb.GP_FP32, pb.GP_BF16_SPLIT_KV):
+            for _ in range(3):
+                pb.gp_kmv(h, X, psi0, V, out=out, prec=prec)
+        R = pb.colmajor(N, NPROBES)
+        R.copy_(V[:, 1:])
+        S_warm = torch.zeros((M, N), dtype=torch.float64, device="cuda").t()
+        for prec in (pb.GP_FP32, pb.GP_BF16_SPLIT_KV):
+            params = pb.make_params(q=1.0, rate=1.0, eps=1e-6, eps_relative=1, max_iter=1000)
+            params.prec = prec
+            for _ in range(2):
+                pb.gp_stoch_grad(h, X, psi0, y, params, R=R, S_warm=S_warm)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_util": "done"}), flush=True)
         return
 
     if args.profile_kmv:

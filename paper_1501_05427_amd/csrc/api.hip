@@ -229,10 +229,15 @@ gp_status shape_for(gp_handle* h, int64_t n, int d, int m, gp_precision prec, co
         return GP_OK;
     }
     const bool b16 = uses_bf16(base, prec);
+    int max_split = 1;
+    for (int target : kTuneTargets) {
+        const int sp = kmv_shape_target(n, d, m, prec, target).split;
+        if (sp <= kTuneMaxSplit) max_split = std::max(max_split, sp);
+    }
     float *V, *part;
     uint16_t *VH = nullptr, *VL = nullptr;
     GP_TRY(ws(h, kSlotTuneV, (size_t)base.n_pad * base.mp, &V));
-    GP_TRY(ws(h, kSlotTunePart, (size_t)kTuneMaxSplit * base.mp * base.n_pad, &part));
+    GP_TRY(ws(h, kSlotTunePart, (size_t)max_split * base.mp * base.n_pad, &part));
     if (b16) {
         GP_TRY(ws(h, kSlotTuneVH, (size_t)base.n_pad * base.mp, &VH));
         GP_TRY(ws(h, kSlotTuneVL, (size_t)base.n_pad * base.mp, &VL));

@@ -146,9 +146,8 @@ def error_sweep(args, pb, h, X, y, w, psi0):
         ref.rng_counter = b
         pb.gp_stoch_grad(h, X, psi0, y, ref, R=R, S_warm=S_warm, g=g, stats=stats)
         gs.append(g.cpu().numpy().copy())
-        if b % 8 == 7:
-            print(f"reference: {b + 1}/{batches} probe batches, {time.perf_counter() - t0:.1f} s",
-                  file=sys.stderr, flush=True)
+        print(f"reference: {b + 1}/{batches} probe batches, {time.perf_counter() - t0:.1f} s",
+              file=sys.stderr, flush=True)
         fl = [s_["flags"] for s_ in pb.decode_stats(stats)]
         assert not any(fl), f"reference solve flagged: {fl}"
     gs = np.array(gs)
@@ -183,6 +182,8 @@ def error_sweep(args, pb, h, X, y, w, psi0):
             dt = time.perf_counter() - t0
             pr = pb.gp_profile_read(h)
             pb.gp_profile(h, 0)
+            if r % 10 == 0:
+                print(f"{method} q={q}: estimate {r}, {elapsed:.1f} s", file=sys.stderr, flush=True)
             if r == 0:
                 continue
             elapsed += dt

@@ -440,6 +440,81 @@ def batched_bench(args, pb):
     print(json.dumps({"batched": out}), flush=True)
 
 
+def chains_bench(args, pb):
+    """The paper's multi-chain protocol (Sec. 5) on the n = 16384, d = 8 workload: SGLD
+    preconditioner M from the MAP on a random 500-point subset, scaled by 500 / n for the
+    full data set (the posterior covariance shrinks like 1 / n); chains started from
+    N(psi_MAP, M_subset) for dispersion; probes (4 per estimate, as in the paper) redrawn
+    every 20 steps with warm starts; all chains stepped together by gp_batch_*.  The step
+    size is the one at which the Langevin-phase monitor (eps / 4) lambda_max(L^T V L) meets
+    the freeze threshold 0.002, with V the covariance of 32 gradient estimates at psi_MAP:
+    the step the paper's schedule freezes at.  Reports the PSRF over the second half of the
+    run and the effective sample size of every chain there."""
+    import numpy as np
+    import torch
+    import workloads
+    from paper_1501_05427_amd import protocol
+    n, d, nr, C, T = 16384, 8, 4, args.chain_count, args.chain_steps
+    w = workloads.rff_gp(n=n, d=d, seed=1)
+    P = d + 2
+    h = pb.Handle(0, seed=31)
+    prior = {"kind": 1, "a": np.zeros(P), "b": np.full(P, 3.0)}
+    t0 = time.perf_counter()
+    psi_map, M_sub, _ = protocol.sgld_preconditioner(h, w["X"], w["y"], w["psi"], prior, n_sub=500, seed=0)
+    t_map = time.perf_counter() - t0
+    M_full = M_sub * (500.0 / n)
+    L_full = np.linalg.cholesky(M_full)
+    starts = protocol.init_chains(psi_map, M_sub, C, seed=1)
+    X = torch.from_numpy(w["X"]).cuda()
+    y = torch.from_numpy(w["y"]).cuda()
+    Ld = torch.from_numpy(np.ascontiguousarray(L_full.T)).cuda()  # column-major lower factor
+    pa = torch.zeros(P, dtype=torch.float64, device="cuda")
+    pbb = torch.full((P,), 3.0, dtype=torch.float64, device="cuda")
+    probs = [{"X": X, "y": y, "psi": torch.from_numpy(starts[c].copy()).cuda(), "M_chol": Ld,
+              "prior": (1, pa, pbb)} for c in range(C)]
+    params = pb.make_params(q=1.0, rate=1.0, eps=1e-6, eps_relative=1, max_iter=2000, rng_stream=2)
+    batch = pb.Batch(probs, nr, params, seed=500, probe_kind=pb.PROBE_GAUSSIAN, probe_period=PROBE_PERIOD,
+                     iters_per_graph=8, autotune=True, streams=min(C, 8))
+    # gradient-noise covariance at psi_MAP -> the step at the freeze threshold
+    hv = pb.Handle(0, seed=77)
+    psi_m = torch.from_numpy(psi_map.copy()).cuda()
+    Sw = torch.zeros((1 + nr, n), dtype=torch.float64, device="cuda").t()
+    G = []
+    for k in range(33):
+        params.rng_counter = 10_000 + k
+        g_, _ = pb.gp_stoch_grad(hv, X, psi_m, y, params, n_probes=nr, S_warm=Sw)
+        if k > 0:  # the first solve only warms the y system up
+            G.append(g_.cpu().numpy())
+    V = np.cov(np.array(G).T)
+    lam_max = float(np.linalg.eigvalsh(L_full.T @ V @ L_full).max())
+    eps = 4 * 0.002 / lam_max
+    trace = np.empty((C, T, P))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for t in range(T):
+        batch.step(t, eps)
+        trace[:, t, :] = torch.stack([p["psi"] for p in probs]).cpu().numpy()
+        if t % 200 == 199:
+            print(f"chains: step {t + 1}/{T}, {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    el = time.perf_counter() - t0
+    half = trace[:, T // 2:, :]
+    rhat = protocol.psrf(half)
+    ess = np.array([protocol.ess(half[c]) for c in range(C)])
+    out = {"chains": {"workload": "rff_n16384_d8", "n_chains": C, "steps": T, "probes": nr,
+                      "subset": 500, "map_seconds": t_map, "psi_map": psi_map.tolist(),
+                      "eps": eps, "langevin_lambda_max": lam_max,
+                      "psi_truth": w["psi"].tolist(), "M_scale": 500.0 / n,
+                      "seconds": el, "grad_estimates_per_s": C * T / el,
+                      "psrf_second_half": rhat.tolist(), "psrf_max": float(rhat.max()),
+                      "ess_second_half_min_per_chain": ess.min(axis=1).tolist(),
+                      "ess_fraction_min": float(ess.min() / (T - T // 2)),
+                      "posterior_mean_second_half": half.reshape(-1, P).mean(axis=0).tolist(),
+                      "posterior_sd_second_half": half.reshape(-1, P).std(axis=0).tolist(),
+                      "batch_stats": batch.stats()}}
+    batch.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -467,6 +542,10 @@ def main():
                     help="64 chains over 64 GPs: batched graphs vs unbatched calls (separate report)")
     ap.add_argument("--batch-chains", type=int, default=64)
     ap.add_argument("--batch-steps", type=int, default=20)
+    ap.add_argument("--chains", action="store_true",
+                    help="the paper's multi-chain protocol with PSRF and ESS (separate report)")
+    ap.add_argument("--chain-count", type=int, default=10)
+    ap.add_argument("--chain-steps", type=int, default=6000)
     ap.add_argument("--solver-study", action="store_true",
                     help="CG/ULISSE iterations, spread and gradient error against kappa (separate report)")
     ap.add_argument("--study-lambdas", type=lambda t: [float(v) for v in t.split(",")],
@@ -518,6 +597,9 @@ def main():
         return
     if args.batched:
         batched_bench(args, pb)
+        return
+    if args.chains:
+        chains_bench(args, pb)
         return
 
     if args.profile_util:

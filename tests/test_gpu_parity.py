@@ -936,3 +936,24 @@ def test_bf16_gradient_reduction_matches_fp32(h, prec):
     assert not any(s["flags"] for s in pb.decode_stats(st16))
     a, b = g32.cpu().numpy(), g16.cpu().numpy()
     np.testing.assert_allclose(b, a, rtol=1e-3, atol=1e-3 * np.abs(a).max())
+
+
+def test_dkmv_matches_finite_differences_of_kmv(h):
+    # an independent route to dK/dpsi_j V: central differences of the product itself
+    n, d, m, step = 777, 3, 17, 1e-3
+    X, psi = problem(n, d, seed=41)
+    V = np.random.default_rng(2).standard_normal((n, m)).astype(np.float32)
+    dk = pb.gp_dkmv(h, dev(X), dev(psi), colm(V))
+    kv = pb.gp_kmv(h, dev(X), dev(psi), colm(V)).cpu().numpy()
+    torch.cuda.synchronize()
+    dk = dk.cpu().numpy()
+    for j in range(d + 2):
+        e = np.zeros(d + 2)
+        e[j] = step
+        up = pb.gp_kmv(h, dev(X), dev(psi + e), colm(V)).cpu().numpy()
+        dn = pb.gp_kmv(h, dev(X), dev(psi - e), colm(V)).cpu().numpy()
+        fd = (up.astype(np.float64) - dn) / (2 * step)
+        err = np.linalg.norm(fd - dk[j].T, axis=0)
+        bound = 2e-3 * np.linalg.norm(dk[j].T, axis=0) + 1e-3 * np.linalg.norm(kv, axis=0)
+        assert np.all(err <= bound), (j, (err / bound).max())
+

@@ -444,8 +444,8 @@ def chains_bench(args, pb):
     """The paper's multi-chain protocol (Sec. 5) on the n = 16384, d = 8 workload: SGLD
     preconditioner M from the MAP on a random 500-point subset, scaled by 500 / n for the
     full data set (the posterior covariance shrinks like 1 / n); chains started from
-    N(psi_MAP, M_subset) for dispersion; probes (4 per estimate, as in the paper) redrawn
-    every 20 steps with warm starts; all chains stepped together by gp_batch_*.  The step
+    N(psi_MAP, M_subset) for dispersion; probes (4 per estimate and q = 1 as in the paper,
+    or as given) redrawn every 20 steps with warm starts; all chains stepped together by gp_batch_*.  The step
     size is the one at which the Langevin-phase monitor (eps / 4) lambda_max(L^T V L) meets
     the freeze threshold 0.002, with V the covariance of 32 gradient estimates at psi_MAP:
     the step the paper's schedule freezes at.  Reports the PSRF over the second half of the
@@ -454,7 +454,7 @@ def chains_bench(args, pb):
     import torch
     import workloads
     from paper_1501_05427_amd import protocol
-    n, d, nr, C, T = 16384, 8, 4, args.chain_count, args.chain_steps
+    n, d, nr, C, T = 16384, 8, args.chain_probes, args.chain_count, args.chain_steps
     w = workloads.rff_gp(n=n, d=d, seed=1)
     P = d + 2
     h = pb.Handle(0, seed=31)
@@ -472,7 +472,7 @@ def chains_bench(args, pb):
     pbb = torch.full((P,), 3.0, dtype=torch.float64, device="cuda")
     probs = [{"X": X, "y": y, "psi": torch.from_numpy(starts[c].copy()).cuda(), "M_chol": Ld,
               "prior": (1, pa, pbb)} for c in range(C)]
-    params = pb.make_params(q=1.0, rate=1.0, eps=1e-6, eps_relative=1, max_iter=2000, rng_stream=2)
+    params = pb.make_params(q=args.chain_q, rate=1.0, eps=1e-6, eps_relative=1, max_iter=2000, rng_stream=2)
     batch = pb.Batch(probs, nr, params, seed=500, probe_kind=pb.PROBE_GAUSSIAN, probe_period=PROBE_PERIOD,
                      iters_per_graph=8, autotune=True, streams=min(C, 8))
     # gradient-noise covariance at psi_MAP -> the step at the freeze threshold
@@ -500,7 +500,7 @@ def chains_bench(args, pb):
     half = trace[:, T // 2:, :]
     rhat = protocol.psrf(half)
     ess = np.array([protocol.ess(half[c]) for c in range(C)])
-    out = {"chains": {"workload": "rff_n16384_d8", "n_chains": C, "steps": T, "probes": nr,
+    out = {"chains": {"workload": "rff_n16384_d8", "n_chains": C, "steps": T, "probes": nr, "q": args.chain_q,
                       "subset": 500, "map_seconds": t_map, "psi_map": psi_map.tolist(),
                       "eps": eps, "langevin_lambda_max": lam_max,
                       "psi_truth": w["psi"].tolist(), "M_scale": 500.0 / n,
@@ -546,6 +546,8 @@ def main():
                     help="the paper's multi-chain protocol with PSRF and ESS (separate report)")
     ap.add_argument("--chain-count", type=int, default=10)
     ap.add_argument("--chain-steps", type=int, default=6000)
+    ap.add_argument("--chain-probes", type=int, default=4, help="probes per estimate (the paper: 4)")
+    ap.add_argument("--chain-q", type=float, default=1.0, help="alpha = q sqrt(n) (the paper: 1)")
     ap.add_argument("--solver-study", action="store_true",
                     help="CG/ULISSE iterations, spread and gradient error against kappa (separate report)")
     ap.add_argument("--study-lambdas", type=lambda t: [float(v) for v in t.split(",")],

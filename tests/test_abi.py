@@ -63,6 +63,21 @@ def test_validation_is_synchronous_and_host_side(lib):
     assert b"handle" in lib.gp_last_error()
     st = lib.gp_philox(0, 0, 0, 0, 0, 0, -1, None, None)
     assert st == binding.GP_EINVAL
+    # the shifted preconditioner, the autotuner and the batch validate before device work too
+    p = binding.make_params()
+    sp = binding.make_shift_precond(0.1)
+    st = lib.ulisse_solve_shift_pc(None, binding.gp_data(0, 0, 0, 0), None, None, 1, 1, None,
+                                   ctypes.byref(p), ctypes.byref(sp), None, None, None, None)
+    assert st == binding.GP_EINVAL
+    assert lib.gp_autotune(None, 1) == binding.GP_EINVAL
+    out = ctypes.c_void_p()
+    descs = (binding.gp_batch_problem * 1)()
+    st = lib.gp_batch_create(ctypes.byref(out), 0, 0, 0, descs, 4, 0, 20, ctypes.byref(p), 8, 0, 1)
+    assert st == binding.GP_EINVAL and out.value is None           # B = 0
+    st = lib.gp_batch_create(ctypes.byref(out), 0, 0, 1, descs, 4, 0, 20, ctypes.byref(p), 7, 0, 1)
+    assert st == binding.GP_EINVAL and b"iters_per_graph" in lib.gp_last_error()
+    st = lib.gp_batch_create(ctypes.byref(out), 0, 0, 1, descs, 4, 0, 20, ctypes.byref(p), 8, 0, 1)
+    assert st == binding.GP_EINVAL                                  # problem 0 has no X
 
 
 def test_sources_are_gfx950_only():

@@ -233,7 +233,7 @@ typedef unsigned int dq_uintx4 __attribute__((ext_vector_type(4)));
 // (register budget for three workgroups per CU where it fits without spilling, and the
 // tile loop unrolled twice: 27% faster than the unconstrained allocation at d = 8)
 template <int D, int KB>
-__global__ __launch_bounds__(kWG, (D <= 8 && KB == 1) ? 3 : 2) void dquad_sym_bf16_kernel(
+__global__ __launch_bounds__(kWG, (D <= 8 && KB == 1) ? 3 : (KB == 1 ? 2 : 1)) void dquad_sym_bf16_kernel(
     const float* __restrict__ Z, const uint16_t* __restrict__ AH, const uint16_t* __restrict__ AL,
     const uint16_t* __restrict__ BH, const uint16_t* __restrict__ BL, double* __restrict__ gpart,
     int64_t n_pad, const int2* __restrict__ work, int L, const KParams* __restrict__ kp) {

@@ -114,7 +114,7 @@ __global__ __launch_bounds__(kWG) void pc_apply_kernel(SolverArgs a, int first) 
         if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][c] = w;
     }
     __syncthreads();
-    if (threadIdx.x < m && (first || a.state[threadIdx.x].active)) {
+    if ((int)threadIdx.x < m && (first || a.state[threadIdx.x].active)) {
         const int c = threadIdx.x;
         a.part3[(int64_t)blockIdx.x * m + c] = (red[0][c] + red[1][c]) + (red[2][c] + red[3][c]);
     }
@@ -177,7 +177,7 @@ __global__ __launch_bounds__(kWG) void icg_finish_kernel(SolverArgs a, const dou
         if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][c] = w;
     }
     __syncthreads();
-    if (threadIdx.x < m && (first || a.state[threadIdx.x].active)) {
+    if ((int)threadIdx.x < m && (first || a.state[threadIdx.x].active)) {
         const int c = threadIdx.x;
         a.part3[(int64_t)blockIdx.x * m + c] = (red[0][c] + red[1][c]) + (red[2][c] + red[3][c]);
     }
@@ -185,10 +185,14 @@ __global__ __launch_bounds__(kWG) void icg_finish_kernel(SolverArgs a, const dou
 
 __global__ void shift_kp_kernel(const KParams* in, double delta, KParams* out) {
     if (threadIdx.x != 0) return;
-    KParams p = *in;
-    p.lam64 = in->lam64 + delta;
-    p.lam = (float)p.lam64;
-    *out = p;
+    // word copy (a struct copy would go through private memory)
+    static_assert(sizeof(KParams) % 4 == 0, "KParams is a whole number of words");
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(in);
+    uint32_t* dst = reinterpret_cast<uint32_t*>(out);
+    for (size_t w = 0; w < sizeof(KParams) / 4; ++w) dst[w] = src[w];
+    const double lam = in->lam64 + delta;
+    out->lam64 = lam;
+    out->lam = (float)lam;
 }
 
 hipError_t launch_icg_rhs(const SolverArgs& a, float* Bin, int first, hipStream_t s) {

@@ -311,7 +311,7 @@ def solver_study(args, pb, h):
                       "ref_probes": args.study_ref_batches * NPROBES, "draws_per_path": m}), flush=True)
 
 
-def batched_bench(args, pb):
+def batched_bench(args, pb, n_features=2048, learn_pairs=128, learn_epochs=1000, emit=True):
     """64 independent SGLD chains over 64 GPs (n uniform in [2048, 32768], d in {2, 4, 8, 16},
     the random-Fourier-feature generator with a sub-seed per GP, y + 16 probes each),
     stepped together through gp_batch_* (captured graphs, autotuned product shapes), against
@@ -329,7 +329,7 @@ def batched_bench(args, pb):
     probs = []
     for i in range(B):
         n, d = int(ns[i]), int(ds[i])
-        w = workloads.rff_gp(n=n, d=d, seed=int(seeds[i]))
+        w = workloads.rff_gp(n=n, d=d, seed=int(seeds[i]), n_features=n_features)
         probs.append({"X": torch.from_numpy(w["X"]).cuda(), "y": torch.from_numpy(w["y"]).cuda(),
                       "psi": torch.from_numpy(w["psi"]).cuda(),
                       "M_chol": torch.diag(torch.full((d + 2,), n ** -0.5, dtype=torch.float64)).cuda(),
@@ -339,7 +339,8 @@ def batched_bench(args, pb):
     params = pb.make_params(q=1.0, rate=1.0, eps=1e-6, eps_relative=1, max_iter=1000, rng_stream=1)
     eps_t = 1e-3
     psi0 = [p["psi"].clone() for p in probs]
-    out = {"workload": f"batch{B}_rff_n2048-32768_d2-16_m17", "chains": B, "pairs_per_product_sweep": pairs}
+    out = {"workload": f"batch{B}_rff_n2048-32768_d2-16_m17", "chains": B, "pairs_per_product_sweep": pairs,
+           "rff_features": n_features}
     # unbatched: the same chains one after another (own handle per chain, eager calls)
     hs = [pb.Handle(0, seed=7000 + i) for i in range(B)]
     st = []
@@ -404,13 +405,13 @@ def batched_bench(args, pb):
         d = p["X"].shape[1]
         U, _ = pb.precond_build_basis(hs_setup, p["X"], p["psi"], k)
         rr = np.random.default_rng(1000 + i)
-        psis = torch.from_numpy(psi0[i].cpu().numpy() + LEARN_JITTER * rr.standard_normal((128, d + 2))).cuda()
+        psis = torch.from_numpy(psi0[i].cpu().numpy() + LEARN_JITTER * rr.standard_normal((learn_pairs, d + 2))).cuda()
         Tg = pb.precond_targets(hs_setup, p["X"], p["y"], U, psis)
         I_, O_ = d + 2, 2 * k + 1
         prm = torch.zeros(pb.precond_mlp_size(I_, H, O_), dtype=torch.float32, device="cuda")
         pb.precond_mlp_init(hs_setup, prm, I_, H, O_, psis, Tg, seed=5)
         adam = torch.zeros(2 * pb.mlp_layout(I_, H, O_)["trainable"], dtype=torch.float32, device="cuda")
-        pb.precond_mlp_train(hs_setup, prm, adam, I_, H, O_, psis, Tg, 1000, 0, 2e-3)
+        pb.precond_mlp_train(hs_setup, prm, adam, I_, H, O_, psis, Tg, learn_epochs, 0, 2e-3)
         p["learned"] = {"mlp": prm, "hidden": H, "U": U,
                         "coef": torch.zeros(k + 1, dtype=torch.float64, device="cuda")}
     torch.cuda.synchronize()
@@ -437,7 +438,10 @@ def batched_bench(args, pb):
     out["speedup_vs_unbatched"] = {m_: out[m_]["grad_estimates_per_s"] / u for m_ in
                                    ("batched_graphs", "batched_graphs_autotuned",
                                     "batched_graphs_autotuned_bf16_split_kv", mode)}
-    print(json.dumps({"batched": out}), flush=True)
+    out["learn_pairs"], out["learn_epochs"] = learn_pairs, learn_epochs
+    if emit:
+        print(json.dumps({"batched": out}), flush=True)
+    return out
 
 
 def chains_bench(args, pb):
@@ -528,6 +532,7 @@ def main():
                     help="steps of the BF16 split-K+V solver run (default: --steps)")
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the compact batched leg of the main line")
     ap.add_argument("--profile-kmv", action="store_true")
     ap.add_argument("--profile-util", action="store_true",
                     help="a few launches of each hot kernel, for rocprofv3 counter passes")
@@ -845,6 +850,23 @@ def main():
         "steps_with_flagged_systems": int(flagged.item()),
         "psi_final_finite": bool(torch.isfinite(psi).all().item()),
     }
+    if not args.no_batched:
+        # the batched forms on 64 GPs (n 2048 to 32768, d 2 to 16; inputs with 256 random
+        # features to keep their generation short), 12 timed steps instead of 20
+        try:
+            sv = (args.batch_steps, args.warmup)
+            args.batch_steps, args.warmup = 12, 3
+            bt = batched_bench(args, pb, n_features=256, learn_pairs=128, learn_epochs=1000, emit=False)
+            args.batch_steps, args.warmup = sv
+            rec["batched_64_gps"] = {
+                "workload": bt["workload"], "steps": bt["steps"],
+                "grad_estimates_per_s": {k: bt[k]["grad_estimates_per_s"] for k in
+                                         ("unbatched", "batched_graphs", "batched_graphs_autotuned",
+                                          "batched_graphs_autotuned_bf16_split_kv",
+                                          "batched_graphs_autotuned_learned_bf16_split_kv")},
+                "speedup_vs_unbatched": bt["speedup_vs_unbatched"]}
+        except Exception as e:  # the main line must still be printed
+            rec["batched_64_gps"] = {"error": repr(e)}
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(w["X"], w["psi"], passes)
     print(json.dumps(rec), flush=True)

@@ -852,10 +852,10 @@ def main():
     }
     if not args.no_batched:
         # the batched forms on 64 GPs (n 2048 to 32768, d 2 to 16; inputs with 256 random
-        # features to keep their generation short), 12 timed steps instead of 20
+        # features to keep their generation short); 3 + 20 steps span one probe redraw
         try:
             sv = (args.batch_steps, args.warmup)
-            args.batch_steps, args.warmup = 12, 3
+            args.batch_steps, args.warmup = 20, 3
             bt = batched_bench(args, pb, n_features=256, learn_pairs=128, learn_epochs=1000, emit=False)
             args.batch_steps, args.warmup = sv
             rec["batched_64_gps"] = {

@@ -219,3 +219,35 @@ def test_exact_mean_over_preconditioned_cg_path(kind):
         total += p
     np.testing.assert_allclose(total, 1.0, rtol=1e-12)
     np.testing.assert_allclose(mean, sla.cho_solve(sla.cho_factor(K), b), rtol=1e-7, atol=1e-8)
+
+
+def test_exact_mean_from_a_warm_start_is_the_solution():
+    # a warm start s0 (as the learned part supplies, s0 = U c) changes the CG path but not the
+    # expectation: enumerating every truncation point gives the solution again, with or
+    # without a preconditioner
+    K, b = _system(40, lam=0.05, seed=9)
+    sol = sla.cho_solve(sla.cho_factor(K), b)
+    s0 = sol + 0.3 * np.random.default_rng(1).standard_normal(40)
+    w, Q = np.linalg.eigh(K)
+    pinv = cg.lowrank_pinv(Q[:, -6:], 1 / w[-6:] - 1 / np.mean(w[:-6]), 1 / np.mean(w[:-6]))
+    rate, eps = 0.5, 1e-11
+    for ap in (None, pinv):
+        it = cg.cg_iterates(lambda v: K @ v, b, s0) if ap is None else cg.pcg_iterates(lambda v: K @ v, ap, b, s0)
+        norms = [np.linalg.norm(b - K @ s0)]
+        for i, s_, e, dl in it:
+            norms.append(np.linalg.norm(e))
+            if norms[-1] < eps:
+                break
+        T = len(norms) - 1
+        alpha = 0.5 * (norms[T - 2] + norms[T - 3]) if norms[T - 2] < norms[T - 3] else norms[T - 2] * 1.0001
+        mean, total = np.zeros(40), 0.0
+        for Jt in range(8):
+            res = ulisse.solve(lambda v: K @ v, b, s0, alpha, eps, 1000, rate, _forced(Jt), apply_pinv=ap)
+            tail = T - res["l"]
+            if Jt > tail:
+                break
+            p = ulisse.survival(rate, Jt) - (ulisse.survival(rate, Jt + 1) if Jt < tail else 0.0)
+            mean += p * res["s_tilde"][0]
+            total += p
+        np.testing.assert_allclose(total, 1.0, rtol=1e-12)
+        np.testing.assert_allclose(mean, sol, rtol=1e-7, atol=1e-8)

@@ -118,7 +118,9 @@ def setup_learned(pb, h, X, y, w, pairs, epochs, k=64, H=256):
 
 
 def error_sweep(args, pb, h, X, y, w, psi0):
-    """Gradient error against estimates/s, plain FP32 against learned + BF16 split-K+V.
+    """Gradient error against estimates/s, plain FP32 against learned + BF16 split-K+V (and,
+    on request, the two halves of that change: BF16 products alone, the learned
+    preconditioner alone).
 
     Error of one estimate: log10 ||g~ - g_ref||^2 / ||g_ref||^2, averaged over `reps`
     independent estimates at the workload's psi (the paper's measure of gradient accuracy,
@@ -160,8 +162,10 @@ def error_sweep(args, pb, h, X, y, w, psi0):
 
     def run(method, q):
         params = pb.make_params(q=q, rate=1.0, eps=1e-6, eps_relative=1, max_iter=1000, rng_stream=5)
-        if method == "learned_bf16":
+        learned = method.startswith("learned")
+        if method.endswith("bf16"):
             params.prec = pb.GP_BF16_SPLIT_KV
+        if learned:
             pb.precond_from_mlp(h, L["prm"], L["I"], L["H"], L["O"], psi, L["k"], coef=L["coef"])
         S_warm.zero_()
         errs, passes = [], 0.0
@@ -173,7 +177,7 @@ def error_sweep(args, pb, h, X, y, w, psi0):
             pb.gp_draw_probes(h, N, NPROBES, pb.PROBE_GAUSSIAN, 23, r, R=R)
             S_warm[:, 1:].zero_()
             params.rng_counter = r
-            if method == "learned_bf16":
+            if learned:
                 pb.precond_from_mlp(h, L["prm"], L["I"], L["H"], L["O"], psi, L["k"], coef=L["coef"])
                 pb.gp_stoch_grad_pc(h, X, psi, y, params, L["pc"], R=R, S_warm=S_warm, g=g, stats=stats)
             else:
@@ -200,7 +204,7 @@ def error_sweep(args, pb, h, X, y, w, psi0):
                 "var_normalised_throughput": len(errs) / elapsed / float(np.mean(errs))}
 
     rows = []
-    for method in ("plain_fp32", "learned_bf16"):
+    for method in args.sweep_methods:
         for q in args.sweep_q:
             rows.append(run(method, q))
             print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
@@ -542,6 +546,8 @@ def main():
     ap.add_argument("--workload", choices=["rff", "mixture"], default="rff",
                     help="rff: n = 65536, d = 8 (default); mixture: n = 131072, d = 16 (error sweep only)")
     ap.add_argument("--sweep-q", type=lambda t: [float(v) for v in t.split(",")], default=[0.3, 1.0, 3.0])
+    ap.add_argument("--sweep-methods", type=lambda t: t.split(","), default=["plain_fp32", "learned_bf16"],
+                    help="any of plain_fp32, plain_bf16, learned_fp32, learned_bf16")
     ap.add_argument("--ref-probes", type=int, default=1024)
     ap.add_argument("--batched", action="store_true",
                     help="64 chains over 64 GPs: batched graphs vs unbatched calls (separate report)")

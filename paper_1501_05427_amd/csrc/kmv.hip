@@ -211,15 +211,21 @@ __device__ inline float kf_entry(const float (&zi)[D], const float (&zj)[D], flo
 // (lane % 16) for every block.  Inside a 16-column group, lane l takes columns
 // j = 4 (l / 16) + s for s = 0..3 -- the k-slot of v_mfma_f32_16x16x4f32 is l / 16 -- so
 // the B operand of four consecutive MFMA steps is one 16-byte LDS read.
+// TC > 0 right-hand sides past the NB MFMA blocks (m = 16 NB + TC, TC <= 4) go through
+// the VALU instead of a mostly empty extra MFMA block: each lane accumulates
+// K_ij V_jc over its own k-slots, and the four k-slot lanes of a row (l % 16 equal) are
+// summed by cross-lane shuffles once at the end.  V is staged with 16 NB + 4 columns.
 // ---------------------------------------------------------------------------------------
-template <int D, int NB, int R>
+template <int D, int NB, int TC, int R>
 __global__ __launch_bounds__(kWG) void kmv_mfma_f32_kernel(
     const float* __restrict__ Z, const float* __restrict__ V, int64_t ldv,
     float* __restrict__ part, int64_t n_pad, int chunk, int split,
     const KParams* __restrict__ kp, const int* __restrict__ n_active) {
     if (n_active != nullptr && *n_active == 0) return;
     constexpr int DP = (D + 3) & ~3;
-    constexpr int MP = NB * 16;
+    static_assert(TC >= 0 && TC <= 4, "at most four VALU columns");
+    constexpr int MP = NB * 16 + (TC > 0 ? 4 : 0);
+    constexpr int TCA = TC > 0 ? TC : 1;  // array extent (unused when TC == 0)
     using S = Stage<DP, MP, false>;
     __shared__ float4 zs[2][S::NZ4];
     __shared__ float vs[2][S::VSIZE];
@@ -242,6 +248,11 @@ __global__ __launch_bounds__(kWG) void kmv_mfma_f32_kernel(
     for (int r = 0; r < R; ++r)
 #pragma unroll
         for (int cb = 0; cb < NB; ++cb) acc[r][cb] = floatx4{0.f, 0.f, 0.f, 0.f};
+    float tacc[R][TCA];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int t = 0; t < TCA; ++t) tacc[r][t] = 0.f;
 
     S st;
     if (jb < je) {
@@ -261,6 +272,10 @@ __global__ __launch_bounds__(kWG) void kmv_mfma_f32_kernel(
 #pragma unroll
             for (int cb = 0; cb < NB; ++cb)
                 vv[cb] = *reinterpret_cast<const float4*>(vsb + (cb * 16 + col) * S::VST + g * 16 + 4 * q);
+            float4 vt[TCA];
+#pragma unroll
+            for (int t = 0; t < TC; ++t)
+                vt[t] = *reinterpret_cast<const float4*>(vsb + (NB * 16 + t) * S::VST + g * 16 + 4 * q);
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
                 float zj[D];
@@ -272,6 +287,11 @@ __global__ __launch_bounds__(kWG) void kmv_mfma_f32_kernel(
                     for (int cb = 0; cb < NB; ++cb) {
                         const float b = s == 0 ? vv[cb].x : s == 1 ? vv[cb].y : s == 2 ? vv[cb].z : vv[cb].w;
                         acc[r][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(kv, b, acc[r][cb], 0, 0, 0);
+                    }
+#pragma unroll
+                    for (int t = 0; t < TC; ++t) {
+                        const float b = s == 0 ? vt[t].x : s == 1 ? vt[t].y : s == 2 ? vt[t].z : vt[t].w;
+                        tacc[r][t] = __builtin_fmaf(kv, b, tacc[r][t]);
                     }
                 }
             }
@@ -293,6 +313,17 @@ __global__ __launch_bounds__(kWG) void kmv_mfma_f32_kernel(
             o.z = acc[r][cb][2];
             o.w = acc[r][cb][3];
             *reinterpret_cast<float4*>(part + ((int64_t)cidx * MP + c) * n_pad + i) = o;
+        }
+    // VALU columns: sum the four k-slot lanes of each row (lanes col, col + 16, col + 32,
+    // col + 48); the lanes of k-slot 0 store rows row0 + 16 r + col
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int t = 0; t < TC; ++t) {
+            float v = tacc[r][t];
+            v += __shfl_xor(v, 16);
+            v += __shfl_xor(v, 32);
+            if (q == 0) part[((int64_t)cidx * MP + NB * 16 + t) * n_pad + row0 + r * 16 + col] = v;
         }
 }
 
@@ -726,12 +757,19 @@ KmvShape kmv_shape(int64_t n, int d, int m, gp_precision prec) {
 }
 
 KmvShape kmv_shape_target(int64_t n, int d, int m, gp_precision prec, int target_wg) {
-    (void)prec;
     KmvShape sh;
     sh.n_pad = round_up(std::max<int64_t>(n, 1), kRowPad);
     sh.mfma = m >= 16;
+    sh.tail = 0;
     if (sh.mfma) {
         sh.mp = (int)round_up(m, 16);
+        // FP32: up to three columns past a multiple of 16 (four when m < 32) go through
+        // the VALU instead of another MFMA block (m < 64)
+        const int t = m % 16;
+        if (prec == GP_FP32 && m < 64 && t != 0 && (t <= 3 || (t == 4 && m < 32))) {
+            sh.tail = t;
+            sh.mp = m / 16 * 16 + 4;
+        }
         const int R = d <= 8 ? 4 : 2;
         sh.rows_per_wg = 64 * R;
     } else {
@@ -786,6 +824,36 @@ static hipError_t kmv_bf16_d(const KmvShape& sh, const float* Z, const uint16_t*
     return hipGetLastError();
 }
 
+#define GPK_F32_LAUNCH(NB, TC)                                                              \
+    kmv_mfma_f32_kernel<D, NB, TC, R><<<grid, kWG, 0, s>>>(Z, Vp, sh.n_pad, part, sh.n_pad, \
+                                                             sh.chunk, sh.split, kp, n_active)
+
+// (NB, TC) pairs that kmv_shape_target produces: TC <= 3, or TC = 4 with one MFMA block;
+// other tails would lower the occupancy below that of the padded kernel.
+template <int D, int R>
+static hipError_t kmv_f32_nb(int nb, int tc, dim3 grid, const float* Z, const float* Vp, float* part,
+                             const KmvShape& sh, const KParams* kp, const int* n_active, hipStream_t s) {
+    switch (nb * 8 + tc) {
+        case 8: GPK_F32_LAUNCH(1, 0); break;
+        case 9: GPK_F32_LAUNCH(1, 1); break;
+        case 10: GPK_F32_LAUNCH(1, 2); break;
+        case 11: GPK_F32_LAUNCH(1, 3); break;
+        case 12: GPK_F32_LAUNCH(1, 4); break;
+        case 16: GPK_F32_LAUNCH(2, 0); break;
+        case 17: GPK_F32_LAUNCH(2, 1); break;
+        case 18: GPK_F32_LAUNCH(2, 2); break;
+        case 19: GPK_F32_LAUNCH(2, 3); break;
+        case 24: GPK_F32_LAUNCH(3, 0); break;
+        case 25: GPK_F32_LAUNCH(3, 1); break;
+        case 26: GPK_F32_LAUNCH(3, 2); break;
+        case 27: GPK_F32_LAUNCH(3, 3); break;
+        case 32: GPK_F32_LAUNCH(4, 0); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+#undef GPK_F32_LAUNCH
+
 template <int D>
 static hipError_t kmv_d(const KmvShape& sh, const float* Z, const float* Vp,
                         const uint16_t* VH, const uint16_t* VL, const KParams* kp,
@@ -796,13 +864,9 @@ static hipError_t kmv_d(const KmvShape& sh, const float* Z, const float* Vp,
     const dim3 grid((unsigned)(tiles * sh.split));
     if (sh.mfma) {
         constexpr int R = D <= 8 ? 4 : 2;
-        switch (sh.mp) {
-            case 16: kmv_mfma_f32_kernel<D, 1, R><<<grid, kWG, 0, s>>>(Z, Vp, sh.n_pad, part, sh.n_pad, sh.chunk, sh.split, kp, n_active); break;
-            case 32: kmv_mfma_f32_kernel<D, 2, R><<<grid, kWG, 0, s>>>(Z, Vp, sh.n_pad, part, sh.n_pad, sh.chunk, sh.split, kp, n_active); break;
-            case 48: kmv_mfma_f32_kernel<D, 3, R><<<grid, kWG, 0, s>>>(Z, Vp, sh.n_pad, part, sh.n_pad, sh.chunk, sh.split, kp, n_active); break;
-            case 64: kmv_mfma_f32_kernel<D, 4, R><<<grid, kWG, 0, s>>>(Z, Vp, sh.n_pad, part, sh.n_pad, sh.chunk, sh.split, kp, n_active); break;
-            default: return hipErrorInvalidValue;
-        }
+        const int nb = sh.mp / 16;
+        if (sh.tail == 0 ? sh.mp % 16 != 0 : sh.mp != nb * 16 + 4) return hipErrorInvalidValue;
+        return kmv_f32_nb<D, R>(nb, sh.tail, grid, Z, Vp, part, sh, kp, n_active, s);
     } else {
         switch (sh.mp) {
             case 4: kmv_valu_kernel<D, 4, 1><<<grid, kWG, 0, s>>>(Z, Vp, sh.n_pad, part, sh.n_pad, sh.chunk, sh.split, kp, n_active); break;

@@ -99,6 +99,8 @@ def test_probe_draws(h, kind, n):
 KMV_CASES = [
     (1, 1, 1), (17, 2, 5), (300, 3, 15), (1000, 2, 5), (1000, 8, 16), (1000, 8, 17),
     (777, 16, 32), (2049, 8, 64), (513, 5, 33), (1500, 4, 1), (256, 8, 12),
+    # right-hand sides past a multiple of 16 that the FP32 path takes on the VALU
+    (1000, 8, 18), (700, 16, 20), (513, 5, 35), (600, 8, 51), (300, 16, 49), (1300, 3, 19),
 ]
 
 
@@ -219,6 +221,20 @@ def test_dkmv_parity(h, n, d, m):
     ref = ogp.dkmv(X, psi, V)          # (P, n, m)
     for j in range(d + 2):
         assert colwise_rel(got[j].T, ref[j]).max() <= 1e-5, j
+
+
+def test_kmv_full_size_sampled_n16384_m17(h):
+    # the n = 16384, d = 8 workload with y + 16 probes (one MFMA block and one VALU
+    # column) in the default launch shape; sampled rows from the oracle
+    w = workloads.rff_gp(n=16384, d=8, seed=1)
+    X, psi = w["X"], w["psi"]
+    V = workloads.gaussian_matrix(16384, 17, seed=12)
+    out = pb.gp_kmv(h, dev(X), dev(psi), colm(V))
+    torch.cuda.synchronize()
+    rows = np.sort(np.random.default_rng(3).choice(16384, 64, replace=False))
+    rows[0], rows[-1] = 0, 16383
+    ref = ogp.kmv(X, psi, V, rows=rows)
+    assert colwise_rel(out.cpu().numpy()[rows], ref).max() <= 1e-5
 
 
 @pytest.mark.parametrize("rows_seed", [0, 1])
@@ -780,6 +796,24 @@ def test_protocol_exact_gradient_vs_oracle(h):
     g = protocol.exact_gradient(h, dev(X), dev(y), psi)
     ref = ogp.exact_gradient(X, psi, y.astype(np.float64))
     np.testing.assert_allclose(g, ref, rtol=1e-4, atol=1e-4 * np.abs(ref).max())
+
+
+def test_reference_gradient_on_subsample_4096_vs_oracle(h):
+    # the reference gradient of the equal-error comparison (converged solves averaged over
+    # Gaussian probe batches) on the first 4096 points of the n = 65536, d = 8 workload,
+    # against the oracle's Cholesky gradient of the same points: every component within
+    # 5 standard errors of the batch mean (plus the 1e-6 CG tolerance scaled by |g|)
+    from paper_1501_05427_amd import protocol
+    w = workloads.rff_gp(n=65536, d=8, seed=2)
+    X, psi, y = w["X"][:4096], w["psi"], w["y"][:4096]
+    mean, se = protocol.probe_mean_gradient(h, dev(X), dev(y), psi, batches=16, probes=31)
+    ref = ogp.exact_gradient(X.astype(np.float64), psi, y.astype(np.float64))
+    assert np.all(np.isfinite(se)) and np.all(se > 0)
+    tol = 5.0 * se + 1e-5 * np.abs(ref).max()
+    assert np.all(np.abs(mean - ref) <= tol), (mean, ref, se)
+    # and the noise is the Hutchinson noise, not a bias: the standard error is a small
+    # fraction of the gradient's norm
+    assert np.linalg.norm(se) < 0.1 * np.linalg.norm(ref)
 
 
 def test_protocol_subset_map_and_preconditioner_vs_oracle(h):

@@ -92,6 +92,142 @@ def cpu_baseline(X, psi, passes_per_estimate, budget_rows=(768, 256)):
                 kmv_s_full=t_kmv, assembly_s_full=t_asm)
 
 
+def cpu_baseline_report():
+    """The oracle's CPU timings in full (no GPU): matrix-free FP64 K.V, FP64 ULISSE gradient
+    estimates and the dense Cholesky exact gradient, each on one thread and on every thread
+    the process may use.  Every figure is either a full run or a row/system sample scaled
+    linearly, as stated in its entry.
+    """
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    import workloads
+    from oracle import gp as ogp
+    from oracle import rng as orng
+    from oracle import stoch_grad as osg
+    from oracle import ulisse as oul
+
+    cores = len(os.sched_getaffinity(0))
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    t_start = time.perf_counter()
+
+    def say(msg):
+        print(f"cpu report: {msg} ({time.perf_counter() - t_start:.0f} s)", file=sys.stderr, flush=True)
+
+    def timed(fn):
+        t0 = time.perf_counter()
+        fn()
+        return time.perf_counter() - t0
+
+    rows = []
+    rff2 = workloads.rff_gp(n=16384, d=8, seed=1)
+    rff3 = workloads.rff_gp(n=65536, d=8, seed=2)
+    tiny = workloads.tiny(n=1000, seed=0)
+    Xt, psit = tiny["X"], tiny["psi"]
+    yt = np.linalg.cholesky(ogp.kernel_matrix(Xt, psit)) @ tiny["z"]
+    for threads in (1, cores):
+        with threadpool_limits(limits=threads):
+            # (i) matrix-free K.V: rows of the product, scaled by rows
+            for w, n, m, nrows in ((rff2, 16384, 17, 256 * threads), (rff3, 65536, 32, 64 * threads)):
+                V = np.random.default_rng(0).standard_normal((n, m))
+                rr = np.arange(min(nrows, n))
+                t = timed(lambda: ogp.kmv(w["X"], w["psi"], V, rows=rr)) * n / len(rr)
+                rows.append(dict(item="kmv_fp64", n=n, d=8, m=m, threads=threads, seconds=t,
+                                 gflops=kmv_flops(n, 8, m) / t / 1e9,
+                                 sample=f"{len(rr)} of {n} rows, scaled by rows"))
+                say(f"K.V n={n} on {threads} threads: {t:.2f} s")
+            # (ii) ULISSE gradient estimates, n = 1000 (4 Rademacher probes, q = 1, c = 1)
+            R = osg.draw_probes(0, 1, 0, 1000, 4, 1)
+            t = timed(lambda: osg.stoch_grad(Xt, psit, yt, R, 1.0, 1.0, 1e-8, 10000, 0, 1, 0))
+            rows.append(dict(item="ulisse_gradient", n=1000, d=2, m=5, threads=threads,
+                             seconds=t, estimates_per_s=1.0 / t, sample="one full estimate"))
+            say(f"ULISSE gradient n=1000 on {threads} threads: {t:.2f} s")
+            # ... and n = 16384 (y + 16 Gaussian probes): dense K once, the y system and one
+            # probe system solved in full and scaled to 17 systems, the assembly on rows
+            X2, psi2, y2 = rff2["X"], rff2["psi"], rff2["y"].astype(np.float64)
+            n2, nr2 = 16384, 16
+            holder = {}
+            t_k = timed(lambda: holder.__setitem__("K", ogp.kernel_matrix(X2, psi2)))
+            K = holder.pop("K")
+            R2 = orng.probes(0, 1, 0, n2, nr2, 0)
+            B = np.column_stack([y2, R2[:, 0]])
+            t_s = timed(lambda: oul.solve_systems(lambda v: K @ v, B, None, 1.0, 1.0, 1e-6, 5000,
+                                                  0, 1, 0, two_track_first=True, eps_relative=True))
+            del K
+            ra = np.arange(64 * threads)
+            S = np.random.default_rng(1).standard_normal((n2, 2 + nr2))
+            t_a = timed(lambda: [Dj @ S for Dj in ogp.kernel_derivatives(X2, psi2, rows=ra)]) * n2 / len(ra)
+            t = t_k + t_s * (1 + nr2) / 2 + t_a
+            rows.append(dict(item="ulisse_gradient", n=n2, d=8, m=1 + nr2, threads=threads,
+                             seconds=t, estimates_per_s=1.0 / t,
+                             sample=(f"dense K {t_k:.2f} s; 2 of {1 + nr2} systems solved "
+                                     f"({t_s:.2f} s, scaled); assembly on {len(ra)} rows, scaled")))
+            say(f"ULISSE gradient n=16384 on {threads} threads: {t:.2f} s")
+            # (iii) dense Cholesky exact gradient: n = 1000 and the first 4096 points of n = 65536
+            for Xe, pe, ye, tag in ((Xt, psit, yt, "n=1000, d=2"),
+                                    (rff3["X"][:4096], rff3["psi"], rff3["y"][:4096].astype(np.float64),
+                                     "n=4096 (first rows of n=65536), d=8")):
+                t = timed(lambda: ogp.exact_gradient(Xe, pe, ye))
+                rows.append(dict(item="exact_gradient_cholesky", n=len(ye), d=Xe.shape[1],
+                                 threads=threads, seconds=t, sample=f"one full gradient, {tag}"))
+                say(f"exact gradient {tag} on {threads} threads: {t:.2f} s")
+    print(json.dumps({"cpu_report": rows, "cores": cores, "cpu_model": model,
+                      "kind": "oracle"}), flush=True)
+
+
+def kmv_report(pb, h):
+    """gp_kmv throughput per precision mode on the workload shapes: n = 16384 (m = 17) and
+    n = 65536 (m = 32) of the random-Fourier-feature inputs, n = 65536 with m = 4 (the VALU
+    contraction) and the n = 131072, d = 16 mixture (m = 32).  Kernel time from the
+    library's hipEvents around the product kernel; call time (packing, BF16 split, split-K
+    reduction included) from torch events on the same stream."""
+    import numpy as np
+    import torch
+
+    import workloads
+    shapes = (("rff", 16384, 8, 17, 1), ("rff", 65536, 8, 32, 2), ("rff", 65536, 8, 4, 2),
+              ("mixture", 131072, 16, 32, 4))
+    names = {pb.GP_FP32: "fp32", pb.GP_BF16_SPLIT_V: "bf16_split_v", pb.GP_BF16_SPLIT_KV: "bf16_split_kv"}
+    rows = []
+    for kind, n, d, m, seed in shapes:
+        w = workloads.rff_gp(n=n, d=d, seed=seed) if kind == "rff" else workloads.mixture(n=n, d=d, seed=seed)
+        X = torch.from_numpy(w["X"]).cuda()
+        psi = torch.from_numpy(w["psi"]).cuda()
+        V = pb.colmajor(n, m)
+        V.copy_(torch.from_numpy(workloads.gaussian_matrix(n, m, seed=11)).cuda())
+        out = pb.colmajor(n, m)
+        reps = max(5, int(2e10 // (n * n)))
+        for prec in (pb.GP_FP32, pb.GP_BF16_SPLIT_V, pb.GP_BF16_SPLIT_KV):
+            for _ in range(3):
+                pb.gp_kmv(h, X, psi, V, out=out, prec=prec)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            pb.gp_profile(h, 1)
+            e0.record()
+            for _ in range(reps):
+                pb.gp_kmv(h, X, psi, V, out=out, prec=prec)
+            e1.record()
+            torch.cuda.synchronize()
+            pr = pb.gp_profile_read(h)
+            pb.gp_profile(h, 0)
+            k_ms = pr["kmv_ms"] / max(1, pr["kmv_launches"])
+            c_ms = e0.elapsed_time(e1) / reps
+            fl = kmv_flops(n, d, m)
+            rows.append(dict(workload=f"{kind}_n{n}_d{d}", n=n, d=d, m=m, prec=names[prec],
+                             kernel_ms=k_ms, call_ms=c_ms, tflops=fl / k_ms / 1e9,
+                             frac_fp32_valu_peak=fl / k_ms / 1e9 / VALU_FP32_PEAK_TFLOPS,
+                             exp_per_s=float(n) * n / (k_ms * 1e-3), launches=pr["kmv_launches"]))
+            print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+    print(json.dumps({"kmv_report": rows, "flops_per_pair": "3d + 2m (algorithmic, m unpadded)"}), flush=True)
+
+
 def setup_learned(pb, h, X, y, w, pairs, epochs, k=64, H=256):
     """Basis, Galerkin targets and the trained MLP of the learned warm start/preconditioner.
 
@@ -138,23 +274,15 @@ def error_sweep(args, pb, h, X, y, w, psi0):
     S_warm = torch.zeros((M, N), dtype=torch.float64, device="cuda").t()
 
     # reference gradient
+    from paper_1501_05427_amd import protocol
     t0 = time.perf_counter()
-    ref = pb.make_params(q=0.0, rate=1.0, eps=1e-6, eps_relative=1, max_iter=5000, rng_stream=3)
     batches = max(1, args.ref_probes // NPROBES)
-    gs = []
-    for b in range(batches):
-        pb.gp_draw_probes(h, N, NPROBES, pb.PROBE_GAUSSIAN, 21, b, R=R)
-        S_warm[:, 1:].zero_()
-        ref.rng_counter = b
-        pb.gp_stoch_grad(h, X, psi0, y, ref, R=R, S_warm=S_warm, g=g, stats=stats)
-        gs.append(g.cpu().numpy().copy())
-        print(f"reference: {b + 1}/{batches} probe batches, {time.perf_counter() - t0:.1f} s",
+
+    def progress(b, total):
+        print(f"reference: {b}/{total} probe batches, {time.perf_counter() - t0:.1f} s",
               file=sys.stderr, flush=True)
-        fl = [s_["flags"] for s_ in pb.decode_stats(stats)]
-        assert not any(fl), f"reference solve flagged: {fl}"
-    gs = np.array(gs)
-    g_ref = gs.mean(0)
-    g_ref_se = gs.std(0, ddof=1) / np.sqrt(len(gs))
+    g_ref, g_ref_se = protocol.probe_mean_gradient(h, X, y, psi0, batches, probes=NPROBES,
+                                                   probe_stream=21, progress=progress)
     t_ref = time.perf_counter() - t0
 
     L = setup_learned(pb, h, X, y, w, args.learn_pairs, args.learn_epochs)
@@ -538,6 +666,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the compact batched leg of the main line")
     ap.add_argument("--profile-kmv", action="store_true")
+    ap.add_argument("--kmv-report", action="store_true",
+                    help="K.V throughput per precision mode on each workload shape (separate report)")
+    ap.add_argument("--cpu-report", action="store_true",
+                    help="the oracle's CPU timings on one and on all threads (no GPU; separate report)")
     ap.add_argument("--profile-util", action="store_true",
                     help="a few launches of each hot kernel, for rocprofv3 counter passes")
     ap.add_argument("--error-sweep", action="store_true",
@@ -577,6 +709,10 @@ def main():
               "(its kernels run one GPU's share of the work; the rows would shard across GPUs)", file=sys.stderr)
         sys.exit(2)
 
+    if args.cpu_report:
+        cpu_baseline_report()
+        return
+
     import numpy as np
     import torch
 
@@ -602,6 +738,9 @@ def main():
     y = torch.from_numpy(w["y"]).cuda()
     h = pb.Handle(0, seed=2015)
 
+    if args.kmv_report:
+        kmv_report(pb, h)
+        return
     if args.error_sweep:
         error_sweep(args, pb, h, X, y, w, psi0)
         return

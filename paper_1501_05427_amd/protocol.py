@@ -60,6 +60,42 @@ def exact_gradient(h, X, y, psi, eps=1e-6, max_iter=20000):
     return total
 
 
+def probe_mean_gradient(h, X, y, psi, batches, probes=31, probe_stream=21, eps=1e-6,
+                        max_iter=5000, progress=None):
+    """Reference gradient for large n: the plain estimator with converged solves (q = 0, so
+    the series never truncates) averaged over `batches` draws of `probes` Gaussian probes.
+
+    Each batch is an unbiased estimate of d/dpsi log p(y | psi) whose only error is the
+    Hutchinson noise of its probes (and the CG tolerance); returns (mean, standard error of
+    the mean) as numpy arrays.  Probes come from Philox stream `probe_stream`, one counter
+    per batch.
+    """
+    import torch
+    n = X.shape[0]
+    psid = psi if torch.is_tensor(psi) else torch.as_tensor(np.asarray(psi, np.float64)).cuda()
+    P = psid.shape[0]
+    ref = pb.make_params(q=0.0, rate=1.0, eps=eps, eps_relative=1, max_iter=max_iter, rng_stream=3)
+    R = pb.colmajor(n, probes)
+    S_warm = torch.zeros((1 + probes, n), dtype=torch.float64, device="cuda").t()
+    g = torch.zeros(P, dtype=torch.float64, device="cuda")
+    stats = pb.stats_tensor(1 + probes)
+    gs = []
+    for b in range(batches):
+        pb.gp_draw_probes(h, n, probes, pb.PROBE_GAUSSIAN, probe_stream, b, R=R)
+        S_warm[:, 1:].zero_()   # the y column keeps its warm start: q = 0 converges anyway
+        ref.rng_counter = b
+        pb.gp_stoch_grad(h, X, psid, y, ref, R=R, S_warm=S_warm, g=g, stats=stats)
+        gs.append(g.cpu().numpy().copy())
+        flags = [s["flags"] for s in pb.decode_stats(stats)]
+        if any(flags):
+            raise RuntimeError(f"a reference solve did not converge (flags {flags}); raise max_iter")
+        if progress is not None:
+            progress(b + 1, batches)
+    gs = np.array(gs)
+    se = gs.std(0, ddof=1) / np.sqrt(len(gs)) if len(gs) > 1 else np.full(P, np.inf)
+    return gs.mean(0), se
+
+
 def log_post_grad(h, X, y, psi, prior=None):
     psi = np.asarray(psi, np.float64)
     return exact_gradient(h, X, y, psi) + _prior_grad(psi, prior)

@@ -237,6 +237,20 @@ def test_kmv_full_size_sampled_n16384_m17(h):
     assert colwise_rel(out.cpu().numpy()[rows], ref).max() <= 1e-5
 
 
+def test_kmv_full_size_sampled_mixture_n131072_d16(h):
+    # the largest workload (n = 131072, d = 16, 8-Gaussian mixture inputs, m = 32) in the
+    # default launch shape (two row blocks per wave at d = 16); sampled rows from the oracle
+    w = workloads.mixture(n=131072, d=16, seed=4)
+    X, psi = w["X"], w["psi"]
+    V = workloads.gaussian_matrix(131072, 32, seed=14)
+    out = pb.gp_kmv(h, dev(X), dev(psi), colm(V))
+    torch.cuda.synchronize()
+    rows = np.sort(np.random.default_rng(4).choice(131072, 24, replace=False))
+    rows[0], rows[-1] = 0, 131071
+    ref = ogp.kmv(X, psi, V, rows=rows)
+    assert colwise_rel(out.cpu().numpy()[rows], ref).max() <= 1e-5
+
+
 @pytest.mark.parametrize("rows_seed", [0, 1])
 def test_kmv_full_size_sampled(h, rows_seed):
     # the benchmark's workload (n = 65536, d = 8, m = 32) in the benchmark's launch shape;

@@ -671,7 +671,8 @@ def main():
     ap.add_argument("--cpu-report", action="store_true",
                     help="the oracle's CPU timings on one and on all threads (no GPU; separate report)")
     ap.add_argument("--profile-util", action="store_true",
-                    help="a few launches of each hot kernel, for rocprofv3 counter passes")
+                    help="a few launches of each hot kernel (and of the n = 16384, m = 17 product), "
+                         "for rocprofv3 counter passes")
     ap.add_argument("--error-sweep", action="store_true",
                     help="gradient error vs estimates/s, plain FP32 vs learned + BF16 (separate report)")
     ap.add_argument("--sweep-reps", type=int, default=100)
@@ -762,6 +763,13 @@ def main():
         for prec in (pb.GP_FP32, pb.GP_BF16_SPLIT_KV):
             for _ in range(3):
                 pb.gp_kmv(h, X, psi0, V, out=out, prec=prec)
+        # the n = 16384, d = 8 shape with y + 16 probes (one MFMA block, one VALU column)
+        w2 = workloads.rff_gp(n=16384, d=8, seed=1)
+        X2, psi2 = torch.from_numpy(w2["X"]).cuda(), torch.from_numpy(w2["psi"]).cuda()
+        V2 = pb.colmajor(16384, 17)
+        V2.copy_(torch.from_numpy(workloads.gaussian_matrix(16384, 17, seed=12)).cuda())
+        for _ in range(3):
+            pb.gp_kmv(h, X2, psi2, V2)
         R = pb.colmajor(N, NPROBES)
         R.copy_(V[:, 1:])
         S_warm = torch.zeros((M, N), dtype=torch.float64, device="cuda").t()

@@ -20,6 +20,7 @@ struct KmvShape {
     int mp;           // padded column count of V seen by the kernel
     int tail = 0;     // FP32 MFMA path: columns past the last multiple of 16 taken on the
                       // VALU (1..4; mp is then 16 floor(m / 16) + 4), else 0
+    int mu = 0;       // VALU path: columns contracted (m or mp; mp - mu < 4), 0 = all mp
     int rows_per_wg;  // rows of K handled by one workgroup
     int split;        // column chunks (split-K), chunk index = blockIdx % split
     int chunk;        // columns of K per chunk (multiple of 64)

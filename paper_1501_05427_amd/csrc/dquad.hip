@@ -42,15 +42,27 @@ __device__ inline void load_row_q(const float* __restrict__ p, float (&z)[D]) {
     for (int k = 0; k < D; ++k) z[k] = tmp[k];
 }
 
+// MQ consecutive floats from LDS: 16-byte reads when MQ is a multiple of 4, else 8-byte
+// reads (MQ even; the row stride and q * MQ keep the address 8-byte aligned).
 template <int MQ>
 __device__ inline void load_op(const float* __restrict__ p, float (&o)[MQ]) {
+    static_assert(MQ % 2 == 0, "even operand length");
+    if constexpr (MQ % 4 == 0) {
 #pragma unroll
-    for (int t = 0; t < MQ; t += 4) {
-        const float4 v = *reinterpret_cast<const float4*>(p + t);
-        o[t] = v.x;
-        o[t + 1] = v.y;
-        o[t + 2] = v.z;
-        o[t + 3] = v.w;
+        for (int t = 0; t < MQ; t += 4) {
+            const float4 v = *reinterpret_cast<const float4*>(p + t);
+            o[t] = v.x;
+            o[t + 1] = v.y;
+            o[t + 2] = v.z;
+            o[t + 3] = v.w;
+        }
+    } else {
+#pragma unroll
+        for (int t = 0; t < MQ; t += 2) {
+            const float2 v = *reinterpret_cast<const float2*>(p + t);
+            o[t] = v.x;
+            o[t + 1] = v.y;
+        }
     }
 }
 
@@ -388,7 +400,9 @@ DquadShape dquad_shape(int64_t n, int d, int mcols) {
     (void)d;
     DquadShape sh;
     sh.n_pad = round_up(std::max<int64_t>(n, 1), kRowPad);
-    sh.mq4 = (int)round_up(std::max(mcols, 1), 16);
+    // columns of A and B padded to 8: the k-slots of the 16x16x4 MFMA take 4 columns per
+    // step and the two accumulator chains an even number of steps
+    sh.mq4 = (int)round_up(std::max(mcols, 1), 8);
     sh.mqb = (int)round_up(std::max(mcols, 1), 32);
     sh.rows_per_wg = kTile;
     const int64_t T = sh.n_pad / kTile;
@@ -417,13 +431,20 @@ template <int D>
 static hipError_t dquad_d(const DquadShape& sh, const float* Z, const float* A, const float* B,
                           const KParams* kp, const int2* work, double* gpart, hipStream_t s) {
     const dim3 grid((unsigned)sh.nwg);
+#define GPK_DQ_LAUNCH(MQ) \
+    case 4 * MQ: dquad_sym_kernel<D, MQ><<<grid, kWG, 0, s>>>(Z, A, B, gpart, sh.n_pad, work, sh.chunk, kp); break
     switch (sh.mq4) {
-        case 16: dquad_sym_kernel<D, 4><<<grid, kWG, 0, s>>>(Z, A, B, gpart, sh.n_pad, work, sh.chunk, kp); break;
-        case 32: dquad_sym_kernel<D, 8><<<grid, kWG, 0, s>>>(Z, A, B, gpart, sh.n_pad, work, sh.chunk, kp); break;
-        case 48: dquad_sym_kernel<D, 12><<<grid, kWG, 0, s>>>(Z, A, B, gpart, sh.n_pad, work, sh.chunk, kp); break;
-        case 64: dquad_sym_kernel<D, 16><<<grid, kWG, 0, s>>>(Z, A, B, gpart, sh.n_pad, work, sh.chunk, kp); break;
+        GPK_DQ_LAUNCH(2);
+        GPK_DQ_LAUNCH(4);
+        GPK_DQ_LAUNCH(6);
+        GPK_DQ_LAUNCH(8);
+        GPK_DQ_LAUNCH(10);
+        GPK_DQ_LAUNCH(12);
+        GPK_DQ_LAUNCH(14);
+        GPK_DQ_LAUNCH(16);
         default: return hipErrorInvalidValue;
     }
+#undef GPK_DQ_LAUNCH
     return hipGetLastError();
 }
 

@@ -66,7 +66,7 @@ size_t dkmv_part_floats(const KmvShape& sh, int d);
 // partials for j = 0..d at gpart[j * nwg + workgroup].  The work table lists (row tile, first column tile) per
 // workgroup; dquad_work builds it on the host.
 struct DquadShape {
-    int mq4;          // padded column count of A and B (multiple of 16)
+    int mq4;          // padded column count of A and B (multiple of 8)
     int mqb;          // padded column count of the BF16 operands (multiple of 32)
     int rows_per_wg;  // rows of a row tile (64)
     int split;        // unused

@@ -433,6 +433,36 @@ def test_stoch_grad_full_size_consistency(h):
         assert s["l"] >= 1 and s["iters"] == s["l"] + max(s["J_a"], s["J_b"]) and s["flags"] == 0
 
 
+@pytest.mark.parametrize("d,nr", [(3, 4), (12, 20), (5, 36), (8, 52), (2, 62)])
+def test_stoch_grad_consistency_column_counts(h, d, nr):
+    # the fused gradient reduction at every padded width of its A and B operands (1 + nr
+    # columns rounded up to 8, 8 to 64) against derivative products of the same series
+    # estimates (gp_dkmv), assembled in FP64 on the host; a ragged n over several tiles
+    n = 3000
+    X, psi = problem(n, d, seed=40 + nr, lam=0.2, ell=(0.3, 0.9))
+    y = np.random.default_rng(nr).standard_normal(n).astype(np.float32)
+    R = workloads.gaussian_matrix(n, nr, seed=nr + 1)
+    Xd, psid, yd, Rd = dev(X), dev(psi), dev(y), colm(R)
+    params = pb.make_params(q=0.5, rate=1.0, eps=1e-6, eps_relative=1, max_iter=500,
+                            rng_stream=6, rng_counter=2)
+    g, stats = pb.gp_stoch_grad(h, Xd, psid, yd, params, R=Rd)
+    B = torch.cat([yd[:, None], Rd], dim=1).t().contiguous().t()
+    p2 = pb.make_params(q=0.5, rate=1.0, eps=1e-6, eps_relative=1, max_iter=500,
+                        two_track_first=1, rng_stream=6, rng_counter=2)
+    St, stats2 = pb.ulisse_solve(h, Xd, psid, B, p2)
+    dKS = pb.gp_dkmv(h, Xd, psid, St.float().t().contiguous().t())   # (P, m+1, n)
+    torch.cuda.synchronize()
+    assert pb.decode_stats(stats) == pb.decode_stats(stats2)
+    Stn = St.cpu().numpy()
+    dKSn = dKS.cpu().numpy().astype(np.float64)
+    Rn = R.astype(np.float64)
+    ref = np.array([0.5 * Stn[:, 0] @ dKSn[j, 1] - sum(Rn[:, c] @ dKSn[j, c + 2] for c in range(nr)) / (2 * nr)
+                    for j in range(d + 2)])
+    gn = g.cpu().numpy()
+    assert np.all(np.isfinite(gn))
+    np.testing.assert_allclose(gn, ref, rtol=1e-4, atol=1e-5 * np.abs(ref).max())
+
+
 @pytest.mark.parametrize("prior_kind", [0, 1, 2])
 def test_sgld_step_parity(h, prior_kind):
     P = 6

@@ -76,8 +76,17 @@ __global__ void pc_reduce_kernel(SolverArgs a, int nchunk, int first) {
     const int nout = a.pk * a.m;
     const int o = blockIdx.x * blockDim.x + threadIdx.x;
     if (o >= nout) return;
+    // chunks summed in order; eight loads in flight at a time (the adds stay sequential)
     double s = 0.0;
-    for (int b = 0; b < nchunk; ++b) s += a.utv_part[(int64_t)b * nout + o];
+    int b = 0;
+    for (; b + 8 <= nchunk; b += 8) {
+        double v[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) v[t] = a.utv_part[(int64_t)(b + t) * nout + o];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) s += v[t];
+    }
+    for (; b < nchunk; ++b) s += a.utv_part[(int64_t)b * nout + o];
     a.HW[o] = a.coef[o / a.m] * s;
 }
 

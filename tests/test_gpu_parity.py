@@ -398,7 +398,7 @@ def test_stoch_grad_exact_solve_mean_matches_exact_gradient(h):
     gs = torch.stack(gs).cpu().numpy()
     se = gs.std(axis=0, ddof=1) / np.sqrt(N)
     z = (gs.mean(axis=0) - g_exact) / se
-    assert np.all(np.abs(z) < 4.5), z
+    assert np.all(np.abs(z) < 3.0), z   # gradient means within 3 Monte Carlo standard errors
 
 
 def test_stoch_grad_full_size_consistency(h):
@@ -846,14 +846,14 @@ def test_reference_gradient_on_subsample_4096_vs_oracle(h):
     # the reference gradient of the equal-error comparison (converged solves averaged over
     # Gaussian probe batches) on the first 4096 points of the n = 65536, d = 8 workload,
     # against the oracle's Cholesky gradient of the same points: every component within
-    # 5 standard errors of the batch mean (plus the 1e-6 CG tolerance scaled by |g|)
+    # 3 standard errors of the batch mean (plus the 1e-6 CG tolerance scaled by |g|)
     from paper_1501_05427_amd import protocol
     w = workloads.rff_gp(n=65536, d=8, seed=2)
     X, psi, y = w["X"][:4096], w["psi"], w["y"][:4096]
     mean, se = protocol.probe_mean_gradient(h, dev(X), dev(y), psi, batches=16, probes=31)
     ref = ogp.exact_gradient(X.astype(np.float64), psi, y.astype(np.float64))
     assert np.all(np.isfinite(se)) and np.all(se > 0)
-    tol = 5.0 * se + 1e-5 * np.abs(ref).max()
+    tol = 3.0 * se + 1e-5 * np.abs(ref).max()
     assert np.all(np.abs(mean - ref) <= tol), (mean, ref, se)
     # and the noise is the Hutchinson noise, not a bias: the standard error is a small
     # fraction of the gradient's norm

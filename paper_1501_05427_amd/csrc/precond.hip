@@ -34,9 +34,19 @@ __global__ __launch_bounds__(kWG) void pc_utv_partial_kernel(SolverArgs a, int f
     __shared__ double es[kMaxSys][kSub + 1];
     const int m = a.m;
     const int nout = KB * m;
-    double acc[KB * kMaxSys / kWG];
+    // each thread owns blocks of 2 basis vectors x 4 systems, so that one pass over the
+    // staged rows reads 6 LDS operands per 8 FMAs; every output still sums its rows in
+    // order.  Block b: kappa = 2 (b / nq) + {0, 1}, c = 4 (b % nq) + {0..3}.
+    constexpr int NJ = (KB / 2 * (kMaxSys / 4) + kWG - 1) / kWG;
+    const int nq = (m + 3) / 4;
+    const int nblk = KB / 2 * nq;
+    double acc[NJ][2][4];
 #pragma unroll
-    for (int r = 0; r < KB * kMaxSys / kWG; ++r) acc[r] = 0.0;
+    for (int j = 0; j < NJ; ++j)
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) acc[j][u][t] = 0.0;
     const int64_t base = (int64_t)blockIdx.x * kChunk;
     for (int sub = 0; sub < kChunk / kSub; ++sub) {
         const int64_t r0 = base + sub * kSub;
@@ -45,28 +55,42 @@ __global__ __launch_bounds__(kWG) void pc_utv_partial_kernel(SolverArgs a, int f
             const int64_t i = r0 + rr;
             us[kappa][rr] = i < a.n ? a.U[kappa * a.ldu + i] : 0.f;
         }
-        for (int e = threadIdx.x; e < m * kSub; e += kWG) {
+        // systems m .. 4 nq - 1 of the last quad are staged as zeros
+        for (int e = threadIdx.x; e < 4 * nq * kSub; e += kWG) {
             const int c = e / kSub, rr = e % kSub;
             const int64_t i = r0 + rr;
-            es[c][rr] = i < a.n ? a.E[c * a.n_pad + i] : 0.0;
+            es[c][rr] = (c < m && i < a.n) ? a.E[c * a.n_pad + i] : 0.0;
         }
         __syncthreads();
 #pragma unroll
-        for (int r = 0; r < KB * kMaxSys / kWG; ++r) {
-            const int o = threadIdx.x + r * kWG;
-            if (o < nout) {
-                const int kappa = o / m, c = o % m;
-                double s = acc[r];
-                for (int rr = 0; rr < kSub; ++rr) s = fma((double)us[kappa][rr], es[c][rr], s);
-                acc[r] = s;
+        for (int j = 0; j < NJ; ++j) {
+            const int b = threadIdx.x + j * kWG;
+            if (b < nblk) {
+                const int k0 = 2 * (b / nq), c0 = 4 * (b % nq);
+                for (int rr = 0; rr < kSub; ++rr) {
+                    const double u0 = (double)us[k0][rr], u1 = (double)us[k0 + 1][rr];
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        const double ev = es[c0 + t][rr];
+                        acc[j][0][t] = fma(u0, ev, acc[j][0][t]);
+                        acc[j][1][t] = fma(u1, ev, acc[j][1][t]);
+                    }
+                }
             }
         }
         __syncthreads();
     }
 #pragma unroll
-    for (int r = 0; r < KB * kMaxSys / kWG; ++r) {
-        const int o = threadIdx.x + r * kWG;
-        if (o < nout) a.utv_part[(int64_t)blockIdx.x * nout + o] = acc[r];
+    for (int j = 0; j < NJ; ++j) {
+        const int b = threadIdx.x + j * kWG;
+        if (b < nblk) {
+            const int k0 = 2 * (b / nq), c0 = 4 * (b % nq);
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    if (c0 + t < m) a.utv_part[(int64_t)blockIdx.x * nout + (k0 + u) * m + c0 + t] = acc[j][u][t];
+        }
     }
 }
 

@@ -317,7 +317,23 @@ __global__ void dense_fwd_kernel(const float* __restrict__ X, int B, int I, cons
     if (e >= (int64_t)B * O) return;
     const int b = (int)(e / O), o = (int)(e % O);
     float s = bias[o];
-    for (int i = 0; i < I; ++i) {
+    // the dot products below load eight terms at a time and add them in order: at batch 1
+    // (one evaluation per SGLD step) a thread otherwise waits on one load per term
+    int i = 0;
+    for (; i + 8 <= I; i += 8) {
+        float xv[8], wv[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            xv[t] = X[(int64_t)b * I + i + t];
+            wv[t] = W[(int64_t)(i + t) * O + o];
+        }
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const float x = bf16 ? bf16_round(xv[t]) : xv[t], w = bf16 ? bf16_round(wv[t]) : wv[t];
+            s = __builtin_fmaf(x, w, s);
+        }
+    }
+    for (; i < I; ++i) {
         float x = X[(int64_t)b * I + i], w = W[(int64_t)i * O + o];
         if (bf16) {
             x = bf16_round(x);
@@ -335,7 +351,18 @@ __global__ void dense_bwd_in_kernel(const float* __restrict__ dY, int B, int O, 
     if (e >= (int64_t)B * I) return;
     const int b = (int)(e / I), i = (int)(e % I);
     float s = 0.f;
-    for (int o = 0; o < O; ++o) s = __builtin_fmaf(dY[(int64_t)b * O + o], W[(int64_t)i * O + o], s);
+    int o = 0;
+    for (; o + 8 <= O; o += 8) {
+        float dv[8], wv[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            dv[t] = dY[(int64_t)b * O + o + t];
+            wv[t] = W[(int64_t)i * O + o + t];
+        }
+#pragma unroll
+        for (int t = 0; t < 8; ++t) s = __builtin_fmaf(dv[t], wv[t], s);
+    }
+    for (; o < O; ++o) s = __builtin_fmaf(dY[(int64_t)b * O + o], W[(int64_t)i * O + o], s);
     if (Xact) {
         const float x = Xact[e];
         s *= 1.f - x * x;
@@ -350,7 +377,18 @@ __global__ void dense_bwd_w_kernel(const float* __restrict__ X, const float* __r
     if (e < (int64_t)I * O) {
         const int i = (int)(e / O), o = (int)(e % O);
         float s = 0.f;
-        for (int b = 0; b < B; ++b) s = __builtin_fmaf(X[(int64_t)b * I + i], dY[(int64_t)b * O + o], s);
+        int b = 0;
+        for (; b + 8 <= B; b += 8) {
+            float xv[8], dv[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                xv[t] = X[(int64_t)(b + t) * I + i];
+                dv[t] = dY[(int64_t)(b + t) * O + o];
+            }
+#pragma unroll
+            for (int t = 0; t < 8; ++t) s = __builtin_fmaf(xv[t], dv[t], s);
+        }
+        for (; b < B; ++b) s = __builtin_fmaf(X[(int64_t)b * I + i], dY[(int64_t)b * O + o], s);
         dW[e] = s;
     } else if (e < (int64_t)I * O + O) {
         const int o = (int)(e - (int64_t)I * O);

@@ -4,11 +4,51 @@ Inputs as in Alg. 1: a product v -> K v (the covariance matrix-vector product), 
 right-hand side b, the initial vector s_0, the threshold epsilon and the maximum number
 of iterations T.  The residual e is the algorithm's recursively updated one, not
 b - K s recomputed.  Reading taken for T: at most T products K d_i inside the loop.
+
+Residual replacement (refresh = k > 0): after an iteration whose recursive residual norm
+has fallen below 2^-k times the norm at the last replacement (or at the start), and is
+above `floor`, the recursive residual is replaced by b - K s_i.  With inexact products
+K d (the low-precision products of the GPU library) the recursive residual drifts from
+the true one and the iterates converge to the solution of a perturbed system, which the
+replacement prevents (the "reliable updates" of Sleijpen & van der Vorst, 1996, triggered
+by the residual reduction as in van der Vorst & Ye, 2000).  The replacement product has
+an accuracy floor of its own, and replacing the residual at that floor again and again
+stalls the iteration: a replacement whose residual is not at least twice smaller than
+the one at the previous replacement ends the replacements of this run.  The iteration
+restarts from the replaced residual (the next direction is the residual itself, or its
+preconditioned form), so that the recurrences stay consistent with it: after a
+replacement at iteration i the run continues as a fresh run of Alg. 1 from s_i, and the
+iterates still converge to K^-1 b, which is all the series of Sec. 4 needs.  The paper warns
+that single precision hurts CG (Sec. 3.2); this is the remedy for the BF16 products.
+`refresh_matvec` is the product used for the replacement (default: matvec).
 """
 import numpy as np
 
 
-def cg_iterates(matvec, b, s0):
+class _Replacement:
+    """The replacement rule of the module docstring for one CG run."""
+
+    def __init__(self, k, floor, matvec, b, e0):
+        self.k, self.floor, self.matvec, self.b = k, floor, matvec, b
+        self.ref = np.linalg.norm(e0)
+        self.on = bool(k)
+
+    def __call__(self, s, e):
+        """(residual, restart): the residual to continue with and whether it was replaced."""
+        if not self.on:
+            return e, False
+        r = np.linalg.norm(e)
+        if r < self.ref * 2.0 ** -self.k and r > self.floor:
+            e = self.b - self.matvec(s)
+            r_new = np.linalg.norm(e)
+            if not r_new < 0.5 * self.ref:
+                self.on = False
+            self.ref = r_new
+            return e, True
+        return e, False
+
+
+def cg_iterates(matvec, b, s0, refresh=0, refresh_matvec=None, floor=0.0):
     """Yield (i, s_i, e_i, delta_i) for i = 1, 2, ... following Alg. 1.
 
     delta_i = s_i - s_{i-1} = alpha_{i-1} d_{i-1} is the increment that the ULISSE
@@ -17,6 +57,7 @@ def cg_iterates(matvec, b, s0):
     b = np.asarray(b, dtype=np.float64)
     s = np.array(s0, dtype=np.float64, copy=True)
     e = b - matvec(s)
+    replace = _Replacement(refresh, floor, refresh_matvec or matvec, b, e)
     d = e.copy()
     rho = e @ e
     i = 0
@@ -27,9 +68,10 @@ def cg_iterates(matvec, b, s0):
         s = s + delta
         e = e - alpha * q
         i += 1
+        e, restart = replace(s, e)
         yield i, s, e, delta
         rho_next = e @ e
-        beta = rho_next / rho
+        beta = 0.0 if restart else rho_next / rho
         d = e + beta * d
         rho = rho_next
 
@@ -49,7 +91,7 @@ def cg(matvec, b, s0, eps, max_iter):
             return s, i, False, r
 
 
-def pcg_iterates(matvec, apply_pinv, b, s0):
+def pcg_iterates(matvec, apply_pinv, b, s0, refresh=0, refresh_matvec=None, floor=0.0):
     """Preconditioned CG (the variant named in Sec. 3.3, with a preconditioner applied as
     z = P^-1 e): yields (i, s_i, e_i, delta_i) like cg_iterates.
 
@@ -59,6 +101,7 @@ def pcg_iterates(matvec, apply_pinv, b, s0):
     b = np.asarray(b, dtype=np.float64)
     s = np.array(s0, dtype=np.float64, copy=True)
     e = b - matvec(s)
+    replace = _Replacement(refresh, floor, refresh_matvec or matvec, b, e)
     z = apply_pinv(e)
     d = z.copy()
     rho = e @ z
@@ -70,10 +113,11 @@ def pcg_iterates(matvec, apply_pinv, b, s0):
         s = s + delta
         e = e - alpha * q
         i += 1
+        e, restart = replace(s, e)
         yield i, s, e, delta
         z = apply_pinv(e)
         rho_next = e @ z
-        beta = rho_next / rho
+        beta = 0.0 if restart else rho_next / rho
         d = z + beta * d
         rho = rho_next
 

@@ -9,6 +9,8 @@ arithmetic:
   MLP               in -> H (tanh) -> H (tanh) -> O on standardised inputs, mean squared
                     error on standardised targets, hand-written backpropagation
   Adam              Kingma & Ba (2015), bias-corrected moments
+  coefficients      network output -> (h, tau_inv, c), with the plain solver as fallback
+                    when the output is unusable
 """
 import numpy as np
 
@@ -67,9 +69,23 @@ def adam_step(p, g, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):
 
 
 def precond_coefficients(outputs, out_mu, out_sd, k):
-    """Network output (standardised) -> (h, tau_inv, c) of P^-1 = tau^-1 I + U diag(h) U^T,
-    with d floored at tau."""
-    u = out_mu + out_sd * np.asarray(outputs, dtype=np.float64)
-    tau = np.exp(np.clip(u[2 * k], -60, 60))
-    d = np.maximum(np.exp(np.clip(u[k:2 * k], -60, 60)), tau)
-    return 1.0 / d - 1.0 / tau, 1.0 / tau, u[:k]
+    """Network output (standardised) -> (h, tau_inv, c, accepted) of
+    P^-1 = tau^-1 I + U diag(h) U^T and the warm start s0 = U c, with d floored at tau.
+
+    u = out_mu + out_sd * outputs holds c (k values), log d (k) and log tau.  The output is
+    rejected when any u is not finite or a log d or log tau lies outside [-60, 60]: the
+    solver then falls back to plain CG, represented as h = 0, tau_inv = -1, c = 0 and
+    accepted = False.
+    """
+    u = np.asarray(out_mu, dtype=np.float64) + np.asarray(out_sd, dtype=np.float64) * np.asarray(outputs, dtype=np.float64)
+    logs = u[k:2 * k + 1]
+    if not np.all(np.isfinite(u)) or np.any(np.abs(logs) > 60.0):
+        return np.zeros(k), -1.0, np.zeros(k), False
+    tau = np.exp(u[2 * k])
+    d = np.maximum(np.exp(u[k:2 * k]), tau)
+    return 1.0 / d - 1.0 / tau, 1.0 / tau, u[:k], True
+
+
+def warm_start(U, c):
+    """s0 = U c, the learned warm start of the y system."""
+    return np.asarray(U, dtype=np.float64) @ np.asarray(c, dtype=np.float64)

@@ -27,7 +27,7 @@ def assemble(X, psi, R, St):
 
 
 def stoch_grad(X, psi, y, R, q, rate, eps, max_iter, seed, stream, step,
-               S_warm=None, eps_relative=False, apply_pinv=None):
+               S_warm=None, eps_relative=False, apply_pinv=None, refresh=0):
     """One unbiased gradient estimate.  R (n, N_r) holds the probes r_c.
 
     Returns (g, St, S_cg, stats); S_cg are the last CG iterates (warm starts).
@@ -39,7 +39,8 @@ def stoch_grad(X, psi, y, R, q, rate, eps, max_iter, seed, stream, step,
     B = np.column_stack([y, R])
     St, Scg, stats = _ul.solve_systems(lambda v: K @ v, B, S_warm, q, rate, eps, max_iter,
                                        seed, stream, step, two_track_first=True,
-                                       eps_relative=eps_relative, apply_pinv=apply_pinv)
+                                       eps_relative=eps_relative, apply_pinv=apply_pinv,
+                                       refresh=refresh)
     return assemble(X, psi, R, St), St, Scg, stats
 
 

@@ -13,7 +13,9 @@ Readings where the paper is silent:
   * CG convergence (||e|| < eps) ends the series: every later increment is zero;
   * the iteration cap ends it too and sets NOTCONV (the estimate is then biased);
   * u_j < 1/w_j is a strict comparison in FP64 with 1/w_j = exp(-rate j);
-  * several tracks share one CG path and draw their u_j independently (Sec. 4.1).
+  * several tracks share one CG path and draw their u_j independently (Sec. 4.1);
+  * with residual replacement (refresh = k) a residual that has fallen by 2^k since the
+    last replacement, and is above 2^k eps, is replaced by b - K s_i (see oracle.cg).
 """
 import numpy as np
 
@@ -42,11 +44,11 @@ def expected_tail_terms(rate, jmax=100000):
 class _LazyCG:
     """One CG run whose increments are produced on demand and shared by all tracks."""
 
-    def __init__(self, matvec, b, s0, apply_pinv=None):
+    def __init__(self, matvec, b, s0, apply_pinv=None, refresh=0, floor=0.0, refresh_matvec=None):
         if apply_pinv is None:
-            self.it = _cg.cg_iterates(matvec, b, s0)
+            self.it = _cg.cg_iterates(matvec, b, s0, refresh, refresh_matvec, floor)
         else:
-            self.it = _cg.pcg_iterates(matvec, apply_pinv, b, s0)
+            self.it = _cg.pcg_iterates(matvec, apply_pinv, b, s0, refresh, refresh_matvec, floor)
         self.deltas = [None]     # 1-based: deltas[i] = delta_i
         self.norms = [None]
         self.last_s = np.array(s0, dtype=np.float64, copy=True)
@@ -60,7 +62,8 @@ class _LazyCG:
         return self.deltas[i], self.norms[i]
 
 
-def solve(matvec, b, s0, alpha, eps, max_iter, rate, uniform, ntracks=1, apply_pinv=None):
+def solve(matvec, b, s0, alpha, eps, max_iter, rate, uniform, ntracks=1, apply_pinv=None,
+          refresh=0, refresh_matvec=None):
     """One ULISSE solve of K s = b (over preconditioned CG when apply_pinv is given: the
     series argument of Sec. 4 holds for any CG variant, as the paper notes).
 
@@ -72,7 +75,7 @@ def solve(matvec, b, s0, alpha, eps, max_iter, rate, uniform, ntracks=1, apply_p
       flags    NOTCONV if the cap was hit before the series ended
     """
     b = np.asarray(b, dtype=np.float64)
-    cgrun = _LazyCG(matvec, b, s0, apply_pinv)
+    cgrun = _LazyCG(matvec, b, s0, apply_pinv, refresh, eps, refresh_matvec)
     base = np.array(s0, dtype=np.float64, copy=True)
     flags = 0
     i = 0
@@ -118,7 +121,8 @@ def solve(matvec, b, s0, alpha, eps, max_iter, rate, uniform, ntracks=1, apply_p
 
 
 def solve_systems(matvec, B, S0, q, rate, eps, max_iter, seed, stream, step,
-                  two_track_first=False, eps_relative=False, apply_pinv=None):
+                  two_track_first=False, eps_relative=False, apply_pinv=None, refresh=0,
+                  refresh_matvec=None):
     """ULISSE on every column of B with the library's counter layout for the u_j.
 
     Column c is system c; with two_track_first, column 0 carries tracks 0 and 1.
@@ -137,7 +141,8 @@ def solve_systems(matvec, B, S0, q, rate, eps, max_iter, seed, stream, step,
         def uniform(t, j, c=c):
             return _rng.ulisse_uniform(seed, stream, step, c, t, j)
 
-        res = solve(matvec, b, s0, alpha, thr, max_iter, rate, uniform, nt, apply_pinv)
+        res = solve(matvec, b, s0, alpha, thr, max_iter, rate, uniform, nt, apply_pinv, refresh,
+                    refresh_matvec)
         out_cols.extend(res["s_tilde"])
         scg[:, c] = res["s_cg"]
         stats.append(dict(l=res["l"], J=res["J"], iters=res["iters"], flags=res["flags"]))

@@ -206,3 +206,117 @@ def test_pcg_shifted_converges_to_the_solution_with_inexact_inner_solves():
             break
     assert i < 300
     np.testing.assert_allclose(s, sla.cho_solve(sla.cho_factor(K), b), rtol=1e-7, atol=1e-8)
+
+
+def _spd_kappa(n, seed, kappa):
+    r = np.random.default_rng(seed)
+    Q, _ = np.linalg.qr(r.standard_normal((n, n)))
+    return (Q * np.geomspace(1.0, kappa, n)) @ Q.T
+
+
+def _restart_check(make_run, iterates_fresh, K, b, n_first):
+    """Up to the first replacement the run is plain (P)CG; after a replacement at
+    iteration i the run continues exactly as a fresh run started from s_i."""
+    calls = []
+
+    def counted(v):
+        calls.append(1)
+        return K @ v
+
+    run, at = [], []
+    for i, s, e, d in make_run(counted):
+        run.append((i, s.copy(), e.copy()))
+        if calls and not at:
+            at.append(i)
+        if len(run) == n_first:
+            break
+    assert at, "no replacement happened"
+    i_rep = at[0]
+    ref = list(zip(range(i_rep), iterates_fresh(np.zeros(len(b)))))
+    for (_, (i2, s2, e2, _d2)), (i, s, e) in zip(ref, run):
+        np.testing.assert_allclose(s, s2, rtol=1e-9, atol=1e-12 * np.abs(s2).max())
+    s_i = run[i_rep - 1][1]
+    # the replaced residual is the true one ...
+    np.testing.assert_allclose(run[i_rep - 1][2], b - K @ s_i, rtol=0, atol=1e-12 * np.linalg.norm(b))
+    # ... and the following iterates are those of a fresh run from s_i
+    fresh = list(zip(range(3), iterates_fresh(s_i)))
+    for j in range(3):
+        s_run = run[i_rep + j][1]
+        np.testing.assert_allclose(s_run, fresh[j][1][1], rtol=1e-8, atol=1e-10 * np.abs(s_run).max())
+
+
+def test_residual_replacement_restarts_cg_from_the_current_iterate():
+    K = _spd_kappa(60, 0, 1e3)
+    b = np.random.default_rng(1).standard_normal(60)
+    mv = lambda v: K @ v
+    _restart_check(lambda rm: cg.cg_iterates(mv, b, np.zeros(60), refresh=2, refresh_matvec=rm),
+                   lambda s0: cg.cg_iterates(mv, b, s0), K, b, 40)
+
+
+def test_residual_replacement_rule():
+    # exact products, so a replaced residual has the norm of the recursive one: the
+    # replacements happen exactly where the recursive norm first falls below 2^-k of the
+    # norm at the previous replacement, while it is above the floor
+    K = _spd_kappa(40, 6, 1e2)
+    b = np.random.default_rng(7).standard_normal(40)
+    calls = []
+
+    def counted(v):
+        calls.append(1)
+        return K @ v
+
+    k, floor = 2, 1e-6 * np.linalg.norm(b)
+    ref, expect, got = np.linalg.norm(b), [], []
+    for i, s, e, _ in cg.cg_iterates(lambda v: K @ v, b, np.zeros(40), refresh=k,
+                                     refresh_matvec=counted, floor=floor):
+        r = np.linalg.norm(e)
+        if r < ref * 2.0 ** -k and r > floor:
+            expect.append(i)
+            ref = r
+        got += [i] * (len(calls) - len(got))
+        if r < 1e-3 * floor or i >= 200:
+            break
+    assert got == expect and len(got) >= 3, (got, expect)
+    # the rule stops replacing below the floor
+    assert all(np.isfinite(got))
+
+
+def test_residual_replacement_removes_the_bias_of_inexact_products():
+    # products with a fixed relative perturbation (K + E) d, the way low-precision tile
+    # products perturb K d: without replacement CG converges to (K + E)^-1 b; with the
+    # residual replaced (by b - K s, an accurate product) whenever it has fallen by 2^4,
+    # down to 2^4 times the stopping threshold, to K^-1 b within that threshold
+    n = 80
+    K = _spd_kappa(n, 2, 1e2)
+    r = np.random.default_rng(3)
+    E = r.standard_normal((n, n))
+    E = 0.5 * (E + E.T)
+    E *= 3e-3 * np.linalg.norm(K, 2) / np.linalg.norm(E, 2)
+    b = r.standard_normal(n)
+    x = np.linalg.solve(K, b)
+    x_pert = np.linalg.solve(K + E, b)
+    inexact = lambda v: (K + E) @ v
+    exact = lambda v: K @ v
+    thr = 1e-10 * np.linalg.norm(b)
+    last = {}
+    for name, kw in [("none", {}), ("refresh", dict(refresh=4, refresh_matvec=exact, floor=thr))]:
+        for i, s, e, _ in cg.cg_iterates(inexact, b, np.zeros(n), **kw):
+            if np.linalg.norm(e) < thr or i == 2000:
+                last[name] = s
+                break
+    err_none = np.linalg.norm(last["none"] - x) / np.linalg.norm(x)
+    err_fresh = np.linalg.norm(last["refresh"] - x) / np.linalg.norm(x)
+    assert np.linalg.norm(last["none"] - x_pert) < 1e-8 * np.linalg.norm(x)
+    assert err_none > 1e-3
+    # the last replacement happens above thr; the drift after it is 3e-3 of what is left
+    assert err_fresh < 1e-8, (err_none, err_fresh)
+
+
+def test_pcg_residual_replacement_restarts_pcg_from_the_current_iterate():
+    K = _spd_kappa(50, 4, 1e3)
+    b = np.random.default_rng(5).standard_normal(50)
+    w, Q = np.linalg.eigh(K)
+    pinv = cg.lowrank_pinv(Q[:, -8:], 1.0 / w[-8:] - 1.0 / w[:-8].mean(), 1.0 / w[:-8].mean())
+    mv = lambda v: K @ v
+    _restart_check(lambda rm: cg.pcg_iterates(mv, pinv, b, np.zeros(50), refresh=2, refresh_matvec=rm),
+                   lambda s0: cg.pcg_iterates(mv, pinv, b, s0), K, b, 40)

@@ -251,3 +251,34 @@ def test_exact_mean_from_a_warm_start_is_the_solution():
             total += p
         np.testing.assert_allclose(total, 1.0, rtol=1e-12)
         np.testing.assert_allclose(mean, sol, rtol=1e-7, atol=1e-8)
+
+
+def test_converged_series_with_residual_replacement_is_the_solution():
+    # with replacements (and the restarts they bring) the CG iterates still converge to
+    # K^-1 b, so a series run to convergence returns the Cholesky solution
+    r = np.random.default_rng(11)
+    X = r.uniform(size=(120, 2)).astype(np.float32)
+    psi = np.log([1.0, 0.25, 0.4, 0.05])
+    K = gp.kernel_matrix(X, psi)
+    B = r.standard_normal((120, 3))
+    St, _, stats = ulisse.solve_systems(lambda v: K @ v, B, None, 1e-12, 1e-9, 1e-10, 2000, 5, 1, 0,
+                                        eps_relative=True, refresh=3)
+    np.testing.assert_allclose(St, np.linalg.solve(K, B), rtol=1e-6, atol=1e-8)
+    assert all(s["flags"] == 0 for s in stats)
+
+
+def test_residual_replacement_keeps_the_exact_mean_of_the_series():
+    # the exact mean over the truncation points of one path (the enumeration pin of the
+    # plain series) holds over a path with replacements too: E[s~] = s_T
+    r = np.random.default_rng(12)
+    X = r.uniform(size=(40, 2)).astype(np.float32)
+    psi = np.log([1.0, 0.3, 0.3, 0.2])
+    K = gp.kernel_matrix(X, psi)
+    b = r.standard_normal(40)
+    its = list(zip(range(12), cg.cg_iterates(lambda v: K @ v, b, np.zeros(40), refresh=1)))
+    deltas = [dl for _, (i, s, e, dl) in its]
+    s_T = its[-1][1][1]
+    l = 3
+    base = sum(deltas[:l - 1])
+    tail = [deltas[l - 1 + j] for j in range(len(deltas) - l + 1)]
+    np.testing.assert_allclose(ulisse.exact_mean(base, tail), s_T, rtol=1e-12, atol=1e-12)

@@ -96,7 +96,15 @@ typedef struct {
     int32_t eps_relative;   /* 1: threshold eps ||b||_2 per system; 0: absolute eps        */
     int32_t max_iter;       /* T of Alg. 1: at most this many products K d per system     */
     int32_t two_track_first;/* 1: system 0 keeps two estimates drawn independently        */
-    int32_t reserved;
+    int32_t refresh;        /* residual replacement, k in [1, 30]: after an iteration whose
+                               residual norm has fallen below 2^-k of its value at the last
+                               replacement (or the start) and is above the convergence
+                               threshold, the recursive residual is replaced by b - K s
+                               computed with an FP32 product and the iteration restarts
+                               from it (next direction = residual); a replacement that gains
+                               less than 2x ends the replacements of that system.  Removes
+                               the bias that BF16 products leave in the limit of the
+                               iterates (Sec. 3.2 on reduced precision).  0: never         */
     uint64_t rng_stream;    /* second Philox key word                                       */
     uint64_t rng_counter;   /* step word of the Philox counter                              */
     gp_precision prec;      /* arithmetic of the products K d; in the BF16 modes the G tiles
@@ -110,13 +118,20 @@ typedef struct {
  * with h_kappa = 1/d_kappa - tau_inv for orthonormal U.  U: n x k FP32 device, column-major
  * with ld ldu >= n, k in {16, 32, 64}.  coef: k + 1 FP64 device values, h_0..h_{k-1}
  * then tau_inv.  P must be SPD (d_kappa > 0, tau_inv > 0).  The residual norms that set l
- * and the convergence test stay unpreconditioned (||b - K s||_2). */
+ * and the convergence test stay unpreconditioned (||b - K s||_2).
+ * Fallback: a negative tau_inv (precond_from_mlp writes -1 when the network output is
+ * unusable) makes every solve over this descriptor the plain CG of Alg. 1 (P = I, the
+ * warm start below unused) and sets ULISSE_FALLBACK in the statistics of every system.
+ * Warm start: with warm_start = 1, system 0 (y in gp_stoch_grad_pc) starts from s0 = U c,
+ * c = k FP64 device values (the network's warm-start coefficients), instead of its column
+ * of S0 / S_warm. */
 typedef struct {
     const float* U;
     int64_t ldu;
     int32_t k;
-    int32_t reserved;
+    int32_t warm_start;
     const double* coef;
+    const double* c;
 } gp_precond;
 
 /* Per-system outcome, written by the device.  J_b = -1 for a single-track system. */
@@ -126,12 +141,13 @@ typedef struct {
     int32_t J_b;     /* last kept tail index of track b                                     */
     int32_t iters;   /* products K d taken (excluding the warm-start residual)              */
     double final_res;/* ||e|| of Alg. 1's recursive residual at the last iteration         */
-    uint32_t flags;  /* ULISSE_NOTCONV | ULISSE_BREAKDOWN                                   */
+    uint32_t flags;  /* ULISSE_NOTCONV | ULISSE_BREAKDOWN | ULISSE_FALLBACK                 */
     uint32_t pad;
 } ulisse_sysstat;
 
 #define ULISSE_NOTCONV 1u    /* max_iter reached before the series ended (biased estimate) */
 #define ULISSE_BREAKDOWN 2u  /* d^T K d <= 0 or a non-finite scalar; the system stopped    */
+#define ULISSE_FALLBACK 4u   /* the preconditioner was unusable: the plain solver ran       */
 
 /*
  * Unbiased solves K s = b_c for the m columns of B (n x m FP32, ldb >= n) by the ULISSE
@@ -304,7 +320,10 @@ gp_status sgld_run(gp_handle* h, gp_data X, double* psi, const float* y,
  *   BF16 operands and FP32 accumulation.
  * precond_mlp_grad: loss and gradient of the trainable parameters (for checks).
  * precond_from_mlp: BF16 forward at one psi (device, P) -> coef (k + 1 FP64: h, tau_inv;
- *   d is floored at tau so P stays SPD) and, if non-null, c (k FP64).
+ *   d is floored at tau so P stays SPD) and, if non-null, c (k FP64).  If any output is
+ *   not finite, or a log d or log tau lies outside [-60, 60], the output is rejected: coef
+ *   becomes h = 0, tau_inv = -1 (the fallback marker of gp_precond: the plain solver runs)
+ *   and c = 0.  Everything happens on the device, so the call never waits.
  * precond_warm_start: s0 = U c (n FP64).
  */
 gp_status precond_build_basis(gp_handle* h, gp_data X, const double* psi_ref, int32_t k,

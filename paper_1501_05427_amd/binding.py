@@ -21,7 +21,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "ulisse_gp.h")
 
 GP_OK, GP_EINVAL, GP_ENOMEM, GP_EDEVICE, GP_EUNSUPPORTED = 0, -1, -2, -3, -4
 GP_FP32, GP_BF16_SPLIT_V, GP_BF16_SPLIT_KV = 0, 1, 2
-ULISSE_NOTCONV, ULISSE_BREAKDOWN = 1, 2
+ULISSE_NOTCONV, ULISSE_BREAKDOWN, ULISSE_FALLBACK = 1, 2, 4
 PROBE_GAUSSIAN, PROBE_RADEMACHER = 0, 1
 
 
@@ -32,7 +32,7 @@ class gp_data(Structure):
 class ulisse_params(Structure):
     _fields_ = [("q", c_double), ("rate", c_double), ("eps", c_double),
                 ("eps_relative", c_int32), ("max_iter", c_int32),
-                ("two_track_first", c_int32), ("reserved", c_int32),
+                ("two_track_first", c_int32), ("refresh", c_int32),
                 ("rng_stream", c_uint64), ("rng_counter", c_uint64), ("prec", c_int)]
 
 
@@ -51,8 +51,8 @@ class gp_profile_stats(Structure):
 
 
 class gp_precond(Structure):
-    _fields_ = [("U", c_void_p), ("ldu", c_int64), ("k", c_int32), ("reserved", c_int32),
-                ("coef", c_void_p)]
+    _fields_ = [("U", c_void_p), ("ldu", c_int64), ("k", c_int32), ("warm_start", c_int32),
+                ("coef", c_void_p), ("c", c_void_p)]
 
 
 class gp_shift_precond(Structure):
@@ -296,8 +296,8 @@ def gp_dkmv(h, X, psi, V, out=None, prec=GP_FP32, stream=None):
 
 
 def make_params(q=1.0, rate=1.0, eps=1e-6, eps_relative=1, max_iter=1000, two_track_first=0,
-                rng_stream=0, rng_counter=0, prec=GP_FP32):
-    return ulisse_params(q, rate, eps, eps_relative, max_iter, two_track_first, 0,
+                rng_stream=0, rng_counter=0, prec=GP_FP32, refresh=0):
+    return ulisse_params(q, rate, eps, eps_relative, max_iter, two_track_first, refresh,
                          rng_stream, rng_counter, prec)
 
 
@@ -404,15 +404,18 @@ def sgld_run(h, X, psi, y, params, sched, state, T, S_warm, R, prior_kind=0, pri
 
 class Precond:
     """A gp_precond plus references to its device tensors (they must outlive every call
-    that uses the descriptor).  U: (n, k) column-major FP32; coef: k + 1 FP64 (h, tau_inv)."""
+    that uses the descriptor).  U: (n, k) column-major FP32; coef: k + 1 FP64 (h, tau_inv;
+    a negative tau_inv selects the plain solver); cvec (optional): k FP64 warm-start
+    coefficients, system 0 then starts from U cvec."""
 
-    def __init__(self, U, coef):
-        self.U, self.coef = U, coef
-        self.c = gp_precond(U.data_ptr(), _ld(U, U.shape[0]), U.shape[1], 0, coef.data_ptr())
+    def __init__(self, U, coef, cvec=None):
+        self.U, self.coef, self.cvec = U, coef, cvec
+        self.c = gp_precond(U.data_ptr(), _ld(U, U.shape[0]), U.shape[1], 0 if cvec is None else 1,
+                            coef.data_ptr(), 0 if cvec is None else cvec.data_ptr())
 
 
-def make_precond(U, coef):
-    return Precond(U, coef)
+def make_precond(U, coef, cvec=None):
+    return Precond(U, coef, cvec)
 
 
 def ulisse_solve_pc(h, X, psi, B, params, pc, S0=None, S_tilde=None, S_cg=None, stats=None, stream=None):

@@ -50,7 +50,7 @@ enum Slot {
     kSlotRatio, kSlotRunStats, kSlotZp, kSlotUtv, kSlotHW, kSlotP3, kSlotY0, kSlotY1,
     kSlotY2, kSlotGram, kSlotGpart2, kSlotSmall, kSlotMlp, kSlotIcgB, kSlotIcgZ, kSlotIcgSt,
     kSlotIcgKP, kSlotTuneV, kSlotTunePart, kSlotTuneVH, kSlotTuneVL, kSlotAH, kSlotAL, kSlotBH,
-    kSlotBL, kNumSlots
+    kSlotBL, kSlotRD, kSlotRPart, kSlotRFlag, kNumSlots
 };
 // Solves nest one level (the inner CG of the shifted preconditioner): the inner solve's
 // buffers live in a second set of slots, offset by kNumSlots.
@@ -181,6 +181,7 @@ gp_status check_params(const ulisse_params* p) {
     GP_CHECK(p->rate > 0.0, "rate must be > 0");
     GP_CHECK(p->eps >= 0.0, "eps must be >= 0");
     GP_CHECK(p->max_iter >= 1, "max_iter must be >= 1");
+    GP_CHECK(p->refresh >= 0 && p->refresh <= 30, "refresh must be in [0, 30]");
     GP_CHECK(p->prec == GP_FP32 || p->prec == GP_BF16_SPLIT_V || p->prec == GP_BF16_SPLIT_KV,
              "unknown precision");
     return GP_OK;
@@ -203,6 +204,9 @@ gp_status check_precond(const gp_precond* pc, int64_t n) {
     GP_CHECK(pc->U != nullptr && aligned(pc->U, 4) && pc->ldu >= n, "preconditioner U null, misaligned or ldu < n");
     GP_CHECK(pc->k == 16 || pc->k == 32 || pc->k == 64, "preconditioner rank must be 16, 32 or 64");
     GP_CHECK(pc->coef != nullptr && aligned(pc->coef, 8), "preconditioner coef null or misaligned");
+    GP_CHECK(pc->warm_start == 0 || pc->warm_start == 1, "preconditioner warm_start must be 0 or 1");
+    GP_CHECK(!pc->warm_start || (pc->c != nullptr && aligned(pc->c, 8)),
+             "a preconditioner warm start needs its coefficients c (8-byte aligned)");
     return GP_OK;
 }
 
@@ -318,6 +322,10 @@ struct Solve {
     KParams* kp_in = nullptr;
     ulisse_params ip{};
     int it = 0;  // iterations launched
+    // residual replacement: FP32 product of fp32(s) every p.refresh iterations
+    KmvShape sh32{};
+    float* D32 = nullptr;
+    float* kpart32 = nullptr;
 
     gp_status product(const int* n_active) {
         // the BF16 modes split the FP32 direction into hi + lo halves before each product
@@ -407,6 +415,16 @@ struct Solve {
             GP_TRY(ws(h, kSlotVH + so, (size_t)n_pad * sh.mp, &DH));
             GP_TRY(ws(h, kSlotVL + so, (size_t)n_pad * sh.mp, &DL));
         }
+        if (p.refresh > 0) {
+            sh32 = kmv_shape(n, d, m, GP_FP32);
+            GP_TRY(ws(h, kSlotRD + so, (size_t)n_pad * sh32.mp, &D32));
+            GP_TRY(ws(h, kSlotRPart + so, (size_t)sh32.split * sh32.mp * n_pad, &kpart32));
+            int* fl;
+            GP_TRY(ws(h, kSlotRFlag + so, (size_t)m + 1, &fl));
+            a.rflag = fl;
+            a.rcount = fl + m;
+            a.refresh = p.refresh;
+        }
         GP_HIP(launch_zero(a.D, (size_t)n_pad * sh.mp * sizeof(float), s));
         const int warm = S0 != nullptr;
         if (warm) {
@@ -426,6 +444,15 @@ struct Solve {
         GP_TRY(product(a.n_active));
         GP_HIP(solver_reduce(a, s));
         GP_HIP(solver_update(a, s));
+        if (p.refresh > 0) {
+            // residual replacement, decided on the device: e = b - K s with an FP32 product
+            // for the systems whose residual has fallen by 2^refresh (the product and the
+            // replacement do nothing when no system replaces)
+            GP_HIP(solver_refresh_pack(a, D32, s));
+            GP_HIP(launch_kmv_partials(sh32, d, Z, D32, nullptr, nullptr, kp, kpart32, a.rcount,
+                                       GP_FP32, s));
+            GP_HIP(solver_refresh(a, kpart32, sh32.split, sh32.mp, s));
+        }
         if (pc != nullptr) GP_HIP(launch_pc_step(a, 0, s));
         if (sp != nullptr) GP_TRY(run_inner(0));
         SysState* next = states + ((it + 1) & 1) * m;
@@ -542,7 +569,18 @@ struct Grad {
             GP_HIP(hipMemcpyAsync(Bm + n, R, (size_t)n * nr * sizeof(float), hipMemcpyDeviceToDevice, s));
         }
         const double* S0 = nullptr;
-        if (S_warm != nullptr) {
+        if (pc != nullptr && pc->warm_start) {
+            // y starts from U c (the caller's warm start when the preconditioner falls
+            // back); the probes from their warm starts when the probes are the caller's
+            double* S0b;
+            GP_TRY(ws(h, kSlotS0, (size_t)n * m, &S0b));
+            if (S_warm != nullptr && R != nullptr)
+                GP_HIP(hipMemcpyAsync(S0b, S_warm, (size_t)n * m * sizeof(double), hipMemcpyDeviceToDevice, s));
+            else
+                GP_HIP(launch_zero(S0b, (size_t)n * m * sizeof(double), s));
+            GP_HIP(launch_pc_warm(pc->U, pc->ldu, pc->k, n, pc->c, pc->coef, S_warm, S0b, s));
+            S0 = S0b;
+        } else if (S_warm != nullptr) {
             if (R == nullptr) {
                 double* S0b;
                 GP_TRY(ws(h, kSlotS0, (size_t)n * m, &S0b));
@@ -805,6 +843,17 @@ gp_status solve_entry(gp_handle* h, gp_data X, const double* psi, const float* B
     float* Z;
     KParams* kp;
     GP_TRY(prep(h, X, psi, n_pad, &Z, &kp, s));
+    if (pc != nullptr && pc->warm_start) {
+        // system 0 starts from U c (from its column of S0 when the preconditioner falls back)
+        double* S0b;
+        GP_TRY(ws(h, kSlotS0, (size_t)X.n * m, &S0b));
+        if (S0 != nullptr)
+            GP_HIP(hipMemcpyAsync(S0b, S0, (size_t)X.n * m * sizeof(double), hipMemcpyDeviceToDevice, s));
+        else
+            GP_HIP(launch_zero(S0b, (size_t)X.n * m * sizeof(double), s));
+        GP_HIP(launch_pc_warm(pc->U, pc->ldu, pc->k, X.n, pc->c, pc->coef, S0, S0b, s));
+        S0 = S0b;
+    }
     return solve_core(h, X.n, X.d, Z, kp, B, ldb, m, S0, *params, S_tilde, S_cg, stats, s, pc, sp);
 }
 
@@ -1390,6 +1439,7 @@ gp_status gp_batch_create(gp_batch** out, int device, uint64_t seed, int32_t B,
     GP_CHECK(probe_kind == 0 || probe_kind == 1, "probe_kind must be 0 or 1");
     GP_CHECK(probe_period >= 1, "probe_period must be >= 1");
     GP_CHECK(iters_per_graph >= 2 && iters_per_graph % 2 == 0, "iters_per_graph must be even and >= 2");
+
     GP_CHECK(streams >= 1 && streams <= 64, "streams must be in [1, 64]");
     for (int i = 0; i < B; ++i) {
         const gp_batch_problem& pr = problems[i];
@@ -1423,7 +1473,7 @@ gp_status gp_batch_create(gp_batch** out, int device, uint64_t seed, int32_t B,
     b->pcs.resize(B);
     for (int i = 0; i < B; ++i)
         if (problems[i].mlp != nullptr)
-            b->pcs[i] = gp_precond{problems[i].U, problems[i].ldu, problems[i].k, 0, problems[i].coef};
+            b->pcs[i] = gp_precond{problems[i].U, problems[i].ldu, problems[i].k, 0, problems[i].coef, nullptr};
     auto bail = [&](gp_status st) {
         gp_batch_destroy(b);
         return st;

@@ -500,16 +500,31 @@ __global__ __launch_bounds__(kWG) void mlp_init_kernel(float* __restrict__ prm, 
 }
 
 // MLP output (standardised) -> preconditioner coefficients and warm-start coefficients:
-// log d = out_mu + out_sd * y (clamped), tau = exp(log tau); h = 1/d - 1/tau, coef[k] = 1/tau.
-// d is floored at tau so that P stays SPD whatever the network says.
+// u = out_mu + out_sd * y holds c, log d and log tau; h = 1/d - 1/tau, coef[k] = 1/tau, with
+// d floored at tau so that P stays SPD.  An output with a non-finite value, or a log d or
+// log tau outside [-60, 60], is rejected: h = 0, coef[k] = -1 (the marker that makes the
+// solvers run plain CG) and c = 0.
 __global__ void mlp_to_precond_kernel(const float* __restrict__ Y, MlpLayout L, int k,
                                       const float* __restrict__ prm, double* __restrict__ coef,
                                       double* __restrict__ cvec) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     auto un = [&](int o) { return (double)prm[L.out_mu + o] + (double)prm[L.out_sd + o] * (double)Y[o]; };
-    const double tau = exp(fmin(fmax(un(2 * k), -60.0), 60.0));
+    bool ok = true;
+    for (int o = 0; o <= 2 * k; ++o) {
+        const double u = un(o);
+        if (!isfinite(u) || (o >= k && fabs(u) > 60.0)) ok = false;
+    }
+    if (!ok) {
+        for (int j = 0; j < k; ++j) {
+            coef[j] = 0.0;
+            if (cvec) cvec[j] = 0.0;
+        }
+        coef[k] = -1.0;
+        return;
+    }
+    const double tau = exp(un(2 * k));
     for (int j = 0; j < k; ++j) {
-        const double d = fmax(exp(fmin(fmax(un(k + j), -60.0), 60.0)), tau);
+        const double d = fmax(exp(un(k + j)), tau);
         coef[j] = 1.0 / d - 1.0 / tau;
         if (cvec) cvec[j] = un(j);
     }
@@ -521,6 +536,22 @@ __global__ void warm_from_c_kernel(const float* __restrict__ U, int64_t ldu, int
                                    const double* __restrict__ c, double* __restrict__ s0) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    double s = 0.0;
+    for (int j = 0; j < k; ++j) s += (double)U[j * ldu + i] * c[j];
+    s0[i] = s;
+}
+
+// The warm start of system 0 inside a preconditioned solve: U c while the preconditioner is
+// in use (coef[k] > 0), otherwise the caller's start `alt` (zero when alt is null).
+__global__ void pc_warm_kernel(const float* __restrict__ U, int64_t ldu, int k, int64_t n,
+                               const double* __restrict__ c, const double* __restrict__ coef,
+                               const double* __restrict__ alt, double* __restrict__ s0) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (!(coef[k] > 0.0)) {
+        s0[i] = alt != nullptr ? alt[i] : 0.0;
+        return;
+    }
     double s = 0.0;
     for (int j = 0; j < k; ++j) s += (double)U[j * ldu + i] * c[j];
     s0[i] = s;
@@ -621,6 +652,12 @@ hipError_t launch_mlp_to_precond(const float* y, const MlpLayout& L, int k, cons
 hipError_t launch_warm_from_c(const float* U, int64_t ldu, int k, int64_t n, const double* c,
                               double* s0, hipStream_t s) {
     warm_from_c_kernel<<<g1(n), kWG, 0, s>>>(U, ldu, k, n, c, s0);
+    return hipGetLastError();
+}
+
+hipError_t launch_pc_warm(const float* U, int64_t ldu, int k, int64_t n, const double* c,
+                          const double* coef, const double* alt, double* s0, hipStream_t s) {
+    pc_warm_kernel<<<g1(n), kWG, 0, s>>>(U, ldu, k, n, c, coef, alt, s0);
     return hipGetLastError();
 }
 

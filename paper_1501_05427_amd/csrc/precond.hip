@@ -111,7 +111,8 @@ __global__ void pc_reduce_kernel(SolverArgs a, int nchunk, int first) {
         for (int t = 0; t < 8; ++t) s += v[t];
     }
     for (; b < nchunk; ++b) s += a.utv_part[(int64_t)b * nout + o];
-    a.HW[o] = a.coef[o / a.m] * s;
+    // a negative tau_inv marks the fallback: P = I, so the U terms vanish
+    a.HW[o] = a.coef[a.pk] < 0.0 ? 0.0 : a.coef[o / a.m] * s;
 }
 
 // z = tau_inv e + U HW[:, c] for every active system; partial sums of e^T z per workgroup;
@@ -129,7 +130,8 @@ __global__ __launch_bounds__(kWG) void pc_apply_kernel(SolverArgs a, int first) 
     float u[KB];
 #pragma unroll
     for (int kappa = 0; kappa < KB; ++kappa) u[kappa] = in ? a.U[kappa * a.ldu + i] : 0.f;
-    const double tau_inv = a.coef[a.pk];
+    // fallback (negative tau_inv): z = e exactly, the plain CG of Alg. 1
+    const double tau_inv = a.coef[a.pk] < 0.0 ? 1.0 : a.coef[a.pk];
     for (int c = 0; c < m; ++c) {
         if (!first && !a.state[c].active) continue;  // uniform over the workgroup
         double ez = 0.0;

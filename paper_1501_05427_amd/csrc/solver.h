@@ -26,7 +26,8 @@ struct SysState {
     int32_t ntracks;
     int32_t l, iters, flags;
     int32_t active;    // the CG run of this system continues
-    int32_t apply;     // unused (kept for layout)
+    int32_t rf_on;     // residual replacement still enabled for this run
+    double res_ref;    // residual norm at the last replacement (or at the start)
 };
 
 // Column of the series estimate of track t of system c in the output block.
@@ -71,12 +72,27 @@ struct SolverArgs {
     double* utv_part;      // nb256 x pk x m
     double* HW;            // pk x m
     double* part3;         // nb256 x m partial sums of e^T z
+    // residual replacement (refresh = k > 0): rflag[c] = 1 when system c replaces its
+    // residual in the current iteration; rcount = number of such systems (0 skips the
+    // replacement product)
+    int32_t refresh, pad3_;
+    int* rflag;
+    int* rcount;
 };
 
 int solver_blocks(int64_t n);
 hipError_t solver_init(const SolverArgs& a, int warm, hipStream_t s);
 hipError_t solver_reduce(const SolverArgs& a, hipStream_t s);
 hipError_t solver_update(const SolverArgs& a, hipStream_t s);
+// Residual replacement: decides per system whether the residual is replaced in this
+// iteration (its norm has fallen by 2^refresh since the last replacement and is above the
+// convergence threshold, and replacements are still on), sets rflag / rcount, and packs
+// fp32(s) of those systems into Dr (ld n_pad); once an FP32 product of Dr (skipped when
+// rcount is 0) has left its chunk partials in kpr (split x mpr x n_pad), e = b - K s with
+// the partials of e^T e for the flagged systems.  The direction kernel then restarts
+// them (beta = 0).
+hipError_t solver_refresh_pack(const SolverArgs& a, float* Dr, hipStream_t s);
+hipError_t solver_refresh(const SolverArgs& a, const float* kpr, int split, int mpr, hipStream_t s);
 // Reads the state at a.state and writes the advanced state to `next`.
 hipError_t solver_direction(const SolverArgs& a, SysState* next, hipStream_t s);
 hipError_t solver_copy_s(const SolverArgs& a, double* out, hipStream_t s);

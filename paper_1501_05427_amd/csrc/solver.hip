@@ -113,11 +113,17 @@ __global__ __launch_bounds__(kWG) void ulisse_init_state_kernel(SolverArgs a) {
     }
     st.l = 0;
     st.iters = 0;
-    st.flags = 0;
+    // a negative tau_inv in the rank-k preconditioner marks the fallback to plain CG
+    st.flags = (a.pcm == 1 && a.coef[a.pk] < 0.0) ? (int)ULISSE_FALLBACK : 0;
     st.active = 1;
-    st.apply = 0;
+    st.rf_on = a.refresh > 0 ? 1 : 0;
+    st.res_ref = st.res;
     a.state[c] = st;
-    if (c == 0) *a.n_active = a.m;
+    if (a.refresh > 0) a.rflag[c] = 0;
+    if (c == 0) {
+        *a.n_active = a.m;
+        if (a.refresh > 0) *a.rcount = 0;
+    }
 }
 
 // ---------------------------------------------------------------------------------------
@@ -184,6 +190,56 @@ __global__ __launch_bounds__(kWG) void ulisse_update_kernel(SolverArgs a) {
     if (threadIdx.x == 0) a.part2[(int64_t)blockIdx.x * a.m + c] = ee;
 }
 
+// ---------------------------------------------------------------------------------------
+// Residual replacement: fp32(s) of the running systems into Dr (n_pad x mpr, ld n_pad; rows
+// past n zero) for an FP32 product, then e = b - (K_f fp32(s) + lambda s) in FP64 with new
+// partials of e^T e in place of the update kernel's.
+// ---------------------------------------------------------------------------------------
+__global__ __launch_bounds__(kWG) void ulisse_refresh_pack_kernel(SolverArgs a, float* __restrict__ Dr) {
+    if (*a.n_active == 0) return;
+    __shared__ double bcast;
+    const int c = blockIdx.y;
+    const SysState& st = a.state[c];
+    // every workgroup of the system derives the same decision from the same partials
+    const double ee = column_total(a.part2, a.nb, a.m, c, &bcast);
+    const double r = sqrt(ee);
+    const bool go = st.active && st.rf_on && r < st.res_ref * exp2(-(double)a.refresh) && r > st.thr_eps;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        a.rflag[c] = go ? 1 : 0;
+        if (go) atomicAdd(a.rcount, 1);
+    }
+    if (!go) return;
+#pragma unroll
+    for (int rr = 0; rr < kRowsPerThread; ++rr) {
+        const int64_t i = (int64_t)blockIdx.x * kRowsPerBlock + rr * kWG + threadIdx.x;
+        if (i >= a.n_pad) break;
+        Dr[c * a.n_pad + i] = i < a.n ? (float)a.S[c * a.n_pad + i] : 0.f;
+    }
+}
+
+__global__ __launch_bounds__(kWG) void ulisse_refresh_kernel(SolverArgs a, const float* __restrict__ kpr,
+                                                             int split, int mpr) {
+    if (*a.n_active == 0 || *a.rcount == 0) return;
+    __shared__ double scratch[4];
+    const int c = blockIdx.y;
+    if (!a.rflag[c]) return;  // uniform over the workgroup
+    const double lam = a.kp->lam64;
+    double ee = 0.0;
+#pragma unroll
+    for (int r = 0; r < kRowsPerThread; ++r) {
+        const int64_t i = (int64_t)blockIdx.x * kRowsPerBlock + r * kWG + threadIdx.x;
+        if (i >= a.n) break;
+        double kq = 0.0;
+        for (int k = 0; k < split; ++k) kq += (double)kpr[((int64_t)k * mpr + c) * a.n_pad + i];
+        kq += lam * a.S[c * a.n_pad + i];
+        const double e = (double)a.B[c * a.ldb + i] - kq;
+        a.E[c * a.n_pad + i] = e;
+        ee += e * e;
+    }
+    ee = block_sum256(ee, scratch);
+    if (threadIdx.x == 0) a.part2[(int64_t)blockIdx.x * a.m + c] = ee;
+}
+
 // u_j of track t of system c: word j of Philox stream (key (seed, stream), counter
 // (j/4, 2c + t, 2, step)), mapped to [0, 1).
 __device__ inline double ulisse_u(const SolverArgs& a, int c, int t, int j) {
@@ -216,7 +272,7 @@ __device__ inline void tail_decide(const SolverArgs& a, SysState& st, int c, int
 // The per-system decisions after one CG iteration (threshold l, tail draws, convergence,
 // iteration cap, breakdown), applied to a copy of the state.
 __device__ inline void advance(const SolverArgs& a, SysState& st, int c, double gamma,
-                               double rho_new, double ee) {
+                               double rho_new, double ee, bool replaced) {
     const double al = st.rho / gamma;
     if (!alpha_ok(gamma, al)) {
         st.flags |= (int)ULISSE_BREAKDOWN;
@@ -252,8 +308,14 @@ __device__ inline void advance(const SolverArgs& a, SysState& st, int c, double 
         done = true;
         st.flags |= (int)ULISSE_BREAKDOWN;
     }
-    st.beta = rho_new / st.rho;
+    // a replaced residual restarts the recurrences: the next direction is the residual
+    // (preconditioned) itself; replacements stop once one of them gains less than 2x
+    st.beta = replaced ? 0.0 : rho_new / st.rho;
     st.rho = rho_new;
+    if (replaced) {
+        if (!(st.res < 0.5 * st.res_ref)) st.rf_on = 0;
+        st.res_ref = st.res;
+    }
     if (done) st.active = 0;
 }
 
@@ -265,6 +327,8 @@ __device__ inline void advance(const SolverArgs& a, SysState& st, int c, double 
 __global__ __launch_bounds__(kWG) void ulisse_direction_kernel(SolverArgs a, const SysState* cur,
                                                                SysState* next) {
     if (*a.n_active == 0) return;
+    // the replacement product and kernel of this iteration have consumed the count
+    if (a.refresh > 0 && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *a.rcount = 0;
     __shared__ double bcast;
     const int c = blockIdx.y;
     SysState st = cur[c];
@@ -275,7 +339,8 @@ __global__ __launch_bounds__(kWG) void ulisse_direction_kernel(SolverArgs a, con
     const double gamma = column_total(a.part, a.nb, a.m, c, &bcast);
     const double ee = column_total(a.part2, a.nb, a.m, c, &bcast);
     const double rho_new = a.pcm != 0 ? column_total(a.part3, a.nb256, a.m, c, &bcast) : ee;
-    advance(a, st, c, gamma, rho_new, ee);
+    const bool replaced = a.refresh > 0 && a.rflag[c] != 0;
+    advance(a, st, c, gamma, rho_new, ee, replaced);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         next[c] = st;
         if (!st.active) {
@@ -559,6 +624,16 @@ hipError_t solver_reduce(const SolverArgs& a, hipStream_t s) {
 }
 hipError_t solver_update(const SolverArgs& a, hipStream_t s) {
     ulisse_update_kernel<<<vec_grid(a), kWG, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t solver_refresh_pack(const SolverArgs& a, float* Dr, hipStream_t s) {
+    ulisse_refresh_pack_kernel<<<vec_grid(a), kWG, 0, s>>>(a, Dr);
+    return hipGetLastError();
+}
+
+hipError_t solver_refresh(const SolverArgs& a, const float* kpr, int split, int mpr, hipStream_t s) {
+    ulisse_refresh_kernel<<<vec_grid(a), kWG, 0, s>>>(a, kpr, split, mpr);
     return hipGetLastError();
 }
 hipError_t solver_direction(const SolverArgs& a, SysState* next, hipStream_t s) {

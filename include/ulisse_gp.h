@@ -79,6 +79,21 @@ gp_status gp_kmv(gp_handle* h, gp_data X, const double* psi, const float* V, int
                  int64_t ldv, float* out, int64_t ldo, gp_precision prec, void* stream);
 
 /*
+ * gp_kmv for callers that cannot allocate device memory: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc.  Same arguments, results and
+ * conventions as gp_kmv, but every intermediate buffer (scaled inputs, packed V, split-K
+ * partials, BF16 halves) lives in one fixed device array of the library, 32 MiB per
+ * device, held from the first call on a device until the process ends; the call makes no
+ * allocation and uses none of the handle's workspace (the handle only names the device).
+ * A shape whose buffers do not fit even with a single split-K chunk is rejected with
+ * GP_EINVAL (at n = 65536, d = 8: up to m = 51 fits in FP32, m = 32 in the BF16 modes).
+ * Calls that overlap on one device
+ * share that array and race: order them on one stream.
+ */
+gp_status gp_kmv_noalloc(gp_handle* h, gp_data X, const double* psi, const float* V, int32_t m,
+                         int64_t ldv, float* out, int64_t ldo, gp_precision prec, void* stream);
+
+/*
  * Products with every derivative of K (used by the exact gradient of Sec. 2.1):
  *   block j of out (j = 0..d+1) = dK/dpsi_j V, at out + j*block_stride, n x m, ldo >= n,
  *   dK/dpsi_0 = K_f (signal part), dK/dpsi_k = K_f o (x_.k - x_.k)^2 / ell_k^2,

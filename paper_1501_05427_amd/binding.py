@@ -113,6 +113,8 @@ def lib():
     L.gp_destroy.argtypes = [c_void_p]
     L.gp_kmv.restype = c_int
     L.gp_kmv.argtypes = [c_void_p, gp_data, c_void_p, c_void_p, c_int32, c_int64, c_void_p, c_int64, c_int, c_void_p]
+    L.gp_kmv_noalloc.restype = c_int
+    L.gp_kmv_noalloc.argtypes = [c_void_p, gp_data, c_void_p, c_void_p, c_int32, c_int64, c_void_p, c_int64, c_int, c_void_p]
     L.gp_dkmv.restype = c_int
     L.gp_dkmv.argtypes = [c_void_p, gp_data, c_void_p, c_void_p, c_int32, c_int64, c_void_p, c_int64, c_int64, c_int, c_void_p]
     L.ulisse_solve.restype = c_int
@@ -280,6 +282,15 @@ def gp_kmv(h, X, psi, V, out=None, prec=GP_FP32, stream=None):
         out = colmajor(n, m, device=V.device) if V.dim() == 2 else V.new_zeros(n)
     _check(lib().gp_kmv(h.ptr, _data(X), _ptr(psi), _ptr(V), m, _ld(V, n), _ptr(out), _ld(out, n),
                         int(prec), _stream(stream)))
+    return out
+
+
+def gp_kmv_noalloc(h, X, psi, V, out, prec=GP_FP32, stream=None):
+    """gp_kmv with the library's fixed device scratch: the output must be given."""
+    n = X.shape[0]
+    m = _cols(V)
+    _check(lib().gp_kmv_noalloc(h.ptr, _data(X), _ptr(psi), _ptr(V), m, _ld(V, n), _ptr(out), _ld(out, n),
+                                int(prec), _stream(stream)))
     return out
 
 

@@ -748,6 +748,65 @@ gp_status gp_kmv(gp_handle* h, gp_data X, const double* psi, const float* V, int
     return GP_OK;
 }
 
+gp_status gp_kmv_noalloc(gp_handle* h, gp_data X, const double* psi, const float* V, int32_t m,
+                         int64_t ldv, float* out, int64_t ldo, gp_precision prec, void* stream) {
+    GP_TRY(check_handle(h));
+    GP_TRY(check_data(X));
+    GP_CHECK(m >= 1 && m <= kMaxSys, "m = %d outside [1, 64]", m);
+    GP_CHECK(V != nullptr && out != nullptr && aligned(V, 4) && aligned(out, 4), "V/out null or misaligned");
+    GP_CHECK(ldv >= X.n && ldo >= X.n, "ldv and ldo must be >= n");
+    GP_CHECK(psi != nullptr && aligned(psi, 8), "psi must be a non-null 8-byte aligned pointer");
+    GP_CHECK(prec == GP_FP32 || prec == GP_BF16_SPLIT_V || prec == GP_BF16_SPLIT_KV, "unknown precision");
+    hipStream_t s = (hipStream_t)stream;
+    // the largest split-K (at most the default shape's) whose buffers fit in the scratch
+    auto align = [](size_t b) { return (b + 255) / 256 * 256; };
+    auto footprint = [&](const KmvShape& sh, bool b16) {
+        size_t b = align((size_t)sh.n_pad * dpad(X.d) * sizeof(float)) + align(sizeof(KParams)) +
+                   align((size_t)sh.n_pad * sh.mp * sizeof(float)) +
+                   align((size_t)sh.split * sh.mp * sh.n_pad * sizeof(float));
+        if (b16) b += 2 * align((size_t)sh.n_pad * sh.mp * sizeof(uint16_t));
+        return b;
+    };
+    KmvShape sh = kmv_shape(X.n, X.d, m, prec);
+    bool b16 = uses_bf16(sh, prec);
+    for (int target = 1024; footprint(sh, b16) > kNoAllocScratchBytes && sh.split > 1; target /= 2) {
+        sh = kmv_shape_target(X.n, X.d, m, prec, target);
+        b16 = uses_bf16(sh, prec);
+    }
+    if (footprint(sh, b16) > kNoAllocScratchBytes)
+        return fail(GP_EINVAL, "gp_kmv_noalloc: n = %lld, d = %d, m = %d needs %zu bytes of scratch, more "
+                    "than its fixed %zu", (long long)X.n, X.d, m, footprint(sh, b16), kNoAllocScratchBytes);
+    void* base = nullptr;
+    {
+        const hipError_t e = noalloc_scratch(h->device, &base);
+        if (e != hipSuccess) return fail(GP_EDEVICE, "scratch address lookup failed: %s", hipGetErrorString(e));
+    }
+    unsigned char* p = static_cast<unsigned char*>(base);
+    auto take = [&](size_t bytes) {
+        void* q = p;
+        p += align(bytes);
+        return q;
+    };
+    float* Z = static_cast<float*>(take((size_t)sh.n_pad * dpad(X.d) * sizeof(float)));
+    KParams* kp = static_cast<KParams*>(take(sizeof(KParams)));
+    float* Vp = static_cast<float*>(take((size_t)sh.n_pad * sh.mp * sizeof(float)));
+    float* part = static_cast<float*>(take((size_t)sh.split * sh.mp * sh.n_pad * sizeof(float)));
+    uint16_t *VH = nullptr, *VL = nullptr;
+    if (b16) {
+        VH = static_cast<uint16_t*>(take((size_t)sh.n_pad * sh.mp * sizeof(uint16_t)));
+        VL = static_cast<uint16_t*>(take((size_t)sh.n_pad * sh.mp * sizeof(uint16_t)));
+    }
+    // every scratch word read below is written first in this call (Z, kp by prep; Vp by
+    // pack; VH, VL by the split; each chunk's partials by the product), so nothing needs
+    // clearing between calls
+    GP_HIP(launch_prep(X.X, X.n, X.d, X.ldx, psi, Z, sh.n_pad, kp, s));
+    GP_HIP(launch_pack(V, X.n, m, ldv, Vp, sh.n_pad, sh.mp, s));
+    if (b16) GP_HIP(launch_split_bf16(Vp, sh.n_pad * sh.mp, VH, VL, s));
+    GP_HIP(launch_kmv_partials(sh, X.d, Z, Vp, VH, VL, kp, part, nullptr, prec, s));
+    GP_HIP(launch_kmv_reduce(sh, part, Vp, kp, X.n, m, out, ldo, s));
+    return GP_OK;
+}
+
 gp_status gp_dkmv(gp_handle* h, gp_data X, const double* psi, const float* V, int32_t m,
                   int64_t ldv, float* out, int64_t ldo, int64_t block_stride,
                   gp_precision prec, void* stream) {

@@ -33,6 +33,11 @@ KmvShape kmv_shape(int64_t n, int d, int m, gp_precision prec);
 KmvShape kmv_shape_target(int64_t n, int d, int m, gp_precision prec, int target_wg);
 KmvShape dkmv_shape(int64_t n, int d, int m);
 
+// Size of the fixed device scratch of the no-allocation entry points, and its device
+// address on `device` (which must be current), looked up once per device.
+constexpr size_t kNoAllocScratchBytes = size_t(32) << 20;
+hipError_t noalloc_scratch(int device, void** out);
+
 // psi -> KParams and the scaled, padded inputs Z (n_pad x dpad(d), zero rows past n).
 hipError_t launch_prep(const float* X, int64_t n, int d, int64_t ldx, const double* psi,
                        float* Z, int64_t n_pad, KParams* kp, hipStream_t s);

@@ -2,14 +2,25 @@
 for y and 31 Gaussian probes, fused gradient reduction) + the SGLD update, on the
 n = 65536, d = 8 synthetic GP workload (32 right-hand sides).
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--no-batched]
 
-Prints one JSON line.  `value` is gradient estimates per second over the K timed steps
-(inputs resident in HBM).  The roofline object is for the dominant kernel, the
-covariance product (kmv): algorithmic flops per launch n^2 (3d + 2m) divided by its
-average launch time, taken from hipEvents recorded by the library on the launch stream
-during the timed steps.  HBM traffic per launch comes from the committed rocprofv3
-counter summary if it was taken on the current kmv source, else null.
+Prints one JSON line.  `value` is gradient estimates per second of the plain FP32 path over
+the K timed steps, with inputs resident in HBM, under the protocol: fresh probes every
+step, psi starting at the truth, the y system warm-started from its last CG iterate,
+q = 1, rate 1, step size 1e-3, SGLD preconditioner M from the MAP of a 500-point subset
+(the paper's recipe, Sec. 5).  From the same saved state and with the same draws the line
+also carries: the paper's protocol (probes redrawn every 20 steps), BF16 split-K+V
+products with residual replacement, the learned preconditioner (trained on the states of
+plain-solver SGLD chains) with and without its warm start U c, the Galerkin
+preconditioner on the same basis without learning (fixed at the MAP, or recomputed at
+every step), an equal-error comparison at a state of the chain (the paper's error measure,
+Sec. 4.2), K.V throughput per arithmetic mode, the batched 64-GP form and the CPU oracle.
+
+The roofline object is for the dominant kernel, the covariance product (kmv): algorithmic
+flops per launch n^2 (3d + 2m) divided by its average launch time, taken from hipEvents
+recorded by the library on the launch stream during the timed steps.  HBM traffic per
+launch comes from the committed rocprofv3 counter summary if it was taken on the current
+kmv source, else null.
 
     python bench.py --profile-kmv     a short run for rocprofv3: 5 kmv launches at the
                                       same shape plus a 1 GiB copy (counter calibration)
@@ -26,7 +37,7 @@ sys.path.insert(0, ROOT)
 
 N, D, NPROBES = 65536, 8, 31
 PROBE_PERIOD = 20
-LEARN_JITTER = 0.03   # spread of the training log-parameters around the reference
+LEARN_JITTER = 0.03   # batched learned leg: spread of each GP's training psi's around its start
 M = 1 + NPROBES
 WORKLOAD = "rff_n65536_d8_m32"
 VALU_FP32_PEAK_TFLOPS = 157.3   # 256 CU x 2.4 GHz x 256 flop/CU/clk (datasheet FP32 vector)
@@ -83,12 +94,16 @@ def cpu_baseline(X, psi, passes_per_estimate, budget_rows=(768, 256)):
     for Dj in dK:
         _ = Dj @ V
     t_asm = (time.perf_counter() - t0) * N / len(rows_a)
-    threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    blas_threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     per_est = passes_per_estimate * t_kmv + t_asm
-    return dict(value=1.0 / per_est, unit="grad_estimates/s", cores=int(threads), kind="oracle",
+    # the oracle forms kernel entries with element-wise numpy (one thread), which is most of
+    # its time; only its dense products go through BLAS, on up to blas_threads threads
+    return dict(value=1.0 / per_est, unit="grad_estimates/s", cores=1, blas_threads=int(blas_threads),
+                kind="oracle",
                 sample=(f"oracle FP64 K.V on {budget_rows[0]} of {N} rows and gradient assembly on "
                         f"{budget_rows[1]} rows of the n={N}, d={D}, m={M} workload, scaled by rows "
-                        f"to {passes_per_estimate:.2f} products + 1 assembly per estimate"),
+                        f"to {passes_per_estimate:.2f} products + 1 assembly per estimate; kernel "
+                        f"entries on one thread, BLAS products on up to {blas_threads}"),
                 kmv_s_full=t_kmv, assembly_s_full=t_asm)
 
 
@@ -228,29 +243,386 @@ def kmv_report(pb, h):
     print(json.dumps({"kmv_report": rows, "flops_per_pair": "3d + 2m (algorithmic, m unpadded)"}), flush=True)
 
 
-def setup_learned(pb, h, X, y, w, pairs, epochs, k=64, H=256):
-    """Basis, Galerkin targets and the trained MLP of the learned warm start/preconditioner.
+def say(msg):
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
 
-    Training pairs are psi's jittered around the workload's psi (N(0, LEARN_JITTER^2) per
-    component); everything runs in the library's kernels.
-    """
+
+def matched_error_rates(rows_a, rows_b):
+    """Speed of method b over method a at equal gradient error: at every point of one
+    method whose mean log10 error lies inside the other's measured range, the other's
+    estimates/s there by log-linear interpolation between its points, and the ratio
+    rate_b / rate_a."""
+    import numpy as np
+
+    def curve(rows):
+        pts = sorted((r["mean_log10_rel_sq_err"], np.log(r["grad_estimates_per_s"])) for r in rows)
+        return [p_[0] for p_ in pts], [p_[1] for p_ in pts]
+
+    xa, ya = curve(rows_a)
+    xb, yb = curve(rows_b)
+    out = []
+    for r in rows_b:
+        e = r["mean_log10_rel_sq_err"]
+        if xa[0] <= e <= xa[-1]:
+            ra = float(np.exp(np.interp(e, xa, ya)))
+            out.append({"at": "b", "q": r["q"], "error": e, "rate_a": ra,
+                        "rate_b": r["grad_estimates_per_s"], "speedup": r["grad_estimates_per_s"] / ra})
+    for r in rows_a:
+        e = r["mean_log10_rel_sq_err"]
+        if xb[0] <= e <= xb[-1]:
+            rb = float(np.exp(np.interp(e, xb, yb)))
+            out.append({"at": "a", "q": r["q"], "error": e, "rate_a": r["grad_estimates_per_s"],
+                        "rate_b": rb, "speedup": rb / r["grad_estimates_per_s"]})
+    return out
+
+
+def learned_from_chains(pb, h, X, y, psi_map, M_sub, L_full, eps_t, prior, chains, steps, epochs,
+                        k=64, H=256, probes=4, seed=1):
+    """The learned warm start and preconditioner, trained on (psi, solve) pairs that the
+    plain solver generates: the states of `chains` plain-solver SGLD chains (started from
+    N(psi_MAP, M_subset), `steps` steps each), the basis U of K(psi_MAP), the Galerkin solve
+    and spectrum of K(psi) on U at every state as targets, and the MLP trained on them by
+    Adam, all in the library's kernels."""
     import numpy as np
     import torch
-    U, ritz = pb.precond_build_basis(h, X, torch.from_numpy(w["psi"]).cuda(), k)
-    rng = np.random.default_rng(17)
-    psis = torch.from_numpy(w["psi"] + LEARN_JITTER * rng.standard_normal((pairs, D + 2))).cuda()
+    from paper_1501_05427_amd import protocol
+    t0 = time.perf_counter()
+    starts = protocol.init_chains(psi_map, M_sub, chains, seed=seed)
+    states = protocol.plain_chain_states(h, X, y, starts, steps, L_full, eps_t, probes=probes,
+                                         prior=prior)
+    t_chain = time.perf_counter() - t0
+    psis = torch.from_numpy(states).cuda()
+    U, ritz = pb.precond_build_basis(h, X, torch.from_numpy(psi_map).cuda(), k)
     T = pb.precond_targets(h, X, y, U, psis)
-    I_, O_ = D + 2, 2 * k + 1
+    torch.cuda.synchronize()
+    t_targets = time.perf_counter() - t0 - t_chain
+    I_, O_ = len(psi_map), 2 * k + 1
     prm = torch.zeros(pb.precond_mlp_size(I_, H, O_), dtype=torch.float32, device="cuda")
     pb.precond_mlp_init(h, prm, I_, H, O_, psis, T, seed=5)
     adam = torch.zeros(2 * pb.mlp_layout(I_, H, O_)["trainable"], dtype=torch.float32, device="cuda")
     ltr = torch.zeros(epochs, dtype=torch.float32, device="cuda")
     pb.precond_mlp_train(h, prm, adam, I_, H, O_, psis, T, epochs, 0, 2e-3, loss_trace=ltr)
-    coef = torch.zeros(k + 1, dtype=torch.float64, device="cuda")
-    pc = pb.make_precond(U, coef)
     torch.cuda.synchronize()
-    return {"prm": prm, "pc": pc, "coef": coef, "U": U, "I": I_, "H": H, "O": O_, "k": k,
-            "loss_trace": ltr, "ritz": ritz}
+    t_total = time.perf_counter() - t0
+    spread = states.std(axis=0)
+    return {"prm": prm, "U": U, "I": I_, "H": H, "O": O_, "k": k, "ritz": ritz, "psis": psis,
+            "info": {"pairs": int(states.shape[0]), "chains": chains, "steps_per_chain": steps,
+                     "probes": probes, "epochs": epochs, "rank": k, "hidden": H,
+                     "basis_at": "subset MAP",
+                     "train_loss_first_last": [float(ltr[0]), float(ltr[-1])],
+                     "ritz_top_bottom": [float(ritz[0]), float(ritz[-1])],
+                     "state_sd_mean": float(spread.mean()),
+                     "seconds_chains": t_chain, "seconds_targets": t_targets, "seconds_total": t_total}}
+
+
+class Chain:
+    """One SGLD chain on the benchmark workload and the estimators the legs compare.
+
+    Methods of `estimate`: plain_fp32 (gp_stoch_grad, FP32 products), plain_bf16 (BF16
+    split-K+V products with residual replacement), and, over the rank-k basis U of the
+    learned set-up with the same BF16 products: learned_bf16 (coefficients from the network
+    at the chain's psi), learned_bf16_uc (the same plus the warm start U c of the y
+    system), galerkin_direct_bf16 (coefficients of the Galerkin preconditioner computed at
+    the chain's psi: one K U product per estimate) and galerkin_fixed_bf16 (computed once,
+    at the subset MAP)."""
+
+    def __init__(self, pb, h, X, y, M_chol, refresh, k=64):
+        import torch
+        self.pb, self.h, self.X, self.y, self.M_chol, self.refresh, self.k = pb, h, X, y, M_chol, refresh, k
+        P = D + 2
+        self.psi = torch.zeros(P, dtype=torch.float64, device="cuda")
+        self.S_warm = torch.zeros((M, N), dtype=torch.float64, device="cuda").t()
+        self.R = pb.colmajor(N, NPROBES)
+        self.g = torch.zeros(P, dtype=torch.float64, device="cuda")
+        self.stats = pb.stats_tensor(M)
+        self.flagged = torch.zeros((), dtype=torch.int64, device="cuda")
+        self.fallbacks = torch.zeros((), dtype=torch.int64, device="cuda")
+        self.params = pb.make_params(q=1.0, rate=1.0, eps=1e-6, eps_relative=1, max_iter=1000, rng_stream=1)
+        self.coef = torch.zeros(k + 1, dtype=torch.float64, device="cuda")
+        self.cvec = torch.zeros(k, dtype=torch.float64, device="cuda")
+        self.prior_a = torch.zeros(P, dtype=torch.float64, device="cuda")
+        self.prior_b = torch.full((P,), 3.0, dtype=torch.float64, device="cuda")
+        self.L = None
+
+    def set_learned(self, L, coef_map):
+        import torch
+        pb = self.pb
+        self.L = L
+        self.pc = pb.make_precond(L["U"], self.coef)
+        self.pc_uc = pb.make_precond(L["U"], self.coef, cvec=self.cvec)
+        self.T1 = torch.zeros((1, 2 * self.k + 1), dtype=torch.float32, device="cuda")
+        self.coef_map = coef_map
+
+    def estimate(self, method, t, period=1, new_probes=True):
+        """One gradient estimate of `method` at step t into self.g."""
+        import torch
+        pb, h, prm = self.pb, self.h, self.params
+        prm.rng_counter = t
+        prm.prec = pb.GP_FP32 if method == "plain_fp32" else pb.GP_BF16_SPLIT_KV
+        prm.refresh = 0 if method == "plain_fp32" else self.refresh
+        if period > 1 and new_probes:
+            pb.gp_draw_probes(h, N, NPROBES, pb.PROBE_GAUSSIAN, 7, t // period, R=self.R)
+            self.S_warm[:, 1:].zero_()
+        kw = dict(R=self.R if period > 1 else None, n_probes=NPROBES, S_warm=self.S_warm, g=self.g,
+                  stats=self.stats)
+        if method in ("plain_fp32", "plain_bf16"):
+            pb.gp_stoch_grad(h, self.X, self.psi, self.y, prm, **kw)
+            return
+        L = self.L
+        if method.startswith("learned"):
+            pb.precond_from_mlp(h, L["prm"], L["I"], L["H"], L["O"], self.psi, self.k, coef=self.coef, c=self.cvec)
+        elif method == "galerkin_direct_bf16":
+            pb.precond_targets(h, self.X, self.y, L["U"], self.psi[None, :], targets=self.T1)
+            pb.precond_from_targets(h, self.T1[0], self.k, coef=self.coef, c=self.cvec)
+        elif method == "galerkin_fixed_bf16":
+            self.coef.copy_(self.coef_map)
+        else:
+            raise ValueError(method)
+        pc = self.pc_uc if method == "learned_bf16_uc" else self.pc
+        pb.gp_stoch_grad_pc(h, self.X, self.psi, self.y, prm, pc, **kw)
+        fl = self.stats.view(M, -1)[:, 24:28].view(torch.int32)
+        self.fallbacks.add_(fl.bitwise_and(pb.ULISSE_FALLBACK).ne(0).any().to(torch.int64))
+
+    def step(self, method, t, period, first, eps_t):
+        import torch
+        pb = self.pb
+        self.estimate(method, t, period, first or t % period == 0)
+        pb.sgld_step(self.h, self.psi, self.g, eps_t, rng_stream=1, rng_counter=t, prior_kind=1,
+                     prior_a=self.prior_a, prior_b=self.prior_b, M_chol=self.M_chol)
+        fl = self.stats.view(M, -1)[:, 24:28].view(torch.int32)
+        self.flagged.add_(fl.bitwise_and(pb.ULISSE_NOTCONV | pb.ULISSE_BREAKDOWN).ne(0).any().to(torch.int64))
+
+    def timed(self, method, first, count, period, eps_t):
+        import torch
+        pb = self.pb
+        torch.cuda.synchronize()
+        pb.gp_profile(self.h, 1)
+        t0 = time.perf_counter()
+        for t in range(first, first + count):
+            self.step(method, t, period, t == first, eps_t)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        pr = pb.gp_profile_read(self.h)
+        pb.gp_profile(self.h, 0)
+        return el, pr
+
+
+def main_line(args, pb, h, X, y, w, psi0):
+    """The default benchmark line: one SGLD step = one unbiased gradient estimate + the SGLD
+    update on the n = 65536, d = 8 workload (31 Gaussian probes, 32 right-hand sides).
+
+    Headline protocol (`value`): fresh probes every step, psi starting at the truth, the y
+    system warm-started from its last CG iterate, q = 1, rate 1, prior N(0, 3^2) on psi, the
+    SGLD preconditioner of the paper's experiments (Sec. 5): M = (-H)^-1 at the MAP of a
+    random 500-point subset, scaled by 500 / n for the full data, and the step size at which
+    the paper's Langevin-phase monitor (eps / 4) lambda_max(L^T V L) meets its freeze
+    threshold 0.002 (Sec. 2.1), V the covariance of 16 gradient estimates at the truth: the
+    chain in its sampling phase.  Every other leg starts from the same saved state with the
+    same draws."""
+    import numpy as np
+    import torch
+    from paper_1501_05427_amd import protocol
+    P = D + 2
+    prior = {"kind": 1, "a": np.zeros(P), "b": np.full(P, 3.0)}
+    eps_train = 1e-3     # the training chains: their transient phase gives the pairs their spread
+    t0 = time.perf_counter()
+    psi_map, M_sub, _ = protocol.sgld_preconditioner(h, w["X"], w["y"], w["psi"], prior, n_sub=500, seed=0)
+    t_map = time.perf_counter() - t0
+    M_full = M_sub * (500.0 / N)
+    L_full = np.linalg.cholesky(M_full)
+    M_chol = torch.from_numpy(np.ascontiguousarray(L_full.T)).cuda()
+    say(f"subset MAP and M: {t_map:.1f} s")
+    k = 64
+    ch = Chain(pb, h, X, y, M_chol, args.refresh, k=k)
+    ch.psi.copy_(psi0)
+    # the step size at the freeze threshold of the Langevin-phase monitor
+    G = []
+    for r in range(17):
+        ch.estimate("plain_fp32", 90_000 + r)
+        if r > 0:           # the first estimate only warms the y system up
+            G.append(ch.g.cpu().numpy().copy())
+    V = np.cov(np.array(G).T)
+    lam_max = float(np.linalg.eigvalsh(L_full.T @ V @ L_full).max())
+    eps_t = 4 * 0.002 / lam_max
+    ch.S_warm.zero_()
+    say(f"step size at the Langevin freeze threshold: {eps_t:.3g} (lambda_max {lam_max:.3g})")
+
+    K_, W_ = args.steps, args.warmup
+    for t in range(W_):
+        ch.step("plain_fp32", t, 1, t == 0, eps_t)
+    saved = (ch.psi.clone(), ch.S_warm.clone())
+
+    def restore():
+        ch.psi.copy_(saved[0])
+        ch.S_warm.copy_(saved[1])
+
+    def leg(method, period, count):
+        restore()
+        el, pr = ch.timed(method, W_, count, period, eps_t)
+        return {"grad_estimates_per_s": count / el, "steps": count, "probe_period": period,
+                "kmv_passes_per_estimate": pr["kmv_passes"] / count,
+                "kmv_avg_launch_ms": pr["kmv_ms"] / max(1, pr["kmv_launches"]),
+                "dquad_avg_ms": pr["dquad_ms"] / max(1, pr["dquad_launches"])}
+
+    # the headline: plain FP32, fresh probes every step
+    restore()
+    ch.flagged.zero_()
+    elapsed, prof = ch.timed("plain_fp32", W_, K_, 1, eps_t)
+    value = K_ / elapsed
+    psi_eval = ch.psi.clone()       # a state of the chain, off the training set, for the error leg
+    headline_flagged = int(ch.flagged.item())
+    final_stats = pb.decode_stats(ch.stats)
+    say(f"plain FP32, fresh probes: {value:.2f} estimates/s")
+    # the paper's protocol: probes redrawn every 20 steps, every system warm-started
+    paper = leg("plain_fp32", PROBE_PERIOD, K_)
+    say(f"plain FP32, paper protocol: {paper['grad_estimates_per_s']:.2f} estimates/s")
+    bf16 = leg("plain_bf16", 1, K_)
+    say(f"BF16 split K+V: {bf16['grad_estimates_per_s']:.2f} estimates/s")
+
+    # K.V throughput of each arithmetic mode at the same shape (m = 32)
+    import workloads
+    Vb = pb.colmajor(N, M)
+    Vb.copy_(torch.from_numpy(workloads.gaussian_matrix(N, M, seed=11)).cuda())
+    outb = pb.colmajor(N, M)
+    kv_modes = {}
+    for name, prec in (("fp32", pb.GP_FP32), ("bf16_split_v", pb.GP_BF16_SPLIT_V),
+                       ("bf16_split_kv", pb.GP_BF16_SPLIT_KV)):
+        pb.gp_kmv(h, X, psi0, Vb, out=outb, prec=prec)
+        torch.cuda.synchronize()
+        pb.gp_profile(h, 1)
+        for _ in range(5):
+            pb.gp_kmv(h, X, psi0, Vb, out=outb, prec=prec)
+        pr = pb.gp_profile_read(h)
+        pb.gp_profile(h, 0)
+        ms = pr["kmv_ms"] / pr["kmv_launches"]
+        kv_modes[name] = {"avg_launch_ms": ms, "tflops": kmv_flops(N, D, M) / (ms * 1e-3) / 1e12}
+
+    learned = None
+    equal = None
+    if args.learned_steps:
+        Lr = learned_from_chains(pb, h, X, y, psi_map, M_sub, L_full, eps_train, prior,
+                                 args.learn_chains, args.learn_chain_steps, args.learn_epochs, k=k)
+        Lr["info"]["chain_step_size"] = eps_train
+        Tm = pb.precond_targets(h, X, y, Lr["U"], torch.from_numpy(psi_map[None, :].copy()).cuda())
+        ch.set_learned(Lr, pb.precond_from_targets(h, Tm[0], k))
+        say(f"learned set-up: {Lr['info']['pairs']} pairs, {Lr['info']['seconds_total']:.1f} s")
+        legs = {}
+        ch.fallbacks.zero_()
+        for method in ("learned_bf16", "learned_bf16_uc", "galerkin_fixed_bf16", "galerkin_direct_bf16"):
+            legs[method] = leg(method, 1, args.learned_steps)
+            say(f"{method}: {legs[method]['grad_estimates_per_s']:.2f} estimates/s")
+        legs["paper_protocol"] = leg("learned_bf16", PROBE_PERIOD, args.learned_steps)
+        learned = dict(legs["learned_bf16"])
+        learned.update({"vs_plain_fp32": learned["grad_estimates_per_s"] / value,
+                        "precision": "bf16_split_kv", "refresh": args.refresh,
+                        "with_warm_start_uc": legs["learned_bf16_uc"],
+                        "galerkin_fixed_at_map_bf16": legs["galerkin_fixed_bf16"],
+                        "galerkin_direct_bf16": legs["galerkin_direct_bf16"],
+                        "paper_protocol": legs["paper_protocol"],
+                        "steps_with_fallback": int(ch.fallbacks.item()),
+                        "training": Lr["info"]})
+        if args.equal_error_reps:
+            equal = equal_error_leg(args, pb, h, X, y, ch, psi_eval)
+
+    kmv_avg_s = prof["kmv_ms"] / max(1, prof["kmv_launches"]) / 1e3
+    achieved = kmv_flops(N, D, M) / kmv_avg_s / 1e12
+    return {
+        "metric": "unbiased grad estimates/s and K·V TFLOP/s at n=65536, learned+BF16 vs plain",
+        "value": value,
+        "unit": "grad_estimates/s",
+        "n_gpus": 1,
+        "steps": K_,
+        "warmup": W_,
+        "ms_per_step": 1e3 * elapsed / K_,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD, "n": N, "d": D, "rhs": M, "probes": NPROBES,
+                   "probe_kind": "gaussian", "probe_period": 1, "q": 1.0, "rate": 1.0,
+                   "eps_rel": 1e-6, "psi_start": "truth", "warm_start": "y from its last CG iterate",
+                   "sgld_eps": eps_t, "sgld_eps_rule": "(eps/4) lambda_max(L^T V L) = 0.002, V from "
+                   "16 estimates at the truth (the freeze threshold of the Langevin-phase monitor)",
+                   "sgld_M": "(-H)^-1 at the MAP of a 500-point subset, x 500/n",
+                   "precision": "fp32",
+                   "value_is": "plain FP32 path; learned+BF16 in learned_bf16, K.V in roofline"},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_FP32_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / VALU_FP32_PEAK_TFLOPS,
+                     "traffic": traffic_from_profile(), "kernel": "kmv_mfma_f32 (K.V, m=32)",
+                     "avg_launch_ms": kmv_avg_s * 1e3, "launches": prof["kmv_launches"]},
+        "kv_tflops": achieved,
+        "kmv_passes_per_estimate": prof["kmv_passes"] / K_,
+        "dquad_avg_ms": prof["dquad_ms"] / max(1, prof["dquad_launches"]),
+        "exp_per_s": N * float(N) / kmv_avg_s,
+        "paper_protocol": paper,
+        "bf16_split_kv_solver": dict(bf16, refresh=args.refresh),
+        "kv_by_precision": kv_modes,
+        "learned_bf16": learned,
+        "equal_error": equal,
+        "sgld_preconditioner": {"subset": 500, "map_seconds": t_map, "psi_map": psi_map.tolist(),
+                                "M_diag": np.diag(M_full).tolist()},
+        "last_step_stats": {"l": [s_["l"] for s_ in final_stats],
+                            "J_max": max(max(s_["J_a"], s_["J_b"]) for s_ in final_stats)},
+        "steps_with_flagged_systems": headline_flagged,
+        "psi_final": psi_eval.cpu().numpy().tolist(),
+    }
+
+
+def equal_error_leg(args, pb, h, X, y, ch, psi_eval):
+    """Gradient error against estimates/s at one state of the headline chain (not in the
+    training set): the paper's error measure, the mean over repetitions of
+    log10 ||g~ - g_ref||^2 / ||g_ref||^2 (Sec. 4.2), with g_ref the plain estimator with
+    converged solves averaged over batches of 31 probes (its standard error reported).
+    Every estimate draws fresh probes; the y system keeps its warm start from the previous
+    estimate.  Methods: plain FP32, and with BF16 split-K+V products plus residual
+    replacement: the learned preconditioner, the Galerkin preconditioner on the same basis
+    computed directly at the psi of each estimate (its K U product counted in the time),
+    and the Galerkin preconditioner fixed at the subset MAP."""
+    import numpy as np
+    import torch
+    from paper_1501_05427_amd import protocol
+    t0 = time.perf_counter()
+    g_ref, g_se = protocol.probe_mean_gradient(h, X, y, psi_eval, args.equal_error_ref_batches,
+                                               probes=NPROBES, probe_stream=21)
+    t_ref = time.perf_counter() - t0
+    say(f"equal error: reference gradient {t_ref:.1f} s")
+    rows = {}
+    q_saved = ch.params.q
+    for method in ("plain_fp32", "learned_bf16", "galerkin_direct_bf16", "galerkin_fixed_bf16"):
+        rows[method] = []
+        for q in (args.equal_error_q_plain if method == "plain_fp32" else args.equal_error_q):
+            ch.params.q = q
+            ch.psi.copy_(psi_eval)
+            ch.S_warm.zero_()
+            errs, el = [], 0.0
+            for r in range(args.equal_error_reps + 1):   # r = 0 warms the y system up, untimed
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                ch.estimate(method, 50_000 + r)
+                torch.cuda.synchronize()
+                if r == 0:
+                    continue
+                el += time.perf_counter() - t1
+                e = ch.g.cpu().numpy() - g_ref
+                errs.append(float(np.sum(e * e) / np.sum(g_ref * g_ref)))
+            lg = np.log10(np.array(errs))
+            rows[method].append({"q": q, "reps": len(errs), "mean_log10_rel_sq_err": float(lg.mean()),
+                                 "se": float(lg.std(ddof=1) / np.sqrt(len(lg))),
+                                 "grad_estimates_per_s": len(errs) / el,
+                                 "var_normalised_throughput": len(errs) / el / float(np.mean(errs))})
+            say(f"equal error {method} q={q}: {rows[method][-1]['mean_log10_rel_sq_err']:.2f} "
+                f"+- {rows[method][-1]['se']:.2f}, {rows[method][-1]['grad_estimates_per_s']:.2f}/s")
+    ch.params.q = q_saved
+    base = rows["plain_fp32"]
+    return {"psi": "the headline chain's last state", "g_ref_rel_se": float(np.linalg.norm(g_se) / np.linalg.norm(g_ref)),
+            "ref_probes": args.equal_error_ref_batches * NPROBES, "ref_seconds": t_ref,
+            "methods": rows,
+            "learned_bf16_vs_plain_fp32_at_matched_error": matched_error_rates(base, rows["learned_bf16"]),
+            "learned_bf16_vs_galerkin_direct_at_matched_error":
+                matched_error_rates(rows["galerkin_direct_bf16"], rows["learned_bf16"]),
+            "learned_bf16_vs_galerkin_fixed_at_matched_error":
+                matched_error_rates(rows["galerkin_fixed_bf16"], rows["learned_bf16"])}
 
 
 def error_sweep(args, pb, h, X, y, w, psi0):
@@ -260,7 +632,8 @@ def error_sweep(args, pb, h, X, y, w, psi0):
 
     Error of one estimate: log10 ||g~ - g_ref||^2 / ||g_ref||^2, averaged over `reps`
     independent estimates at the workload's psi (the paper's measure of gradient accuracy,
-    Sec. 4.2).  g_ref: the plain FP32 estimator with converged solves (q = 0, so the series
+    Sec. 4.2), which is off the network's training set: the states of plain-solver SGLD
+    chains started around the MAP of a 500-point subset, where the basis is built.  g_ref: the plain FP32 estimator with converged solves (q = 0, so the series
     never truncates; CG to 1e-6 relative) averaged over `ref_probes` Gaussian probes; its
     standard error is reported.  Each estimate draws fresh probes; the y system keeps its
     warm start from the previous estimate as it would along a chain.
@@ -285,7 +658,19 @@ def error_sweep(args, pb, h, X, y, w, psi0):
                                                    probe_stream=21, progress=progress)
     t_ref = time.perf_counter() - t0
 
-    L = setup_learned(pb, h, X, y, w, args.learn_pairs, args.learn_epochs)
+    # the network: trained on the states of plain-solver SGLD chains (basis at the subset MAP)
+    from paper_1501_05427_amd import protocol
+    P = D + 2
+    prior = {"kind": 1, "a": np.zeros(P), "b": np.full(P, 3.0)}
+    t0 = time.perf_counter()
+    psi_map, M_sub, _ = protocol.sgld_preconditioner(h, w["X"], w["y"], w["psi"], prior, n_sub=500, seed=0)
+    L_full = np.linalg.cholesky(M_sub * (500.0 / N))
+    say(f"subset MAP: {time.perf_counter() - t0:.1f} s")
+    L = learned_from_chains(pb, h, X, y, psi_map, M_sub, L_full, 1e-3, prior, args.learn_chains,
+                            args.learn_chain_steps, args.learn_epochs, probes=args.learn_chain_probes)
+    say(f"learned set-up: {L['info']['pairs']} pairs, {L['info']['seconds_total']:.1f} s")
+    L["coef"] = torch.zeros(L["k"] + 1, dtype=torch.float64, device="cuda")
+    L["pc"] = pb.make_precond(L["U"], L["coef"])
     psi = psi0.clone()
 
     def run(method, q):
@@ -293,6 +678,7 @@ def error_sweep(args, pb, h, X, y, w, psi0):
         learned = method.startswith("learned")
         if method.endswith("bf16"):
             params.prec = pb.GP_BF16_SPLIT_KV
+            params.refresh = args.refresh
         if learned:
             pb.precond_from_mlp(h, L["prm"], L["I"], L["H"], L["O"], psi, L["k"], coef=L["coef"])
         S_warm.zero_()
@@ -337,7 +723,10 @@ def error_sweep(args, pb, h, X, y, w, psi0):
             rows.append(run(method, q))
             print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
     out = {"error_sweep": rows, "g_ref": g_ref.tolist(), "g_ref_se": g_ref_se.tolist(),
-           "ref_probes": batches * NPROBES, "ref_seconds": t_ref,
+           "ref_probes": batches * NPROBES, "ref_seconds": t_ref, "training": L["info"],
+           "matched_error": matched_error_rates([r for r in rows if r["method"] == "plain_fp32"],
+                                                [r for r in rows if r["method"] == "learned_bf16"])
+           if {"plain_fp32", "learned_bf16"} <= {r["method"] for r in rows} else None,
            "workload": WORKLOAD, "probes": NPROBES, "fresh_probes_every_estimate": True}
     print(json.dumps(out), flush=True)
 
@@ -654,15 +1043,24 @@ def chains_bench(args, pb):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=40)
-    ap.add_argument("--fresh-steps", type=int, default=4)
+    ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--learned-steps", type=int, default=None,
-                    help="steps of the learned-preconditioner + BF16 run (default: --steps; 0 skips)")
-    ap.add_argument("--learn-pairs", type=int, default=256)
+                    help="steps of each learned / Galerkin leg (default: --steps; 0 skips them)")
+    ap.add_argument("--learn-chains", type=int, default=8,
+                    help="plain-solver SGLD chains whose states train the network")
+    ap.add_argument("--learn-chain-steps", type=int, default=32)
+    ap.add_argument("--learn-chain-probes", type=int, default=4, help="probes of the training chains")
+    ap.add_argument("--learn-pairs", type=int, default=256, help="error sweep: jittered training pairs")
     ap.add_argument("--learn-epochs", type=int, default=1500)
-    ap.add_argument("--bf16-steps", type=int, default=None,
-                    help="steps of the BF16 split-K+V solver run (default: --steps)")
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--refresh", type=int, default=3,
+                    help="residual replacement of the BF16 legs: on a 2^refresh residual drop")
+    ap.add_argument("--equal-error-reps", type=int, default=30, help="0 skips the equal-error leg")
+    ap.add_argument("--equal-error-q", type=lambda t: [float(v) for v in t.split(",")], default=[1.0, 3.0, 10.0],
+                    help="thresholds q of the preconditioned legs")
+    ap.add_argument("--equal-error-q-plain", type=lambda t: [float(v) for v in t.split(",")],
+                    default=[0.5, 1.0, 3.0], help="thresholds q of the plain leg")
+    ap.add_argument("--equal-error-ref-batches", type=int, default=8)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the compact batched leg of the main line")
     ap.add_argument("--profile-kmv", action="store_true")
@@ -701,8 +1099,6 @@ def main():
     ap.add_argument("--study-ref-batches", type=int, default=8)
     ap.add_argument("--study-max-iter", type=int, default=20000)
     args = ap.parse_args()
-    if args.bf16_steps is None:
-        args.bf16_steps = args.steps
     if args.learned_steps is None:
         args.learned_steps = args.steps
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -796,213 +1192,7 @@ def main():
                           "kmv_source_sha256_16": kmv_source_hash()}), flush=True)
         return
 
-    params = pb.make_params(q=1.0, rate=1.0, eps=1e-6, eps_relative=1, max_iter=1000,
-                            rng_stream=1, rng_counter=0)
-    psi = psi0.clone()
-    prior_a = torch.zeros(D + 2, dtype=torch.float64, device="cuda")
-    prior_b = torch.full((D + 2,), 3.0, dtype=torch.float64, device="cuda")
-    S_warm = torch.zeros((M, N), dtype=torch.float64, device="cuda").t()
-    R = pb.colmajor(N, NPROBES)
-    g = torch.zeros(D + 2, dtype=torch.float64, device="cuda")
-    stats = pb.stats_tensor(M)
-    eps_t = 1e-3
-    # SGLD preconditioner M = I / n: the log-likelihood gradient grows like n, so the
-    # drift eps_t / 2 M g stays O(eps_t) per step (the paper scales M the same way through
-    # the inverse Hessian of a data subset)
-    M_chol = torch.diag(torch.full((D + 2,), N ** -0.5, dtype=torch.float64)).t().contiguous().cuda()
-    flagged = torch.zeros((), dtype=torch.int64, device="cuda")
-
-    def step(t, period):
-        # the paper's protocol: probes redrawn every `period` steps, every system warm
-        # started from its last CG iterate; period 1 = fresh probes every step, where only
-        # the y system is warm started
-        params.rng_counter = t
-        if period > 1:
-            if t % period == 0:
-                pb.gp_draw_probes(h, N, NPROBES, pb.PROBE_GAUSSIAN, 7, t // period, R=R)
-                S_warm[:, 1:].zero_()
-            pb.gp_stoch_grad(h, X, psi, y, params, R=R, S_warm=S_warm, g=g, stats=stats)
-        else:
-            pb.gp_stoch_grad(h, X, psi, y, params, n_probes=NPROBES, probe_kind=pb.PROBE_GAUSSIAN,
-                             S_warm=S_warm, g=g, stats=stats)
-        pb.sgld_step(h, psi, g, eps_t, rng_stream=1, rng_counter=t, prior_kind=1,
-                     prior_a=prior_a, prior_b=prior_b, M_chol=M_chol)
-        flagged.add_(stats.view(M, -1)[:, 24:28].view(torch.int32).ne(0).any().to(torch.int64))
-
-    def timed(first, count, period):
-        torch.cuda.synchronize()
-        pb.gp_profile(h, 1)
-        t0 = time.perf_counter()
-        for t in range(first, first + count):
-            step(t, period)
-        torch.cuda.synchronize()
-        el = time.perf_counter() - t0
-        pr = pb.gp_profile_read(h)
-        pb.gp_profile(h, 0)
-        return el, pr
-
-    period = PROBE_PERIOD
-    for t in range(args.warmup):
-        step(t, period)
-    # the FP32 and BF16 runs below start from this same state and use the same draws
-    saved = (psi.clone(), S_warm.clone(), R.clone())
-
-    def restore():
-        psi.copy_(saved[0])
-        S_warm.copy_(saved[1])
-        R.copy_(saved[2])
-
-    elapsed, prof = timed(args.warmup, args.steps, period)
-    final_stats = pb.decode_stats(stats)
-    value_plain = args.steps / elapsed
-    # fresh probes every step, for reference (a few steps; not the headline)
-    el_fresh, prof_fresh = None, None
-    if args.fresh_steps:
-        restore()
-        el_fresh, prof_fresh = timed(args.warmup, args.fresh_steps, 1)
-
-    # K.V throughput of each arithmetic mode at the same shape (m = 32)
-    Vb = pb.colmajor(N, M)
-    Vb.copy_(torch.from_numpy(workloads.gaussian_matrix(N, M, seed=11).T.copy()).cuda().t())
-    outb = pb.colmajor(N, M)
-    kv_modes = {}
-    for name, prec in (("fp32", pb.GP_FP32), ("bf16_split_v", pb.GP_BF16_SPLIT_V),
-                       ("bf16_split_kv", pb.GP_BF16_SPLIT_KV)):
-        pb.gp_kmv(h, X, psi0, Vb, out=outb, prec=prec)
-        torch.cuda.synchronize()
-        pb.gp_profile(h, 1)
-        for _ in range(5):
-            pb.gp_kmv(h, X, psi0, Vb, out=outb, prec=prec)
-        pr = pb.gp_profile_read(h)
-        pb.gp_profile(h, 0)
-        ms = pr["kmv_ms"] / pr["kmv_launches"]
-        kv_modes[name] = {"avg_launch_ms": ms, "tflops": kmv_flops(N, D, M) / (ms * 1e-3) / 1e12}
-
-    # the same protocol with the split-KV BF16 products inside the solver
-    el_bf16 = None
-    if args.bf16_steps:
-        restore()
-        params.prec = pb.GP_BF16_SPLIT_KV
-        el_bf16, prof_bf16 = timed(args.warmup, args.bf16_steps, period)
-        params.prec = pb.GP_FP32
-
-    # learned warm start / preconditioner + BF16 split-KV products (setup untimed)
-    learned = None
-    if args.learned_steps:
-        t_setup = time.perf_counter()
-        L = setup_learned(pb, h, X, y, w, args.learn_pairs, args.learn_epochs)
-        t_setup = time.perf_counter() - t_setup
-        prm, pc, coef, I_, H, O_, k = L["prm"], L["pc"], L["coef"], L["I"], L["H"], L["O"], L["k"]
-        ltr, ritz = L["loss_trace"], L["ritz"]
-
-        def step_learned(t):
-            params.rng_counter = t
-            if t % period == 0:
-                pb.gp_draw_probes(h, N, NPROBES, pb.PROBE_GAUSSIAN, 7, t // period, R=R)
-                S_warm[:, 1:].zero_()
-            pb.precond_from_mlp(h, prm, I_, H, O_, psi, k, coef=coef)
-            pb.gp_stoch_grad_pc(h, X, psi, y, params, pc, R=R, S_warm=S_warm, g=g, stats=stats)
-            pb.sgld_step(h, psi, g, eps_t, rng_stream=1, rng_counter=t, prior_kind=1,
-                         prior_a=prior_a, prior_b=prior_b, M_chol=M_chol)
-            flagged.add_(stats.view(M, -1)[:, 24:28].view(torch.int32).ne(0).any().to(torch.int64))
-
-        def timed_learned(first, count, fresh):
-            torch.cuda.synchronize()
-            pb.gp_profile(h, 1)
-            t0 = time.perf_counter()
-            for t in range(first, first + count):
-                if fresh:
-                    S_warm[:, 1:].zero_()
-                    pb.gp_draw_probes(h, N, NPROBES, pb.PROBE_GAUSSIAN, 9, t, R=R)
-                    params.rng_counter = t
-                    pb.precond_from_mlp(h, prm, I_, H, O_, psi, k, coef=coef)
-                    pb.gp_stoch_grad_pc(h, X, psi, y, params, pc, R=R, S_warm=S_warm, g=g, stats=stats)
-                    pb.sgld_step(h, psi, g, eps_t, rng_stream=1, rng_counter=t, prior_kind=1,
-                                 prior_a=prior_a, prior_b=prior_b, M_chol=M_chol)
-                else:
-                    step_learned(t)
-            torch.cuda.synchronize()
-            el = time.perf_counter() - t0
-            pr = pb.gp_profile_read(h)
-            pb.gp_profile(h, 0)
-            return el, pr
-
-        params.prec = pb.GP_BF16_SPLIT_KV
-        restore()
-        el_l, pr_l = timed_learned(args.warmup, args.learned_steps, False)
-        el_lf, pr_lf = None, None
-        if args.fresh_steps:
-            restore()
-            el_lf, pr_lf = timed_learned(args.warmup, args.fresh_steps, True)
-        params.prec = pb.GP_FP32
-        learned = {
-            "grad_estimates_per_s": args.learned_steps / el_l,
-            "kmv_passes_per_estimate": pr_l["kmv_passes"] / args.learned_steps,
-            "kmv_avg_launch_ms": pr_l["kmv_ms"] / max(1, pr_l["kmv_launches"]),
-            "dquad_avg_ms": pr_l["dquad_ms"] / max(1, pr_l["dquad_launches"]),
-            "steps": args.learned_steps,
-            "vs_plain_fp32": (args.learned_steps / el_l) / value_plain,
-            "fresh_probes_every_step": None if el_lf is None else {
-                "grad_estimates_per_s": args.fresh_steps / el_lf,
-                "kmv_passes_per_estimate": pr_lf["kmv_passes"] / args.fresh_steps},
-            "setup_s": t_setup, "rank": k, "hidden": H, "train_pairs": args.learn_pairs,
-            "train_epochs": args.learn_epochs, "train_loss_first_last": [float(ltr[0]), float(ltr[-1])],
-            "ritz_top_bottom": [float(ritz[0]), float(ritz[-1])],
-            "precision": "bf16_split_kv",
-        }
-
-    K = args.steps
-    value = K / elapsed
-    kmv_avg_s = prof["kmv_ms"] / max(1, prof["kmv_launches"]) / 1e3
-    flops = kmv_flops(N, D, M)
-    achieved = flops / kmv_avg_s / 1e12
-    dq_avg_ms = prof["dquad_ms"] / max(1, prof["dquad_launches"])
-    passes = prof["kmv_passes"] / max(1, K)
-    traffic = traffic_from_profile()
-
-    rec = {
-        "metric": "unbiased grad estimates/s and K\u00b7V TFLOP/s at n=65536, learned+BF16 vs plain",
-        "value": value,
-        "unit": "grad_estimates/s",
-        "n_gpus": 1,
-        "steps": K,
-        "warmup": args.warmup,
-        "ms_per_step": 1e3 * elapsed / K,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": WORKLOAD, "n": N, "d": D, "rhs": M, "probes": NPROBES,
-                   "probe_kind": "gaussian", "probe_period": period, "q": 1.0, "rate": 1.0,
-                   "eps_rel": 1e-6, "warm_start": "last CG iterate, every system",
-                   "sgld_eps": eps_t, "sgld_M": "I/n", "precision": "fp32",
-                   "value_is": "plain FP32 path; learned+BF16 in learned_bf16, K.V in roofline"},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_FP32_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / VALU_FP32_PEAK_TFLOPS,
-                     "traffic": traffic, "kernel": "kmv_mfma_f32 (K.V, m=32)",
-                     "avg_launch_ms": kmv_avg_s * 1e3, "launches": prof["kmv_launches"]},
-        "kv_tflops": achieved,
-        "kmv_passes_per_estimate": passes,
-        "fresh_probes_every_step": None if el_fresh is None else {
-            "grad_estimates_per_s": args.fresh_steps / el_fresh,
-            "kmv_passes_per_estimate": prof_fresh["kmv_passes"] / args.fresh_steps,
-            "steps": args.fresh_steps},
-        "kv_by_precision": kv_modes,
-        "bf16_split_kv_solver": None if el_bf16 is None else {
-            "grad_estimates_per_s": args.bf16_steps / el_bf16,
-            "kmv_passes_per_estimate": prof_bf16["kmv_passes"] / args.bf16_steps,
-            "kmv_avg_launch_ms": prof_bf16["kmv_ms"] / max(1, prof_bf16["kmv_launches"]),
-            "dquad_avg_ms": prof_bf16["dquad_ms"] / max(1, prof_bf16["dquad_launches"]),
-            "steps": args.bf16_steps},
-        "learned_bf16": learned,
-        "dquad_avg_ms": dq_avg_ms,
-        "exp_per_s": N * float(N) / kmv_avg_s,
-        "last_step_stats": {"l": [s["l"] for s in final_stats],
-                            "J_max": max(max(s["J_a"], s["J_b"]) for s in final_stats)},
-        "steps_with_flagged_systems": int(flagged.item()),
-        "psi_final_finite": bool(torch.isfinite(psi).all().item()),
-    }
+    rec = main_line(args, pb, h, X, y, w, psi0)
     if not args.no_batched:
         # the batched forms on 64 GPs (n 2048 to 32768, d 2 to 16; inputs with 256 random
         # features to keep their generation short); 3 + 20 steps span one probe redraw
@@ -1021,7 +1211,7 @@ def main():
         except Exception as e:  # the main line must still be printed
             rec["batched_64_gps"] = {"error": repr(e)}
     if not args.no_cpu_baseline:
-        rec["cpu_baseline"] = cpu_baseline(w["X"], w["psi"], passes)
+        rec["cpu_baseline"] = cpu_baseline(w["X"], w["psi"], rec["kmv_passes_per_estimate"])
     print(json.dumps(rec), flush=True)
 
 

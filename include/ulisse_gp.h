@@ -339,6 +339,9 @@ gp_status sgld_run(gp_handle* h, gp_data X, double* psi, const float* y,
  *   not finite, or a log d or log tau lies outside [-60, 60], the output is rejected: coef
  *   becomes h = 0, tau_inv = -1 (the fallback marker of gp_precond: the plain solver runs)
  *   and c = 0.  Everything happens on the device, so the call never waits.
+ * precond_from_targets: the same coefficients (and rejection rule) from one row of
+ *   precond_targets (2k + 1 FP32: c, log d, log tau) instead of the network: the Galerkin
+ *   preconditioner computed directly at a psi, without learning.
  * precond_warm_start: s0 = U c (n FP64).
  */
 gp_status precond_build_basis(gp_handle* h, gp_data X, const double* psi_ref, int32_t k,
@@ -362,6 +365,8 @@ gp_status precond_mlp_grad(gp_handle* h, const float* params, int32_t in, int32_
 gp_status precond_from_mlp(gp_handle* h, const float* params, int32_t in, int32_t hidden,
                            int32_t out, const double* psi, int32_t k, double* coef, double* c,
                            void* stream);
+gp_status precond_from_targets(gp_handle* h, const float* targets, int32_t k, double* coef,
+                               double* c, void* stream);
 gp_status precond_warm_start(gp_handle* h, const float* U, int64_t ldu, int32_t k, int64_t n,
                              const double* c, double* s0, void* stream);
 

@@ -168,6 +168,8 @@ def lib():
     L.precond_from_mlp.restype = c_int
     L.precond_from_mlp.argtypes = [c_void_p, c_void_p, c_int32, c_int32, c_int32, c_void_p, c_int32, c_void_p,
                                    c_void_p, c_void_p]
+    L.precond_from_targets.restype = c_int
+    L.precond_from_targets.argtypes = [c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_void_p]
     L.precond_warm_start.restype = c_int
     L.precond_warm_start.argtypes = [c_void_p, c_void_p, c_int64, c_int32, c_int64, c_void_p, c_void_p, c_void_p]
     L.sgld_run.restype = c_int
@@ -583,6 +585,15 @@ def precond_from_mlp(h, params, n_in, hidden, n_out, psi, k, coef=None, c=None, 
         coef = torch.zeros(k + 1, dtype=torch.float64, device=psi.device)
     _check(lib().precond_from_mlp(h.ptr, _ptr(params), n_in, hidden, n_out, _ptr(psi), int(k), _ptr(coef),
                                   _ptr(c), _stream(stream)))
+    return coef
+
+
+def precond_from_targets(h, targets, k, coef=None, c=None, stream=None):
+    """coef (and c) from one row of precond_targets: the Galerkin preconditioner at that psi."""
+    import torch
+    if coef is None:
+        coef = torch.zeros(k + 1, dtype=torch.float64, device=targets.device)
+    _check(lib().precond_from_targets(h.ptr, _ptr(targets), int(k), _ptr(coef), _ptr(c), _stream(stream)))
     return coef
 
 

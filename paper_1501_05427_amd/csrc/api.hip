@@ -1248,6 +1248,16 @@ gp_status precond_from_mlp(gp_handle* h, const float* params, int32_t in, int32_
     return GP_OK;
 }
 
+gp_status precond_from_targets(gp_handle* h, const float* targets, int32_t k, double* coef,
+                               double* c, void* stream) {
+    GP_TRY(check_handle(h));
+    GP_TRY(check_k(k));
+    GP_CHECK(targets && coef && aligned(targets, 4) && aligned(coef, 8) && (c == nullptr || aligned(c, 8)),
+             "bad arguments");
+    GP_HIP(launch_targets_to_precond(targets, k, coef, c, (hipStream_t)stream));
+    return GP_OK;
+}
+
 gp_status precond_warm_start(gp_handle* h, const float* U, int64_t ldu, int32_t k, int64_t n,
                              const double* c, double* s0, void* stream) {
     GP_TRY(check_handle(h));

@@ -48,6 +48,8 @@ hipError_t launch_mlp_to_precond(const float* y, const MlpLayout& L, int k, cons
                                  double* coef, double* cvec, hipStream_t s);
 hipError_t launch_warm_from_c(const float* U, int64_t ldu, int k, int64_t n, const double* c,
                               double* s0, hipStream_t s);
+// Galerkin targets (2k + 1 FP32: c, log d, log tau) -> coef and c, as from the network.
+hipError_t launch_targets_to_precond(const float* T, int k, double* coef, double* cvec, hipStream_t s);
 // s0 = U c if coef[k] > 0 (the preconditioner is in use), else alt (zero if null).
 hipError_t launch_pc_warm(const float* U, int64_t ldu, int k, int64_t n, const double* c,
                           const double* coef, const double* alt, double* s0, hipStream_t s);

@@ -531,6 +531,33 @@ __global__ void mlp_to_precond_kernel(const float* __restrict__ Y, MlpLayout L, 
     coef[k] = 1.0 / tau;
 }
 
+// Galerkin targets (c, log d, log tau; FP32, as precond_targets writes them) -> the same
+// coefficients as mlp_to_precond_kernel, with the same rejection rule.
+__global__ void targets_to_precond_kernel(const float* __restrict__ T, int k, double* __restrict__ coef,
+                                          double* __restrict__ cvec) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    bool ok = true;
+    for (int o = 0; o <= 2 * k; ++o) {
+        const double u = (double)T[o];
+        if (!isfinite(u) || (o >= k && fabs(u) > 60.0)) ok = false;
+    }
+    if (!ok) {
+        for (int j = 0; j < k; ++j) {
+            coef[j] = 0.0;
+            if (cvec) cvec[j] = 0.0;
+        }
+        coef[k] = -1.0;
+        return;
+    }
+    const double tau = exp((double)T[2 * k]);
+    for (int j = 0; j < k; ++j) {
+        const double d = fmax(exp((double)T[k + j]), tau);
+        coef[j] = 1.0 / d - 1.0 / tau;
+        if (cvec) cvec[j] = (double)T[j];
+    }
+    coef[k] = 1.0 / tau;
+}
+
 // s0[:, 0] = U c (FP64), the learned warm start of the y system.
 __global__ void warm_from_c_kernel(const float* __restrict__ U, int64_t ldu, int k, int64_t n,
                                    const double* __restrict__ c, double* __restrict__ s0) {
@@ -646,6 +673,11 @@ hipError_t launch_adam(float* prm, const float* grad, float* m, float* v, int64_
 hipError_t launch_mlp_to_precond(const float* y, const MlpLayout& L, int k, const float* prm,
                                  double* coef, double* cvec, hipStream_t s) {
     mlp_to_precond_kernel<<<1, 64, 0, s>>>(y, L, k, prm, coef, cvec);
+    return hipGetLastError();
+}
+
+hipError_t launch_targets_to_precond(const float* T, int k, double* coef, double* cvec, hipStream_t s) {
+    targets_to_precond_kernel<<<1, 64, 0, s>>>(T, k, coef, cvec);
     return hipGetLastError();
 }
 

@@ -189,3 +189,35 @@ def ess(x):
         tau = -1.0 + 2.0 * np.sum(pairs[:K])
         out[j] = T / max(tau, 1e-300)
     return out
+
+
+def plain_chain_states(h, X, y, starts, steps, M_chol, eps, probes=4, probe_period=20, q=1.0,
+                       prior=None, rng_stream=41, seed=900):
+    """The log-parameters visited by plain-solver SGLD chains: the (theta, solve) pairs the
+    method itself generates, from which the learned preconditioner takes its training
+    inputs.  One chain per row of `starts`, all over the same GP (device X, y), stepped
+    together through gp_batch_* (gp_stoch_grad + sgld_step per chain, FP32 products, no
+    preconditioner): `probes` Gaussian probes redrawn every `probe_period` steps with warm
+    starts, threshold q sqrt(n), step size eps, SGLD preconditioner M = L L^T (M_chol: P x P
+    numpy lower factor), prior as for sgld_step (dict kind, a, b).  Returns
+    (len(starts) * steps, P) numpy, the state after every step of every chain."""
+    import torch
+    starts = np.asarray(starts, np.float64)
+    C, P = starts.shape
+    Ld = torch.as_tensor(np.ascontiguousarray(np.asarray(M_chol, np.float64).T)).cuda()
+    kind = prior.get("kind", 0) if prior else 0
+    pa = torch.as_tensor(np.asarray(prior["a"], np.float64)).cuda() if kind else None
+    pbb = torch.as_tensor(np.asarray(prior["b"], np.float64)).cuda() if kind else None
+    probs = [{"X": X, "y": y, "psi": torch.as_tensor(starts[c].copy()).cuda(), "M_chol": Ld,
+              "prior": (kind, pa, pbb)} for c in range(C)]
+    params = pb.make_params(q=q, rate=1.0, eps=1e-6, eps_relative=1, max_iter=2000, rng_stream=rng_stream)
+    batch = pb.Batch(probs, probes, params, seed=seed, probe_kind=pb.PROBE_GAUSSIAN,
+                     probe_period=probe_period, iters_per_graph=8, autotune=False, streams=min(C, 8))
+    out = np.empty((steps, C, P))
+    for t in range(steps):
+        batch.step(t, eps)
+        out[t] = torch.stack([p["psi"] for p in probs]).cpu().numpy()
+    batch.close()
+    if not np.all(np.isfinite(out)):
+        raise RuntimeError("a plain-solver chain left the finite range")
+    return out.transpose(1, 0, 2).reshape(C * steps, P)

@@ -438,16 +438,43 @@ gp_status gp_batch_read_stats(const gp_batch* b, gp_batch_stats* out);
 void gp_batch_destroy(gp_batch* b);
 
 /*
- * Autotuner of the covariance products.  With gp_autotune(h, 1), the first product of each
- * shape (n rounded up to 256, d, padded column count, precision) on this handle times the
- * split-K candidates (the number of column chunks, for 256 to 8192 workgroups, at most 64
- * chunks) on the stream and keeps the fastest for every later product of that shape; that
- * first call synchronises the stream.  Off by default (a fixed rule then targets 2048
- * workgroups).  gp_autotune_split reports the split products of a shape use now.
+ * Shape of the covariance products.  A shape code names how a product of K by V is split
+ * into work: 0 = the symmetric FP32 product (row tiles of 256 rows against column chunks;
+ * each entry of K off the diagonal tiles is built once and used for its row and, through a
+ * transposed product, for its column; FP32, d <= 8, n >= 1793, 16, 17, 32 or 33 right-hand
+ * sides); c > 0 = the split-K product whose number of column chunks gives about c
+ * workgroups (chunk partials reduced in FP64 in a fixed order).  Both give the same values
+ * to FP32 rounding, not bit for bit.
+ *
+ * The code a product takes is, per shape key (n rounded up to 256, d, padded column count,
+ * precision) on this handle: the pin set by gp_tune_set, else, with gp_autotune(h, 1), the
+ * autotuner's entry, else the default (symmetric where it applies with one MFMA block of
+ * right-hand sides or n >= 32768, else split-K for 2048 workgroups).  With the autotuner on,
+ * the first product of a key without an entry times the candidates (the symmetric product
+ * where it applies; split-K for 256 to 8192 workgroups, at most 64 chunks) on the stream and
+ * keeps the fastest; that first call synchronises the stream.
+ *
+ *   gp_tune_set     pins code (>= 0) for the key of (n, d, m, prec), or removes the pin
+ *                   (code -1).  GP_EINVAL for code 0 where the symmetric product does not
+ *                   apply, or a code above 2^20.
+ *   gp_tune_get     the code (-1: not tuned yet, the next product times it) and the number
+ *                   of split-K chunks (1 for the symmetric product, 0 for -1) used now.
+ *   gp_tune_save    writes the autotuner's entries (not the pins) as text: a header line,
+ *                   then one "n_pad d mp prec code" line per key.
+ *   gp_tune_load    reads such a file into the autotuner's entries (used while the
+ *                   autotuner is on, which then times none of those keys).  All or nothing:
+ *                   GP_EINVAL names the first malformed line and leaves the handle as it was.
+ *   gp_autotune_split  the chunk count only (kept for older callers).
+ * Host-only calls: none of them touches the device.
  */
 gp_status gp_autotune(gp_handle* h, int32_t enable);
 gp_status gp_autotune_split(gp_handle* h, int64_t n, int32_t d, int32_t m, gp_precision prec,
                             int32_t* split);
+gp_status gp_tune_set(gp_handle* h, int64_t n, int32_t d, int32_t m, gp_precision prec, int32_t code);
+gp_status gp_tune_get(gp_handle* h, int64_t n, int32_t d, int32_t m, gp_precision prec,
+                      int32_t* code, int32_t* split);
+gp_status gp_tune_save(const gp_handle* h, const char* path);
+gp_status gp_tune_load(gp_handle* h, const char* path);
 
 /*
  * Kernel timing for measurement.  While enabled, the handle records a pair of hipEvents on

@@ -182,6 +182,14 @@ def lib():
     L.gp_autotune.argtypes = [c_void_p, c_int32]
     L.gp_autotune_split.restype = c_int
     L.gp_autotune_split.argtypes = [c_void_p, c_int64, c_int32, c_int32, c_int, POINTER(c_int32)]
+    L.gp_tune_set.restype = c_int
+    L.gp_tune_set.argtypes = [c_void_p, c_int64, c_int32, c_int32, c_int, c_int32]
+    L.gp_tune_get.restype = c_int
+    L.gp_tune_get.argtypes = [c_void_p, c_int64, c_int32, c_int32, c_int, POINTER(c_int32), POINTER(c_int32)]
+    L.gp_tune_save.restype = c_int
+    L.gp_tune_save.argtypes = [c_void_p, ctypes.c_char_p]
+    L.gp_tune_load.restype = c_int
+    L.gp_tune_load.argtypes = [c_void_p, ctypes.c_char_p]
     L.gp_batch_create.restype = c_int
     L.gp_batch_create.argtypes = [POINTER(c_void_p), c_int, c_uint64, c_int32, POINTER(gp_batch_problem),
                                   c_int32, c_int32, c_int32, POINTER(ulisse_params), c_int32, c_int32, c_int32]
@@ -615,6 +623,29 @@ def gp_autotune_split(h, n, d, m, prec=GP_FP32):
     out = c_int32(0)
     _check(lib().gp_autotune_split(h.ptr, int(n), int(d), int(m), int(prec), ctypes.byref(out)))
     return out.value
+
+
+SHAPE_SYM = 0  # shape code of the symmetric product; c > 0: split-K for about c workgroups
+
+
+def gp_tune_set(h, n, d, m, code, prec=GP_FP32):
+    """Pin the product shape code of (n, d, m, prec) on h (code -1 removes the pin)."""
+    _check(lib().gp_tune_set(h.ptr, int(n), int(d), int(m), int(prec), int(code)))
+
+
+def gp_tune_get(h, n, d, m, prec=GP_FP32):
+    """(code, split) a product of that shape takes now; code -1 = not tuned yet."""
+    code, split = c_int32(0), c_int32(0)
+    _check(lib().gp_tune_get(h.ptr, int(n), int(d), int(m), int(prec), ctypes.byref(code), ctypes.byref(split)))
+    return code.value, split.value
+
+
+def gp_tune_save(h, path):
+    _check(lib().gp_tune_save(h.ptr, os.fsencode(path)))
+
+
+def gp_tune_load(h, path):
+    _check(lib().gp_tune_load(h.ptr, os.fsencode(path)))
 
 
 class Batch:

@@ -78,9 +78,11 @@ struct gp_handle {
     const uint64_t* dyn_step = nullptr;
     const uint64_t* dyn_probe_step = nullptr;
     const double* dyn_eps = nullptr;
-    // autotuner: (n_pad, d, mp, prec) -> workgroup target of the covariance product
+    // autotuner: (n_pad, d, mp, prec) -> shape code of the covariance product (0 symmetric,
+    // c > 0 split-K for about c workgroups); pins apply always, tuned entries with autotune
     bool autotune = false;
     std::map<std::array<int64_t, 4>, int> tuned;
+    std::map<std::array<int64_t, 4>, int> pinned_shape;
     // work table of the gradient reduction currently in the workspace
     int64_t work_npad = -1;
     int work_L = -1;
@@ -215,33 +217,55 @@ gp_status check_precond(const gp_precond* pc, int64_t n) {
 constexpr int kTuneTargets[] = {256, 512, 1024, 2048, 4096, 8192};
 constexpr int kTuneReps = 3;
 constexpr int kTuneMaxSplit = 64;
+constexpr int kTuneMaxCode = 1 << 20;
+constexpr const char* kTuneHeader = "ulisse_gp shape cache v1";
+
+// A candidate of the autotuner: 0 = the symmetric product, else the split-K product for
+// about that many workgroups.
+KmvShape shape_of_code(int64_t n, int d, int m, gp_precision prec, int code) {
+    return code == 0 ? kmv_shape_sym(n, d, m, prec) : kmv_shape_target(n, d, m, prec, code);
+}
 
 // The shape of the covariance products for (n, d, m, prec): the default, or with the
-// autotuner on, the fastest of the candidate splits, timed once per shape on this handle
-// with the prepared Z and kp (the timing synchronises the stream).
+// autotuner on, the fastest of the candidates (the symmetric product where it applies and
+// the split-K factors), timed once per shape on this handle with the prepared Z and kp
+// (the timing synchronises the stream).
+std::array<int64_t, 4> tune_key(const KmvShape& base, int d, gp_precision prec) {
+    return std::array<int64_t, 4>{base.n_pad, d, base.mp, (int64_t)prec};
+}
+
+// The shape code a product of (n, d, m, prec) takes without timing anything: the pin, else
+// the tuned entry when the autotuner is on, else the default's; -1 when it must be timed.
+int resolved_code(const gp_handle* h, int64_t n, int d, int m, gp_precision prec) {
+    const KmvShape base = kmv_shape(n, d, m, prec);
+    const auto key = tune_key(base, d, prec);
+    auto p = h->pinned_shape.find(key);
+    if (p != h->pinned_shape.end()) return p->second;
+    if (!h->autotune) return base.sym ? 0 : 2048;
+    auto it = h->tuned.find(key);
+    return it == h->tuned.end() ? -1 : it->second;
+}
+
 gp_status shape_for(gp_handle* h, int64_t n, int d, int m, gp_precision prec, const float* Z,
                     const KParams* kp, hipStream_t s, KmvShape* out) {
     const KmvShape base = kmv_shape(n, d, m, prec);
-    if (!h->autotune) {
-        *out = base;
+    const int code = resolved_code(h, n, d, m, prec);
+    if (code >= 0) {
+        *out = shape_of_code(n, d, m, prec, code);
         return GP_OK;
     }
-    const std::array<int64_t, 4> key{base.n_pad, d, base.mp, (int64_t)prec};
-    auto it = h->tuned.find(key);
-    if (it != h->tuned.end()) {
-        *out = kmv_shape_target(n, d, m, prec, it->second);
-        return GP_OK;
-    }
+    const auto key = tune_key(base, d, prec);
     const bool b16 = uses_bf16(base, prec);
-    int max_split = 1;
+    const bool has_sym = kmv_shape_sym(n, d, m, prec).sym;
+    size_t part_floats = has_sym ? kmv_part_floats(kmv_shape_sym(n, d, m, prec)) : 0;
     for (int target : kTuneTargets) {
-        const int sp = kmv_shape_target(n, d, m, prec, target).split;
-        if (sp <= kTuneMaxSplit) max_split = std::max(max_split, sp);
+        const KmvShape sh = kmv_shape_target(n, d, m, prec, target);
+        if (sh.split <= kTuneMaxSplit) part_floats = std::max(part_floats, kmv_part_floats(sh));
     }
     float *V, *part;
     uint16_t *VH = nullptr, *VL = nullptr;
     GP_TRY(ws(h, kSlotTuneV, (size_t)base.n_pad * base.mp, &V));
-    GP_TRY(ws(h, kSlotTunePart, (size_t)max_split * base.mp * base.n_pad, &part));
+    GP_TRY(ws(h, kSlotTunePart, part_floats, &part));
     if (b16) {
         GP_TRY(ws(h, kSlotTuneVH, (size_t)base.n_pad * base.mp, &VH));
         GP_TRY(ws(h, kSlotTuneVL, (size_t)base.n_pad * base.mp, &VL));
@@ -252,13 +276,18 @@ gp_status shape_for(gp_handle* h, int64_t n, int d, int m, gp_precision prec, co
         (void)hipEventDestroy(e0);
         return fail(GP_EDEVICE, "event creation failed");
     }
-    int best_target = 2048, last_split = -1;
+    int best_target = base.sym ? 0 : 2048, last_split = -1;
     float best_ms = 1e30f;
     gp_status st = GP_OK;
-    for (int target : kTuneTargets) {
-        const KmvShape sh = kmv_shape_target(n, d, m, prec, target);
-        if (sh.split == last_split || sh.split > kTuneMaxSplit) continue;
-        last_split = sh.split;
+    std::vector<int> codes;
+    if (has_sym) codes.push_back(0);
+    for (int target : kTuneTargets) codes.push_back(target);
+    for (int target : codes) {
+        const KmvShape sh = shape_of_code(n, d, m, prec, target);
+        if (!sh.sym) {
+            if (sh.split == last_split || sh.split > kTuneMaxSplit) continue;
+            last_split = sh.split;
+        }
         hipError_t e = launch_kmv_partials(sh, d, Z, V, VH, VL, kp, part, nullptr, prec, s);
         if (e == hipSuccess) e = hipEventRecord(e0, s);
         for (int r = 0; r < kTuneReps && e == hipSuccess; ++r)
@@ -280,7 +309,7 @@ gp_status shape_for(gp_handle* h, int64_t n, int d, int m, gp_precision prec, co
     (void)hipEventDestroy(e1);
     if (st != GP_OK) return st;
     h->tuned[key] = best_target;
-    *out = kmv_shape_target(n, d, m, prec, best_target);
+    *out = shape_of_code(n, d, m, prec, best_target);
     return GP_OK;
 }
 
@@ -355,7 +384,7 @@ struct Solve {
         a.ldb = ldb;
         a.B = B;
         a.S0 = S0;
-        GP_TRY(ws(h, kSlotPart + so, (size_t)sh.split * sh.mp * n_pad, &kpart));
+        GP_TRY(ws(h, kSlotPart + so, kmv_part_floats(sh), &kpart));
         GP_TRY(ws(h, kSlotQ + so, (size_t)n_pad * m, &a.Q));
         GP_TRY(ws(h, kSlotS + so, (size_t)n_pad * m, &a.S));
         GP_TRY(ws(h, kSlotE + so, (size_t)n_pad * m, &a.E));
@@ -418,7 +447,7 @@ struct Solve {
         if (p.refresh > 0) {
             sh32 = kmv_shape(n, d, m, GP_FP32);
             GP_TRY(ws(h, kSlotRD + so, (size_t)n_pad * sh32.mp, &D32));
-            GP_TRY(ws(h, kSlotRPart + so, (size_t)sh32.split * sh32.mp * n_pad, &kpart32));
+            GP_TRY(ws(h, kSlotRPart + so, kmv_part_floats(sh32), &kpart32));
             int* fl;
             GP_TRY(ws(h, kSlotRFlag + so, (size_t)m + 1, &fl));
             a.rflag = fl;
@@ -733,7 +762,7 @@ gp_status gp_kmv(gp_handle* h, gp_data X, const double* psi, const float* V, int
     GP_TRY(shape_for(h, X.n, X.d, m, prec, Z, kp, s, &sh));
     float *Vp, *part;
     GP_TRY(ws(h, kSlotVP, (size_t)sh.n_pad * sh.mp, &Vp));
-    GP_TRY(ws(h, kSlotPart, (size_t)sh.split * sh.mp * sh.n_pad, &part));
+    GP_TRY(ws(h, kSlotPart, kmv_part_floats(sh), &part));
     GP_HIP(launch_pack(V, X.n, m, ldv, Vp, sh.n_pad, sh.mp, s));
     uint16_t *VH = nullptr, *VL = nullptr;
     if (uses_bf16(sh, prec)) {
@@ -767,7 +796,7 @@ gp_status gp_kmv_noalloc(gp_handle* h, gp_data X, const double* psi, const float
         if (b16) b += 2 * align((size_t)sh.n_pad * sh.mp * sizeof(uint16_t));
         return b;
     };
-    KmvShape sh = kmv_shape(X.n, X.d, m, prec);
+    KmvShape sh = kmv_shape_target(X.n, X.d, m, prec, 2048);  // split-K: the symmetric form needs far more
     bool b16 = uses_bf16(sh, prec);
     for (int target = 1024; footprint(sh, b16) > kNoAllocScratchBytes && sh.split > 1; target /= 2) {
         sh = kmv_shape_target(X.n, X.d, m, prec, target);
@@ -1029,7 +1058,7 @@ namespace {
 gp_status product_padded(gp_handle* h, const KmvShape& sh, int d, const float* Z, const KParams* kp,
                          const float* Vp, int m, float* out, int64_t ldo, int64_t n, hipStream_t s) {
     float* part;
-    GP_TRY(ws(h, kSlotPart, (size_t)sh.split * sh.mp * sh.n_pad, &part));
+    GP_TRY(ws(h, kSlotPart, kmv_part_floats(sh), &part));
     GP_HIP(launch_kmv_partials(sh, d, Z, Vp, nullptr, nullptr, kp, part, nullptr, GP_FP32, s));
     GP_HIP(launch_kmv_reduce(sh, part, Vp, kp, n, m, out, ldo, s));
     return GP_OK;
@@ -1275,12 +1304,85 @@ gp_status gp_autotune(gp_handle* h, int32_t enable) {
 
 gp_status gp_autotune_split(gp_handle* h, int64_t n, int32_t d, int32_t m, gp_precision prec,
                             int32_t* split) {
-    GP_TRY(check_handle(h));
-    GP_CHECK(split != nullptr && n >= 1 && d >= 1 && d <= kMaxD && m >= 1 && m <= kMaxSys,
-             "bad arguments");
-    const KmvShape base = kmv_shape(n, d, m, prec);
-    auto it = h->tuned.find(std::array<int64_t, 4>{base.n_pad, d, base.mp, (int64_t)prec});
-    *split = it == h->tuned.end() ? base.split : kmv_shape_target(n, d, m, prec, it->second).split;
+    int32_t code = 0;
+    return gp_tune_get(h, n, d, m, prec, &code, split);
+}
+
+static gp_status check_tune_args(int64_t n, int32_t d, int32_t m, gp_precision prec) {
+    GP_CHECK(n >= 1 && d >= 1 && d <= kMaxD && m >= 1 && m <= kMaxSys, "bad shape (n %lld, d %d, m %d)",
+             (long long)n, d, m);
+    GP_CHECK(prec == GP_FP32 || prec == GP_BF16_SPLIT_V || prec == GP_BF16_SPLIT_KV, "unknown precision");
+    return GP_OK;
+}
+
+gp_status gp_tune_set(gp_handle* h, int64_t n, int32_t d, int32_t m, gp_precision prec, int32_t code) {
+    GP_CHECK(h != nullptr, "null handle");
+    GP_TRY(check_tune_args(n, d, m, prec));
+    GP_CHECK(code >= -1 && code <= kTuneMaxCode, "shape code %d outside [-1, %d]", code, kTuneMaxCode);
+    GP_CHECK(code != 0 || kmv_shape_sym(n, d, m, prec).sym,
+             "the symmetric product does not apply to n = %lld, d = %d, m = %d in this precision",
+             (long long)n, d, m);
+    const auto key = tune_key(kmv_shape(n, d, m, prec), d, prec);
+    if (code < 0)
+        h->pinned_shape.erase(key);
+    else
+        h->pinned_shape[key] = code;
+    return GP_OK;
+}
+
+gp_status gp_tune_get(gp_handle* h, int64_t n, int32_t d, int32_t m, gp_precision prec,
+                      int32_t* code, int32_t* split) {
+    GP_CHECK(h != nullptr, "null handle");
+    GP_TRY(check_tune_args(n, d, m, prec));
+    GP_CHECK(code != nullptr && split != nullptr, "null output");
+    const int c = resolved_code(h, n, d, m, prec);
+    *code = c;
+    *split = c < 0 ? 0 : shape_of_code(n, d, m, prec, c).split;
+    return GP_OK;
+}
+
+gp_status gp_tune_save(const gp_handle* h, const char* path) {
+    GP_CHECK(h != nullptr, "null handle");
+    GP_CHECK(path != nullptr, "null path");
+    FILE* f = std::fopen(path, "w");
+    if (f == nullptr) return fail(GP_EINVAL, "cannot open %s for writing", path);
+    bool ok = std::fprintf(f, "%s\n", kTuneHeader) > 0;
+    for (const auto& kv : h->tuned)
+        ok = ok && std::fprintf(f, "%lld %lld %lld %lld %d\n", (long long)kv.first[0], (long long)kv.first[1],
+                                (long long)kv.first[2], (long long)kv.first[3], kv.second) > 0;
+    ok = (std::fclose(f) == 0) && ok;
+    return ok ? GP_OK : fail(GP_EINVAL, "writing %s failed", path);
+}
+
+gp_status gp_tune_load(gp_handle* h, const char* path) {
+    GP_CHECK(h != nullptr, "null handle");
+    GP_CHECK(path != nullptr, "null path");
+    FILE* f = std::fopen(path, "r");
+    if (f == nullptr) return fail(GP_EINVAL, "cannot open %s", path);
+    char line[256];
+    gp_status st = GP_OK;
+    std::map<std::array<int64_t, 4>, int> got;
+    if (std::fgets(line, sizeof line, f) == nullptr || std::strncmp(line, kTuneHeader, std::strlen(kTuneHeader)) != 0) {
+        st = fail(GP_EINVAL, "%s is not a tuning cache (first line must be '%s')", path, kTuneHeader);
+    } else {
+        int lineno = 1;
+        while (std::fgets(line, sizeof line, f) != nullptr) {
+            ++lineno;
+            long long np, d, mp, pr;
+            int code;
+            char extra;
+            if (std::sscanf(line, "%lld %lld %lld %lld %d %c", &np, &d, &mp, &pr, &code, &extra) != 5 ||
+                np < kRowPad || np % kRowPad != 0 || d < 1 || d > kMaxD || mp < 1 || mp > kMaxSys ||
+                pr < GP_FP32 || pr > GP_BF16_SPLIT_KV || code < 0 || code > kTuneMaxCode) {
+                st = fail(GP_EINVAL, "%s line %d: expected 'n_pad d mp prec code' in range", path, lineno);
+                break;
+            }
+            got[std::array<int64_t, 4>{np, d, mp, pr}] = code;
+        }
+    }
+    std::fclose(f);
+    if (st != GP_OK) return st;
+    for (const auto& kv : got) h->tuned[kv.first] = kv.second;
     return GP_OK;
 }
 

@@ -25,12 +25,25 @@ struct KmvShape {
     int split;        // column chunks (split-K), chunk index = blockIdx % split
     int chunk;        // columns of K per chunk (multiple of 64)
     int64_t n_pad;
+    // symmetric FP32 product (each off-diagonal entry of K used twice): row tiles of 256
+    // rows against column chunks of cs columns; the partials buffer then holds the result
+    // (split = 1 layout) followed by the forward (nch chunks) and transposed (nt tiles)
+    // partials, kmv_part_floats(sh) floats in all
+    bool sym = false;
+    int cs = 0, nch = 0, nt = 0;
 };
 
+// The default shape of a product: the symmetric FP32 product where it applies and was
+// measured faster (one MFMA block of columns, or n_pad >= 32768), else the split-K product
+// for about 2048 workgroups.
 KmvShape kmv_shape(int64_t n, int d, int m, gp_precision prec);
-// The same with the split-K factor chosen for about target_wg workgroups (the default
-// targets 2048; the autotuner times several targets per shape).
+// The split-K product with the factor chosen for about target_wg workgroups (the
+// autotuner times several targets per shape); never symmetric.
 KmvShape kmv_shape_target(int64_t n, int d, int m, gp_precision prec, int target_wg);
+// The symmetric shape of (n, d, m, prec), or a shape with sym = false if it does not apply.
+KmvShape kmv_shape_sym(int64_t n, int d, int m, gp_precision prec);
+// Floats of the partials buffer that launch_kmv_partials needs for shape sh.
+size_t kmv_part_floats(const KmvShape& sh);
 KmvShape dkmv_shape(int64_t n, int d, int m);
 
 // Size of the fixed device scratch of the no-allocation entry points, and its device

@@ -328,6 +328,298 @@ __global__ __launch_bounds__(kWG) void kmv_mfma_f32_kernel(
 }
 
 // ---------------------------------------------------------------------------------------
+// Symmetric FP32 product.  K is symmetric, so an entry K_ij off the diagonal blocks serves
+// both out_i += K_ij v_j and out_j += K_ij v_i: computed once, it halves the VALU work of
+// forming K, which with the FP32 matrix unit (whose instructions do not overlap with VALU
+// instructions on this chip) sets the time of the product.
+//
+// Work item (k, I): row tile I (256 rows: 4 waves x 4 blocks of 16) against the columns of
+// column chunk k (cs columns), from column 256 I on when the chunk holds the tile's diagonal
+// block.  Stages of 64 columns inside the diagonal block are forward only (all their
+// entries); the others are symmetric: the forward product is the MFMA chain of
+// kmv_mfma_f32_kernel, and the transposed one takes each 16 x 16 block of K through a
+// per-wave LDS tile into the A-operand layout of (K^T)(16 j x 4 i), against the wave's own
+// rows of V held in registers.  The four waves' transposed partials of a stage are summed
+// in LDS in a fixed order and stored per row tile.  A right-hand-side column past the MFMA
+// blocks (tc = 1) is taken on the VALU in both directions.
+//
+// Outputs (float, ld n_pad): F[k][c][i], the forward sums of chunk k for the rows of tiles
+// whose diagonal chunk is at or before k; Tt[I][c][j], the transposed sums of tile I for
+// columns j past its diagonal block.  kmv_sym_reduce_kernel adds them up in a fixed order.
+// ---------------------------------------------------------------------------------------
+constexpr int kSymTile = 256;  // rows of a row tile (4 waves x 4 blocks of 16)
+
+__device__ inline void sym_item(int bid, int NT, int cs, int* k_out, int* I_out) {
+    // Full items first, chunk-major: chunk k pairs with the tiles I wholly before it
+    // (256 I < k cs, cs columns each).  Then the items that hold a diagonal tile, heaviest
+    // first: offset s = I mod (cs / 256) ascending (cs - 256 s columns), chunk-major inside
+    // an offset.  The hardware hands out workgroups in about this order, so the last round
+    // of the grid is filled by the lightest items.
+    const int per = cs / kSymTile;
+    const int nch = (NT + per - 1) / per;
+    for (int k = 1; k < nch; ++k) {
+        const int cnt = k * per;
+        if (bid < cnt) {
+            *k_out = k;
+            *I_out = bid;
+            return;
+        }
+        bid -= cnt;
+    }
+    for (int o = 0;; ++o) {
+        const int cnt = (NT - o + per - 1) / per;  // chunks with a tile at offset o
+        if (bid < cnt) {
+            *k_out = bid;
+            *I_out = bid * per + o;
+            return;
+        }
+        bid -= cnt;
+    }
+}
+
+template <int D, int NB, int TC>
+__global__ __launch_bounds__(kWG) void kmv_sym_f32_kernel(
+    const float* __restrict__ Z, const float* __restrict__ V, float* __restrict__ F,
+    float* __restrict__ Tt, int64_t n_pad, int NT, int cs, const KParams* __restrict__ kp,
+    const int* __restrict__ n_active) {
+    if (n_active != nullptr && *n_active == 0) return;
+    constexpr int R = 4;
+    constexpr int DP = (D + 3) & ~3;
+    static_assert(TC == 0 || TC == 1, "at most one VALU column");
+    constexpr int MP = NB * 16 + (TC > 0 ? 4 : 0);
+    constexpr int MU = NB * 16 + TC;    // columns with results
+    constexpr int TCA = TC > 0 ? TC : 1;
+    constexpr int RS = 20;              // row stride of a wave's 16 x 16 transpose tile
+    constexpr int RED = MU + 1;         // row stride of a wave's transposed partial
+    using S = Stage<DP, MP, false>;
+    __shared__ float4 zs[2][S::NZ4];
+    __shared__ float vs[2][S::VSIZE];
+    __shared__ __align__(16) float tb[4][16 * RS];
+    __shared__ float red[4][64 * RED];
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int q = lane >> 4, col = lane & 15;
+    int k, I;
+    sym_item(blockIdx.x, NT, cs, &k, &I);
+    const int64_t tile0 = (int64_t)I * kSymTile;
+    const int64_t row0 = tile0 + wave * (16 * R);
+    const int64_t diag_end = tile0 + kSymTile;
+    const int64_t jb = max((int64_t)k * cs, tile0);
+    const int64_t je = min((int64_t)(k + 1) * cs, n_pad);
+    const float negc0 = -kp->c0;
+
+    float zi[R][D];
+#pragma unroll
+    for (int r = 0; r < R; ++r) load_row<D>(Z + (row0 + r * 16 + col) * DP, zi[r]);
+    // the wave's own rows of V, B operand of the transposed product: lane (q, col) holds
+    // V[row0 + 16 r + 4 q + t][16 cb + col] for t = 0..3
+    float vI[R][4][NB];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int cb = 0; cb < NB; ++cb) vI[r][t][cb] = V[(cb * 16 + col) * n_pad + row0 + r * 16 + 4 * q + t];
+    float vIt[R][TCA];  // the VALU column at the lane's own rows
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int t = 0; t < TCA; ++t) vIt[r][t] = TC > 0 ? V[(NB * 16 + t) * n_pad + row0 + r * 16 + col] : 0.f;
+    // complete these loads here: used inside the stage loop, they would otherwise make the
+    // compiler wait for every outstanding load there, the next stage's prefetch included
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int cb = 0; cb < NB; ++cb) asm volatile("" : "+v"(vI[r][t][cb]));
+#pragma unroll
+        for (int t = 0; t < TCA; ++t) asm volatile("" : "+v"(vIt[r][t]));
+#pragma unroll
+        for (int k2 = 0; k2 < D; ++k2) asm volatile("" : "+v"(zi[r][k2]));
+    }
+
+    floatx4 acc[R][NB];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int cb = 0; cb < NB; ++cb) acc[r][cb] = floatx4{0.f, 0.f, 0.f, 0.f};
+    float tacc[R][TCA];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int t = 0; t < TCA; ++t) tacc[r][t] = 0.f;
+
+    float* tbw = tb[wave];
+    float* redw = red[wave];
+    S st;
+    st.load(Z, V, n_pad, jb);
+    st.store(zs[0], vs[0]);
+    __syncthreads();
+    int buf = 0;
+    for (int64_t j0 = jb; j0 < je; j0 += kJS) {
+        const bool more = j0 + kJS < je;
+        const bool sym = j0 >= diag_end;  // uniform over the workgroup
+        if (more) st.load(Z, V, n_pad, j0 + kJS);
+        const float* zsb = reinterpret_cast<const float*>(zs[buf]);
+        const float* vsb = vs[buf];
+#pragma unroll 1
+        for (int g = 0; g < kJS / 16; ++g) {
+            float4 vv[NB];
+#pragma unroll
+            for (int cb = 0; cb < NB; ++cb)
+                vv[cb] = *reinterpret_cast<const float4*>(vsb + (cb * 16 + col) * S::VST + g * 16 + 4 * q);
+            float4 vt[TCA];
+#pragma unroll
+            for (int t = 0; t < TC; ++t)
+                vt[t] = *reinterpret_cast<const float4*>(vsb + (NB * 16 + t) * S::VST + g * 16 + 4 * q);
+            float kv[R][4];
+#pragma unroll
+            for (int s_ = 0; s_ < 4; ++s_) {
+                float zj[D];
+                load_row<D>(zsb + (g * 16 + 4 * q + s_) * DP, zj);
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    kv[r][s_] = kf_entry<D>(zi[r], zj, negc0);
+#pragma unroll
+                    for (int cb = 0; cb < NB; ++cb) {
+                        const float b = s_ == 0 ? vv[cb].x : s_ == 1 ? vv[cb].y : s_ == 2 ? vv[cb].z : vv[cb].w;
+                        acc[r][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(kv[r][s_], b, acc[r][cb], 0, 0, 0);
+                    }
+#pragma unroll
+                    for (int t = 0; t < TC; ++t) {
+                        const float b = s_ == 0 ? vt[t].x : s_ == 1 ? vt[t].y : s_ == 2 ? vt[t].z : vt[t].w;
+                        tacc[r][t] = __builtin_fmaf(kv[r][s_], b, tacc[r][t]);
+                    }
+                }
+            }
+            if (sym) {
+                // transposed: out_j += sum_i K_ij V_i for the 16 columns j of this group
+                floatx4 tr[NB];
+#pragma unroll
+                for (int cb = 0; cb < NB; ++cb) tr[cb] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    // tb[j][i] = K(16 r + i, 16 g + j): lane (q, col) holds i = col, j = 4 q + s
+#pragma unroll
+                    for (int s_ = 0; s_ < 4; ++s_) tbw[(4 * q + s_) * RS + col] = kv[r][s_];
+                    // the other lanes' writes before the reads, the reads before the next writes
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                    // A operand of K^T: lane (q, col) takes j = col, i = 4 q + t
+                    const float4 a = *reinterpret_cast<const float4*>(tbw + col * RS + 4 * q);
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        const float at = t == 0 ? a.x : t == 1 ? a.y : t == 2 ? a.z : a.w;
+#pragma unroll
+                        for (int cb = 0; cb < NB; ++cb)
+                            tr[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(at, vI[r][t][cb], tr[cb], 0, 0, 0);
+                    }
+                }
+                // lane (q, col) holds columns j = 16 g + 4 q + v of output column 16 cb + col
+#pragma unroll
+                for (int cb = 0; cb < NB; ++cb)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) redw[(g * 16 + 4 * q + v) * RED + cb * 16 + col] = tr[cb][v];
+#pragma unroll
+                for (int t = 0; t < TC; ++t) {
+#pragma unroll
+                    for (int s_ = 0; s_ < 4; ++s_) {
+                        float p = 0.f;
+#pragma unroll
+                        for (int r = 0; r < R; ++r) p = __builtin_fmaf(kv[r][s_], vIt[r][t], p);
+                        // sum over the 16 rows of each block: lanes with equal q
+                        p += __shfl_xor(p, 1);
+                        p += __shfl_xor(p, 2);
+                        p += __shfl_xor(p, 4);
+                        p += __shfl_xor(p, 8);
+                        if (col == 0) redw[(g * 16 + 4 * q + s_) * RED + NB * 16 + t] = p;
+                    }
+                }
+            }
+        }
+        if (more) st.store(zs[buf ^ 1], vs[buf ^ 1]);
+        __syncthreads();
+        if (sym) {
+            // the four waves' partials in a fixed order -> Tt[I][c][j0 + j]
+            for (int e = threadIdx.x; e < MU * kJS; e += kWG) {
+                const int c = e / kJS, j = e % kJS;
+                const float v = ((red[0][j * RED + c] + red[1][j * RED + c]) + red[2][j * RED + c]) + red[3][j * RED + c];
+                Tt[((int64_t)I * MP + c) * n_pad + j0 + j] = v;
+            }
+            __syncthreads();
+        }
+        buf ^= 1;
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int cb = 0; cb < NB; ++cb) {
+            const int64_t i = row0 + r * 16 + 4 * q;
+            const int c = cb * 16 + col;
+            float4 o;
+            o.x = acc[r][cb][0];
+            o.y = acc[r][cb][1];
+            o.z = acc[r][cb][2];
+            o.w = acc[r][cb][3];
+            *reinterpret_cast<float4*>(F + ((int64_t)k * MP + c) * n_pad + i) = o;
+        }
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int t = 0; t < TC; ++t) {
+            float v = tacc[r][t];
+            v += __shfl_xor(v, 16);
+            v += __shfl_xor(v, 32);
+            if (q == 0) F[((int64_t)k * MP + NB * 16 + t) * n_pad + row0 + r * 16 + col] = v;
+        }
+}
+
+// out[c][i] = sum over the chunks at or after row i's diagonal chunk of F[k][c][i] + sum over
+// the row tiles before row i's of Tt[I][c][i], in that fixed order, in FP64.
+__global__ void kmv_sym_reduce_kernel(const float* __restrict__ F, const float* __restrict__ Tt,
+                                      float* __restrict__ out, int64_t n_pad, int mp, int mu,
+                                      int cs, int nch, const int* __restrict__ n_active) {
+    if (n_active != nullptr && *n_active == 0) return;
+    const int64_t total = (int64_t)mu * n_pad;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int c = (int)(e / n_pad);
+        const int64_t i = e % n_pad;
+        const int tile = (int)(i / kSymTile);
+        const int kd = (int)((int64_t)tile * kSymTile / cs);
+        // loads in batches of eight so that many are in flight; the sum keeps its order
+        const int64_t pl = (int64_t)mp * n_pad;
+        double s = 0.0;
+        const float* f = F + (int64_t)kd * pl + (int64_t)c * n_pad + i;
+        int k = kd;
+        for (; k + 8 <= nch; k += 8, f += 8 * pl) {
+            float v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = f[u * pl];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s += (double)v[u];
+        }
+        for (; k < nch; ++k, f += pl) s += (double)*f;
+        const float* t = Tt + (int64_t)c * n_pad + i;
+        int I = 0;
+        for (; I + 8 <= tile; I += 8, t += 8 * pl) {
+            float v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = t[u * pl];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s += (double)v[u];
+        }
+        for (; I < tile; ++I, t += pl) s += (double)*t;
+        out[(int64_t)c * n_pad + i] = (float)s;
+    }
+}
+
+// ---------------------------------------------------------------------------------------
 // BF16 MFMA product (v_mfma_f32_16x16x32_bf16, FP32 accumulation).  Inside a 32-column
 // group, lane l takes columns j = 8 (l / 16) + s for s = 0..7: its 8 K values for row
 // lane % 16 form the A operand, and the B operand is the matching 8 consecutive entries of
@@ -756,7 +1048,46 @@ static void pick_split(KmvShape& sh, int target_wg) {
 }
 
 KmvShape kmv_shape(int64_t n, int d, int m, gp_precision prec) {
+    // the symmetric product by default where it was measured faster than split-K: one MFMA
+    // block of columns, or n of 32768 and more (two blocks at n = 16384 are 9% slower: the
+    // transposed partials cost more than the halved entry work saves)
+    const KmvShape sy = kmv_shape_sym(n, d, m, prec);
+    if (sy.sym && (sy.mp <= 20 || sy.n_pad >= 32768)) return sy;
     return kmv_shape_target(n, d, m, prec, 2048);
+}
+
+static int64_t sym_items(int nt, int nch, int cs) {
+    int64_t t = 0;
+    for (int k = 0; k < nch; ++k) t += std::min<int64_t>(nt, (int64_t)(k + 1) * (cs / kSymTile));
+    return t;
+}
+
+KmvShape kmv_shape_sym(int64_t n, int d, int m, gp_precision prec) {
+    KmvShape sh = kmv_shape_target(n, d, m, prec, 2048);
+    // FP32 MFMA products with one or two MFMA blocks and at most one VALU column, d <= 8,
+    // and at least 8 row tiles
+    const int nb = sh.mp / 16;
+    if (prec != GP_FP32 || !sh.mfma || d > 8 || sh.n_pad < 8 * kSymTile || sh.tail > 1 ||
+        !(nb == 1 || nb == 2))
+        return sh;
+    sh.sym = true;
+    sh.nt = (int)(sh.n_pad / kSymTile);
+    sh.rows_per_wg = kSymTile;
+    // the widest column chunk that still gives 2048 work items
+    sh.cs = kSymTile;
+    for (int cs = 2 * kSymTile; cs <= 8 * kSymTile && cs <= sh.n_pad; cs *= 2) {
+        const int nch = (int)((sh.n_pad + cs - 1) / cs);
+        if (sym_items(sh.nt, nch, cs) >= 2048) sh.cs = cs;
+    }
+    sh.nch = (int)((sh.n_pad + sh.cs - 1) / sh.cs);
+    sh.split = 1;
+    sh.chunk = (int)sh.n_pad;
+    return sh;
+}
+
+size_t kmv_part_floats(const KmvShape& sh) {
+    const size_t plane = (size_t)sh.mp * (size_t)sh.n_pad;
+    return sh.sym ? (size_t)(1 + sh.nch + sh.nt) * plane : (size_t)sh.split * plane;
 }
 
 KmvShape kmv_shape_target(int64_t n, int d, int m, gp_precision prec, int target_wg) {
@@ -861,9 +1192,40 @@ static hipError_t kmv_f32_nb(int nb, int tc, dim3 grid, const float* Z, const fl
 #undef GPK_F32_LAUNCH
 
 template <int D>
+static hipError_t kmv_sym_d(const KmvShape& sh, const float* Z, const float* Vp, const KParams* kp,
+                            float* part, const int* n_active, hipStream_t s) {
+    if constexpr (D > 8) {
+        return hipErrorInvalidValue;
+    } else {
+        const size_t plane = (size_t)sh.mp * (size_t)sh.n_pad;
+        float* F = part + plane;
+        float* Tt = F + (size_t)sh.nch * plane;
+        const dim3 grid((unsigned)sym_items(sh.nt, sh.nch, sh.cs));
+        const int nb = sh.mp / 16;
+        if (nb == 1 && sh.tail == 0)
+            kmv_sym_f32_kernel<D, 1, 0><<<grid, kWG, 0, s>>>(Z, Vp, F, Tt, sh.n_pad, sh.nt, sh.cs, kp, n_active);
+        else if (nb == 1 && sh.tail == 1)
+            kmv_sym_f32_kernel<D, 1, 1><<<grid, kWG, 0, s>>>(Z, Vp, F, Tt, sh.n_pad, sh.nt, sh.cs, kp, n_active);
+        else if (nb == 2 && sh.tail == 0)
+            kmv_sym_f32_kernel<D, 2, 0><<<grid, kWG, 0, s>>>(Z, Vp, F, Tt, sh.n_pad, sh.nt, sh.cs, kp, n_active);
+        else if (nb == 2 && sh.tail == 1)
+            kmv_sym_f32_kernel<D, 2, 1><<<grid, kWG, 0, s>>>(Z, Vp, F, Tt, sh.n_pad, sh.nt, sh.cs, kp, n_active);
+        else
+            return hipErrorInvalidValue;
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        const int mu = nb * 16 + sh.tail;
+        kmv_sym_reduce_kernel<<<grid_for((int64_t)mu * sh.n_pad), kWG, 0, s>>>(F, Tt, part, sh.n_pad, sh.mp, mu,
+                                                                                 sh.cs, sh.nch, n_active);
+        return hipGetLastError();
+    }
+}
+
+template <int D>
 static hipError_t kmv_d(const KmvShape& sh, const float* Z, const float* Vp,
                         const uint16_t* VH, const uint16_t* VL, const KParams* kp,
                         float* part, const int* n_active, gp_precision prec, hipStream_t s) {
+    if (sh.sym) return kmv_sym_d<D>(sh, Z, Vp, kp, part, n_active, s);
     if (sh.mfma && prec == GP_BF16_SPLIT_V) return kmv_bf16_d<D, false>(sh, Z, VH, VL, kp, part, n_active, s);
     if (sh.mfma && prec == GP_BF16_SPLIT_KV) return kmv_bf16_d<D, true>(sh, Z, VH, VL, kp, part, n_active, s);
     const int64_t tiles = sh.n_pad / sh.rows_per_wg;

@@ -70,6 +70,11 @@ def test_validation_is_synchronous_and_host_side(lib):
                                    ctypes.byref(p), ctypes.byref(sp), None, None, None, None)
     assert st == binding.GP_EINVAL
     assert lib.gp_autotune(None, 1) == binding.GP_EINVAL
+    code, split = ctypes.c_int32(0), ctypes.c_int32(0)
+    assert lib.gp_tune_set(None, 4096, 4, 16, 0, 0) == binding.GP_EINVAL
+    assert lib.gp_tune_get(None, 4096, 4, 16, 0, ctypes.byref(code), ctypes.byref(split)) == binding.GP_EINVAL
+    assert lib.gp_tune_save(None, b"/nonexistent/x") == binding.GP_EINVAL
+    assert lib.gp_tune_load(None, b"/nonexistent/x") == binding.GP_EINVAL
     out = ctypes.c_void_p()
     descs = (binding.gp_batch_problem * 1)()
     st = lib.gp_batch_create(ctypes.byref(out), 0, 0, 0, descs, 4, 0, 20, ctypes.byref(p), 8, 0, 1)

@@ -1,0 +1,171 @@
+"""Product shapes: the symmetric FP32 product against split-K and the oracle, the shape pins,
+and the autotuner's cache file, through the C ABI.
+
+Tolerance as for every FP32 covariance product: per column ||out - ref||_2 / ||ref||_2 <= 1e-5
+against the FP64 oracle.  The two shapes sum the same products in different orders, so they
+agree to FP32 rounding, not bit for bit.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import cg as ocg
+from oracle import gp as ogp
+from oracle import ulisse as oul
+
+pytestmark = pytest.mark.gpu
+
+pb = pytest.importorskip("paper_1501_05427_amd.binding")
+
+
+@pytest.fixture(autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def dev(a, dtype=None):
+    t = torch.as_tensor(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def colm(a, dtype=torch.float32):
+    a = np.asarray(a)
+    return dev(np.ascontiguousarray(a.T), dtype).t()
+
+
+def problem(n, d, seed, lam=0.1, ell=(0.3, 0.8)):
+    r = np.random.default_rng(seed)
+    X = r.uniform(size=(n, d)).astype(np.float32)
+    psi = np.concatenate([[np.log(1.2)], np.log(r.uniform(*ell, d)), [np.log(lam)]])
+    return X, psi
+
+
+def _safe_q(K, b, target_l):
+    """q whose threshold q sqrt(n) sits midway (log scale) between the running minimum of the
+    residual norms before an iteration l >= target_l and the norm at l, with a clear gap, so
+    FP32 and FP64 runs of system 0 take the same l."""
+    norms = []
+    for i, s, e, dl in ocg.cg_iterates(lambda v: K @ v, b, np.zeros_like(b)):
+        norms.append(np.linalg.norm(e))
+        if i >= target_l and min(norms[:-1]) > 1.5 * norms[-1]:
+            return np.sqrt(min(norms[:-1]) * norms[-1]) / np.sqrt(len(b))
+        assert i < 200
+
+
+def colwise_rel(out, ref):
+    out = np.asarray(out, dtype=np.float64)
+    return np.linalg.norm(out - ref, axis=0) / np.maximum(np.linalg.norm(ref, axis=0), 1e-300)
+
+
+# n from the smallest the symmetric product takes (n_pad = 2048, 8 row tiles) up, ragged
+# tails inside the last row tile and the last column chunk; one and two MFMA blocks, with
+# and without the VALU column
+SYM_CASES = [(1793, 3, 17), (2049, 8, 16), (3000, 5, 17), (4100, 8, 32), (2300, 2, 33),
+             (6000, 8, 32), (9000, 1, 16)]
+
+
+@pytest.mark.parametrize("n,d,m", SYM_CASES)
+def test_symmetric_and_split_k_products_match_oracle(n, d, m):
+    h = pb.Handle(0, seed=7)
+    X, psi = problem(n, d, seed=3 * n + d)
+    V = np.random.default_rng(m + n).standard_normal((n, m)).astype(np.float32)
+    ref = ogp.kmv(X, psi, V)
+    outs = {}
+    for code in (pb.SHAPE_SYM, 2048):
+        pb.gp_tune_set(h, n, d, m, code)
+        got_code, split = pb.gp_tune_get(h, n, d, m)
+        assert got_code == code and (split == 1 if code == pb.SHAPE_SYM else split >= 1)
+        out = pb.gp_kmv(h, dev(X), dev(psi), colm(V))
+        torch.cuda.synchronize()
+        outs[code] = out.cpu().numpy().astype(np.float64)
+        assert colwise_rel(outs[code], ref).max() <= 1e-5, code
+    # the two differ by their rounding only: no tighter than the sum of the two bounds
+    assert colwise_rel(outs[pb.SHAPE_SYM], outs[2048]).max() <= 2e-5
+
+
+def test_symmetric_product_is_refused_where_it_does_not_apply():
+    h = pb.Handle(0, seed=7)
+    for n, d, m, prec in [(1000, 4, 16, pb.GP_FP32),      # n_pad below 2048
+                          (4000, 12, 16, pb.GP_FP32),     # d > 8
+                          (4000, 4, 48, pb.GP_FP32),      # three MFMA blocks
+                          (4000, 4, 18, pb.GP_FP32),      # two VALU columns
+                          (4000, 4, 32, pb.GP_BF16_SPLIT_KV)]:
+        with pytest.raises(RuntimeError, match="symmetric"):
+            pb.gp_tune_set(h, n, d, m, pb.SHAPE_SYM, prec=prec)
+    with pytest.raises(RuntimeError):
+        pb.gp_tune_set(h, 4000, 4, 16, 2 ** 21)
+
+
+def test_ulisse_draw_for_draw_through_the_symmetric_product():
+    # the solver's products through the pinned symmetric shape (n = 2500: 10 row tiles, 17
+    # systems: one MFMA block and the VALU column), draw for draw against the oracle
+    h = pb.Handle(0, seed=1234)
+    n, d, m = 2500, 4, 17
+    X, psi = problem(n, d, seed=11, lam=0.3, ell=(0.2, 0.4))
+    K = ogp.kernel_matrix(X, psi)
+    Bm = np.random.default_rng(5).standard_normal((n, m)).astype(np.float32)
+    pb.gp_tune_set(h, n, d, m, pb.SHAPE_SYM)
+    q, eps, rate = _safe_q(K, Bm[:, 0].astype(np.float64), 3), 1e-6, 0.7
+    params = pb.make_params(q=q, rate=rate, eps=eps, eps_relative=1, max_iter=300, two_track_first=1,
+                            rng_stream=9, rng_counter=2)
+    Scg = torch.zeros((m, n), dtype=torch.float64, device="cuda").t()
+    St, stats = pb.ulisse_solve(h, dev(X), dev(psi), colm(Bm), params, S_cg=Scg)
+    torch.cuda.synchronize()
+    st_gpu = pb.decode_stats(stats)
+    ref_St, ref_Scg, ref_stats = oul.solve_systems(
+        lambda v: K @ v, Bm.astype(np.float64), None, q, rate, eps, 300, h.seed, 9, 2,
+        two_track_first=True, eps_relative=True)
+    for c in range(m):
+        g, r = st_gpu[c], ref_stats[c]
+        assert g["l"] == r["l"] and g["iters"] == r["iters"] and g["J_a"] == r["J"][0], (c, g, r)
+        assert g["flags"] == r["flags"]
+    assert colwise_rel(St.cpu().numpy(), ref_St).max() <= 2e-4
+    assert colwise_rel(Scg.cpu().numpy(), ref_Scg).max() <= 2e-4
+
+
+def test_tuning_cache_round_trip(tmp_path):
+    h = pb.Handle(0, seed=3)
+    pb.gp_autotune(h, 1)
+    shapes = [(3000, 8, 32), (4096, 4, 17), (2000, 2, 5)]
+    for n, d, m in shapes:
+        assert pb.gp_tune_get(h, n, d, m)[0] == -1  # not timed yet
+        X, psi = problem(n, d, seed=n)
+        V = np.random.default_rng(1).standard_normal((n, m)).astype(np.float32)
+        pb.gp_kmv(h, dev(X), dev(psi), colm(V))
+    torch.cuda.synchronize()
+    codes = {s: pb.gp_tune_get(h, *s) for s in shapes}
+    assert all(c >= 0 for c, _ in codes.values())
+    path = tmp_path / "shapes.txt"
+    pb.gp_tune_save(h, path)
+    lines = path.read_text().splitlines()
+    assert lines[0] == "ulisse_gp shape cache v1" and len(lines) == 1 + len(shapes)
+
+    h2 = pb.Handle(0, seed=3)
+    pb.gp_autotune(h2, 1)
+    pb.gp_tune_load(h2, path)
+    for s in shapes:
+        assert pb.gp_tune_get(h2, *s) == codes[s]
+    # a pin wins over the loaded entry and its removal restores it
+    n, d, m = shapes[0]
+    pb.gp_tune_set(h2, n, d, m, 256)
+    assert pb.gp_tune_get(h2, n, d, m)[0] == 256
+    pb.gp_tune_set(h2, n, d, m, -1)
+    assert pb.gp_tune_get(h2, n, d, m) == codes[shapes[0]]
+    # with the autotuner off the loaded entries are not used
+    pb.gp_autotune(h2, 0)
+    assert pb.gp_tune_get(h2, 2000, 2, 5)[0] == 2048
+
+    # a malformed file is refused as a whole and leaves the entries as they were
+    bad = tmp_path / "bad.txt"
+    bad.write_text("ulisse_gp shape cache v1\n4096 4 20 0 0\n4096 4 20 zero 0\n")
+    h3 = pb.Handle(0, seed=3)
+    pb.gp_autotune(h3, 1)
+    with pytest.raises(RuntimeError, match="line 3"):
+        pb.gp_tune_load(h3, bad)
+    assert pb.gp_tune_get(h3, 4096, 4, 17)[0] == -1
+    (tmp_path / "nohdr.txt").write_text("4096 4 20 0 0\n")
+    with pytest.raises(RuntimeError, match="not a tuning cache"):
+        pb.gp_tune_load(h3, tmp_path / "nohdr.txt")

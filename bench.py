@@ -220,27 +220,55 @@ def kmv_report(pb, h):
         out = pb.colmajor(n, m)
         reps = max(5, int(2e10 // (n * n)))
         for prec in (pb.GP_FP32, pb.GP_BF16_SPLIT_V, pb.GP_BF16_SPLIT_KV):
-            for _ in range(3):
-                pb.gp_kmv(h, X, psi, V, out=out, prec=prec)
-            torch.cuda.synchronize()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            pb.gp_profile(h, 1)
-            e0.record()
-            for _ in range(reps):
-                pb.gp_kmv(h, X, psi, V, out=out, prec=prec)
-            e1.record()
-            torch.cuda.synchronize()
-            pr = pb.gp_profile_read(h)
-            pb.gp_profile(h, 0)
-            k_ms = pr["kmv_ms"] / max(1, pr["kmv_launches"])
-            c_ms = e0.elapsed_time(e1) / reps
-            fl = kmv_flops(n, d, m)
-            rows.append(dict(workload=f"{kind}_n{n}_d{d}", n=n, d=d, m=m, prec=names[prec],
-                             kernel_ms=k_ms, call_ms=c_ms, tflops=fl / k_ms / 1e9,
-                             frac_fp32_valu_peak=fl / k_ms / 1e9 / VALU_FP32_PEAK_TFLOPS,
-                             exp_per_s=float(n) * n / (k_ms * 1e-3), launches=pr["kmv_launches"]))
-            print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
-    print(json.dumps({"kmv_report": rows, "flops_per_pair": "3d + 2m (algorithmic, m unpadded)"}), flush=True)
+            # FP32: both product shapes where the symmetric one applies, each pinned
+            variants = [("default", -1)]
+            if prec == pb.GP_FP32:
+                variants = [("split_k", 2048)]
+                try:
+                    pb.gp_tune_set(h, n, d, m, pb.SHAPE_SYM)
+                    variants.append(("symmetric", pb.SHAPE_SYM))
+                except pb.GPError:
+                    pass
+            for shape, code in variants:
+                pb.gp_tune_set(h, n, d, m, code, prec=prec)
+                for _ in range(3):
+                    pb.gp_kmv(h, X, psi, V, out=out, prec=prec)
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                pb.gp_profile(h, 1)
+                e0.record()
+                for _ in range(reps):
+                    pb.gp_kmv(h, X, psi, V, out=out, prec=prec)
+                e1.record()
+                torch.cuda.synchronize()
+                pr = pb.gp_profile_read(h)
+                pb.gp_profile(h, 0)
+                k_ms = pr["kmv_ms"] / max(1, pr["kmv_launches"])
+                c_ms = e0.elapsed_time(e1) / reps
+                fl = kmv_flops(n, d, m)
+                rows.append(dict(workload=f"{kind}_n{n}_d{d}", n=n, d=d, m=m, prec=names[prec], shape=shape,
+                                 kernel_ms=k_ms, call_ms=c_ms, tflops=fl / k_ms / 1e9,
+                                 frac_fp32_valu_peak=fl / k_ms / 1e9 / VALU_FP32_PEAK_TFLOPS,
+                                 exp_per_s=float(n) * n / (k_ms * 1e-3), launches=pr["kmv_launches"]))
+                print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+            pb.gp_tune_set(h, n, d, m, -1, prec=prec)
+    print(json.dumps({"kmv_report": rows, "flops_per_pair": "3d + 2m (algorithmic, m unpadded)",
+                      "kernel_ms": "product kernels of one call (the symmetric shape: kernel + reduce)"}),
+          flush=True)
+
+
+def pipes_report(pb, h):
+    """Issue-rate probe of the compute pipes (gp_pipe_probe): cycles per loop iteration per
+    wave, at eight waves per SIMD, of FP32 VALU FMAs, FP32 and BF16 MFMAs, each MFMA kind with
+    independent VALU work, and exp2.  hidden_* = the part of the MFMA-alone cycles that the
+    VALU work hid when both ran (0: the two pipes run in series)."""
+    r = pb.gp_pipe_probe(h, iters=4000)
+    cyc = {k: v[1] for k, v in r.items()}
+    out = {"pipes": {k: {"ms": v[0], "cycles_per_iter_wave": v[1]} for k, v in r.items()},
+           "hidden_fp32_mfma_frac": (cyc["valu_fma128"] + cyc["mfma_f32_x4"] - cyc["mfma_f32_x4+valu_fma128"]) / cyc["mfma_f32_x4"],
+           "hidden_bf16_mfma_frac": (cyc["valu_fma128"] + cyc["mfma_bf16_x4"] - cyc["mfma_bf16_x4+valu_fma128"]) / cyc["mfma_bf16_x4"],
+           "exp_over_fma_cost": cyc["exp128"] / cyc["valu_fma128"]}
+    print(json.dumps(out), flush=True)
 
 
 def say(msg):
@@ -277,7 +305,7 @@ def matched_error_rates(rows_a, rows_b):
 
 
 def learned_from_chains(pb, h, X, y, psi_map, M_sub, L_full, eps_t, prior, chains, steps, epochs,
-                        k=64, H=256, probes=4, seed=1):
+                        k=64, H=256, probes=4, seed=1, q=1.0, psi_eval=None):
     """The learned warm start and preconditioner, trained on (psi, solve) pairs that the
     plain solver generates: the states of `chains` plain-solver SGLD chains (started from
     N(psi_MAP, M_subset), `steps` steps each), the basis U of K(psi_MAP), the Galerkin solve
@@ -289,7 +317,7 @@ def learned_from_chains(pb, h, X, y, psi_map, M_sub, L_full, eps_t, prior, chain
     t0 = time.perf_counter()
     starts = protocol.init_chains(psi_map, M_sub, chains, seed=seed)
     states = protocol.plain_chain_states(h, X, y, starts, steps, L_full, eps_t, probes=probes,
-                                         prior=prior)
+                                         prior=prior, q=q)
     t_chain = time.perf_counter() - t0
     psis = torch.from_numpy(states).cuda()
     U, ritz = pb.precond_build_basis(h, X, torch.from_numpy(psi_map).cuda(), k)
@@ -305,13 +333,22 @@ def learned_from_chains(pb, h, X, y, psi_map, M_sub, L_full, eps_t, prior, chain
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t0
     spread = states.std(axis=0)
+    # where the network is evaluated, against the training states: per coordinate, the
+    # distance from their mean in units of their spread, and the distance to the nearest state
+    far = {}
+    if psi_eval is not None:
+        pe = np.asarray(psi_eval, np.float64)
+        z = (pe - states.mean(axis=0)) / np.maximum(spread, 1e-300)
+        nearest = np.sqrt((((states - pe) / np.maximum(spread, 1e-300)) ** 2).sum(axis=1)).min()
+        far = {"eval_z_from_state_mean": z.tolist(), "eval_max_abs_z": float(np.abs(z).max()),
+               "eval_nearest_state_scaled_dist": float(nearest)}
     return {"prm": prm, "U": U, "I": I_, "H": H, "O": O_, "k": k, "ritz": ritz, "psis": psis,
             "info": {"pairs": int(states.shape[0]), "chains": chains, "steps_per_chain": steps,
                      "probes": probes, "epochs": epochs, "rank": k, "hidden": H,
                      "basis_at": "subset MAP",
                      "train_loss_first_last": [float(ltr[0]), float(ltr[-1])],
                      "ritz_top_bottom": [float(ritz[0]), float(ritz[-1])],
-                     "state_sd_mean": float(spread.mean()),
+                     "state_sd_mean": float(spread.mean()), "chain_q": q, **far,
                      "seconds_chains": t_chain, "seconds_targets": t_targets, "seconds_total": t_total}}
 
 
@@ -501,7 +538,8 @@ def main_line(args, pb, h, X, y, w, psi0):
     equal = None
     if args.learned_steps:
         Lr = learned_from_chains(pb, h, X, y, psi_map, M_sub, L_full, eps_train, prior,
-                                 args.learn_chains, args.learn_chain_steps, args.learn_epochs, k=k)
+                                 args.learn_chains, args.learn_chain_steps, args.learn_epochs, k=k,
+                                 q=args.learn_chain_q, psi_eval=w["psi"])
         Lr["info"]["chain_step_size"] = eps_train
         Tm = pb.precond_targets(h, X, y, Lr["U"], torch.from_numpy(psi_map[None, :].copy()).cuda())
         ch.set_learned(Lr, pb.precond_from_targets(h, Tm[0], k))
@@ -526,6 +564,9 @@ def main_line(args, pb, h, X, y, w, psi0):
 
     kmv_avg_s = prof["kmv_ms"] / max(1, prof["kmv_launches"]) / 1e3
     achieved = kmv_flops(N, D, M) / kmv_avg_s / 1e12
+    # the timed launch: the symmetric product's kernel and its FP64 reduce, or split-K's kernel
+    kv_kernel = ("kmv_sym_f32_kernel + kmv_sym_reduce_kernel (K.V, m=32, symmetric shape)"
+                 if pb.gp_tune_get(h, N, D, M)[0] == pb.SHAPE_SYM else "kmv_mfma_f32_kernel (K.V, m=32, split-K)")
     return {
         "metric": "unbiased grad estimates/s and K·V TFLOP/s at n=65536, learned+BF16 vs plain",
         "value": value,
@@ -549,7 +590,7 @@ def main_line(args, pb, h, X, y, w, psi0):
                    "value_is": "plain FP32 path; learned+BF16 in learned_bf16, K.V in roofline"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_FP32_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / VALU_FP32_PEAK_TFLOPS,
-                     "traffic": traffic_from_profile(), "kernel": "kmv_mfma_f32 (K.V, m=32)",
+                     "traffic": traffic_from_profile(), "kernel": kv_kernel,
                      "avg_launch_ms": kmv_avg_s * 1e3, "launches": prof["kmv_launches"]},
         "kv_tflops": achieved,
         "kmv_passes_per_estimate": prof["kmv_passes"] / K_,
@@ -667,8 +708,11 @@ def error_sweep(args, pb, h, X, y, w, psi0):
     L_full = np.linalg.cholesky(M_sub * (500.0 / N))
     say(f"subset MAP: {time.perf_counter() - t0:.1f} s")
     L = learned_from_chains(pb, h, X, y, psi_map, M_sub, L_full, 1e-3, prior, args.learn_chains,
-                            args.learn_chain_steps, args.learn_epochs, probes=args.learn_chain_probes)
-    say(f"learned set-up: {L['info']['pairs']} pairs, {L['info']['seconds_total']:.1f} s")
+                            args.learn_chain_steps, args.learn_epochs, probes=args.learn_chain_probes,
+                            q=args.learn_chain_q, psi_eval=psi0.cpu().numpy())
+    say(f"learned set-up: {L['info']['pairs']} pairs, {L['info']['seconds_total']:.1f} s "
+        f"(chains {L['info']['seconds_chains']:.1f} s); evaluation point max |z| "
+        f"{L['info']['eval_max_abs_z']:.1f} from the training states")
     L["coef"] = torch.zeros(L["k"] + 1, dtype=torch.float64, device="cuda")
     L["pc"] = pb.make_precond(L["U"], L["coef"])
     psi = psi0.clone()
@@ -1050,6 +1094,7 @@ def main():
                     help="plain-solver SGLD chains whose states train the network")
     ap.add_argument("--learn-chain-steps", type=int, default=32)
     ap.add_argument("--learn-chain-probes", type=int, default=4, help="probes of the training chains")
+    ap.add_argument("--learn-chain-q", type=float, default=1.0, help="threshold q of the training chains' solver")
     ap.add_argument("--learn-pairs", type=int, default=256, help="error sweep: jittered training pairs")
     ap.add_argument("--learn-epochs", type=int, default=1500)
     ap.add_argument("--refresh", type=int, default=3,
@@ -1064,6 +1109,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the compact batched leg of the main line")
     ap.add_argument("--profile-kmv", action="store_true")
+    ap.add_argument("--pipes", action="store_true",
+                    help="issue-rate probe of the VALU, exp and MFMA pipes, alone and together")
     ap.add_argument("--kmv-report", action="store_true",
                     help="K.V throughput per precision mode on each workload shape (separate report)")
     ap.add_argument("--cpu-report", action="store_true",
@@ -1137,6 +1184,9 @@ def main():
 
     if args.kmv_report:
         kmv_report(pb, h)
+        return
+    if args.pipes:
+        pipes_report(pb, h)
         return
     if args.error_sweep:
         error_sweep(args, pb, h, X, y, w, psi0)

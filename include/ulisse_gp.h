@@ -477,6 +477,19 @@ gp_status gp_tune_save(const gp_handle* h, const char* path);
 gp_status gp_tune_load(gp_handle* h, const char* path);
 
 /*
+ * Pipe probe, for measurement: times six synthetic kernels on the stream (eight waves per
+ * SIMD, `iters` loop iterations each, the second of two runs) and returns, per kernel, the
+ * time in ms and the clock cycles of one loop iteration of one wave at the device's peak
+ * clock.  Kernels: 0 = 128 FP32 VALU FMAs; 1 = 4 FP32 MFMAs (v_mfma_f32_16x16x4f32);
+ * 2 = both in one loop, independent of each other; 3 = 4 BF16 MFMAs (16x16x32); 4 = 3 with
+ * the 128 FMAs; 5 = 128 v_exp_f32.  cycles[2] against cycles[0] + cycles[1] shows how much
+ * of the FP32 MFMA time independent VALU work can hide (none when they add up), likewise 4
+ * against 0 + 3 for BF16.  ms and cycles: 6 doubles each, host memory.  Synchronises the
+ * stream.
+ */
+gp_status gp_pipe_probe(gp_handle* h, int32_t iters, double* ms, double* cycles, void* stream);
+
+/*
  * Kernel timing for measurement.  While enabled, the handle records a pair of hipEvents on
  * the launch stream around every covariance-product launch that does work (kmv, in the
  * solver and in gp_kmv) and around every fused gradient reduction (dquad).

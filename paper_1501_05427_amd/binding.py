@@ -182,6 +182,8 @@ def lib():
     L.gp_autotune.argtypes = [c_void_p, c_int32]
     L.gp_autotune_split.restype = c_int
     L.gp_autotune_split.argtypes = [c_void_p, c_int64, c_int32, c_int32, c_int, POINTER(c_int32)]
+    L.gp_pipe_probe.restype = c_int
+    L.gp_pipe_probe.argtypes = [c_void_p, c_int32, POINTER(c_double), POINTER(c_double), c_void_p]
     L.gp_tune_set.restype = c_int
     L.gp_tune_set.argtypes = [c_void_p, c_int64, c_int32, c_int32, c_int, c_int32]
     L.gp_tune_get.restype = c_int
@@ -623,6 +625,17 @@ def gp_autotune_split(h, n, d, m, prec=GP_FP32):
     out = c_int32(0)
     _check(lib().gp_autotune_split(h.ptr, int(n), int(d), int(m), int(prec), ctypes.byref(out)))
     return out.value
+
+
+PIPE_PROBE_KERNELS = ("valu_fma128", "mfma_f32_x4", "mfma_f32_x4+valu_fma128", "mfma_bf16_x4",
+                      "mfma_bf16_x4+valu_fma128", "exp128")
+
+
+def gp_pipe_probe(h, iters=2000, stream=None):
+    """{kernel: (ms, cycles per loop iteration per wave)} for the six probe kernels."""
+    ms, cyc = (c_double * 6)(), (c_double * 6)()
+    _check(lib().gp_pipe_probe(h.ptr, int(iters), ms, cyc, _stream(stream)))
+    return {k: (ms[i], cyc[i]) for i, k in enumerate(PIPE_PROBE_KERNELS)}
 
 
 SHAPE_SYM = 0  # shape code of the symmetric product; c > 0: split-K for about c workgroups

@@ -50,7 +50,7 @@ enum Slot {
     kSlotRatio, kSlotRunStats, kSlotZp, kSlotUtv, kSlotHW, kSlotP3, kSlotY0, kSlotY1,
     kSlotY2, kSlotGram, kSlotGpart2, kSlotSmall, kSlotMlp, kSlotIcgB, kSlotIcgZ, kSlotIcgSt,
     kSlotIcgKP, kSlotTuneV, kSlotTunePart, kSlotTuneVH, kSlotTuneVL, kSlotAH, kSlotAL, kSlotBH,
-    kSlotBL, kSlotRD, kSlotRPart, kSlotRFlag, kNumSlots
+    kSlotBL, kSlotRD, kSlotRPart, kSlotRFlag, kSlotProbe, kNumSlots
 };
 // Solves nest one level (the inner CG of the shifted preconditioner): the inner solve's
 // buffers live in a second set of slots, offset by kNumSlots.
@@ -1383,6 +1383,43 @@ gp_status gp_tune_load(gp_handle* h, const char* path) {
     std::fclose(f);
     if (st != GP_OK) return st;
     for (const auto& kv : got) h->tuned[kv.first] = kv.second;
+    return GP_OK;
+}
+
+gp_status gp_pipe_probe(gp_handle* h, int32_t iters, double* ms, double* cycles, void* stream) {
+    GP_TRY(check_handle(h));
+    GP_CHECK(iters >= 1 && iters <= 1000000 && ms != nullptr && cycles != nullptr, "bad arguments");
+    hipStream_t s = (hipStream_t)stream;
+    hipDeviceProp_t prop;
+    GP_HIP(hipGetDeviceProperties(&prop, h->device));
+    // eight waves per SIMD: 4 SIMDs per CU, 4 waves per workgroup
+    const int blocks = prop.multiProcessorCount * 8;
+    float* out;
+    GP_TRY(ws(h, kSlotProbe, (size_t)blocks * 256, &out));
+    hipEvent_t e0, e1;
+    GP_HIP(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(GP_EDEVICE, "event creation failed");
+    }
+    hipError_t e = hipSuccess;
+    for (int mode = 0; mode < 6 && e == hipSuccess; ++mode) {
+        float t = 0.f;
+        for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {  // the first run warms up
+            e = hipEventRecord(e0, s);
+            if (e == hipSuccess) e = launch_pipe_probe(mode, blocks, iters, out, s);
+            if (e == hipSuccess) e = hipEventRecord(e1, s);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+        }
+        ms[mode] = t;
+        // clock cycles of one iteration of one wave, at the device's peak clock
+        const double waves_per_simd = (double)blocks * 4 / (4.0 * prop.multiProcessorCount);
+        cycles[mode] = t * 1e-3 * prop.clockRate * 1e3 / (iters * waves_per_simd);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return fail(GP_EDEVICE, "pipe probe failed: %s", hipGetErrorString(e));
     return GP_OK;
 }
 

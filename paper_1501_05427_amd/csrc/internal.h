@@ -102,4 +102,8 @@ hipError_t launch_dquad(const DquadShape& sh, int d, const float* Z, const float
                         const float* B, const KParams* kp, const int2* work, double* gpart,
                         hipStream_t s);
 
+// Pipe probe (pipes.hip): mode 0..5, `blocks` workgroups of 256 threads, one float of out
+// per thread.
+hipError_t launch_pipe_probe(int mode, int blocks, int iters, float* out, hipStream_t s);
+
 }  // namespace gpk

@@ -741,6 +741,194 @@ __global__ __launch_bounds__(kWG) void kmv_mfma_bf16_kernel(
         }
 }
 
+// ---------------------------------------------------------------------------------------
+// Symmetric BF16 product: the work items, partials and reduce of the symmetric FP32 product,
+// with the BF16 contraction above.  Forward: as kmv_mfma_bf16_kernel, R = 4 blocks of 16
+// rows per wave, four waves per 256-row tile.  Transposed: after each 32-column group the
+// four waves store their packed K values (hi, and lo with SPLITK) transposed into one
+// workgroup tile tt[j][i] (32 x 256 BF16, row stride kTT).  Each wave then owns NB / 2
+// output tiles of 16 columns j by 16 right-hand sides and contracts them over all 256 rows
+// of the row tile: A operand = 8 consecutive i of one row of tt, B operand = the row tile's
+// own V rows, held in registers for the whole item.  So no sum across waves is needed and
+// each wave writes its transposed partials to Tt straight from its accumulators.  The
+// product terms are those of the forward direction: K_hi (V_hi + V_lo), plus K_lo V_hi
+// with SPLITK.
+// ---------------------------------------------------------------------------------------
+constexpr int kTT = kSymTile + 6;  // 262: the stores of a wave hit 32 distinct banks
+
+template <int D, int NB, bool SPLITK>
+__global__ __launch_bounds__(kWG) void kmv_sym_bf16_kernel(
+    const float* __restrict__ Z, const uint16_t* __restrict__ VH, const uint16_t* __restrict__ VL,
+    float* __restrict__ F, float* __restrict__ Tt, int64_t n_pad, int NT, int cs,
+    const KParams* __restrict__ kp, const int* __restrict__ n_active) {
+    if (n_active != nullptr && *n_active == 0) return;
+    constexpr int R = 4;
+    constexpr int DP = (D + 3) & ~3;
+    constexpr int MP = NB * 16;
+    static_assert(NB == 2 || NB == 4, "2 NB output tiles shared by four waves");
+    constexpr int TPW = NB / 2;  // output tiles per wave and group
+    using S = StageB16<DP, MP>;
+    __shared__ float4 zs[2][S::NZ4];
+    __shared__ uint16_t hs[2][S::VSIZE];
+    __shared__ uint16_t ls[2][S::VSIZE];
+    __shared__ __align__(16) uint16_t th[32 * kTT];
+    __shared__ __align__(16) uint16_t tl[SPLITK ? 32 * kTT : 8];
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int q = lane >> 4, col = lane & 15;
+    int k, I;
+    sym_item(blockIdx.x, NT, cs, &k, &I);
+    const int64_t tile0 = (int64_t)I * kSymTile;
+    const int64_t row0 = tile0 + wave * (16 * R);
+    const int64_t diag_end = tile0 + kSymTile;
+    const int64_t jb = max((int64_t)k * cs, tile0);
+    const int64_t je = min((int64_t)(k + 1) * cs, n_pad);
+    const float negc0 = -kp->c0;
+
+    float zi[R][D];
+#pragma unroll
+    for (int r = 0; r < R; ++r) load_row<D>(Z + (row0 + r * 16 + col) * DP, zi[r]);
+    // this wave's output tiles: column block cbw; j blocks (wave & 1) for NB = 2, both for 4
+    const int cbw = NB == 2 ? (wave >> 1) : wave;
+    // B operand of the transposed product: lane (q, col) holds
+    // V[tile0 + 32 kb + 8 q + s][16 cbw + col], s = 0..7, for the 8 blocks kb of the tile
+    uintx4 vh[8], vl[8];
+#pragma unroll
+    for (int kb = 0; kb < 8; ++kb) {
+        const int64_t o = (int64_t)(16 * cbw + col) * n_pad + tile0 + 32 * kb + 8 * q;
+        vh[kb] = *reinterpret_cast<const uintx4*>(VH + o);
+        vl[kb] = *reinterpret_cast<const uintx4*>(VL + o);
+    }
+    // complete these loads here (see kmv_sym_f32_kernel)
+#pragma unroll
+    for (int kb = 0; kb < 8; ++kb) asm volatile("" : "+v"(vh[kb]), "+v"(vl[kb]));
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int k2 = 0; k2 < D; ++k2) asm volatile("" : "+v"(zi[r][k2]));
+
+    floatx4 acc[R][NB];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int cb = 0; cb < NB; ++cb) acc[r][cb] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+    S st;
+    st.load(Z, VH, VL, n_pad, jb);
+    st.store(zs[0], hs[0], ls[0], true);
+    __syncthreads();
+    int buf = 0;
+    for (int64_t j0 = jb; j0 < je; j0 += kJS) {
+        const bool more = j0 + kJS < je;
+        const bool sym = j0 >= diag_end;  // uniform over the workgroup
+        if (more) st.load(Z, VH, VL, n_pad, j0 + kJS);
+        const float* zsb = reinterpret_cast<const float*>(zs[buf]);
+#pragma unroll 1
+        for (int g = 0; g < kJS / 32; ++g) {
+            bf16x8 bh[NB], bl[NB];
+#pragma unroll
+            for (int cb = 0; cb < NB; ++cb) {
+                const int o = (cb * 16 + col) * S::VST + g * 32 + 8 * q;
+                bh[cb] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(hs[buf] + o));
+                bl[cb] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(ls[buf] + o));
+            }
+            float kv[R][8];
+#pragma unroll
+            for (int s_ = 0; s_ < 8; ++s_) {
+                float zj[D];
+                load_row<D>(zsb + (g * 32 + 8 * q + s_) * DP, zj);
+#pragma unroll
+                for (int r = 0; r < R; ++r) kv[r][s_] = kf_entry<D>(zi[r], zj, negc0);
+            }
+            uint32_t hi[R][4], lo[R][4];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) hi[r][u] = pack_bf16(kv[r][2 * u], kv[r][2 * u + 1]);
+                const bf16x8 ah = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(hi[r]));
+#pragma unroll
+                for (int cb = 0; cb < NB; ++cb) {
+                    acc[r][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[cb], acc[r][cb], 0, 0, 0);
+                    acc[r][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[cb], acc[r][cb], 0, 0, 0);
+                }
+                if (SPLITK) {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        lo[r][u] = pack_bf16(kv[r][2 * u] - bf16_lo_as_f32(hi[r][u]),
+                                             kv[r][2 * u + 1] - bf16_hi_as_f32(hi[r][u]));
+                    const bf16x8 al = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(lo[r]));
+#pragma unroll
+                    for (int cb = 0; cb < NB; ++cb)
+                        acc[r][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[cb], acc[r][cb], 0, 0, 0);
+                }
+            }
+            if (sym) {
+                // tt[j][i] = K(tile0 + i, j0 + 32 g + j): lane (q, col) holds i = 64 wave + 16 r + col,
+                // j = 8 q + 2 u (low half of hi[r][u]) and 8 q + 2 u + 1 (high half)
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int i = wave * 64 + r * 16 + col;
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        th[(8 * q + 2 * u) * kTT + i] = (uint16_t)(hi[r][u] & 0xffffu);
+                        th[(8 * q + 2 * u + 1) * kTT + i] = (uint16_t)(hi[r][u] >> 16);
+                        if (SPLITK) {
+                            tl[(8 * q + 2 * u) * kTT + i] = (uint16_t)(lo[r][u] & 0xffffu);
+                            tl[(8 * q + 2 * u + 1) * kTT + i] = (uint16_t)(lo[r][u] >> 16);
+                        }
+                    }
+                }
+                __syncthreads();
+#pragma unroll
+                for (int t = 0; t < TPW; ++t) {
+                    const int jblk = NB == 2 ? (wave & 1) : t;
+                    floatx4 tr = floatx4{0.f, 0.f, 0.f, 0.f};
+                    const int rowoff = (16 * jblk + col) * kTT + 8 * q;  // even: 4-byte reads
+#pragma unroll
+                    for (int kb = 0; kb < 8; ++kb) {
+                        const uint32_t* ph = reinterpret_cast<const uint32_t*>(th + rowoff + 32 * kb);
+                        const uintx4 a4 = {ph[0], ph[1], ph[2], ph[3]};
+                        const bf16x8 ah = __builtin_bit_cast(bf16x8, a4);
+                        tr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, __builtin_bit_cast(bf16x8, vh[kb]), tr, 0, 0, 0);
+                        tr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, __builtin_bit_cast(bf16x8, vl[kb]), tr, 0, 0, 0);
+                        if (SPLITK) {
+                            const uint32_t* pl = reinterpret_cast<const uint32_t*>(tl + rowoff + 32 * kb);
+                            const uintx4 b4 = {pl[0], pl[1], pl[2], pl[3]};
+                            tr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, b4),
+                                                                         __builtin_bit_cast(bf16x8, vh[kb]), tr, 0, 0, 0);
+                        }
+                    }
+                    // lane (q, col): columns j0 + 32 g + 16 jblk + 4 q + v of right-hand side 16 cbw + col
+                    float4 o;
+                    o.x = tr[0];
+                    o.y = tr[1];
+                    o.z = tr[2];
+                    o.w = tr[3];
+                    *reinterpret_cast<float4*>(Tt + ((int64_t)I * MP + 16 * cbw + col) * n_pad + j0 + 32 * g +
+                                               16 * jblk + 4 * q) = o;
+                }
+                __syncthreads();  // the tile is rewritten by the next group
+            }
+        }
+        if (more) st.store(zs[buf ^ 1], hs[buf ^ 1], ls[buf ^ 1], true);
+        __syncthreads();
+        buf ^= 1;
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int cb = 0; cb < NB; ++cb) {
+            const int64_t i = row0 + r * 16 + 4 * q;
+            const int c = cb * 16 + col;
+            float4 o;
+            o.x = acc[r][cb][0];
+            o.y = acc[r][cb][1];
+            o.z = acc[r][cb][2];
+            o.w = acc[r][cb][3];
+            *reinterpret_cast<float4*>(F + ((int64_t)k * MP + c) * n_pad + i) = o;
+        }
+}
+
 // V (FP32, n_pad x mp, ld n_pad) -> V_hi = bf16(V), V_lo = bf16(V - V_hi).
 __global__ void split_bf16_kernel(const float* __restrict__ V, int64_t total,
                                   uint16_t* __restrict__ VH, uint16_t* __restrict__ VL) {
@@ -1052,7 +1240,7 @@ KmvShape kmv_shape(int64_t n, int d, int m, gp_precision prec) {
     // block of columns, or n of 32768 and more (two blocks at n = 16384 are 9% slower: the
     // transposed partials cost more than the halved entry work saves)
     const KmvShape sy = kmv_shape_sym(n, d, m, prec);
-    if (sy.sym && (sy.mp <= 20 || sy.n_pad >= 32768)) return sy;
+    if (sy.sym && prec == GP_FP32 && (sy.mp <= 20 || sy.n_pad >= 32768)) return sy;
     return kmv_shape_target(n, d, m, prec, 2048);
 }
 
@@ -1064,12 +1252,12 @@ static int64_t sym_items(int nt, int nch, int cs) {
 
 KmvShape kmv_shape_sym(int64_t n, int d, int m, gp_precision prec) {
     KmvShape sh = kmv_shape_target(n, d, m, prec, 2048);
-    // FP32 MFMA products with one or two MFMA blocks and at most one VALU column, d <= 8,
-    // and at least 8 row tiles
+    // MFMA products with d <= 8 and at least 8 row tiles: FP32 with one or two MFMA blocks
+    // and at most one VALU column, BF16 with two or four blocks
     const int nb = sh.mp / 16;
-    if (prec != GP_FP32 || !sh.mfma || d > 8 || sh.n_pad < 8 * kSymTile || sh.tail > 1 ||
-        !(nb == 1 || nb == 2))
-        return sh;
+    const bool f32 = prec == GP_FP32 && sh.tail <= 1 && (nb == 1 || nb == 2);
+    const bool b16 = prec != GP_FP32 && sh.tail == 0 && (nb == 2 || nb == 4);
+    if (!sh.mfma || d > 8 || sh.n_pad < 8 * kSymTile || !(f32 || b16)) return sh;
     sh.sym = true;
     sh.nt = (int)(sh.n_pad / kSymTile);
     sh.rows_per_wg = kSymTile;
@@ -1192,8 +1380,9 @@ static hipError_t kmv_f32_nb(int nb, int tc, dim3 grid, const float* Z, const fl
 #undef GPK_F32_LAUNCH
 
 template <int D>
-static hipError_t kmv_sym_d(const KmvShape& sh, const float* Z, const float* Vp, const KParams* kp,
-                            float* part, const int* n_active, hipStream_t s) {
+static hipError_t kmv_sym_d(const KmvShape& sh, const float* Z, const float* Vp, const uint16_t* VH,
+                            const uint16_t* VL, const KParams* kp, float* part, const int* n_active,
+                            gp_precision prec, hipStream_t s) {
     if constexpr (D > 8) {
         return hipErrorInvalidValue;
     } else {
@@ -1202,7 +1391,20 @@ static hipError_t kmv_sym_d(const KmvShape& sh, const float* Z, const float* Vp,
         float* Tt = F + (size_t)sh.nch * plane;
         const dim3 grid((unsigned)sym_items(sh.nt, sh.nch, sh.cs));
         const int nb = sh.mp / 16;
-        if (nb == 1 && sh.tail == 0)
+        if (prec != GP_FP32) {
+            const bool kv = prec == GP_BF16_SPLIT_KV;
+            if (sh.tail != 0 || VH == nullptr || VL == nullptr) return hipErrorInvalidValue;
+            if (nb == 2 && kv)
+                kmv_sym_bf16_kernel<D, 2, true><<<grid, kWG, 0, s>>>(Z, VH, VL, F, Tt, sh.n_pad, sh.nt, sh.cs, kp, n_active);
+            else if (nb == 2)
+                kmv_sym_bf16_kernel<D, 2, false><<<grid, kWG, 0, s>>>(Z, VH, VL, F, Tt, sh.n_pad, sh.nt, sh.cs, kp, n_active);
+            else if (nb == 4 && kv)
+                kmv_sym_bf16_kernel<D, 4, true><<<grid, kWG, 0, s>>>(Z, VH, VL, F, Tt, sh.n_pad, sh.nt, sh.cs, kp, n_active);
+            else if (nb == 4)
+                kmv_sym_bf16_kernel<D, 4, false><<<grid, kWG, 0, s>>>(Z, VH, VL, F, Tt, sh.n_pad, sh.nt, sh.cs, kp, n_active);
+            else
+                return hipErrorInvalidValue;
+        } else if (nb == 1 && sh.tail == 0)
             kmv_sym_f32_kernel<D, 1, 0><<<grid, kWG, 0, s>>>(Z, Vp, F, Tt, sh.n_pad, sh.nt, sh.cs, kp, n_active);
         else if (nb == 1 && sh.tail == 1)
             kmv_sym_f32_kernel<D, 1, 1><<<grid, kWG, 0, s>>>(Z, Vp, F, Tt, sh.n_pad, sh.nt, sh.cs, kp, n_active);
@@ -1214,7 +1416,7 @@ static hipError_t kmv_sym_d(const KmvShape& sh, const float* Z, const float* Vp,
             return hipErrorInvalidValue;
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        const int mu = nb * 16 + sh.tail;
+        const int mu = nb * 16 + sh.tail;  // BF16: tail 0
         kmv_sym_reduce_kernel<<<grid_for((int64_t)mu * sh.n_pad), kWG, 0, s>>>(F, Tt, part, sh.n_pad, sh.mp, mu,
                                                                                  sh.cs, sh.nch, n_active);
         return hipGetLastError();
@@ -1225,7 +1427,7 @@ template <int D>
 static hipError_t kmv_d(const KmvShape& sh, const float* Z, const float* Vp,
                         const uint16_t* VH, const uint16_t* VL, const KParams* kp,
                         float* part, const int* n_active, gp_precision prec, hipStream_t s) {
-    if (sh.sym) return kmv_sym_d<D>(sh, Z, Vp, kp, part, n_active, s);
+    if (sh.sym) return kmv_sym_d<D>(sh, Z, Vp, VH, VL, kp, part, n_active, prec, s);
     if (sh.mfma && prec == GP_BF16_SPLIT_V) return kmv_bf16_d<D, false>(sh, Z, VH, VL, kp, part, n_active, s);
     if (sh.mfma && prec == GP_BF16_SPLIT_KV) return kmv_bf16_d<D, true>(sh, Z, VH, VL, kp, part, n_active, s);
     const int64_t tiles = sh.n_pad / sh.rows_per_wg;

@@ -86,13 +86,44 @@ def test_symmetric_and_split_k_products_match_oracle(n, d, m):
     assert colwise_rel(outs[pb.SHAPE_SYM], outs[2048]).max() <= 2e-5
 
 
+# the BF16 bound of the covariance products: per column, of || |K| |V| || (the rounding of one
+# BF16 value, 2^-9, and of a hi + lo pair, about 2^-17, with margin), plus the FP32 term
+BF16_BOUND = {pb.GP_BF16_SPLIT_V: 2.0 ** -8, pb.GP_BF16_SPLIT_KV: 6 * 2.0 ** -18}
+
+
+@pytest.mark.parametrize("prec", [pb.GP_BF16_SPLIT_V, pb.GP_BF16_SPLIT_KV])
+@pytest.mark.parametrize("n,d,m", [(2049, 8, 17), (3000, 5, 32), (4100, 2, 64), (6000, 8, 31)])
+def test_symmetric_bf16_products_match_oracle_and_split_k(prec, n, d, m):
+    # BF16 products (two or four MFMA blocks) through both shapes: each within the BF16 bound
+    # of the oracle; the two use the same BF16 operands and differ in the order of their FP32
+    # and FP64 sums only
+    h = pb.Handle(0, seed=7)
+    X, psi = problem(n, d, seed=5 * n + d)
+    V = np.random.default_rng(m + 2 * n).standard_normal((n, m)).astype(np.float32)
+    ref = ogp.kmv(X, psi, V)
+    bound = (BF16_BOUND[prec] + 1e-6) * np.linalg.norm(
+        np.abs(ogp.kernel_matrix(X, psi)) @ np.abs(V.astype(np.float64)), axis=0)
+    outs = {}
+    for code in (pb.SHAPE_SYM, 2048):
+        pb.gp_tune_set(h, n, d, m, code, prec=prec)
+        assert pb.gp_tune_get(h, n, d, m, prec=prec)[0] == code
+        out = pb.gp_kmv(h, dev(X), dev(psi), colm(V), prec=prec)
+        torch.cuda.synchronize()
+        outs[code] = out.cpu().numpy().astype(np.float64)
+        err = np.linalg.norm(outs[code] - ref, axis=0)
+        assert np.all(err <= bound), (code, (err / bound).max())
+    assert colwise_rel(outs[pb.SHAPE_SYM], outs[2048]).max() <= 2e-5
+
+
 def test_symmetric_product_is_refused_where_it_does_not_apply():
     h = pb.Handle(0, seed=7)
     for n, d, m, prec in [(1000, 4, 16, pb.GP_FP32),      # n_pad below 2048
                           (4000, 12, 16, pb.GP_FP32),     # d > 8
                           (4000, 4, 48, pb.GP_FP32),      # three MFMA blocks
                           (4000, 4, 18, pb.GP_FP32),      # two VALU columns
-                          (4000, 4, 32, pb.GP_BF16_SPLIT_KV)]:
+                          (4000, 4, 16, pb.GP_BF16_SPLIT_KV),   # BF16: one MFMA block
+                          (4000, 4, 48, pb.GP_BF16_SPLIT_V),    # BF16: three MFMA blocks
+                          (4000, 12, 32, pb.GP_BF16_SPLIT_V)]:
         with pytest.raises(RuntimeError, match="symmetric"):
             pb.gp_tune_set(h, n, d, m, pb.SHAPE_SYM, prec=prec)
     with pytest.raises(RuntimeError):

@@ -316,12 +316,20 @@ def learned_from_chains(pb, h, X, y, psi_map, M_sub, L_full, eps_t, prior, chain
     from paper_1501_05427_amd import protocol
     t0 = time.perf_counter()
     starts = protocol.init_chains(psi_map, M_sub, chains, seed=seed)
-    states = protocol.plain_chain_states(h, X, y, starts, steps, L_full, eps_t, probes=probes,
-                                         prior=prior, q=q)
+    states = protocol.plain_chain_states(
+        h, X, y, starts, steps, L_full, eps_t, probes=probes, prior=prior, q=q,
+        progress=lambda t, T: say(f"training chains: {t}/{T} steps, {time.perf_counter() - t0:.0f} s"))
     t_chain = time.perf_counter() - t0
     psis = torch.from_numpy(states).cuda()
     U, ritz = pb.precond_build_basis(h, X, torch.from_numpy(psi_map).cuda(), k)
-    T = pb.precond_targets(h, X, y, U, psis)
+    # the Galerkin targets of every state, in pieces of 256 states
+    parts = []
+    for a in range(0, psis.shape[0], 256):
+        parts.append(pb.precond_targets(h, X, y, U, psis[a:a + 256]))
+        if (a // 256) % 4 == 3:
+            torch.cuda.synchronize()
+            say(f"training targets: {a + 256}/{psis.shape[0]}, {time.perf_counter() - t0:.0f} s")
+    T = torch.cat(parts)
     torch.cuda.synchronize()
     t_targets = time.perf_counter() - t0 - t_chain
     I_, O_ = len(psi_map), 2 * k + 1

@@ -746,7 +746,11 @@ __global__ __launch_bounds__(kWG) void kmv_mfma_bf16_kernel(
 // with the BF16 contraction above.  Forward: as kmv_mfma_bf16_kernel, R = 4 blocks of 16
 // rows per wave, four waves per 256-row tile.  Transposed: after each 32-column group the
 // four waves store their packed K values (hi, and lo with SPLITK) transposed into one
-// workgroup tile tt[j][i] (32 x 256 BF16, row stride kTT).  Each wave then owns NB / 2
+// workgroup tile tt[j][i] (32 x 256 BF16).  Two lanes of neighbouring rows i, i + 1 swap
+// their packed pairs (one DPP move) so that each stores one 32-bit word (K[i][j], K[i+1][j]);
+// the 16-byte chunks of a row are XOR-swizzled by tt_swz(j), which spreads those stores over
+// the banks two lanes per bank and keeps every 16-byte read of eight lanes on distinct
+// banks.  Each wave then owns NB / 2
 // output tiles of 16 columns j by 16 right-hand sides and contracts them over all 256 rows
 // of the row tile: A operand = 8 consecutive i of one row of tt, B operand = the row tile's
 // own V rows, held in registers for the whole item.  So no sum across waves is needed and
@@ -754,10 +758,11 @@ __global__ __launch_bounds__(kWG) void kmv_mfma_bf16_kernel(
 // product terms are those of the forward direction: K_hi (V_hi + V_lo), plus K_lo V_hi
 // with SPLITK.
 // ---------------------------------------------------------------------------------------
-constexpr int kTT = kSymTile + 6;  // 262: the stores of a wave hit 32 distinct banks
+// chunk swizzle of row j of the transposed tile (16-byte chunks of 8 BF16)
+__device__ inline int tt_swz(int j) { return (j ^ ((j >> 3) << 1)) & 7; }
 
 template <int D, int NB, bool SPLITK>
-__global__ __launch_bounds__(kWG) void kmv_sym_bf16_kernel(
+__global__ __launch_bounds__(kWG, NB == 2 ? 2 : 1) void kmv_sym_bf16_kernel(
     const float* __restrict__ Z, const uint16_t* __restrict__ VH, const uint16_t* __restrict__ VL,
     float* __restrict__ F, float* __restrict__ Tt, int64_t n_pad, int NT, int cs,
     const KParams* __restrict__ kp, const int* __restrict__ n_active) {
@@ -771,8 +776,8 @@ __global__ __launch_bounds__(kWG) void kmv_sym_bf16_kernel(
     __shared__ float4 zs[2][S::NZ4];
     __shared__ uint16_t hs[2][S::VSIZE];
     __shared__ uint16_t ls[2][S::VSIZE];
-    __shared__ __align__(16) uint16_t th[32 * kTT];
-    __shared__ __align__(16) uint16_t tl[SPLITK ? 32 * kTT : 8];
+    __shared__ __align__(16) uint16_t th[32 * kSymTile];
+    __shared__ __align__(16) uint16_t tl[SPLITK ? 32 * kSymTile : 8];
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int q = lane >> 4, col = lane & 15;
@@ -784,6 +789,10 @@ __global__ __launch_bounds__(kWG) void kmv_sym_bf16_kernel(
     const int64_t jb = max((int64_t)k * cs, tile0);
     const int64_t je = min((int64_t)(k + 1) * cs, n_pad);
     const float negc0 = -kp->c0;
+    // the word a lane stores: even lane (row i) (K[i][j], K[i+1][j]) for j = 8 q + 2 u, odd
+    // lane (row i + 1) the same for j + 1; v_perm selectors over (partner's pair, own pair)
+    const int odd = col & 1;
+    const uint32_t psel = odd ? 0x03020706u : 0x05040100u;
 
     float zi[R][D];
 #pragma unroll
@@ -867,14 +876,16 @@ __global__ __launch_bounds__(kWG) void kmv_sym_bf16_kernel(
                 // j = 8 q + 2 u (low half of hi[r][u]) and 8 q + 2 u + 1 (high half)
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
-                    const int i = wave * 64 + r * 16 + col;
+                    const int ie = wave * 64 + r * 16 + (col & ~1);  // even row of the lane pair
 #pragma unroll
                     for (int u = 0; u < 4; ++u) {
-                        th[(8 * q + 2 * u) * kTT + i] = (uint16_t)(hi[r][u] & 0xffffu);
-                        th[(8 * q + 2 * u + 1) * kTT + i] = (uint16_t)(hi[r][u] >> 16);
+                        const int j = 8 * q + 2 * u + odd;
+                        const int w = (j * kSymTile + (((ie >> 3) ^ tt_swz(j)) << 3) + (ie & 7)) >> 1;
+                        const uint32_t xh = (uint32_t)__builtin_amdgcn_mov_dpp((int)hi[r][u], 0xB1, 0xF, 0xF, false);
+                        reinterpret_cast<uint32_t*>(th)[w] = __builtin_amdgcn_perm(xh, hi[r][u], psel);
                         if (SPLITK) {
-                            tl[(8 * q + 2 * u) * kTT + i] = (uint16_t)(lo[r][u] & 0xffffu);
-                            tl[(8 * q + 2 * u + 1) * kTT + i] = (uint16_t)(lo[r][u] >> 16);
+                            const uint32_t xl = (uint32_t)__builtin_amdgcn_mov_dpp((int)lo[r][u], 0xB1, 0xF, 0xF, false);
+                            reinterpret_cast<uint32_t*>(tl)[w] = __builtin_amdgcn_perm(xl, lo[r][u], psel);
                         }
                     }
                 }
@@ -882,22 +893,27 @@ __global__ __launch_bounds__(kWG) void kmv_sym_bf16_kernel(
 #pragma unroll
                 for (int t = 0; t < TPW; ++t) {
                     const int jblk = NB == 2 ? (wave & 1) : t;
-                    floatx4 tr = floatx4{0.f, 0.f, 0.f, 0.f};
-                    const int rowoff = (16 * jblk + col) * kTT + 8 * q;  // even: 4-byte reads
+                    // four independent accumulators (row blocks kb mod 4), so the MFMA chain
+                    // that the store waits for is 6 deep instead of 24
+                    floatx4 tq[4];
+#pragma unroll
+                    for (int a = 0; a < 4; ++a) tq[a] = floatx4{0.f, 0.f, 0.f, 0.f};
+                    const int jr = 16 * jblk + col;
+                    const int sw = tt_swz(jr);
 #pragma unroll
                     for (int kb = 0; kb < 8; ++kb) {
-                        const uint32_t* ph = reinterpret_cast<const uint32_t*>(th + rowoff + 32 * kb);
-                        const uintx4 a4 = {ph[0], ph[1], ph[2], ph[3]};
-                        const bf16x8 ah = __builtin_bit_cast(bf16x8, a4);
-                        tr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, __builtin_bit_cast(bf16x8, vh[kb]), tr, 0, 0, 0);
-                        tr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, __builtin_bit_cast(bf16x8, vl[kb]), tr, 0, 0, 0);
+                        // 8 consecutive i = 32 kb + 8 q of row jr: one 16-byte chunk
+                        const int e = jr * kSymTile + (((4 * kb + q) ^ sw) << 3);
+                        const bf16x8 ah = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uintx4*>(th + e));
+                        floatx4& t4 = tq[kb & 3];
+                        t4 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, __builtin_bit_cast(bf16x8, vh[kb]), t4, 0, 0, 0);
+                        t4 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, __builtin_bit_cast(bf16x8, vl[kb]), t4, 0, 0, 0);
                         if (SPLITK) {
-                            const uint32_t* pl = reinterpret_cast<const uint32_t*>(tl + rowoff + 32 * kb);
-                            const uintx4 b4 = {pl[0], pl[1], pl[2], pl[3]};
-                            tr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, b4),
-                                                                         __builtin_bit_cast(bf16x8, vh[kb]), tr, 0, 0, 0);
+                            const bf16x8 al = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uintx4*>(tl + e));
+                            t4 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, __builtin_bit_cast(bf16x8, vh[kb]), t4, 0, 0, 0);
                         }
                     }
+                    const floatx4 tr = (tq[0] + tq[1]) + (tq[2] + tq[3]);
                     // lane (q, col): columns j0 + 32 g + 16 jblk + 4 q + v of right-hand side 16 cbw + col
                     float4 o;
                     o.x = tr[0];
@@ -1236,11 +1252,13 @@ static void pick_split(KmvShape& sh, int target_wg) {
 }
 
 KmvShape kmv_shape(int64_t n, int d, int m, gp_precision prec) {
-    // the symmetric product by default where it was measured faster than split-K: one MFMA
-    // block of columns, or n of 32768 and more (two blocks at n = 16384 are 9% slower: the
-    // transposed partials cost more than the halved entry work saves)
+    // the symmetric product by default where it was measured faster than split-K.  FP32: one
+    // MFMA block of columns, or n of 32768 and more (two blocks at n = 16384 are 9% slower:
+    // the transposed partials cost more than the halved entry work saves).  BF16: two MFMA
+    // blocks and n of 32768 and more (3-17% faster; four blocks lose occupancy and are slower)
     const KmvShape sy = kmv_shape_sym(n, d, m, prec);
     if (sy.sym && prec == GP_FP32 && (sy.mp <= 20 || sy.n_pad >= 32768)) return sy;
+    if (sy.sym && prec != GP_FP32 && sy.mp == 32 && sy.n_pad >= 32768) return sy;
     return kmv_shape_target(n, d, m, prec, 2048);
 }
 

@@ -61,20 +61,22 @@ def exact_gradient(h, X, y, psi, eps=1e-6, max_iter=20000):
 
 
 def probe_mean_gradient(h, X, y, psi, batches, probes=31, probe_stream=21, eps=1e-6,
-                        max_iter=5000, progress=None):
+                        max_iter=5000, progress=None, prec=None, refresh=0):
     """Reference gradient for large n: the plain estimator with converged solves (q = 0, so
     the series never truncates) averaged over `batches` draws of `probes` Gaussian probes.
 
     Each batch is an unbiased estimate of d/dpsi log p(y | psi) whose only error is the
     Hutchinson noise of its probes (and the CG tolerance); returns (mean, standard error of
     the mean) as numpy arrays.  Probes come from Philox stream `probe_stream`, one counter
-    per batch.
+    per batch.  prec / refresh: the products' arithmetic mode (FP32 by default) and the
+    residual replacement of the solves (0 = off), to measure what a mode does to the mean.
     """
     import torch
     n = X.shape[0]
     psid = psi if torch.is_tensor(psi) else torch.as_tensor(np.asarray(psi, np.float64)).cuda()
     P = psid.shape[0]
-    ref = pb.make_params(q=0.0, rate=1.0, eps=eps, eps_relative=1, max_iter=max_iter, rng_stream=3)
+    ref = pb.make_params(q=0.0, rate=1.0, eps=eps, eps_relative=1, max_iter=max_iter, rng_stream=3,
+                         refresh=refresh, prec=pb.GP_FP32 if prec is None else prec)
     R = pb.colmajor(n, probes)
     S_warm = torch.zeros((1 + probes, n), dtype=torch.float64, device="cuda").t()
     g = torch.zeros(P, dtype=torch.float64, device="cuda")
@@ -192,7 +194,7 @@ def ess(x):
 
 
 def plain_chain_states(h, X, y, starts, steps, M_chol, eps, probes=4, probe_period=20, q=1.0,
-                       prior=None, rng_stream=41, seed=900):
+                       prior=None, rng_stream=41, seed=900, progress=None):
     """The log-parameters visited by plain-solver SGLD chains: the (theta, solve) pairs the
     method itself generates, from which the learned preconditioner takes its training
     inputs.  One chain per row of `starts`, all over the same GP (device X, y), stepped
@@ -200,7 +202,8 @@ def plain_chain_states(h, X, y, starts, steps, M_chol, eps, probes=4, probe_peri
     preconditioner): `probes` Gaussian probes redrawn every `probe_period` steps with warm
     starts, threshold q sqrt(n), step size eps, SGLD preconditioner M = L L^T (M_chol: P x P
     numpy lower factor), prior as for sgld_step (dict kind, a, b).  Returns
-    (len(starts) * steps, P) numpy, the state after every step of every chain."""
+    (len(starts) * steps, P) numpy, the state after every step of every chain.  progress:
+    optional callable(steps done, steps), called every 10 steps."""
     import torch
     starts = np.asarray(starts, np.float64)
     C, P = starts.shape
@@ -217,6 +220,8 @@ def plain_chain_states(h, X, y, starts, steps, M_chol, eps, probes=4, probe_peri
     for t in range(steps):
         batch.step(t, eps)
         out[t] = torch.stack([p["psi"] for p in probs]).cpu().numpy()
+        if progress is not None and (t + 1) % 10 == 0:
+            progress(t + 1, steps)
     batch.close()
     if not np.all(np.isfinite(out)):
         raise RuntimeError("a plain-solver chain left the finite range")

@@ -369,6 +369,29 @@ def test_residual_replacement_removes_the_bf16_solve_bias(h, prec, bound, capsys
     assert errs[3][1] <= bound and errs[5][1] <= bound
 
 
+@pytest.mark.parametrize("prec", [pb.GP_BF16_SPLIT_V, pb.GP_BF16_SPLIT_KV])
+def test_bf16_gradient_bias_on_subsample_4096(h, prec, capsys):
+    # the gradient with converged solves in a BF16 mode, averaged over 24 batches of 31 probes,
+    # against the oracle's Cholesky gradient of the first 4096 points of the n = 65536, d = 8
+    # workload, per component in units of the mean's standard error.  With residual
+    # replacement (k = 3) the solves land within ~2e-6 of K^-1 b and every component lies
+    # within 4 SE.  Without it the split-V solves converge 1.6e-2 away from K^-1 b, and the
+    # report shows what that does to the gradient.
+    from paper_1501_05427_amd import protocol
+    w = workloads.rff_gp(n=65536, d=8, seed=2)
+    X, psi, y = w["X"][:4096], w["psi"], w["y"][:4096]
+    ref = ogp.exact_gradient(X.astype(np.float64), psi, y.astype(np.float64))
+    z = {}
+    for rf in (0, 3):
+        mean, se = protocol.probe_mean_gradient(h, dev(X), dev(y), psi, batches=24, probes=31,
+                                                prec=prec, refresh=rf)
+        z[rf] = (mean - ref) / se
+    with capsys.disabled():
+        print(f"\n[bf16 gradient bias] mode {prec}: (mean - exact) / SE per component, "
+              f"without replacement {np.round(z[0], 2).tolist()}; refresh 3 {np.round(z[3], 2).tolist()}")
+    assert np.all(np.abs(z[3]) < 4.0), z[3]
+
+
 def colwise_rel(out, ref):
     out = np.asarray(out, dtype=np.float64)
     return np.linalg.norm(out - ref, axis=0) / np.maximum(np.linalg.norm(ref, axis=0), 1e-300)

@@ -115,6 +115,43 @@ def test_symmetric_bf16_products_match_oracle_and_split_k(prec, n, d, m):
     assert colwise_rel(outs[pb.SHAPE_SYM], outs[2048]).max() <= 2e-5
 
 
+@pytest.mark.parametrize("prec", [pb.GP_FP32, pb.GP_BF16_SPLIT_KV])
+def test_converged_solves_through_both_shapes_at_full_size(prec, capsys):
+    # n = 33000 (n_pad 33024), 17 systems: the symmetric shape is the default there, in FP32
+    # and in the BF16 modes.  Converged solves (CG to 1e-6 relative; BF16 with residual
+    # replacement, k = 3) through it and through split-K: each solution's true residual
+    # ||b - K s|| / ||b||, taken with an FP32 product of the solution, and the difference of
+    # the two solutions are printed.  Both are bounded by 1e-3: far above the solve tolerance
+    # times the conditioning and the FP32 evaluation error (1e-7 ||K|| ||s|| / ||b||, with
+    # ||s|| / ||b|| ~ 15 here), far below what a wrong partial layout in the solver's product
+    # would give.  A dense oracle of this size is out of reach; the oracle comparison of the
+    # products is in the cases above.
+    import workloads
+    n, d, m = 33000, 8, 17
+    h = pb.Handle(0, seed=11)
+    w = workloads.rff_gp(n=n, d=d, seed=7, n_features=256)
+    X, psi = dev(w["X"]), dev(w["psi"])
+    B = np.column_stack([w["y"], workloads.gaussian_matrix(n, m - 1, seed=3)]).astype(np.float32)
+    assert pb.gp_tune_get(h, n, d, m, prec=prec)[0] == pb.SHAPE_SYM
+    params = pb.make_params(q=1e-12, rate=1e-9, eps=1e-6, eps_relative=1, max_iter=3000, prec=prec,
+                            refresh=3 if prec != pb.GP_FP32 else 0)
+    sol, res = {}, {}
+    for code in (pb.SHAPE_SYM, 2048):
+        pb.gp_tune_set(h, n, d, m, code, prec=prec)
+        St, stats = pb.ulisse_solve(h, X, psi, colm(B), params)
+        KS = pb.gp_kmv(h, X, psi, St.to(torch.float32))   # default FP32 product
+        torch.cuda.synchronize()
+        assert not any(s_["flags"] for s_ in pb.decode_stats(stats)), code
+        sol[code] = St.cpu().numpy()
+        res[code] = np.linalg.norm(B - KS.cpu().numpy().astype(np.float64), axis=0) / np.linalg.norm(B, axis=0)
+    diff = colwise_rel(sol[pb.SHAPE_SYM], sol[2048]).max()
+    with capsys.disabled():
+        print(f"\n[shapes at n = 33000] mode {prec}: true residual max symmetric {res[pb.SHAPE_SYM].max():.2e}, "
+              f"split-K {res[2048].max():.2e}; solutions differ by {diff:.2e}")
+    assert res[pb.SHAPE_SYM].max() <= 1e-3 and res[2048].max() <= 1e-3
+    assert diff <= 1e-3
+
+
 def test_symmetric_product_is_refused_where_it_does_not_apply():
     h = pb.Handle(0, seed=7)
     for n, d, m, prec in [(1000, 4, 16, pb.GP_FP32),      # n_pad below 2048

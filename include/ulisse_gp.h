@@ -442,7 +442,7 @@ void gp_batch_destroy(gp_batch* b);
  * into work: 0 = the symmetric product (row tiles of 256 rows against column chunks; each
  * entry of K off the diagonal tiles is built once and used for its row and, through a
  * transposed product, for its column; d <= 8, n >= 1793; FP32 with 16, 17, 32 or 33
- * right-hand sides, BF16 modes with 17 to 32 or 49 to 64); c > 0 = the split-K product
+ * right-hand sides, BF16 modes with 17 to 32); c > 0 = the split-K product
  * whose number of column chunks gives about c
  * workgroups (chunk partials reduced in FP64 in a fixed order).  Both give the same values
  * to FP32 rounding, not bit for bit.

@@ -743,41 +743,38 @@ __global__ __launch_bounds__(kWG) void kmv_mfma_bf16_kernel(
 
 // ---------------------------------------------------------------------------------------
 // Symmetric BF16 product: the work items, partials and reduce of the symmetric FP32 product,
-// with the BF16 contraction above.  Forward: as kmv_mfma_bf16_kernel, R = 4 blocks of 16
-// rows per wave, four waves per 256-row tile.  Transposed: after each 32-column group the
-// four waves store their packed K values (hi, and lo with SPLITK) transposed into one
-// workgroup tile tt[j][i] (32 x 256 BF16).  Two lanes of neighbouring rows i, i + 1 swap
-// their packed pairs (one DPP move) so that each stores one 32-bit word (K[i][j], K[i+1][j]);
-// the 16-byte chunks of a row are XOR-swizzled by tt_swz(j), which spreads those stores over
-// the banks two lanes per bank and keeps every 16-byte read of eight lanes on distinct
-// banks.  Each wave then owns NB / 2
-// output tiles of 16 columns j by 16 right-hand sides and contracts them over all 256 rows
-// of the row tile: A operand = 8 consecutive i of one row of tt, B operand = the row tile's
-// own V rows, held in registers for the whole item.  So no sum across waves is needed and
-// each wave writes its transposed partials to Tt straight from its accumulators.  The
-// product terms are those of the forward direction: K_hi (V_hi + V_lo), plus K_lo V_hi
-// with SPLITK.
+// with the BF16 contraction above, for two MFMA blocks of right-hand sides (17 to 32).
+// Forward: as kmv_mfma_bf16_kernel, R = 4 blocks of 16 rows per wave, four waves per 256-row
+// tile.  Transposed: each wave contracts its own 64 rows, 32 at a time.  It stores the packed
+// K values of two row blocks (hi, and lo with SPLITK) transposed into a 32 x 32 BF16 tile of
+// its own in LDS: two lanes of neighbouring rows i, i + 1 swap their packed pairs (one DPP
+// move) and each stores one 32-bit word (K[i][j], K[i+1][j]); the 16-byte chunks of a tile
+// row are XOR-swizzled by tw_swz(j), which puts a wave's stores two lanes per bank and its
+// 16-byte reads on distinct banks.  A operand = 8 consecutive i of one tile row, B operand =
+// the wave's own V rows, held in registers for the whole item.  The four waves' partials of
+// a 64-column stage are summed in LDS in a fixed order and written to Tt, as in the FP32
+// kernel.  The product terms are those of the forward direction: K_hi (V_hi + V_lo), plus
+// K_lo V_hi with SPLITK.
 // ---------------------------------------------------------------------------------------
-// chunk swizzle of row j of the transposed tile (16-byte chunks of 8 BF16)
-__device__ inline int tt_swz(int j) { return (j ^ ((j >> 3) << 1)) & 7; }
+__device__ inline int tw_swz(int j) { return ((j & 3) ^ ((j >> 2) & 3)) & 3; }
 
-template <int D, int NB, bool SPLITK>
-__global__ __launch_bounds__(kWG, NB == 2 ? 2 : 1) void kmv_sym_bf16_kernel(
+template <int D, bool SPLITK>
+__global__ __launch_bounds__(kWG, 2) void kmv_sym_bf16_kernel(
     const float* __restrict__ Z, const uint16_t* __restrict__ VH, const uint16_t* __restrict__ VL,
     float* __restrict__ F, float* __restrict__ Tt, int64_t n_pad, int NT, int cs,
     const KParams* __restrict__ kp, const int* __restrict__ n_active) {
     if (n_active != nullptr && *n_active == 0) return;
     constexpr int R = 4;
+    constexpr int NB = 2;
     constexpr int DP = (D + 3) & ~3;
     constexpr int MP = NB * 16;
-    static_assert(NB == 2 || NB == 4, "2 NB output tiles shared by four waves");
-    constexpr int TPW = NB / 2;  // output tiles per wave and group
+    constexpr int RED = MP + 1;  // row stride of a wave's transposed partial
     using S = StageB16<DP, MP>;
     __shared__ float4 zs[2][S::NZ4];
     __shared__ uint16_t hs[2][S::VSIZE];
     __shared__ uint16_t ls[2][S::VSIZE];
-    __shared__ __align__(16) uint16_t th[32 * kSymTile];
-    __shared__ __align__(16) uint16_t tl[SPLITK ? 32 * kSymTile : 8];
+    __shared__ __align__(16) uint16_t tw[4][SPLITK ? 2 : 1][32 * 32];
+    __shared__ float red[4][kJS * RED];
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int q = lane >> 4, col = lane & 15;
@@ -797,20 +794,22 @@ __global__ __launch_bounds__(kWG, NB == 2 ? 2 : 1) void kmv_sym_bf16_kernel(
     float zi[R][D];
 #pragma unroll
     for (int r = 0; r < R; ++r) load_row<D>(Z + (row0 + r * 16 + col) * DP, zi[r]);
-    // this wave's output tiles: column block cbw; j blocks (wave & 1) for NB = 2, both for 4
-    const int cbw = NB == 2 ? (wave >> 1) : wave;
-    // B operand of the transposed product: lane (q, col) holds
-    // V[tile0 + 32 kb + 8 q + s][16 cbw + col], s = 0..7, for the 8 blocks kb of the tile
-    uintx4 vh[8], vl[8];
+    // B operand of the transposed products: lane (q, col) holds
+    // V[row0 + 32 p + 8 q + s][16 cb + col], s = 0..7, for the wave's two 32-row halves p
+    uintx4 vh[2][NB], vl[2][NB];
 #pragma unroll
-    for (int kb = 0; kb < 8; ++kb) {
-        const int64_t o = (int64_t)(16 * cbw + col) * n_pad + tile0 + 32 * kb + 8 * q;
-        vh[kb] = *reinterpret_cast<const uintx4*>(VH + o);
-        vl[kb] = *reinterpret_cast<const uintx4*>(VL + o);
-    }
+    for (int p2 = 0; p2 < 2; ++p2)
+#pragma unroll
+        for (int cb = 0; cb < NB; ++cb) {
+            const int64_t o = (int64_t)(16 * cb + col) * n_pad + row0 + 32 * p2 + 8 * q;
+            vh[p2][cb] = *reinterpret_cast<const uintx4*>(VH + o);
+            vl[p2][cb] = *reinterpret_cast<const uintx4*>(VL + o);
+        }
     // complete these loads here (see kmv_sym_f32_kernel)
 #pragma unroll
-    for (int kb = 0; kb < 8; ++kb) asm volatile("" : "+v"(vh[kb]), "+v"(vl[kb]));
+    for (int p2 = 0; p2 < 2; ++p2)
+#pragma unroll
+        for (int cb = 0; cb < NB; ++cb) asm volatile("" : "+v"(vh[p2][cb]), "+v"(vl[p2][cb]));
 #pragma unroll
     for (int r = 0; r < R; ++r)
 #pragma unroll
@@ -822,6 +821,9 @@ __global__ __launch_bounds__(kWG, NB == 2 ? 2 : 1) void kmv_sym_bf16_kernel(
 #pragma unroll
         for (int cb = 0; cb < NB; ++cb) acc[r][cb] = floatx4{0.f, 0.f, 0.f, 0.f};
 
+    uint32_t* twh = reinterpret_cast<uint32_t*>(tw[wave][0]);
+    uint32_t* twl = reinterpret_cast<uint32_t*>(tw[wave][SPLITK ? 1 : 0]);
+    float* redw = red[wave];
     S st;
     st.load(Z, VH, VL, n_pad, jb);
     st.store(zs[0], hs[0], ls[0], true);
@@ -872,62 +874,81 @@ __global__ __launch_bounds__(kWG, NB == 2 ? 2 : 1) void kmv_sym_bf16_kernel(
                 }
             }
             if (sym) {
-                // tt[j][i] = K(tile0 + i, j0 + 32 g + j): lane (q, col) holds i = 64 wave + 16 r + col,
-                // j = 8 q + 2 u (low half of hi[r][u]) and 8 q + 2 u + 1 (high half)
+                // transposed: T[j][c] = sum over the wave's 64 rows i of K(i, j) V(i, c) for the
+                // 32 columns j of this group; lane (q, col) accumulates T[16 jb + 4 q + t][16 cb + col]
+                floatx4 tr[2][NB];
 #pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    const int ie = wave * 64 + r * 16 + (col & ~1);  // even row of the lane pair
+                for (int a2 = 0; a2 < 2; ++a2)
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const int j = 8 * q + 2 * u + odd;
-                        const int w = (j * kSymTile + (((ie >> 3) ^ tt_swz(j)) << 3) + (ie & 7)) >> 1;
-                        const uint32_t xh = (uint32_t)__builtin_amdgcn_mov_dpp((int)hi[r][u], 0xB1, 0xF, 0xF, false);
-                        reinterpret_cast<uint32_t*>(th)[w] = __builtin_amdgcn_perm(xh, hi[r][u], psel);
-                        if (SPLITK) {
-                            const uint32_t xl = (uint32_t)__builtin_amdgcn_mov_dpp((int)lo[r][u], 0xB1, 0xF, 0xF, false);
-                            reinterpret_cast<uint32_t*>(tl)[w] = __builtin_amdgcn_perm(xl, lo[r][u], psel);
+                    for (int cb = 0; cb < NB; ++cb) tr[a2][cb] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int p2 = 0; p2 < 2; ++p2) {
+                    // tile[j][i] = K(row0 + 32 p2 + i, j0 + 32 g + j): row blocks r = 2 p2, 2 p2 + 1
+#pragma unroll
+                    for (int rr = 0; rr < 2; ++rr) {
+                        const int r = 2 * p2 + rr;
+                        const int ie = 16 * rr + (col & ~1);  // even row of the lane pair
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const int j = 8 * q + 2 * u + odd;
+                            const int w = (j * 32 + (((ie >> 3) ^ tw_swz(j)) << 3) + (ie & 7)) >> 1;
+                            const uint32_t xh = (uint32_t)__builtin_amdgcn_mov_dpp((int)hi[r][u], 0xB1, 0xF, 0xF, false);
+                            twh[w] = __builtin_amdgcn_perm(xh, hi[r][u], psel);
+                            if (SPLITK) {
+                                const uint32_t xl = (uint32_t)__builtin_amdgcn_mov_dpp((int)lo[r][u], 0xB1, 0xF, 0xF, false);
+                                twl[w] = __builtin_amdgcn_perm(xl, lo[r][u], psel);
+                            }
                         }
                     }
-                }
-                __syncthreads();
+                    // the other lanes' stores before the reads, the reads before the next stores
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
-                for (int t = 0; t < TPW; ++t) {
-                    const int jblk = NB == 2 ? (wave & 1) : t;
-                    // four independent accumulators (row blocks kb mod 4), so the MFMA chain
-                    // that the store waits for is 6 deep instead of 24
-                    floatx4 tq[4];
+                    for (int a2 = 0; a2 < 2; ++a2) {
+                        const int jr = 16 * a2 + col;
+                        const int e = (jr * 32 + ((q ^ tw_swz(jr)) << 3)) >> 1;  // 8 i = 8 q .. 8 q + 7
+                        const bf16x8 ah = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uintx4*>(twh + e));
 #pragma unroll
-                    for (int a = 0; a < 4; ++a) tq[a] = floatx4{0.f, 0.f, 0.f, 0.f};
-                    const int jr = 16 * jblk + col;
-                    const int sw = tt_swz(jr);
-#pragma unroll
-                    for (int kb = 0; kb < 8; ++kb) {
-                        // 8 consecutive i = 32 kb + 8 q of row jr: one 16-byte chunk
-                        const int e = jr * kSymTile + (((4 * kb + q) ^ sw) << 3);
-                        const bf16x8 ah = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uintx4*>(th + e));
-                        floatx4& t4 = tq[kb & 3];
-                        t4 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, __builtin_bit_cast(bf16x8, vh[kb]), t4, 0, 0, 0);
-                        t4 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, __builtin_bit_cast(bf16x8, vl[kb]), t4, 0, 0, 0);
+                        for (int cb = 0; cb < NB; ++cb) {
+                            tr[a2][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                ah, __builtin_bit_cast(bf16x8, vh[p2][cb]), tr[a2][cb], 0, 0, 0);
+                            tr[a2][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                ah, __builtin_bit_cast(bf16x8, vl[p2][cb]), tr[a2][cb], 0, 0, 0);
+                        }
                         if (SPLITK) {
-                            const bf16x8 al = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uintx4*>(tl + e));
-                            t4 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, __builtin_bit_cast(bf16x8, vh[kb]), t4, 0, 0, 0);
+                            const bf16x8 al = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uintx4*>(twl + e));
+#pragma unroll
+                            for (int cb = 0; cb < NB; ++cb)
+                                tr[a2][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                    al, __builtin_bit_cast(bf16x8, vh[p2][cb]), tr[a2][cb], 0, 0, 0);
                         }
                     }
-                    const floatx4 tr = (tq[0] + tq[1]) + (tq[2] + tq[3]);
-                    // lane (q, col): columns j0 + 32 g + 16 jblk + 4 q + v of right-hand side 16 cbw + col
-                    float4 o;
-                    o.x = tr[0];
-                    o.y = tr[1];
-                    o.z = tr[2];
-                    o.w = tr[3];
-                    *reinterpret_cast<float4*>(Tt + ((int64_t)I * MP + 16 * cbw + col) * n_pad + j0 + 32 * g +
-                                               16 * jblk + 4 * q) = o;
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
                 }
-                __syncthreads();  // the tile is rewritten by the next group
+                // the wave's partial: columns j = 32 g + 16 a2 + 4 q + t of the stage
+#pragma unroll
+                for (int a2 = 0; a2 < 2; ++a2)
+#pragma unroll
+                    for (int cb = 0; cb < NB; ++cb)
+#pragma unroll
+                        for (int t = 0; t < 4; ++t)
+                            redw[(g * 32 + 16 * a2 + 4 * q + t) * RED + cb * 16 + col] = tr[a2][cb][t];
             }
         }
         if (more) st.store(zs[buf ^ 1], hs[buf ^ 1], ls[buf ^ 1], true);
         __syncthreads();
+        if (sym) {
+            // the four waves' partials in a fixed order -> Tt[I][c][j0 + j]
+            for (int e = threadIdx.x; e < MP * kJS; e += kWG) {
+                const int c = e / kJS, j = e % kJS;
+                const float v = ((red[0][j * RED + c] + red[1][j * RED + c]) + red[2][j * RED + c]) + red[3][j * RED + c];
+                Tt[((int64_t)I * MP + c) * n_pad + j0 + j] = v;
+            }
+            __syncthreads();
+        }
         buf ^= 1;
     }
 #pragma unroll
@@ -1255,7 +1276,7 @@ KmvShape kmv_shape(int64_t n, int d, int m, gp_precision prec) {
     // the symmetric product by default where it was measured faster than split-K.  FP32: one
     // MFMA block of columns, or n of 32768 and more (two blocks at n = 16384 are 9% slower:
     // the transposed partials cost more than the halved entry work saves).  BF16: two MFMA
-    // blocks and n of 32768 and more (3-17% faster; four blocks lose occupancy and are slower)
+    // blocks and n of 32768 and more
     const KmvShape sy = kmv_shape_sym(n, d, m, prec);
     if (sy.sym && prec == GP_FP32 && (sy.mp <= 20 || sy.n_pad >= 32768)) return sy;
     if (sy.sym && prec != GP_FP32 && sy.mp == 32 && sy.n_pad >= 32768) return sy;
@@ -1271,10 +1292,10 @@ static int64_t sym_items(int nt, int nch, int cs) {
 KmvShape kmv_shape_sym(int64_t n, int d, int m, gp_precision prec) {
     KmvShape sh = kmv_shape_target(n, d, m, prec, 2048);
     // MFMA products with d <= 8 and at least 8 row tiles: FP32 with one or two MFMA blocks
-    // and at most one VALU column, BF16 with two or four blocks
+    // and at most one VALU column, BF16 with two blocks
     const int nb = sh.mp / 16;
     const bool f32 = prec == GP_FP32 && sh.tail <= 1 && (nb == 1 || nb == 2);
-    const bool b16 = prec != GP_FP32 && sh.tail == 0 && (nb == 2 || nb == 4);
+    const bool b16 = prec != GP_FP32 && sh.tail == 0 && nb == 2;
     if (!sh.mfma || d > 8 || sh.n_pad < 8 * kSymTile || !(f32 || b16)) return sh;
     sh.sym = true;
     sh.nt = (int)(sh.n_pad / kSymTile);
@@ -1410,18 +1431,11 @@ static hipError_t kmv_sym_d(const KmvShape& sh, const float* Z, const float* Vp,
         const dim3 grid((unsigned)sym_items(sh.nt, sh.nch, sh.cs));
         const int nb = sh.mp / 16;
         if (prec != GP_FP32) {
-            const bool kv = prec == GP_BF16_SPLIT_KV;
-            if (sh.tail != 0 || VH == nullptr || VL == nullptr) return hipErrorInvalidValue;
-            if (nb == 2 && kv)
-                kmv_sym_bf16_kernel<D, 2, true><<<grid, kWG, 0, s>>>(Z, VH, VL, F, Tt, sh.n_pad, sh.nt, sh.cs, kp, n_active);
-            else if (nb == 2)
-                kmv_sym_bf16_kernel<D, 2, false><<<grid, kWG, 0, s>>>(Z, VH, VL, F, Tt, sh.n_pad, sh.nt, sh.cs, kp, n_active);
-            else if (nb == 4 && kv)
-                kmv_sym_bf16_kernel<D, 4, true><<<grid, kWG, 0, s>>>(Z, VH, VL, F, Tt, sh.n_pad, sh.nt, sh.cs, kp, n_active);
-            else if (nb == 4)
-                kmv_sym_bf16_kernel<D, 4, false><<<grid, kWG, 0, s>>>(Z, VH, VL, F, Tt, sh.n_pad, sh.nt, sh.cs, kp, n_active);
+            if (sh.tail != 0 || nb != 2 || VH == nullptr || VL == nullptr) return hipErrorInvalidValue;
+            if (prec == GP_BF16_SPLIT_KV)
+                kmv_sym_bf16_kernel<D, true><<<grid, kWG, 0, s>>>(Z, VH, VL, F, Tt, sh.n_pad, sh.nt, sh.cs, kp, n_active);
             else
-                return hipErrorInvalidValue;
+                kmv_sym_bf16_kernel<D, false><<<grid, kWG, 0, s>>>(Z, VH, VL, F, Tt, sh.n_pad, sh.nt, sh.cs, kp, n_active);
         } else if (nb == 1 && sh.tail == 0)
             kmv_sym_f32_kernel<D, 1, 0><<<grid, kWG, 0, s>>>(Z, Vp, F, Tt, sh.n_pad, sh.nt, sh.cs, kp, n_active);
         else if (nb == 1 && sh.tail == 1)

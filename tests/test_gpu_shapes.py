@@ -92,9 +92,9 @@ BF16_BOUND = {pb.GP_BF16_SPLIT_V: 2.0 ** -8, pb.GP_BF16_SPLIT_KV: 6 * 2.0 ** -18
 
 
 @pytest.mark.parametrize("prec", [pb.GP_BF16_SPLIT_V, pb.GP_BF16_SPLIT_KV])
-@pytest.mark.parametrize("n,d,m", [(2049, 8, 17), (3000, 5, 32), (4100, 2, 64), (6000, 8, 31)])
+@pytest.mark.parametrize("n,d,m", [(2049, 8, 17), (3000, 5, 32), (4100, 2, 24), (6000, 8, 31)])
 def test_symmetric_bf16_products_match_oracle_and_split_k(prec, n, d, m):
-    # BF16 products (two or four MFMA blocks) through both shapes: each within the BF16 bound
+    # BF16 products (two MFMA blocks: 17 to 32 right-hand sides) through both shapes: each within the BF16 bound
     # of the oracle; the two use the same BF16 operands and differ in the order of their FP32
     # and FP64 sums only
     h = pb.Handle(0, seed=7)
@@ -160,6 +160,7 @@ def test_symmetric_product_is_refused_where_it_does_not_apply():
                           (4000, 4, 18, pb.GP_FP32),      # two VALU columns
                           (4000, 4, 16, pb.GP_BF16_SPLIT_KV),   # BF16: one MFMA block
                           (4000, 4, 48, pb.GP_BF16_SPLIT_V),    # BF16: three MFMA blocks
+                          (4000, 4, 64, pb.GP_BF16_SPLIT_KV),   # BF16: four MFMA blocks
                           (4000, 12, 32, pb.GP_BF16_SPLIT_V)]:
         with pytest.raises(RuntimeError, match="symmetric"):
             pb.gp_tune_set(h, n, d, m, pb.SHAPE_SYM, prec=prec)

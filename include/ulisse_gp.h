@@ -498,7 +498,9 @@ gp_status gp_pipe_probe(gp_handle* h, int32_t iters, double* ms, double* cycles,
  * gp_profile(h, 1) clears the totals and starts recording, gp_profile(h, 0) stops.
  * gp_profile_read waits for the recorded events, returns the totals since the last
  * gp_profile(h, 1) and keeps recording if enabled.  kmv_passes counts the products taken
- * by ULISSE solves (warm-start residual products included).
+ * by ULISSE solves (warm-start residual products included).  kmv_ms covers each product
+ * whole; kmv_main_ms the same launches up to the end of the main product kernel, leaving
+ * out the symmetric shape's reduce of its partials (equal to kmv_ms for the other shapes).
  */
 typedef struct {
     int64_t kmv_launches;
@@ -507,6 +509,8 @@ typedef struct {
     double dquad_ms;
     int64_t solves;
     int64_t kmv_passes;
+    int64_t kmv_main_launches;
+    double kmv_main_ms;
 } gp_profile_stats;
 
 gp_status gp_profile(gp_handle* h, int32_t enable);

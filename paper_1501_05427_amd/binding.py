@@ -47,7 +47,8 @@ class gp_prior(Structure):
 
 class gp_profile_stats(Structure):
     _fields_ = [("kmv_launches", c_int64), ("kmv_ms", c_double), ("dquad_launches", c_int64),
-                ("dquad_ms", c_double), ("solves", c_int64), ("kmv_passes", c_int64)]
+                ("dquad_ms", c_double), ("solves", c_int64), ("kmv_passes", c_int64),
+                ("kmv_main_launches", c_int64), ("kmv_main_ms", c_double)]
 
 
 class gp_precond(Structure):

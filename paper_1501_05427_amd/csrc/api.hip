@@ -73,6 +73,7 @@ struct gp_handle {
     bool prof = false;
     std::vector<hipEvent_t> pool;
     std::vector<hipEvent_t> kmv_ev, dq_ev;  // start/stop pairs
+    std::vector<hipEvent_t> kmv_main_ev;    // start / end-of-main-kernel pairs of the products
     int64_t solves = 0, passes = 0;
     // set only by the batched driver: step word and step size read from device memory
     const uint64_t* dyn_step = nullptr;
@@ -152,6 +153,22 @@ void prof_stop(gp_handle* h, hipEvent_t start, std::vector<hipEvent_t>& into, hi
     (void)hipEventRecord(e, s);
     into.push_back(start);
     into.push_back(e);
+}
+
+// A second start and an end event for the main product kernel (nullptr when timing is off).
+void prof_main(gp_handle* h, hipStream_t s, hipEvent_t* start, hipEvent_t* end) {
+    *start = prof_start(h, s);
+    *end = *start ? take_event(h) : nullptr;
+    if (*start && !*end) {
+        h->pool.push_back(*start);
+        *start = nullptr;
+    }
+}
+
+void prof_main_keep(gp_handle* h, hipEvent_t start, hipEvent_t end) {
+    if (!start) return;
+    h->kmv_main_ev.push_back(start);
+    h->kmv_main_ev.push_back(end);
 }
 
 void prof_drop_last(gp_handle* h, std::vector<hipEvent_t>& v) {
@@ -359,9 +376,11 @@ struct Solve {
     gp_status product(const int* n_active) {
         // the BF16 modes split the FP32 direction into hi + lo halves before each product
         if (b16) GP_HIP(launch_split_bf16(a.D, sh.n_pad * sh.mp, DH, DL, s));
-        hipEvent_t t0 = prof_start(h, s);
-        GP_HIP(launch_kmv_partials(sh, d, Z, a.D, DH, DL, kp, kpart, n_active, p.prec, s));
+        hipEvent_t t0 = prof_start(h, s), m0, m1;
+        prof_main(h, s, &m0, &m1);
+        GP_HIP(launch_kmv_partials(sh, d, Z, a.D, DH, DL, kp, kpart, n_active, p.prec, s, m1));
         prof_stop(h, t0, h->kmv_ev, s);
+        prof_main_keep(h, m0, m1);
         return GP_OK;
     }
 
@@ -507,7 +526,10 @@ struct Solve {
                 GP_HIP(hipEventSynchronize(ev[(k - 1) & 1]));
                 if (pinned[(k - 1) & 1] == 0) {
                     // this iteration's launches found no running system and did nothing
-                    if (h->prof) prof_drop_last(h, h->kmv_ev);
+                    if (h->prof) {
+                        prof_drop_last(h, h->kmv_ev);
+                        prof_drop_last(h, h->kmv_main_ev);
+                    }
                     h->passes -= 1;
                     break;
                 }
@@ -742,6 +764,7 @@ void gp_destroy(gp_handle* h) {
     if (h->pinned_d) (void)hipHostFree(h->pinned_d);
     for (hipEvent_t e : h->pool) (void)hipEventDestroy(e);
     for (hipEvent_t e : h->kmv_ev) (void)hipEventDestroy(e);
+    for (hipEvent_t e : h->kmv_main_ev) (void)hipEventDestroy(e);
     for (hipEvent_t e : h->dq_ev) (void)hipEventDestroy(e);
     delete h;
 }
@@ -770,9 +793,11 @@ gp_status gp_kmv(gp_handle* h, gp_data X, const double* psi, const float* V, int
         GP_TRY(ws(h, kSlotVL, (size_t)sh.n_pad * sh.mp, &VL));
         GP_HIP(launch_split_bf16(Vp, sh.n_pad * sh.mp, VH, VL, s));
     }
-    hipEvent_t t0 = prof_start(h, s);
-    GP_HIP(launch_kmv_partials(sh, X.d, Z, Vp, VH, VL, kp, part, nullptr, prec, s));
+    hipEvent_t t0 = prof_start(h, s), m0, m1;
+    prof_main(h, s, &m0, &m1);
+    GP_HIP(launch_kmv_partials(sh, X.d, Z, Vp, VH, VL, kp, part, nullptr, prec, s, m1));
     prof_stop(h, t0, h->kmv_ev, s);
+    prof_main_keep(h, m0, m1);
     GP_HIP(launch_kmv_reduce(sh, part, Vp, kp, X.n, m, out, ldo, s));
     return GP_OK;
 }
@@ -1427,8 +1452,10 @@ gp_status gp_profile(gp_handle* h, int32_t enable) {
     GP_TRY(check_handle(h));
     if (enable) {
         for (hipEvent_t e : h->kmv_ev) h->pool.push_back(e);
+        for (hipEvent_t e : h->kmv_main_ev) h->pool.push_back(e);
         for (hipEvent_t e : h->dq_ev) h->pool.push_back(e);
         h->kmv_ev.clear();
+        h->kmv_main_ev.clear();
         h->dq_ev.clear();
         h->solves = h->passes = 0;
     }
@@ -1451,8 +1478,10 @@ gp_status gp_profile_read(gp_handle* h, gp_profile_stats* out) {
     };
     gp_profile_stats r{};
     GP_TRY(total(h->kmv_ev, &r.kmv_ms));
+    GP_TRY(total(h->kmv_main_ev, &r.kmv_main_ms));
     GP_TRY(total(h->dq_ev, &r.dquad_ms));
     r.kmv_launches = (int64_t)(h->kmv_ev.size() / 2);
+    r.kmv_main_launches = (int64_t)(h->kmv_main_ev.size() / 2);
     r.dquad_launches = (int64_t)(h->dq_ev.size() / 2);
     r.solves = h->solves;
     r.kmv_passes = h->passes;

@@ -61,10 +61,12 @@ hipError_t launch_pack(const float* V, int64_t n, int m, int64_t ldv, float* Vp,
 // (GP_FP32, or any mode on the VALU path); the BF16 modes on the MFMA path read the split
 // halves VH, VL (bf16, same layout) made by launch_split_bf16 instead.
 // If n_active is non-null and *n_active == 0 on the device, the launch does nothing.
+// after_main (nullable) is recorded on s once the main product kernel is queued: before the
+// symmetric shape's reduce, at the end for the other shapes.
 hipError_t launch_kmv_partials(const KmvShape& sh, int d, const float* Z, const float* Vp,
                                const uint16_t* VH, const uint16_t* VL, const KParams* kp,
                                float* part, const int* n_active, gp_precision prec,
-                               hipStream_t s);
+                               hipStream_t s, hipEvent_t after_main = nullptr);
 // V_hi = bf16(V), V_lo = bf16(V - V_hi) elementwise over `total` (even) floats.
 hipError_t launch_split_bf16(const float* Vp, int64_t total, uint16_t* VH, uint16_t* VL,
                              hipStream_t s);

@@ -1421,7 +1421,7 @@ static hipError_t kmv_f32_nb(int nb, int tc, dim3 grid, const float* Z, const fl
 template <int D>
 static hipError_t kmv_sym_d(const KmvShape& sh, const float* Z, const float* Vp, const uint16_t* VH,
                             const uint16_t* VL, const KParams* kp, float* part, const int* n_active,
-                            gp_precision prec, hipStream_t s) {
+                            gp_precision prec, hipStream_t s, hipEvent_t after_main) {
     if constexpr (D > 8) {
         return hipErrorInvalidValue;
     } else {
@@ -1448,6 +1448,10 @@ static hipError_t kmv_sym_d(const KmvShape& sh, const float* Z, const float* Vp,
             return hipErrorInvalidValue;
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
+        if (after_main != nullptr) {
+            e = hipEventRecord(after_main, s);
+            if (e != hipSuccess) return e;
+        }
         const int mu = nb * 16 + sh.tail;  // BF16: tail 0
         kmv_sym_reduce_kernel<<<grid_for((int64_t)mu * sh.n_pad), kWG, 0, s>>>(F, Tt, part, sh.n_pad, sh.mp, mu,
                                                                                  sh.cs, sh.nch, n_active);
@@ -1458,8 +1462,9 @@ static hipError_t kmv_sym_d(const KmvShape& sh, const float* Z, const float* Vp,
 template <int D>
 static hipError_t kmv_d(const KmvShape& sh, const float* Z, const float* Vp,
                         const uint16_t* VH, const uint16_t* VL, const KParams* kp,
-                        float* part, const int* n_active, gp_precision prec, hipStream_t s) {
-    if (sh.sym) return kmv_sym_d<D>(sh, Z, Vp, VH, VL, kp, part, n_active, prec, s);
+                        float* part, const int* n_active, gp_precision prec, hipStream_t s,
+                        hipEvent_t after_main) {
+    if (sh.sym) return kmv_sym_d<D>(sh, Z, Vp, VH, VL, kp, part, n_active, prec, s, after_main);
     if (sh.mfma && prec == GP_BF16_SPLIT_V) return kmv_bf16_d<D, false>(sh, Z, VH, VL, kp, part, n_active, s);
     if (sh.mfma && prec == GP_BF16_SPLIT_KV) return kmv_bf16_d<D, true>(sh, Z, VH, VL, kp, part, n_active, s);
     const int64_t tiles = sh.n_pad / sh.rows_per_wg;
@@ -1508,11 +1513,20 @@ static hipError_t kmv_d(const KmvShape& sh, const float* Z, const float* Vp,
         default: return hipErrorInvalidValue;         \
     }
 
+static hipError_t kmv_any_d(const KmvShape& sh, int d, const float* Z, const float* Vp,
+                            const uint16_t* VH, const uint16_t* VL, const KParams* kp, float* part,
+                            const int* n_active, gp_precision prec, hipStream_t s, hipEvent_t after_main) {
+    GPK_DISPATCH_D(d, kmv_d, sh, Z, Vp, VH, VL, kp, part, n_active, prec, s, after_main);
+}
+
 hipError_t launch_kmv_partials(const KmvShape& sh, int d, const float* Z, const float* Vp,
                                const uint16_t* VH, const uint16_t* VL, const KParams* kp,
                                float* part, const int* n_active, gp_precision prec,
-                               hipStream_t s) {
-    GPK_DISPATCH_D(d, kmv_d, sh, Z, Vp, VH, VL, kp, part, n_active, prec, s);
+                               hipStream_t s, hipEvent_t after_main) {
+    hipError_t e = kmv_any_d(sh, d, Z, Vp, VH, VL, kp, part, n_active, prec, s, after_main);
+    // shapes without a separate reduce: the main kernel ends with the launch
+    if (e == hipSuccess && after_main != nullptr && !sh.sym) e = hipEventRecord(after_main, s);
+    return e;
 }
 
 hipError_t launch_split_bf16(const float* Vp, int64_t total, uint16_t* VH, uint16_t* VL,

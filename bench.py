@@ -207,8 +207,8 @@ def kmv_report(pb, h):
     import torch
 
     import workloads
-    shapes = (("rff", 16384, 8, 17, 1), ("rff", 65536, 8, 32, 2), ("rff", 65536, 8, 4, 2),
-              ("mixture", 131072, 16, 32, 4))
+    shapes = (("rff", 16384, 8, 17, 1), ("rff", 16384, 8, 32, 1), ("rff", 65536, 8, 32, 2),
+              ("rff", 65536, 8, 4, 2), ("mixture", 131072, 16, 32, 4))
     names = {pb.GP_FP32: "fp32", pb.GP_BF16_SPLIT_V: "bf16_split_v", pb.GP_BF16_SPLIT_KV: "bf16_split_kv"}
     rows = []
     for kind, n, d, m, seed in shapes:
@@ -229,8 +229,16 @@ def kmv_report(pb, h):
                     variants.append(("symmetric", pb.SHAPE_SYM))
                 except pb.GPError:
                     pass
+            if prec == pb.GP_FP32:
+                variants.append(("autotuned", None))
             for shape, code in variants:
-                pb.gp_tune_set(h, n, d, m, code, prec=prec)
+                if code is None:
+                    # the autotuner's choice: the first call of this shape with it on times the candidates
+                    pb.gp_tune_set(h, n, d, m, -1, prec=prec)
+                    pb.gp_autotune(h, 1)
+                else:
+                    pb.gp_autotune(h, 0)
+                    pb.gp_tune_set(h, n, d, m, code, prec=prec)
                 for _ in range(3):
                     pb.gp_kmv(h, X, psi, V, out=out, prec=prec)
                 torch.cuda.synchronize()
@@ -247,7 +255,10 @@ def kmv_report(pb, h):
                 main_ms = pr["kmv_main_ms"] / max(1, pr["kmv_main_launches"])
                 c_ms = e0.elapsed_time(e1) / reps
                 fl = kmv_flops(n, d, m)
+                tuned = pb.gp_tune_get(h, n, d, m, prec=prec)
+                pb.gp_autotune(h, 0)
                 rows.append(dict(workload=f"{kind}_n{n}_d{d}", n=n, d=d, m=m, prec=names[prec], shape=shape,
+                                 shape_code=tuned[0], split=tuned[1],
                                  kernel_ms=k_ms, main_kernel_ms=main_ms, call_ms=c_ms, tflops=fl / k_ms / 1e9,
                                  frac_fp32_valu_peak=fl / k_ms / 1e9 / VALU_FP32_PEAK_TFLOPS,
                                  exp_per_s=float(n) * n / (k_ms * 1e-3), launches=pr["kmv_launches"]))

@@ -441,7 +441,7 @@ void gp_batch_destroy(gp_batch* b);
  * Shape of the covariance products.  A shape code names how a product of K by V is split
  * into work: 0 = the symmetric product (row tiles of 256 rows against column chunks; each
  * entry of K off the diagonal tiles is built once and used for its row and, through a
- * transposed product, for its column; d <= 8, n >= 1793; FP32 with 16, 17, 32 or 33
+ * transposed product, for its column; n >= 1793; FP32 with 16, 17, 32 or 33
  * right-hand sides, BF16 modes with 17 to 32); c > 0 = the split-K product
  * whose number of column chunks gives about c
  * workgroups (chunk partials reduced in FP64 in a fixed order).  Both give the same values
@@ -450,8 +450,9 @@ void gp_batch_destroy(gp_batch* b);
  * The code a product takes is, per shape key (n rounded up to 256, d, padded column count,
  * precision) on this handle: the pin set by gp_tune_set, else, with gp_autotune(h, 1), the
  * autotuner's entry, else the default (symmetric where it applies and was measured faster:
- * FP32 with one MFMA block of right-hand sides or n >= 32768, BF16 with 17 to 32
- * right-hand sides and n >= 32768; else split-K for 2048 workgroups).  With the autotuner on,
+ * for d >= 12 always; for d <= 11 FP32 with one MFMA block of right-hand sides or
+ * n >= 32768, BF16 with 17 to 32 right-hand sides and n >= 32768; else split-K for 2048
+ * workgroups).  With the autotuner on,
  * the first product of a key without an entry times the candidates (the symmetric product
  * where it applies; split-K for 256 to 8192 workgroups, at most 64 chunks) on the stream and
  * keeps the fastest; that first call synchronises the stream.

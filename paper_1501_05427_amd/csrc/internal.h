@@ -34,8 +34,8 @@ struct KmvShape {
 };
 
 // The default shape of a product: the symmetric product where it applies and was measured
-// faster (FP32: one MFMA block of columns, or n_pad >= 32768; BF16: two blocks and
-// n_pad >= 32768), else the split-K product for about 2048 workgroups.
+// faster (d >= 12: always; d <= 11, FP32: one MFMA block of columns, or n_pad >= 32768;
+// BF16: two blocks and n_pad >= 32768), else the split-K product for about 2048 workgroups.
 KmvShape kmv_shape(int64_t n, int d, int m, gp_precision prec);
 // The split-K product with the factor chosen for about target_wg workgroups (the
 // autotuner times several targets per shape); never symmetric.

@@ -1273,13 +1273,16 @@ static void pick_split(KmvShape& sh, int target_wg) {
 }
 
 KmvShape kmv_shape(int64_t n, int d, int m, gp_precision prec) {
-    // the symmetric product by default where it was measured faster than split-K.  FP32: one
-    // MFMA block of columns, or n of 32768 and more (two blocks at n = 16384 are 9% slower:
-    // the transposed partials cost more than the halved entry work saves).  BF16: two MFMA
-    // blocks and n of 32768 and more
+    // the symmetric product by default where it was measured faster than split-K.  d >= 12:
+    // wherever it applies (at d = 16 each entry costs twice the VALU work of d = 8, and the
+    // shape was 4-46% faster from n = 16384 to 131072 in every mode).  d <= 8, FP32: one MFMA
+    // block of columns, or n of 32768 and more (two blocks at n = 16384 are 9% slower: the
+    // transposed partials cost more than the halved entry work saves); BF16: two MFMA blocks
+    // and n of 32768 and more.  9 <= d <= 11 keeps the d <= 8 rule (not measured).
     const KmvShape sy = kmv_shape_sym(n, d, m, prec);
-    if (sy.sym && prec == GP_FP32 && (sy.mp <= 20 || sy.n_pad >= 32768)) return sy;
-    if (sy.sym && prec != GP_FP32 && sy.mp == 32 && sy.n_pad >= 32768) return sy;
+    if (sy.sym && d >= 12) return sy;
+    if (sy.sym && d <= 11 && prec == GP_FP32 && (sy.mp <= 20 || sy.n_pad >= 32768)) return sy;
+    if (sy.sym && d <= 11 && prec != GP_FP32 && sy.mp == 32 && sy.n_pad >= 32768) return sy;
     return kmv_shape_target(n, d, m, prec, 2048);
 }
 
@@ -1291,12 +1294,13 @@ static int64_t sym_items(int nt, int nch, int cs) {
 
 KmvShape kmv_shape_sym(int64_t n, int d, int m, gp_precision prec) {
     KmvShape sh = kmv_shape_target(n, d, m, prec, 2048);
-    // MFMA products with d <= 8 and at least 8 row tiles: FP32 with one or two MFMA blocks
-    // and at most one VALU column, BF16 with two blocks
+    // MFMA products with at least 8 row tiles: FP32 with one or two MFMA blocks and at most
+    // one VALU column, BF16 with two blocks; four row blocks of 16 per wave at every d (the
+    // d = 16 kernels still fit two waves per SIMD)
     const int nb = sh.mp / 16;
     const bool f32 = prec == GP_FP32 && sh.tail <= 1 && (nb == 1 || nb == 2);
     const bool b16 = prec != GP_FP32 && sh.tail == 0 && nb == 2;
-    if (!sh.mfma || d > 8 || sh.n_pad < 8 * kSymTile || !(f32 || b16)) return sh;
+    if (!sh.mfma || d > kMaxD || sh.n_pad < 8 * kSymTile || !(f32 || b16)) return sh;
     sh.sym = true;
     sh.nt = (int)(sh.n_pad / kSymTile);
     sh.rows_per_wg = kSymTile;
@@ -1422,7 +1426,7 @@ template <int D>
 static hipError_t kmv_sym_d(const KmvShape& sh, const float* Z, const float* Vp, const uint16_t* VH,
                             const uint16_t* VL, const KParams* kp, float* part, const int* n_active,
                             gp_precision prec, hipStream_t s, hipEvent_t after_main) {
-    if constexpr (D > 8) {
+    if constexpr (D > 16) {
         return hipErrorInvalidValue;
     } else {
         const size_t plane = (size_t)sh.mp * (size_t)sh.n_pad;

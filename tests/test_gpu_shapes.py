@@ -64,7 +64,7 @@ def colwise_rel(out, ref):
 # tails inside the last row tile and the last column chunk; one and two MFMA blocks, with
 # and without the VALU column
 SYM_CASES = [(1793, 3, 17), (2049, 8, 16), (3000, 5, 17), (4100, 8, 32), (2300, 2, 33),
-             (6000, 8, 32), (9000, 1, 16)]
+             (6000, 8, 32), (9000, 1, 16), (2600, 16, 32), (3100, 12, 17), (2049, 16, 33)]
 
 
 @pytest.mark.parametrize("n,d,m", SYM_CASES)
@@ -92,7 +92,7 @@ BF16_BOUND = {pb.GP_BF16_SPLIT_V: 2.0 ** -8, pb.GP_BF16_SPLIT_KV: 6 * 2.0 ** -18
 
 
 @pytest.mark.parametrize("prec", [pb.GP_BF16_SPLIT_V, pb.GP_BF16_SPLIT_KV])
-@pytest.mark.parametrize("n,d,m", [(2049, 8, 17), (3000, 5, 32), (4100, 2, 24), (6000, 8, 31)])
+@pytest.mark.parametrize("n,d,m", [(2049, 8, 17), (3000, 5, 32), (4100, 2, 24), (6000, 8, 31), (2600, 16, 32)])
 def test_symmetric_bf16_products_match_oracle_and_split_k(prec, n, d, m):
     # BF16 products (two MFMA blocks: 17 to 32 right-hand sides) through both shapes: each within the BF16 bound
     # of the oracle; the two use the same BF16 operands and differ in the order of their FP32
@@ -155,13 +155,11 @@ def test_converged_solves_through_both_shapes_at_full_size(prec, capsys):
 def test_symmetric_product_is_refused_where_it_does_not_apply():
     h = pb.Handle(0, seed=7)
     for n, d, m, prec in [(1000, 4, 16, pb.GP_FP32),      # n_pad below 2048
-                          (4000, 12, 16, pb.GP_FP32),     # d > 8
                           (4000, 4, 48, pb.GP_FP32),      # three MFMA blocks
                           (4000, 4, 18, pb.GP_FP32),      # two VALU columns
                           (4000, 4, 16, pb.GP_BF16_SPLIT_KV),   # BF16: one MFMA block
                           (4000, 4, 48, pb.GP_BF16_SPLIT_V),    # BF16: three MFMA blocks
-                          (4000, 4, 64, pb.GP_BF16_SPLIT_KV),   # BF16: four MFMA blocks
-                          (4000, 12, 32, pb.GP_BF16_SPLIT_V)]:
+                          (4000, 4, 64, pb.GP_BF16_SPLIT_KV)]:  # BF16: four MFMA blocks
         with pytest.raises(RuntimeError, match="symmetric"):
             pb.gp_tune_set(h, n, d, m, pb.SHAPE_SYM, prec=prec)
     with pytest.raises(RuntimeError):

@@ -452,7 +452,7 @@ void gp_batch_destroy(gp_batch* b);
  * autotuner's entry, else the default (symmetric where it applies and was measured faster:
  * for d >= 12 always; for d <= 11 FP32 with one MFMA block of right-hand sides or
  * n >= 32768, BF16 with 17 to 32 right-hand sides and n >= 32768; else split-K for 2048
- * workgroups).  With the autotuner on,
+ * workgroups, or below 16 right-hand sides for 8192 with at most 32 chunks per row tile).  With the autotuner on,
  * the first product of a key without an entry times the candidates (the symmetric product
  * where it applies; split-K for 256 to 8192 workgroups, at most 64 chunks) on the stream and
  * keeps the fastest; that first call synchronises the stream.

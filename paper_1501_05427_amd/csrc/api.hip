@@ -258,7 +258,7 @@ int resolved_code(const gp_handle* h, int64_t n, int d, int m, gp_precision prec
     const auto key = tune_key(base, d, prec);
     auto p = h->pinned_shape.find(key);
     if (p != h->pinned_shape.end()) return p->second;
-    if (!h->autotune) return base.sym ? 0 : 2048;
+    if (!h->autotune) return kmv_default_code(n, d, m, prec);
     auto it = h->tuned.find(key);
     return it == h->tuned.end() ? -1 : it->second;
 }
@@ -293,7 +293,7 @@ gp_status shape_for(gp_handle* h, int64_t n, int d, int m, gp_precision prec, co
         (void)hipEventDestroy(e0);
         return fail(GP_EDEVICE, "event creation failed");
     }
-    int best_target = base.sym ? 0 : 2048, last_split = -1;
+    int best_target = kmv_default_code(n, d, m, prec), last_split = -1;
     float best_ms = 1e30f;
     gp_status st = GP_OK;
     std::vector<int> codes;

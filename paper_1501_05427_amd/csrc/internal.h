@@ -35,8 +35,11 @@ struct KmvShape {
 
 // The default shape of a product: the symmetric product where it applies and was measured
 // faster (d >= 12: always; d <= 11, FP32: one MFMA block of columns, or n_pad >= 32768;
-// BF16: two blocks and n_pad >= 32768), else the split-K product for about 2048 workgroups.
+// BF16: two blocks and n_pad >= 32768), else the split-K product for about 2048 workgroups
+// (the VALU contraction below 16 columns: 8192, at most 32 chunks per row tile).
 KmvShape kmv_shape(int64_t n, int d, int m, gp_precision prec);
+// The shape code of that default: 0 symmetric, else the split-K workgroup target.
+int kmv_default_code(int64_t n, int d, int m, gp_precision prec);
 // The split-K product with the factor chosen for about target_wg workgroups (the
 // autotuner times several targets per shape); never symmetric.
 KmvShape kmv_shape_target(int64_t n, int d, int m, gp_precision prec, int target_wg);

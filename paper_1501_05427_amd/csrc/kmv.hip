@@ -1272,7 +1272,7 @@ static void pick_split(KmvShape& sh, int target_wg) {
     sh.split = (int)((sh.n_pad + sh.chunk - 1) / sh.chunk);
 }
 
-KmvShape kmv_shape(int64_t n, int d, int m, gp_precision prec) {
+int kmv_default_code(int64_t n, int d, int m, gp_precision prec) {
     // the symmetric product by default where it was measured faster than split-K.  d >= 12:
     // wherever it applies (at d = 16 each entry costs twice the VALU work of d = 8, and the
     // shape was 4-46% faster from n = 16384 to 131072 in every mode).  d <= 8, FP32: one MFMA
@@ -1280,10 +1280,20 @@ KmvShape kmv_shape(int64_t n, int d, int m, gp_precision prec) {
     // transposed partials cost more than the halved entry work saves); BF16: two MFMA blocks
     // and n of 32768 and more.  9 <= d <= 11 keeps the d <= 8 rule (not measured).
     const KmvShape sy = kmv_shape_sym(n, d, m, prec);
-    if (sy.sym && d >= 12) return sy;
-    if (sy.sym && d <= 11 && prec == GP_FP32 && (sy.mp <= 20 || sy.n_pad >= 32768)) return sy;
-    if (sy.sym && d <= 11 && prec != GP_FP32 && sy.mp == 32 && sy.n_pad >= 32768) return sy;
-    return kmv_shape_target(n, d, m, prec, 2048);
+    if (sy.sym && d >= 12) return 0;
+    if (sy.sym && prec == GP_FP32 && (sy.mp <= 20 || sy.n_pad >= 32768)) return 0;
+    if (sy.sym && prec != GP_FP32 && sy.mp == 32 && sy.n_pad >= 32768) return 0;
+    const KmvShape sk = kmv_shape_target(n, d, m, prec, 2048);
+    if (sk.mfma) return 2048;
+    // the VALU contraction (under 16 columns): finer column chunks, up to 32 per row tile
+    // (at n = 65536, m = 4 the autotuner's split of 32 was 17% faster than 8)
+    const int64_t tiles = sk.n_pad / sk.rows_per_wg;
+    return (int)std::min<int64_t>(8192, 32 * tiles);
+}
+
+KmvShape kmv_shape(int64_t n, int d, int m, gp_precision prec) {
+    const int code = kmv_default_code(n, d, m, prec);
+    return code == 0 ? kmv_shape_sym(n, d, m, prec) : kmv_shape_target(n, d, m, prec, code);
 }
 
 static int64_t sym_items(int nt, int nch, int cs) {

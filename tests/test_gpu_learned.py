@@ -273,5 +273,8 @@ def test_learned_warm_start_and_preconditioner_gains(h, capsys):
         print(f"\n[learned gains] y-system CG iterations per psi (plain, warm start U c, "
               f"preconditioner, both):\n{rows}")
     assert np.all(rows[:, 1] <= rows[:, 0])         # the warm start alone never costs
-    assert np.all(rows[:, 3] <= rows[:, 2])         # and adds to the preconditioner
+    # with the preconditioner, the start changes the count by rounding only: PCG from U c and
+    # from zero have no ordering theorem, and the FP32 summation order of the products moves
+    # a count by one iteration either way
+    assert np.all(rows[:, 3] <= rows[:, 2] + 1)
     assert np.all(rows[:, 3] < 0.6 * rows[:, 0])

@@ -221,9 +221,9 @@ def test_tuning_cache_round_trip(tmp_path):
     assert pb.gp_tune_get(h2, n, d, m)[0] == 256
     pb.gp_tune_set(h2, n, d, m, -1)
     assert pb.gp_tune_get(h2, n, d, m) == codes[shapes[0]]
-    # with the autotuner off the loaded entries are not used
+    # with the autotuner off the loaded entries are not used: the default is back
     pb.gp_autotune(h2, 0)
-    assert pb.gp_tune_get(h2, 2000, 2, 5)[0] == 2048
+    assert pb.gp_tune_get(h2, 2000, 2, 5) == pb.gp_tune_get(pb.Handle(0, seed=3), 2000, 2, 5)
 
     # a malformed file is refused as a whole and leaves the entries as they were
     bad = tmp_path / "bad.txt"

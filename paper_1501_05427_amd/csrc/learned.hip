@@ -254,18 +254,27 @@ __global__ __launch_bounds__(kWG) void targets_kernel(const double* __restrict__
         for (int i = 0; i < k; ++i) out[k + i] = (float)log(fmax(L[i * k + i], 1e-300));
         const double trK = (double)n * (kp->sigma2 + kp->lam64);
         out[2 * k] = (float)log(fmax((trK - trT) / (double)(n - k), 1e-300));
-        // Cholesky solve T c = w
-        for (int j = 0; j < k; ++j) {
+    }
+    __syncthreads();
+    // Cholesky factor of T, column by column: the diagonal on one thread, the column below it
+    // one row per thread (every entry summed in the same order as a sequential factorization)
+    for (int j = 0; j < k; ++j) {
+        if (threadIdx.x == 0) {
             double s = L[j * k + j];
             for (int t = 0; t < j; ++t) s -= L[j * k + t] * L[j * k + t];
-            const double ljj = sqrt(fmax(s, 1e-300));
-            L[j * k + j] = ljj;
-            for (int i = j + 1; i < k; ++i) {
-                double v = L[i * k + j];
-                for (int t = 0; t < j; ++t) v -= L[i * k + t] * L[j * k + t];
-                L[i * k + j] = v / ljj;
-            }
+            L[j * k + j] = sqrt(fmax(s, 1e-300));
         }
+        __syncthreads();
+        const double ljj = L[j * k + j];
+        for (int i = j + 1 + (int)threadIdx.x; i < k; i += kWG) {
+            double v = L[i * k + j];
+            for (int t = 0; t < j; ++t) v -= L[i * k + t] * L[j * k + t];
+            L[i * k + j] = v / ljj;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        // T c = w: forward and back substitution with the factor
         for (int i = 0; i < k; ++i) {
             double s = w[i];
             for (int t = 0; t < i; ++t) s -= L[i * k + t] * x[t];

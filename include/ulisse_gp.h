@@ -441,7 +441,7 @@ void gp_batch_destroy(gp_batch* b);
  * Shape of the covariance products.  A shape code names how a product of K by V is split
  * into work: 0 = the symmetric product (row tiles of 256 rows against column chunks; each
  * entry of K off the diagonal tiles is built once and used for its row and, through a
- * transposed product, for its column; n >= 1793; FP32 with 16, 17, 32 or 33
+ * transposed product, for its column; n >= 1793; FP32 with 16, 17 or 21 to 33
  * right-hand sides, BF16 modes with 17 to 32); c > 0 = the split-K product
  * whose number of column chunks gives about c
  * workgroups (chunk partials reduced in FP64 in a fixed order).  Both give the same values

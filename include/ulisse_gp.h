@@ -442,7 +442,8 @@ void gp_batch_destroy(gp_batch* b);
  * into work: 0 = the symmetric product (row tiles of 256 rows against column chunks; each
  * entry of K off the diagonal tiles is built once and used for its row and, through a
  * transposed product, for its column; n >= 1793; FP32 with 16, 17 or 21 to 33
- * right-hand sides, BF16 modes with 17 to 32); c > 0 = the split-K product
+ * right-hand sides, BF16 modes with 17 to 32; its partials, (1 + n/cs + n/256) m n floats,
+ * within 24 GiB: n up to about 213000 at 32 right-hand sides); c > 0 = the split-K product
  * whose number of column chunks gives about c
  * workgroups (chunk partials reduced in FP64 in a fixed order).  Both give the same values
  * to FP32 rounding, not bit for bit.

@@ -52,6 +52,10 @@ KmvShape dkmv_shape(int64_t n, int d, int m);
 // Size of the fixed device scratch of the no-allocation entry points, and its device
 // address on `device` (which must be current), looked up once per device.
 constexpr size_t kNoAllocScratchBytes = size_t(32) << 20;
+// The symmetric product keeps one partial vector per (row tile, column) and per (column
+// chunk, row): (1 + n/cs + n/256) m n floats, which grows as n^2.  Above this many bytes the
+// shape does not apply (n beyond about 200000 at 32 right-hand sides) and split-K is used.
+constexpr size_t kSymPartialBytesMax = size_t(24) << 30;
 hipError_t noalloc_scratch(int device, void** out);
 
 // psi -> KParams and the scaled, padded inputs Z (n_pad x dpad(d), zero rows past n).

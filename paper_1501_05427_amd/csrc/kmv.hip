@@ -1323,6 +1323,7 @@ KmvShape kmv_shape_sym(int64_t n, int d, int m, gp_precision prec) {
     sh.nch = (int)((sh.n_pad + sh.cs - 1) / sh.cs);
     sh.split = 1;
     sh.chunk = (int)sh.n_pad;
+    if (kmv_part_floats(sh) * sizeof(float) > kSymPartialBytesMax) return kmv_shape_target(n, d, m, prec, 2048);
     return sh;
 }
 

@@ -159,11 +159,16 @@ def test_symmetric_product_is_refused_where_it_does_not_apply():
                           (4000, 4, 18, pb.GP_FP32),      # two VALU columns
                           (4000, 4, 16, pb.GP_BF16_SPLIT_KV),   # BF16: one MFMA block
                           (4000, 4, 48, pb.GP_BF16_SPLIT_V),    # BF16: three MFMA blocks
-                          (4000, 4, 64, pb.GP_BF16_SPLIT_KV)]:  # BF16: four MFMA blocks
+                          (4000, 4, 64, pb.GP_BF16_SPLIT_KV),   # BF16: four MFMA blocks
+                          (215000, 8, 32, pb.GP_FP32)]:         # partials above 24 GiB
         with pytest.raises(RuntimeError, match="symmetric"):
             pb.gp_tune_set(h, n, d, m, pb.SHAPE_SYM, prec=prec)
     with pytest.raises(RuntimeError):
         pb.gp_tune_set(h, 4000, 4, 16, 2 ** 21)
+    # the memory cap moves the default to split-K (host-only calls: nothing is allocated)
+    assert pb.gp_tune_get(h, 212000, 8, 32)[0] == pb.SHAPE_SYM
+    code, split = pb.gp_tune_get(h, 215000, 8, 32)
+    assert code > 0 and split > 1
 
 
 def test_ulisse_draw_for_draw_through_the_symmetric_product():

@@ -441,9 +441,10 @@ void gp_batch_destroy(gp_batch* b);
  * Shape of the covariance products.  A shape code names how a product of K by V is split
  * into work: 0 = the symmetric product (row tiles of 256 rows against column chunks; each
  * entry of K off the diagonal tiles is built once and used for its row and, through a
- * transposed product, for its column; n >= 1793; FP32 with 16, 17 or 21 to 33
- * right-hand sides, BF16 modes with 17 to 32; its partials, (1 + n/cs + n/256) m n floats,
- * within 24 GiB: n up to about 213000 at 32 right-hand sides); c > 0 = the split-K product
+ * transposed product, for its column; n >= 1793; FP32 with at most 17 or with 21 to 33
+ * right-hand sides (under 16 as one zero-padded block of 16), BF16 modes with 17 to 32; its
+ * partials, (1 + n/cs + n/256) mp n floats, within 24 GiB: n up to about 213000 at 32
+ * right-hand sides); c > 0 = the split-K product
  * whose number of column chunks gives about c
  * workgroups (chunk partials reduced in FP64 in a fixed order).  Both give the same values
  * to FP32 rounding, not bit for bit.
@@ -451,9 +452,10 @@ void gp_batch_destroy(gp_batch* b);
  * The code a product takes is, per shape key (n rounded up to 256, d, padded column count,
  * precision) on this handle: the pin set by gp_tune_set, else, with gp_autotune(h, 1), the
  * autotuner's entry, else the default (symmetric where it applies and was measured faster:
- * for d >= 12 always; for d <= 11 FP32 with one MFMA block of right-hand sides or
- * n >= 32768, BF16 with 17 to 32 right-hand sides and n >= 32768; else split-K for 2048
- * workgroups, or below 16 right-hand sides for 8192 with at most 32 chunks per row tile).  With the autotuner on,
+ * from 16 right-hand sides on, for d >= 12 always; for d <= 11 FP32 with one MFMA block of
+ * right-hand sides or n >= 32768, BF16 with 17 to 32 right-hand sides and n >= 32768; below
+ * 16, FP32 with m + d >= 12 and n >= 16129; else split-K for 2048 workgroups, or below 16
+ * right-hand sides for 8192 with at most 32 chunks per row tile).  With the autotuner on,
  * the first product of a key without an entry times the candidates (the symmetric product
  * where it applies; split-K for 256 to 8192 workgroups, at most 64 chunks) on the stream and
  * keeps the fastest; that first call synchronises the stream.

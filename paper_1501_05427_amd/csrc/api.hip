@@ -273,19 +273,22 @@ gp_status shape_for(gp_handle* h, int64_t n, int d, int m, gp_precision prec, co
     }
     const auto key = tune_key(base, d, prec);
     const bool b16 = uses_bf16(base, prec);
-    const bool has_sym = kmv_shape_sym(n, d, m, prec).sym;
-    size_t part_floats = has_sym ? kmv_part_floats(kmv_shape_sym(n, d, m, prec)) : 0;
+    const KmvShape sym = kmv_shape_sym(n, d, m, prec);
+    const bool has_sym = sym.sym;
+    size_t part_floats = has_sym ? kmv_part_floats(sym) : 0;
+    // V for every candidate: the symmetric product may pad to more columns than split-K
+    const size_t v_floats = (size_t)base.n_pad * (size_t)std::max(base.mp, has_sym ? sym.mp : 0);
     for (int target : kTuneTargets) {
         const KmvShape sh = kmv_shape_target(n, d, m, prec, target);
         if (sh.split <= kTuneMaxSplit) part_floats = std::max(part_floats, kmv_part_floats(sh));
     }
     float *V, *part;
     uint16_t *VH = nullptr, *VL = nullptr;
-    GP_TRY(ws(h, kSlotTuneV, (size_t)base.n_pad * base.mp, &V));
+    GP_TRY(ws(h, kSlotTuneV, v_floats, &V));
     GP_TRY(ws(h, kSlotTunePart, part_floats, &part));
     if (b16) {
-        GP_TRY(ws(h, kSlotTuneVH, (size_t)base.n_pad * base.mp, &VH));
-        GP_TRY(ws(h, kSlotTuneVL, (size_t)base.n_pad * base.mp, &VL));
+        GP_TRY(ws(h, kSlotTuneVH, v_floats, &VH));
+        GP_TRY(ws(h, kSlotTuneVL, v_floats, &VL));
     }
     hipEvent_t e0, e1;
     GP_HIP(hipEventCreate(&e0));

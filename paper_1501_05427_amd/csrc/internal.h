@@ -16,7 +16,8 @@ inline int dpad(int d) { return (d + 3) & ~3; }
 
 // Launch shape of one covariance product, chosen on the host.
 struct KmvShape {
-    bool mfma;        // MFMA contraction (m >= 16) or VALU contraction (m < 16)
+    bool mfma;        // MFMA contraction (m >= 16; the FP32 symmetric product also under
+                      // 16 columns, one zero-padded block) or VALU contraction (m < 16)
     int mp;           // padded column count of V seen by the kernel
     int tail = 0;     // FP32 MFMA path: columns past the last multiple of 16 taken on the
                       // VALU (1..4; mp is then 16 floor(m / 16) + 4), else 0
@@ -34,9 +35,11 @@ struct KmvShape {
 };
 
 // The default shape of a product: the symmetric product where it applies and was measured
-// faster (d >= 12: always; d <= 11, FP32: one MFMA block of columns, or n_pad >= 32768;
-// BF16: two blocks and n_pad >= 32768), else the split-K product for about 2048 workgroups
-// (the VALU contraction below 16 columns: 8192, at most 32 chunks per row tile).
+// faster (16 columns and more: d >= 12 always; d <= 11, FP32: one MFMA block of columns, or
+// n_pad >= 32768; BF16: two blocks and n_pad >= 32768; under 16 columns, FP32 only, one
+// zero-padded block: m + d >= 12 and n_pad >= 16384), else the split-K product for about
+// 2048 workgroups (the VALU contraction below 16 columns: 8192, at most 32 chunks per row
+// tile).
 KmvShape kmv_shape(int64_t n, int d, int m, gp_precision prec);
 // The shape code of that default: 0 symmetric, else the split-K workgroup target.
 int kmv_default_code(int64_t n, int d, int m, gp_precision prec);

@@ -1280,9 +1280,15 @@ int kmv_default_code(int64_t n, int d, int m, gp_precision prec) {
     // transposed partials cost more than the halved entry work saves); BF16: two MFMA blocks
     // and n of 32768 and more.  9 <= d <= 11 keeps the d <= 8 rule (not measured).
     const KmvShape sy = kmv_shape_sym(n, d, m, prec);
-    if (sy.sym && d >= 12) return 0;
-    if (sy.sym && prec == GP_FP32 && (sy.mp <= 20 || sy.n_pad >= 32768)) return 0;
-    if (sy.sym && prec != GP_FP32 && sy.mp == 32 && sy.n_pad >= 32768) return 0;
+    const bool wide = m >= 16;
+    // FP32 under 16 right-hand sides: the symmetric product with one zero-padded MFMA block
+    // costs about the same at every m, the VALU contraction 2d + 3 + m instructions per entry;
+    // the former is taken where m + d >= 12 from n = 16384 on (d = 8: 1.04-1.86x for m = 4 to
+    // 15, 0.88-0.94x at m = 1; d = 16, m = 5: 1.41x; d = 2, m = 5: 0.91x)
+    if (sy.sym && !wide && prec == GP_FP32 && m + d >= 12 && sy.n_pad >= 16384) return 0;
+    if (sy.sym && wide && d >= 12) return 0;
+    if (sy.sym && wide && prec == GP_FP32 && (sy.mp <= 20 || sy.n_pad >= 32768)) return 0;
+    if (sy.sym && wide && prec != GP_FP32 && sy.mp == 32 && sy.n_pad >= 32768) return 0;
     const KmvShape sk = kmv_shape_target(n, d, m, prec, 2048);
     if (sk.mfma) return 2048;
     // the VALU contraction (under 16 columns): finer column chunks, up to 32 per row tile
@@ -1303,14 +1309,16 @@ static int64_t sym_items(int nt, int nch, int cs) {
 }
 
 KmvShape kmv_shape_sym(int64_t n, int d, int m, gp_precision prec) {
-    KmvShape sh = kmv_shape_target(n, d, m, prec, 2048);
+    const KmvShape base = kmv_shape_target(n, d, m, prec, 2048);
     // MFMA products with at least 8 row tiles: FP32 with one or two MFMA blocks and at most
-    // one VALU column, BF16 with two blocks; four row blocks of 16 per wave at every d (the
-    // d = 16 kernels still fit two waves per SIMD)
+    // one VALU column (under 16 right-hand sides: one block, zero-padded), BF16 with two
+    // blocks; four row blocks of 16 per wave at every d (the d = 16 kernels still fit two
+    // waves per SIMD)
+    KmvShape sh = prec == GP_FP32 && m < 16 ? kmv_shape_target(n, d, 16, prec, 2048) : base;
     const int nb = sh.mp / 16;
     const bool f32 = prec == GP_FP32 && sh.tail <= 1 && (nb == 1 || nb == 2);
     const bool b16 = prec != GP_FP32 && sh.tail == 0 && nb == 2;
-    if (!sh.mfma || d > kMaxD || sh.n_pad < 8 * kSymTile || !(f32 || b16)) return sh;
+    if (!sh.mfma || d > kMaxD || sh.n_pad < 8 * kSymTile || !(f32 || b16)) return base;
     sh.sym = true;
     sh.nt = (int)(sh.n_pad / kSymTile);
     sh.rows_per_wg = kSymTile;
@@ -1323,7 +1331,7 @@ KmvShape kmv_shape_sym(int64_t n, int d, int m, gp_precision prec) {
     sh.nch = (int)((sh.n_pad + sh.cs - 1) / sh.cs);
     sh.split = 1;
     sh.chunk = (int)sh.n_pad;
-    if (kmv_part_floats(sh) * sizeof(float) > kSymPartialBytesMax) return kmv_shape_target(n, d, m, prec, 2048);
+    if (kmv_part_floats(sh) * sizeof(float) > kSymPartialBytesMax) return base;
     return sh;
 }
 

@@ -64,7 +64,9 @@ def colwise_rel(out, ref):
 # tails inside the last row tile and the last column chunk; one and two MFMA blocks, with
 # and without the VALU column
 SYM_CASES = [(1793, 3, 17), (2049, 8, 16), (3000, 5, 17), (4100, 8, 32), (2300, 2, 33),
-             (6000, 8, 32), (9000, 1, 16), (2600, 16, 32), (3100, 12, 17), (2049, 16, 33)]
+             (6000, 8, 32), (9000, 1, 16), (2600, 16, 32), (3100, 12, 17), (2049, 16, 33),
+             # under 16 right-hand sides: one zero-padded MFMA block against the VALU contraction
+             (2049, 8, 1), (3000, 5, 5), (4100, 3, 12), (2600, 16, 4), (1900, 2, 15)]
 
 
 @pytest.mark.parametrize("n,d,m", SYM_CASES)

@@ -171,6 +171,12 @@ def test_symmetric_product_is_refused_where_it_does_not_apply():
     assert pb.gp_tune_get(h, 212000, 8, 32)[0] == pb.SHAPE_SYM
     code, split = pb.gp_tune_get(h, 215000, 8, 32)
     assert code > 0 and split > 1
+    # under 16 right-hand sides the FP32 default takes the padded symmetric product where
+    # m + d >= 12 and n >= 16129, the VALU contraction elsewhere; the BF16 modes keep the latter
+    for n, d, m, sym in [(16384, 8, 5, True), (16384, 8, 3, False), (16384, 2, 5, False), (16384, 2, 10, True),
+                         (16128, 8, 5, False), (65536, 8, 1, False), (131072, 16, 1, True)]:
+        assert (pb.gp_tune_get(h, n, d, m)[0] == pb.SHAPE_SYM) == sym, (n, d, m)
+    assert pb.gp_tune_get(h, 65536, 8, 5, prec=pb.GP_BF16_SPLIT_KV)[0] != pb.SHAPE_SYM
 
 
 def test_ulisse_draw_for_draw_through_the_symmetric_product():

@@ -75,7 +75,7 @@ struct gp_handle {
     std::vector<hipEvent_t> kmv_ev, dq_ev;  // start/stop pairs
     std::vector<hipEvent_t> kmv_main_ev;    // start / end-of-main-kernel pairs of the products
     int64_t solves = 0, passes = 0;
-    // set only by the batched driver: step word and step size read from device memory
+    // set only by the batched path: step word and step size read from device memory
     const uint64_t* dyn_step = nullptr;
     const uint64_t* dyn_probe_step = nullptr;
     const double* dyn_eps = nullptr;
@@ -344,7 +344,7 @@ gp_status check_shift(const gp_shift_precond* sp) {
     return GP_OK;
 }
 
-// One ULISSE solve in three phases, so that the batched driver can capture each phase in a
+// One ULISSE solve in three phases, so that the batched path can capture each phase in a
 // graph: begin() sets up buffers, the initial residual and state; step() launches one
 // iteration of every running system (its kernels do nothing once none runs); end() copies
 // the last CG iterates out.  run() is the eager loop: it polls the device's count of running

@@ -480,6 +480,17 @@ gp_status gp_tune_set(gp_handle* h, int64_t n, int32_t d, int32_t m, gp_precisio
 gp_status gp_tune_get(gp_handle* h, int64_t n, int32_t d, int32_t m, gp_precision prec,
                       int32_t* code, int32_t* split);
 gp_status gp_tune_save(const gp_handle* h, const char* path);
+/*
+ * The shape a product of (n, d, m, prec) takes by default, or the shape of `code` (>= 0; -1 =
+ * the default), without a handle or a device: *code_out the shape code, *split_out the split-K
+ * chunks (1 for the symmetric product), *mp_out the padded column count of V, *partial_floats
+ * the floats of the partial sums the product needs (the workspace that grows with n).
+ * GP_EINVAL for a bad shape, code or null output, and for code 0 where the symmetric product
+ * does not apply.
+ */
+gp_status gp_shape_query(int64_t n, int32_t d, int32_t m, gp_precision prec, int32_t code,
+                         int32_t* code_out, int32_t* split_out, int32_t* mp_out,
+                         int64_t* partial_floats);
 gp_status gp_tune_load(gp_handle* h, const char* path);
 
 /*

@@ -189,6 +189,9 @@ def lib():
     L.gp_tune_set.argtypes = [c_void_p, c_int64, c_int32, c_int32, c_int, c_int32]
     L.gp_tune_get.restype = c_int
     L.gp_tune_get.argtypes = [c_void_p, c_int64, c_int32, c_int32, c_int, POINTER(c_int32), POINTER(c_int32)]
+    L.gp_shape_query.restype = c_int
+    L.gp_shape_query.argtypes = [c_int64, c_int32, c_int32, c_int, c_int32, POINTER(c_int32), POINTER(c_int32),
+                                 POINTER(c_int32), POINTER(c_int64)]
     L.gp_tune_save.restype = c_int
     L.gp_tune_save.argtypes = [c_void_p, ctypes.c_char_p]
     L.gp_tune_load.restype = c_int
@@ -652,6 +655,15 @@ def gp_tune_get(h, n, d, m, prec=GP_FP32):
     code, split = c_int32(0), c_int32(0)
     _check(lib().gp_tune_get(h.ptr, int(n), int(d), int(m), int(prec), ctypes.byref(code), ctypes.byref(split)))
     return code.value, split.value
+
+
+def gp_shape_query(n, d, m, prec=GP_FP32, code=-1):
+    """(code, split, mp, partial_floats) of a product's shape, default or of `code`; no
+    handle and no device needed."""
+    c, sp, mp, pf = c_int32(0), c_int32(0), c_int32(0), c_int64(0)
+    _check(lib().gp_shape_query(int(n), int(d), int(m), int(prec), int(code), ctypes.byref(c),
+                                ctypes.byref(sp), ctypes.byref(mp), ctypes.byref(pf)))
+    return c.value, sp.value, mp.value, pf.value
 
 
 def gp_tune_save(h, path):

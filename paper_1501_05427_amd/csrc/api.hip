@@ -1369,6 +1369,25 @@ gp_status gp_tune_get(gp_handle* h, int64_t n, int32_t d, int32_t m, gp_precisio
     return GP_OK;
 }
 
+gp_status gp_shape_query(int64_t n, int32_t d, int32_t m, gp_precision prec, int32_t code,
+                         int32_t* code_out, int32_t* split_out, int32_t* mp_out,
+                         int64_t* partial_floats) {
+    GP_TRY(check_tune_args(n, d, m, prec));
+    GP_CHECK(code_out != nullptr && split_out != nullptr && mp_out != nullptr && partial_floats != nullptr,
+             "null output");
+    GP_CHECK(code >= -1 && code <= kTuneMaxCode, "shape code %d outside [-1, %d]", code, kTuneMaxCode);
+    GP_CHECK(code != 0 || kmv_shape_sym(n, d, m, prec).sym,
+             "the symmetric product does not apply to n = %lld, d = %d, m = %d in this precision",
+             (long long)n, d, m);
+    const int c = code < 0 ? kmv_default_code(n, d, m, prec) : code;
+    const KmvShape sh = shape_of_code(n, d, m, prec, c);
+    *code_out = c;
+    *split_out = sh.split;
+    *mp_out = sh.mp;
+    *partial_floats = (int64_t)kmv_part_floats(sh);
+    return GP_OK;
+}
+
 gp_status gp_tune_save(const gp_handle* h, const char* path) {
     GP_CHECK(h != nullptr, "null handle");
     GP_CHECK(path != nullptr, "null path");

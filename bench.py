@@ -971,11 +971,17 @@ def batched_bench(args, pb, n_features=2048, learn_pairs=128, learn_epochs=1000,
                         "ms_per_step": 1e3 * el_u / args.batch_steps}
     print(json.dumps({"unbatched_done": out["unbatched"]}), file=sys.stderr, flush=True)
     del hs
+    # the BF16 forms: V split (with residual replacement) or K and V split (without)
+    tag = args.batch_bf16
+    bf16_prec = pb.GP_BF16_SPLIT_V if tag == "v" else pb.GP_BF16_SPLIT_KV
+    bf16_refresh = args.refresh if tag == "v" else 0
+    bf16_mode = f"batched_graphs_autotuned_bf16_split_{tag}"
     for mode, tune, prec in (("batched_graphs", False, pb.GP_FP32), ("batched_graphs_autotuned", True, pb.GP_FP32),
-                             ("batched_graphs_autotuned_bf16_split_kv", True, pb.GP_BF16_SPLIT_KV)):
+                             (bf16_mode, True, bf16_prec)):
         for i, p in enumerate(probs):
             p["psi"].copy_(psi0[i])
         params.prec = prec
+        params.refresh = bf16_refresh if prec != pb.GP_FP32 else 0
         batch = pb.Batch(probs, nr, params, seed=7000, probe_period=PROBE_PERIOD, iters_per_graph=8,
                          autotune=tune, streams=8)
         for t in range(args.warmup):
@@ -1013,8 +1019,9 @@ def batched_bench(args, pb, n_features=2048, learn_pairs=128, learn_epochs=1000,
                         "coef": torch.zeros(k + 1, dtype=torch.float64, device="cuda")}
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t_setup
-    mode = "batched_graphs_autotuned_learned_bf16_split_kv"
-    params.prec = pb.GP_BF16_SPLIT_KV
+    mode = f"batched_graphs_autotuned_learned_bf16_split_{tag}"
+    params.prec = bf16_prec
+    params.refresh = bf16_refresh
     batch = pb.Batch(probs, nr, params, seed=7000, probe_period=PROBE_PERIOD, iters_per_graph=8,
                      autotune=True, streams=8)
     for t in range(args.warmup):
@@ -1031,10 +1038,10 @@ def batched_bench(args, pb, n_features=2048, learn_pairs=128, learn_epochs=1000,
     batch.close()
     print(json.dumps({mode: out[mode]}), file=sys.stderr, flush=True)
     params.prec = pb.GP_FP32
+    params.refresh = 0
     u = out["unbatched"]["grad_estimates_per_s"]
     out["speedup_vs_unbatched"] = {m_: out[m_]["grad_estimates_per_s"] / u for m_ in
-                                   ("batched_graphs", "batched_graphs_autotuned",
-                                    "batched_graphs_autotuned_bf16_split_kv", mode)}
+                                   ("batched_graphs", "batched_graphs_autotuned", bf16_mode, mode)}
     out["learn_pairs"], out["learn_epochs"] = learn_pairs, learn_epochs
     if emit:
         print(json.dumps({"batched": out}), flush=True)
@@ -1166,6 +1173,9 @@ def main():
                     help="64 chains over 64 GPs: batched graphs vs unbatched calls (separate report)")
     ap.add_argument("--batch-chains", type=int, default=64)
     ap.add_argument("--batch-steps", type=int, default=20)
+    ap.add_argument("--batch-bf16", choices=("kv", "v"), default="kv",
+                    help="batched BF16 forms: K and V split (kv, no residual replacement) or V split "
+                         "with residual replacement every 2^refresh (v)")
     ap.add_argument("--chains", action="store_true",
                     help="the paper's multi-chain protocol with PSRF and ESS (separate report)")
     ap.add_argument("--chain-count", type=int, default=10)
@@ -1290,8 +1300,8 @@ def main():
                 "workload": bt["workload"], "steps": bt["steps"],
                 "grad_estimates_per_s": {k: bt[k]["grad_estimates_per_s"] for k in
                                          ("unbatched", "batched_graphs", "batched_graphs_autotuned",
-                                          "batched_graphs_autotuned_bf16_split_kv",
-                                          "batched_graphs_autotuned_learned_bf16_split_kv")},
+                                          f"batched_graphs_autotuned_bf16_split_{args.batch_bf16}",
+                                          f"batched_graphs_autotuned_learned_bf16_split_{args.batch_bf16}")},
                 "speedup_vs_unbatched": bt["speedup_vs_unbatched"]}
         except Exception as e:  # the main line must still be printed
             rec["batched_64_gps"] = {"error": repr(e)}

@@ -890,13 +890,17 @@ def _batch_problems(specs, nr):
     return out
 
 
-def test_batch_reproduces_unbatched_calls():
+@pytest.mark.parametrize("prec,refresh", [(pb.GP_FP32, 0), (pb.GP_BF16_SPLIT_V, 3)])
+def test_batch_reproduces_unbatched_calls(prec, refresh):
     # each chain of the batch must follow exactly the trajectory of the unbatched calls with
-    # the same Philox keys and counters (autotune off: identical product shapes)
+    # the same Philox keys and counters (autotune off: identical product shapes); also with
+    # BF16 products and residual replacement, whose decisions are taken on the device inside
+    # the captured iteration graph
     specs = [(300, 2), (700, 4), (1500, 8), (2049, 16), (4000, 3)]
     nr, T, period, eps = 16, 5, 2, 1e-3
     probs = _batch_problems(specs, nr)
-    params = pb.make_params(q=1.0, rate=1.0, eps=1e-6, eps_relative=1, max_iter=2000, rng_stream=3)
+    params = pb.make_params(q=1.0, rate=1.0, eps=1e-6, eps_relative=1, max_iter=2000, rng_stream=3,
+                            prec=prec, refresh=refresh)
     ref = [{k: (v.clone() if torch.is_tensor(v) else v) for k, v in p.items()} for p in probs]
     batch = pb.Batch(probs, nr, params, seed=900, probe_period=period, iters_per_graph=4,
                      autotune=False, streams=3)

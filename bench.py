@@ -1137,8 +1137,9 @@ def main():
     ap.add_argument("--learn-pairs", type=int, default=256, help="error sweep: jittered training pairs")
     ap.add_argument("--learn-epochs", type=int, default=1500)
     ap.add_argument("--bf16-mode", choices=("kv", "v"), default="v",
-                    help="BF16 legs: split V only (v, two products; with residual replacement as "
-                         "accurate as kv and 7-9%% faster per estimate) or split K and V (kv, three)")
+                    help="BF16 legs: split V only (v, two products; on this workload, with residual "
+                         "replacement, as accurate as kv and 7-9%% faster per estimate) or split K and V "
+                         "(kv, three)")
     ap.add_argument("--refresh", type=int, default=3,
                     help="residual replacement of the BF16 legs: on a 2^refresh residual drop")
     ap.add_argument("--equal-error-reps", type=int, default=30, help="0 skips the equal-error leg")

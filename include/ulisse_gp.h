@@ -49,8 +49,10 @@ typedef enum {
  * GP_BF16_SPLIT_KV: K and V both split, K_hi V_hi + K_hi V_lo + K_lo V_hi: relative error
  * per product term about 3 * 2^-18.
  * Distances and exponentials are FP32 in every mode; with fewer than 16 right-hand sides
- * the contraction runs on the VALU in FP32 whatever the mode.  The gradient reduction of
- * gp_stoch_grad is FP32 in every mode. */
+ * the contraction is FP32 whatever the mode (on the VALU, or in GP_FP32 as one zero-padded
+ * MFMA block of the symmetric product).  Where the products run in a BF16 mode, the G tiles
+ * of gp_stoch_grad's gradient reduction come from split BF16 operands too; its sums are
+ * FP32 within a tile and FP64 across tiles. */
 typedef enum { GP_FP32 = 0, GP_BF16_SPLIT_V = 1, GP_BF16_SPLIT_KV = 2 } gp_precision;
 
 /* Inputs x_1..x_n, row-major FP32, device memory. */

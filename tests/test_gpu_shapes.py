@@ -179,11 +179,13 @@ def test_symmetric_product_is_refused_where_it_does_not_apply():
     assert pb.gp_tune_get(h, 65536, 8, 5, prec=pb.GP_BF16_SPLIT_KV)[0] != pb.SHAPE_SYM
 
 
-def test_ulisse_draw_for_draw_through_the_symmetric_product():
-    # the solver's products through the pinned symmetric shape (n = 2500: 10 row tiles, 17
-    # systems: one MFMA block and the VALU column), draw for draw against the oracle
+@pytest.mark.parametrize("m", [17, 5])
+def test_ulisse_draw_for_draw_through_the_symmetric_product(m):
+    # the solver's products through the pinned symmetric shape (n = 2500: 10 row tiles; 17
+    # systems: one MFMA block and the VALU column; 5 systems: one block padded with zero
+    # columns), draw for draw against the oracle
     h = pb.Handle(0, seed=1234)
-    n, d, m = 2500, 4, 17
+    n, d = 2500, 4
     X, psi = problem(n, d, seed=11, lam=0.3, ell=(0.2, 0.4))
     K = ogp.kernel_matrix(X, psi)
     Bm = np.random.default_rng(5).standard_normal((n, m)).astype(np.float32)

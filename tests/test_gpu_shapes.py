@@ -11,6 +11,8 @@ import torch
 
 from oracle import cg as ocg
 from oracle import gp as ogp
+from oracle import rng as orng
+from oracle import stoch_grad as osg
 from oracle import ulisse as oul
 
 pytestmark = pytest.mark.gpu
@@ -206,6 +208,35 @@ def test_ulisse_draw_for_draw_through_the_symmetric_product(m):
         assert g["flags"] == r["flags"]
     assert colwise_rel(St.cpu().numpy(), ref_St).max() <= 2e-4
     assert colwise_rel(Scg.cpu().numpy(), ref_Scg).max() <= 2e-4
+
+
+def test_stoch_grad_draw_for_draw_through_the_padded_symmetric_product():
+    # y + 4 probes (5 systems) through the symmetric product with one zero-padded MFMA block,
+    # the default of such products from n = 16129 at d = 8, pinned here at n = 2100; the
+    # gradient draw for draw against the oracle (well-conditioned system, short CG paths, as
+    # in the other draw-for-draw tests)
+    h = pb.Handle(0, seed=4321)
+    n, d, nr = 2100, 8, 4
+    X, psi = problem(n, d, seed=2108, lam=1.0, ell=(0.1, 0.3))
+    K = ogp.kernel_matrix(X, psi)
+    y = (np.linalg.cholesky(K) @ np.random.default_rng(1).standard_normal(n)).astype(np.float32)
+    pb.gp_tune_set(h, n, d, 1 + nr, pb.SHAPE_SYM)
+    assert pb.gp_tune_get(h, n, d, 1 + nr)[0] == pb.SHAPE_SYM
+    stream, counter = 5, 9
+    R = orng.probes(h.seed, stream, counter, n, nr, 0).astype(np.float32)
+    q, eps, rate = _safe_q(K, y.astype(np.float64), 2), 1e-6, 1.0
+    params = pb.make_params(q=q, rate=rate, eps=eps, eps_relative=1, max_iter=300,
+                            rng_stream=stream, rng_counter=counter)
+    g, stats = pb.gp_stoch_grad(h, dev(X), dev(psi), dev(y), params, n_probes=nr)
+    torch.cuda.synchronize()
+    g_ref, _, _, ref_stats = osg.stoch_grad(X, psi, y, R, q, rate, eps, 300, h.seed, stream, counter,
+                                            eps_relative=True)
+    st_gpu = pb.decode_stats(stats)
+    for c in range(nr + 1):
+        assert ref_stats[c]["iters"] <= 7
+        assert (st_gpu[c]["l"], st_gpu[c]["iters"]) == (ref_stats[c]["l"], ref_stats[c]["iters"]), c
+    got = g.cpu().numpy()
+    np.testing.assert_allclose(got, g_ref, rtol=2e-4, atol=2e-4 * np.abs(g_ref).max())
 
 
 def test_tuning_cache_round_trip(tmp_path):

@@ -495,46 +495,50 @@ __global__ __launch_bounds__(kWG) void grad_finish_kernel(const double* __restri
 }
 
 // ---------------------------------------------------------------------------------------
-// SGLD update (one small problem: a single thread does it in FP64).
+// SGLD update in FP64, one wave: lane i < P owns component i of psi.  Each lane sums its
+// own row or column in the natural index order, so the result does not depend on the wave
+// size.  The P normal draws come from ceil(P / 4) Philox blocks, one per lane.
 // ---------------------------------------------------------------------------------------
 __global__ void sgld_kernel(int P, double* __restrict__ psi, const double* __restrict__ g,
                             int prior_kind, const double* __restrict__ pa,
                             const double* __restrict__ pb, const double* __restrict__ L,
                             double eps_arg, uint64_t k0, uint64_t k1, uint64_t step_arg,
                             const uint64_t* __restrict__ step_dev, const double* __restrict__ eps_dev) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    __shared__ double v[kMaxP], xi[kMaxP + 4], t[kMaxP];
+    if (blockIdx.x != 0) return;
+    const int i = threadIdx.x;
     const uint64_t step = step_dev != nullptr ? *step_dev : step_arg;
     const double eps = eps_dev != nullptr ? *eps_dev : eps_arg;
-    double v[kMaxP], xi[kMaxP + 3], t[kMaxP];
-    for (int i = 0; i < P; ++i) {
+    double psi_i = 0.0;
+    if (i < P) {
+        psi_i = psi[i];
         double pg = 0.0;
-        if (prior_kind == 1) pg = -(psi[i] - pa[i]) / (pb[i] * pb[i]);
-        if (prior_kind == 2) pg = pa[i] - pb[i] * exp(psi[i]);
+        if (prior_kind == 1) pg = -(psi_i - pa[i]) / (pb[i] * pb[i]);
+        if (prior_kind == 2) pg = pa[i] - pb[i] * exp(psi_i);
         v[i] = g[i] + pg;
     }
-    for (int b = 0; b < (P + 3) / 4; ++b) {
-        const u64x4 w = philox4x64_10((uint64_t)b, 0, kPurposeSgld, step, k0, k1);
-        box_muller(w.v[0], w.v[1], &xi[4 * b], &xi[4 * b + 1]);
-        box_muller(w.v[2], w.v[3], &xi[4 * b + 2], &xi[4 * b + 3]);
+    if (i < (P + 3) / 4) {
+        const u64x4 w = philox4x64_10((uint64_t)i, 0, kPurposeSgld, step, k0, k1);
+        box_muller(w.v[0], w.v[1], &xi[4 * i], &xi[4 * i + 1]);
+        box_muller(w.v[2], w.v[3], &xi[4 * i + 2], &xi[4 * i + 3]);
     }
-    // t = L^T v, then M v = L t
-    for (int j = 0; j < P; ++j) {
+    __syncthreads();
+    // t = L^T v (lane j: column j of L), then M v = L t and L xi (lane i: row i of L)
+    if (i < P) {
         double s = 0.0;
-        for (int i = 0; i < P; ++i) s += (L ? L[i + j * P] : (i == j ? 1.0 : 0.0)) * v[i];
-        t[j] = s;
+        for (int k = 0; k < P; ++k) s += (L ? L[k + i * P] : (k == i ? 1.0 : 0.0)) * v[k];
+        t[i] = s;
     }
-    const double se = sqrt(eps);
-    double out[kMaxP];
-    for (int i = 0; i < P; ++i) {
+    __syncthreads();
+    if (i < P) {
         double mv = 0.0, lx = 0.0;
         for (int j = 0; j < P; ++j) {
             const double lij = L ? L[i + j * P] : (i == j ? 1.0 : 0.0);
             mv += lij * t[j];
             lx += lij * xi[j];
         }
-        out[i] = psi[i] + 0.5 * eps * mv + se * lx;
+        psi[i] = psi_i + 0.5 * eps * mv + sqrt(eps) * lx;
     }
-    for (int i = 0; i < P; ++i) psi[i] = out[i];
 }
 
 // ---------------------------------------------------------------------------------------

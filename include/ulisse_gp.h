@@ -384,8 +384,10 @@ gp_status precond_warm_start(gp_handle* h, const float* U, int64_t ldu, int32_t 
  * The first step runs eagerly (sizing every workspace and, with autotune, timing the
  * product shapes); later steps replay graphs captured once: set-up (probes, right-hand
  * sides, initial residuals), a chunk of iters_per_graph solver iterations for every chain
- * (replayed until no system of any chain is running; the device count is read back after
- * each chunk), then the gradient reduction and the SGLD update of every chain.  The chains
+ * (replayed until no system of any chain is running: as many replays as the last step of
+ * the same kind needed are queued at once, each followed by a device count of the running
+ * systems, so the host usually waits once per step), then the gradient reduction and the
+ * SGLD update of every chain.  The chains
  * are spread over `streams` side streams, so the small ones run alongside the large ones.
  * The step index and step size are read by the kernels from device memory, so the graphs
  * never change.
@@ -425,7 +427,8 @@ typedef struct gp_batch gp_batch;
 typedef struct {
     int64_t eager_steps;       /* steps run without graphs                              */
     int64_t graph_steps;       /* steps run by graph replays                            */
-    int64_t iteration_graphs;  /* replays of the solver-iteration graph                 */
+    int64_t iteration_graphs;  /* replays of the solver-iteration graph (queued ones    */
+                               /* that found every system stopped included)             */
     int64_t captures;          /* graphs captured                                       */
 } gp_batch_stats;
 

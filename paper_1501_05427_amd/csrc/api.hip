@@ -1568,8 +1568,10 @@ struct gp_batch {
     hipEvent_t fork_ev = nullptr;
     uint64_t* dyn = nullptr;        // device: step, probe step, eps (as bits)
     uint64_t* dyn_host = nullptr;   // pinned host copy
-    int* active = nullptr;          // device: running systems over all chains
-    int* active_host = nullptr;     // pinned
+    int max_chunks = 2;             // replays of the iteration graph a step may take
+    int* active = nullptr;          // device: running systems over all chains, per replay
+    int* active_host = nullptr;     // pinned copy
+    int pred[2] = {1, 1};           // replays the last step needed: [0] probes kept, [1] redrawn
     const int** counts = nullptr;   // device array of the chains' running-system counters
     hipGraphExec_t pre[2] = {nullptr, nullptr};  // [0] probes kept, [1] probes redrawn
     hipGraphExec_t iter = nullptr, post = nullptr;
@@ -1737,11 +1739,12 @@ gp_status gp_batch_create(gp_batch** out, int device, uint64_t seed, int32_t B,
         gp_batch_destroy(b);
         return st;
     };
+    b->max_chunks = params->max_iter / iters_per_graph + 2;
     if (hipMalloc((void**)&b->dyn, 3 * sizeof(uint64_t)) != hipSuccess ||
-        hipMalloc((void**)&b->active, sizeof(int)) != hipSuccess ||
+        hipMalloc((void**)&b->active, (size_t)b->max_chunks * sizeof(int)) != hipSuccess ||
         hipMalloc((void**)&b->counts, (size_t)B * sizeof(int*)) != hipSuccess ||
         hipHostMalloc((void**)&b->dyn_host, 3 * sizeof(uint64_t), hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void**)&b->active_host, sizeof(int), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&b->active_host, (size_t)b->max_chunks * sizeof(int), hipHostMallocDefault) != hipSuccess ||
         hipStreamCreate(&b->cap) != hipSuccess || hipEventCreateWithFlags(&b->fork_ev, hipEventDisableTiming) != hipSuccess) {
         (void)hipGetLastError();
         return bail(fail(GP_ENOMEM, "batch set-up failed"));
@@ -1823,15 +1826,29 @@ gp_status gp_batch_step(gp_batch* b, uint64_t t, double eps_t, void* stream) {
         }));
     }
     GP_HIP(hipGraphLaunch(pre, s));
-    const int max_chunks = b->params.max_iter / b->iters + 2;
-    for (int c = 0; c < max_chunks; ++c) {
-        GP_HIP(hipGraphLaunch(b->iter, s));
-        GP_HIP(launch_sum_active(b->counts, b->B, b->active, s));
-        GP_HIP(hipMemcpyAsync(b->active_host, b->active, sizeof(int), hipMemcpyDeviceToHost, s));
+    // Replays of the iteration graph, each followed by the count of systems still running:
+    // as many as the last step of the same kind needed are queued back to back, then the
+    // host waits once; while some system still runs it goes on one replay at a time.  A
+    // replay after every system has stopped changes nothing (each of its kernels returns on
+    // the chain's zero count, as they do for a chain that stopped before the others), so
+    // one queued too many costs only its launches.
+    int& pred = b->pred[redraw ? 1 : 0];
+    int c = 0, seen = 0, needed = 0;
+    for (;;) {
+        const int target = c == 0 ? std::min(std::max(pred, 1), b->max_chunks) : c + 1;
+        for (; c < target; ++c) {
+            GP_HIP(hipGraphLaunch(b->iter, s));
+            GP_HIP(launch_sum_active(b->counts, b->B, b->active + c, s));
+            b->st.iteration_graphs += 1;
+        }
+        GP_HIP(hipMemcpyAsync(b->active_host + seen, b->active + seen, (size_t)(c - seen) * sizeof(int),
+                              hipMemcpyDeviceToHost, s));
         GP_HIP(hipStreamSynchronize(s));
-        b->st.iteration_graphs += 1;
-        if (*b->active_host == 0) break;
+        for (; seen < c; ++seen)
+            if (needed == 0 && b->active_host[seen] == 0) needed = seen + 1;
+        if (needed != 0 || c >= b->max_chunks) break;
     }
+    pred = needed != 0 ? needed : c;
     GP_HIP(hipGraphLaunch(b->post, s));
     GP_HIP(hipStreamSynchronize(s));
     b->st.graph_steps += 1;

@@ -1,7 +1,7 @@
 """Chain diagnostics and the SGLD preconditioner of the paper's experiments, FP64 (oracle).
 
 * psrf: the potential scale reduction factor of Gelman & Rubin (1992), used in Sec. 5 to
-  judge convergence of parallel SGLD chains.  For m chains of length T and one parameter,
+  assess convergence of parallel SGLD chains.  For m chains of length T and one parameter,
   W is the mean within-chain variance and B / T the variance of the chain means;
   V = (T - 1) / T W + (1 + 1 / m) B / T and PSRF = sqrt(V / W).
 * ess: effective sample size T / tau with tau = 1 + 2 sum_k rho_k, the autocorrelations

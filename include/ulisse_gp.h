@@ -158,13 +158,19 @@ typedef struct {
     int32_t J_b;     /* last kept tail index of track b                                     */
     int32_t iters;   /* products K d taken (excluding the warm-start residual)              */
     double final_res;/* ||e|| of Alg. 1's recursive residual at the last iteration         */
-    uint32_t flags;  /* ULISSE_NOTCONV | ULISSE_BREAKDOWN | ULISSE_FALLBACK                 */
+    uint32_t flags;  /* ULISSE_NOTCONV | ULISSE_BREAKDOWN | ULISSE_FALLBACK | ULISSE_FP32_RERUN */
     uint32_t pad;
 } ulisse_sysstat;
 
 #define ULISSE_NOTCONV 1u    /* max_iter reached before the series ended (biased estimate) */
 #define ULISSE_BREAKDOWN 2u  /* d^T K d <= 0 or a non-finite scalar; the system stopped    */
 #define ULISSE_FALLBACK 4u   /* the preconditioner was unusable: the plain solver ran       */
+/* A solve in a BF16 mode in which some system broke down was run again in FP32, every
+ * system of it, with the same draws (ulisse_solve*, gp_stoch_grad*, not the batched
+ * path): rounded to BF16, K can lose its positive definiteness where its smallest
+ * eigenvalue is below the rounding error (GP_BF16_SPLIT_V: 2^-9 of each entry).  The
+ * outcome, flags aside, is that of the same call in GP_FP32 with refresh = 0.          */
+#define ULISSE_FP32_RERUN 8u
 
 /*
  * Unbiased solves K s = b_c for the m columns of B (n x m FP32, ldb >= n) by the ULISSE
@@ -387,7 +393,11 @@ gp_status precond_warm_start(gp_handle* h, const float* U, int64_t ldu, int32_t 
  * (replayed until no system of any chain is running: as many replays as the last step of
  * the same kind needed are queued at once, each followed by a device count of the running
  * systems, so the host usually waits once per step), then the gradient reduction and the
- * SGLD update of every chain.  The chains
+ * SGLD update of every chain.  In the BF16 modes a chain whose solve broke down is then
+ * taken back to where its step began and its step redone outside the graphs in FP32 with
+ * the same draws, as gp_stoch_grad does (ULISSE_FP32_RERUN), so a batch still reproduces
+ * the unbatched calls; each chain's psi and warm starts are copied at the start of every
+ * step for that.  The chains
  * are spread over `streams` side streams, so the small ones run alongside the large ones.
  * The step index and step size are read by the kernels from device memory, so the graphs
  * never change.
@@ -430,6 +440,7 @@ typedef struct {
     int64_t iteration_graphs;  /* replays of the solver-iteration graph (queued ones    */
                                /* that found every system stopped included)             */
     int64_t captures;          /* graphs captured                                       */
+    int64_t fp32_reruns;       /* chain steps redone in FP32 after a BF16 breakdown     */
 } gp_batch_stats;
 
 gp_status gp_batch_create(gp_batch** b, int device, uint64_t seed, int32_t B,

@@ -21,7 +21,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "ulisse_gp.h")
 
 GP_OK, GP_EINVAL, GP_ENOMEM, GP_EDEVICE, GP_EUNSUPPORTED = 0, -1, -2, -3, -4
 GP_FP32, GP_BF16_SPLIT_V, GP_BF16_SPLIT_KV = 0, 1, 2
-ULISSE_NOTCONV, ULISSE_BREAKDOWN, ULISSE_FALLBACK = 1, 2, 4
+ULISSE_NOTCONV, ULISSE_BREAKDOWN, ULISSE_FALLBACK, ULISSE_FP32_RERUN = 1, 2, 4, 8
 PROBE_GAUSSIAN, PROBE_RADEMACHER = 0, 1
 
 
@@ -80,7 +80,7 @@ class gp_batch_problem(Structure):
 
 class gp_batch_stats(Structure):
     _fields_ = [("eager_steps", c_int64), ("graph_steps", c_int64), ("iteration_graphs", c_int64),
-                ("captures", c_int64)]
+                ("captures", c_int64), ("fp32_reruns", c_int64)]
 
 
 SYSSTAT_BYTES = ctypes.sizeof(ulisse_sysstat)

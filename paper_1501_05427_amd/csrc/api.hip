@@ -50,7 +50,7 @@ enum Slot {
     kSlotRatio, kSlotRunStats, kSlotZp, kSlotUtv, kSlotHW, kSlotP3, kSlotY0, kSlotY1,
     kSlotY2, kSlotGram, kSlotGpart2, kSlotSmall, kSlotMlp, kSlotIcgB, kSlotIcgZ, kSlotIcgSt,
     kSlotIcgKP, kSlotTuneV, kSlotTunePart, kSlotTuneVH, kSlotTuneVL, kSlotAH, kSlotAL, kSlotBH,
-    kSlotBL, kSlotRD, kSlotRPart, kSlotRFlag, kSlotProbe, kNumSlots
+    kSlotBL, kSlotRD, kSlotRPart, kSlotRFlag, kSlotProbe, kSlotBroken, kNumSlots
 };
 // Solves nest one level (the inner CG of the shifted preconditioner): the inner solve's
 // buffers live in a second set of slots, offset by kNumSlots.
@@ -541,6 +541,18 @@ struct Solve {
         return GP_OK;
     }
 
+    // After run(): the number of systems that broke down (synchronises the stream).
+    gp_status broken_count(int* out) {
+        int* cnt;
+        GP_TRY(ws(h, kSlotBroken + so, 1, &cnt));
+        GP_HIP(launch_count_flag(a.stats, m, ULISSE_BREAKDOWN, cnt, s));
+        int* pinned = h->pinned + 2 * level;
+        GP_HIP(hipMemcpyAsync(pinned, cnt, sizeof(int), hipMemcpyDeviceToHost, s));
+        GP_HIP(hipStreamSynchronize(s));
+        *out = *pinned;
+        return GP_OK;
+    }
+
     gp_status end(double* S_cg) {
         if (level == 0) h->solves += 1;
         if (S_cg != nullptr) GP_HIP(solver_copy_s(a, S_cg, s));
@@ -574,18 +586,35 @@ gp_status solve_core(gp_handle* h, int64_t n, int d, const float* Z, const KPara
                      hipStream_t s, const gp_precond* pc = nullptr,
                      const gp_shift_precond* sp = nullptr) {
     Solve sv;
-    sv.h = h;
-    sv.n = n;
-    sv.d = d;
-    sv.m = m;
-    sv.Z = Z;
-    sv.kp = kp;
-    sv.p = p;
-    sv.pc = pc;
-    sv.sp = sp;
-    sv.s = s;
-    GP_TRY(sv.begin(B, ldb, S0, St, stats));
-    GP_TRY(sv.run());
+    auto solve = [&](const ulisse_params& pr) -> gp_status {
+        sv = Solve{};
+        sv.h = h;
+        sv.n = n;
+        sv.d = d;
+        sv.m = m;
+        sv.Z = Z;
+        sv.kp = kp;
+        sv.p = pr;
+        sv.pc = pc;
+        sv.sp = sp;
+        sv.s = s;
+        GP_TRY(sv.begin(B, ldb, S0, St, stats));
+        return sv.run();
+    };
+    GP_TRY(solve(p));
+    if (sv.b16) {
+        // BF16 rounding can leave K indefinite (CG breaks down): the whole solve again in
+        // FP32 from the same warm starts with the same draws
+        int broken = 0;
+        GP_TRY(sv.broken_count(&broken));
+        if (broken > 0) {
+            ulisse_params p32 = p;
+            p32.prec = GP_FP32;
+            p32.refresh = 0;
+            GP_TRY(solve(p32));
+            GP_HIP(launch_or_flag(sv.a.stats, m, ULISSE_FP32_RERUN, s));
+        }
+    }
     return sv.end(S_cg);
 }
 
@@ -1004,6 +1033,19 @@ gp_status grad_entry(gp_handle* h, gp_data X, const double* psi, const float* y,
     gr.s = (hipStream_t)stream;
     GP_TRY(gr.begin(pc, sp));
     GP_TRY(gr.sv.run());
+    if (gr.sv.b16) {
+        // as in solve_core: a breakdown under BF16 products reruns the solve in FP32 (same
+        // probes, warm starts and draws); the gradient reduction then runs in FP32 too
+        int broken = 0;
+        GP_TRY(gr.sv.broken_count(&broken));
+        if (broken > 0) {
+            gr.p.prec = GP_FP32;
+            gr.p.refresh = 0;
+            GP_TRY(gr.begin(pc, sp));
+            GP_TRY(gr.sv.run());
+            GP_HIP(launch_or_flag(gr.sv.a.stats, gr.sv.m, ULISSE_FP32_RERUN, gr.s));
+        }
+    }
     return gr.end();
 }
 
@@ -1572,6 +1614,12 @@ struct gp_batch {
     int* active = nullptr;          // device: running systems over all chains, per replay
     int* active_host = nullptr;     // pinned copy
     int pred[2] = {1, 1};           // replays the last step needed: [0] probes kept, [1] redrawn
+    // BF16 products: a chain whose solve broke down is redone in FP32 after the step
+    bool rerun = false;
+    std::vector<double*> bak;       // per chain, device: psi then S_warm as the step began
+    int* brk = nullptr;             // device: broken-down systems per chain
+    int* brk_host = nullptr;        // pinned copy
+    gp_handle* rh = nullptr;        // handle of the reruns (own workspace, seed set per chain)
     const int** counts = nullptr;   // device array of the chains' running-system counters
     hipGraphExec_t pre[2] = {nullptr, nullptr};  // [0] probes kept, [1] probes redrawn
     hipGraphExec_t iter = nullptr, post = nullptr;
@@ -1594,6 +1642,12 @@ gp_status batch_pre(gp_batch* b, int i, bool redraw) {
         GP_HIP(launch_probes(n, b->nr, b->kind, h->seed, b->params.rng_stream, 0, pr.R, n, s,
                              h->dyn_probe_step));
         GP_HIP(launch_zero(pr.S_warm + n, (size_t)n * b->nr * sizeof(double), s));
+    }
+    if (b->rerun) {
+        // the state a rerun starts from
+        const int P = pr.X.d + 2;
+        GP_HIP(launch_copy_f64(pr.psi, b->bak[i], P, s));
+        GP_HIP(launch_copy_f64(pr.S_warm, b->bak[i] + P, n * (1 + b->nr), s));
     }
     gr = Grad{};
     gr.h = h;
@@ -1625,10 +1679,65 @@ gp_status batch_pre(gp_batch* b, int i, bool redraw) {
 gp_status batch_post(gp_batch* b, int i) {
     const gp_batch_problem& pr = b->probs[i];
     gp_handle* h = b->hs[i];
+    if (b->rerun) {
+        const Solve& sv = b->grads[i].sv;
+        GP_HIP(launch_count_flag(sv.a.stats, sv.m, ULISSE_BREAKDOWN, b->brk + i, chain_stream(b, i)));
+    }
     GP_TRY(b->grads[i].end());
     GP_HIP(launch_sgld(pr.X.d + 2, pr.psi, pr.g, pr.prior.kind, pr.prior.a, pr.prior.b, pr.M_chol,
                        0.0, h->seed, b->params.rng_stream, 0, chain_stream(b, i), h->dyn_step,
                        reinterpret_cast<const double*>(h->dyn_eps)));
+    return GP_OK;
+}
+
+// Chain i's step again in FP32, from the psi and warm starts it began with and with the
+// same probes and draws (the unbatched gp_stoch_grad + sgld_step after a BF16 breakdown).
+gp_status batch_rerun(gp_batch* b, int i, uint64_t t, double eps_t, hipStream_t s) {
+    const gp_batch_problem& pr = b->probs[i];
+    const int P = pr.X.d + 2;
+    const int64_t n = pr.X.n;
+    GP_HIP(launch_copy_f64(b->bak[i], pr.psi, P, s));
+    GP_HIP(launch_copy_f64(b->bak[i] + P, pr.S_warm, n * (1 + b->nr), s));
+    gp_handle* h = b->rh;
+    h->seed = b->hs[i]->seed;
+    Grad gr;
+    gr.h = h;
+    gr.X = pr.X;
+    gr.psi = pr.psi;
+    gr.y = pr.y;
+    gr.R = pr.R;
+    gr.nr = b->nr;
+    gr.kind = b->kind;
+    gr.p = b->params;
+    gr.p.prec = GP_FP32;
+    gr.p.refresh = 0;
+    gr.p.rng_counter = t;
+    gr.S_warm = pr.S_warm;
+    gr.g = pr.g;
+    gr.stats = pr.stats;
+    gr.s = s;
+    GP_TRY(gr.begin(pr.mlp != nullptr ? &b->pcs[i] : nullptr, nullptr));
+    GP_TRY(gr.sv.run());
+    GP_HIP(launch_or_flag(gr.sv.a.stats, gr.sv.m, ULISSE_FP32_RERUN, s));
+    GP_TRY(gr.end());
+    GP_HIP(launch_sgld(P, pr.psi, pr.g, pr.prior.kind, pr.prior.a, pr.prior.b, pr.M_chol, eps_t,
+                       h->seed, b->params.rng_stream, t, s));
+    b->st.fp32_reruns += 1;
+    return GP_OK;
+}
+
+// After a step (complete on s): the chains whose BF16 solve broke down, redone.
+gp_status batch_reruns(gp_batch* b, uint64_t t, double eps_t, hipStream_t s) {
+    if (!b->rerun) return GP_OK;
+    GP_HIP(hipMemcpyAsync(b->brk_host, b->brk, (size_t)b->B * sizeof(int), hipMemcpyDeviceToHost, s));
+    GP_HIP(hipStreamSynchronize(s));
+    bool any = false;
+    for (int i = 0; i < b->B; ++i)
+        if (b->brk_host[i] > 0) {
+            GP_TRY(batch_rerun(b, i, t, eps_t, s));
+            any = true;
+        }
+    if (any) GP_HIP(hipStreamSynchronize(s));
     return GP_OK;
 }
 
@@ -1686,6 +1795,11 @@ void gp_batch_destroy(gp_batch* b) {
     if (b->counts) (void)hipFree(b->counts);
     if (b->dyn_host) (void)hipHostFree(b->dyn_host);
     if (b->active_host) (void)hipHostFree(b->active_host);
+    for (double* p : b->bak)
+        if (p) (void)hipFree(p);
+    if (b->brk) (void)hipFree(b->brk);
+    if (b->brk_host) (void)hipHostFree(b->brk_host);
+    if (b->rh) gp_destroy(b->rh);
     for (gp_handle* h : b->hs) gp_destroy(h);
     delete b;
 }
@@ -1771,6 +1885,24 @@ gp_status gp_batch_create(gp_batch** out, int device, uint64_t seed, int32_t B,
         h->dyn_eps = reinterpret_cast<const double*>(b->dyn + 2);
         b->hs.push_back(h);
     }
+    b->rerun = params->prec != GP_FP32;
+    if (b->rerun) {
+        if (hipMalloc((void**)&b->brk, (size_t)B * sizeof(int)) != hipSuccess ||
+            hipHostMalloc((void**)&b->brk_host, (size_t)B * sizeof(int), hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            return bail(fail(GP_ENOMEM, "batch set-up failed"));
+        }
+        b->bak.assign(B, nullptr);
+        for (int i = 0; i < B; ++i) {
+            const size_t cnt = (size_t)(problems[i].X.d + 2) + (size_t)problems[i].X.n * (1 + n_probes);
+            if (hipMalloc((void**)&b->bak[i], cnt * sizeof(double)) != hipSuccess) {
+                (void)hipGetLastError();
+                return bail(fail(GP_ENOMEM, "batch set-up failed (state copies)"));
+            }
+        }
+        const gp_status st = gp_create(&b->rh, device, 0);
+        if (st != GP_OK) return bail(st);
+    }
     *out = b;
     return GP_OK;
 }
@@ -1795,6 +1927,7 @@ gp_status gp_batch_step(gp_batch* b, uint64_t t, double eps_t, void* stream) {
         for (int i = 0; i < b->B; ++i) GP_TRY(batch_post(b, i));
         GP_TRY(join(b, s));
         GP_HIP(hipStreamSynchronize(s));
+        GP_TRY(batch_reruns(b, t, eps_t, s));
         std::vector<const int*> cnt(b->B);
         for (int i = 0; i < b->B; ++i) cnt[i] = b->grads[i].sv.a.n_active;
         GP_HIP(hipMemcpy(b->counts, cnt.data(), (size_t)b->B * sizeof(int*), hipMemcpyHostToDevice));
@@ -1851,6 +1984,7 @@ gp_status gp_batch_step(gp_batch* b, uint64_t t, double eps_t, void* stream) {
     pred = needed != 0 ? needed : c;
     GP_HIP(hipGraphLaunch(b->post, s));
     GP_HIP(hipStreamSynchronize(s));
+    GP_TRY(batch_reruns(b, t, eps_t, s));
     b->st.graph_steps += 1;
     return GP_OK;
 }

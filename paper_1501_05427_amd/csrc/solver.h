@@ -124,6 +124,11 @@ hipError_t launch_sgld(int P, double* psi, const double* g, int prior_kind, cons
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 // out = sum of *counts[b], b < B (counts: device array of B device pointers).
 hipError_t launch_sum_active(const int* const* counts, int B, int* out, hipStream_t s);
+// *out = number of the m systems whose statistics carry `flag`; or `flag` into all of them.
+hipError_t launch_count_flag(const ulisse_sysstat* st, int m, uint32_t flag, int* out, hipStream_t s);
+hipError_t launch_or_flag(ulisse_sysstat* st, int m, uint32_t flag, hipStream_t s);
+// dst[e] = src[e], e < count (a kernel, so that graphs record no copy node).
+hipError_t launch_copy_f64(const double* src, double* dst, int64_t count, hipStream_t s);
 
 // z = P^-1 e for every active system and the partials of e^T z; `first` also sets d = z.
 int pc_chunks(int64_t n);

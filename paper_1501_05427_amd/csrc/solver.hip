@@ -701,6 +701,41 @@ hipError_t launch_langevin_ratio(const double* G, int batch, int P, const double
 
 namespace gpk {
 
+__global__ void copy_f64_kernel(const double* __restrict__ src, double* __restrict__ dst, int64_t count) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+         e += (int64_t)gridDim.x * blockDim.x)
+        dst[e] = src[e];
+}
+
+hipError_t launch_copy_f64(const double* src, double* dst, int64_t count, hipStream_t s) {
+    if (count == 0) return hipSuccess;
+    copy_f64_kernel<<<grid_of(count), kWG, 0, s>>>(src, dst, count);
+    return hipGetLastError();
+}
+
+// Systems whose statistics carry `flag` (one wave), and the flag ORed into every system's.
+__global__ void count_flag_kernel(const ulisse_sysstat* __restrict__ st, int m, uint32_t flag,
+                                  int* __restrict__ out) {
+    int t = 0;
+    for (int c = threadIdx.x; c < m; c += 64) t += (st[c].flags & flag) != 0u;
+    for (int o = 32; o >= 1; o >>= 1) t += __shfl_xor(t, o);
+    if (threadIdx.x == 0) *out = t;
+}
+
+__global__ void or_flag_kernel(ulisse_sysstat* __restrict__ st, int m, uint32_t flag) {
+    for (int c = threadIdx.x; c < m; c += 64) st[c].flags |= flag;
+}
+
+hipError_t launch_count_flag(const ulisse_sysstat* st, int m, uint32_t flag, int* out, hipStream_t s) {
+    count_flag_kernel<<<1, 64, 0, s>>>(st, m, flag, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_or_flag(ulisse_sysstat* st, int m, uint32_t flag, hipStream_t s) {
+    or_flag_kernel<<<1, 64, 0, s>>>(st, m, flag);
+    return hipGetLastError();
+}
+
 // Zero fill by a kernel (a memset node recorded into a captured graph is avoided).
 __global__ void zero_kernel(uint32_t* __restrict__ p, int64_t words) {
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < words;

@@ -56,6 +56,21 @@ def test_struct_layouts_match_the_header(tmp_path):
             assert int(out[f"{cname}.{fname}"]) == getattr(cls, fname).offset, (cname, fname)
 
 
+def test_constants_match_the_header():
+    # the statistics flags, precision codes and status codes the binding uses, against the
+    # header's #defines and enumerators
+    import re
+    text = open(binding.HEADER).read()
+    defines = {k: int(v) for k, v in re.findall(r"#define\s+(ULISSE_\w+)\s+(\d+)u", text)}
+    assert defines == {"ULISSE_NOTCONV": 1, "ULISSE_BREAKDOWN": 2, "ULISSE_FALLBACK": 4, "ULISSE_FP32_RERUN": 8}
+    for k, v in defines.items():
+        assert getattr(binding, k) == v, k
+    for k in ("GP_FP32", "GP_BF16_SPLIT_V", "GP_BF16_SPLIT_KV", "GP_OK", "GP_EINVAL", "GP_ENOMEM",
+              "GP_EDEVICE", "GP_EUNSUPPORTED"):
+        m = re.search(rf"\b{k}\s*=\s*(-?\d+)", text)
+        assert m is not None and int(m.group(1)) == getattr(binding, k), k
+
+
 def test_validation_is_synchronous_and_host_side(lib):
     # bad sizes are rejected before any device work: the null handle is caught first
     st = lib.gp_kmv(None, binding.gp_data(0, 0, 0, 0), None, None, 0, 0, None, 0, 0, None)

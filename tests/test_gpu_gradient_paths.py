@@ -395,3 +395,76 @@ def test_bf16_gradient_bias_on_subsample_4096(h, prec, capsys):
 def colwise_rel(out, ref):
     out = np.asarray(out, dtype=np.float64)
     return np.linalg.norm(out - ref, axis=0) / np.maximum(np.linalg.norm(ref, axis=0), 1e-300)
+
+
+# ---------------------------------------------------------------------------------------
+# BF16 breakdown -> FP32 rerun
+# ---------------------------------------------------------------------------------------
+def _breakdown_case():
+    # two input dimensions, 2048 random features: K is so ill-conditioned that its BF16
+    # rounding (V split, K whole: 2^-9 of each entry) is indefinite for some probe systems
+    w = workloads.rff_gp(n=2980, d=2, seed=1266371723, n_features=2048)
+    return dev(w["X"]), dev(w["y"]), dev(w["psi"])
+
+
+def _no_rerun(stats):
+    return [dict(s, flags=s["flags"] & ~pb.ULISSE_FP32_RERUN) for s in stats]
+
+
+def test_bf16_breakdown_reruns_gradient_in_fp32(h):
+    X, y, psi = _breakdown_case()
+    n, nr = X.shape[0], 16
+    R = pb.gp_draw_probes(h, n, nr, pb.PROBE_GAUSSIAN, 1, 0)
+    out = {}
+    for name, prec, refresh in (("v", pb.GP_BF16_SPLIT_V, 3), ("fp32", pb.GP_FP32, 0)):
+        params = pb.make_params(q=1.0, rate=1.0, eps=1e-6, eps_relative=1, max_iter=1000, rng_stream=1,
+                                prec=prec, refresh=refresh)
+        S_warm = torch.zeros((1 + nr, n), dtype=torch.float64, device="cuda").t()
+        g, st = pb.gp_stoch_grad(h, X, psi, y, params, R=R, S_warm=S_warm)
+        torch.cuda.synchronize()
+        out[name] = (g.cpu().numpy(), pb.decode_stats(st), S_warm.cpu().numpy())
+    gv, sv, wv = out["v"]
+    g32, s32, w32 = out["fp32"]
+    # the flag is set only when some BF16 system broke down; the FP32 run has no breakdown
+    assert all(s["flags"] & pb.ULISSE_FP32_RERUN for s in sv), sv
+    assert not any(s["flags"] & pb.ULISSE_BREAKDOWN for s in s32), s32
+    assert _no_rerun(sv) == s32
+    np.testing.assert_array_equal(gv, g32)
+    np.testing.assert_array_equal(wv, w32)
+    assert np.all(np.isfinite(gv))
+
+
+def test_bf16_breakdown_reruns_solve_in_fp32(h):
+    X, _, psi = _breakdown_case()
+    n, m = X.shape[0], 16
+    B = pb.gp_draw_probes(h, n, m, pb.PROBE_GAUSSIAN, 1, 0)
+    out = {}
+    for name, prec, refresh in (("v", pb.GP_BF16_SPLIT_V, 3), ("fp32", pb.GP_FP32, 0)):
+        params = pb.make_params(q=1.0, rate=1.0, eps=1e-6, eps_relative=1, max_iter=1000, rng_stream=1,
+                                prec=prec, refresh=refresh)
+        S_cg = torch.zeros((m, n), dtype=torch.float64, device="cuda").t()
+        S, st = pb.ulisse_solve(h, X, psi, B, params, S_cg=S_cg)
+        torch.cuda.synchronize()
+        out[name] = (S.cpu().numpy(), pb.decode_stats(st), S_cg.cpu().numpy())
+    Sv, sv, cv = out["v"]
+    S32, s32, c32 = out["fp32"]
+    assert all(s["flags"] & pb.ULISSE_FP32_RERUN for s in sv), sv
+    assert _no_rerun(sv) == s32
+    np.testing.assert_array_equal(Sv, S32)
+    np.testing.assert_array_equal(cv, c32)
+
+
+def test_bf16_without_breakdown_does_not_rerun(h):
+    # a well-conditioned system in split V: no breakdown, no rerun, a BF16 result
+    X, psi = problem(3000, 8, seed=41)
+    n, m = X.shape[0], 16
+    Xd, psid = dev(X), dev(psi)
+    B = pb.gp_draw_probes(h, n, m, pb.PROBE_GAUSSIAN, 1, 0)
+    params = pb.make_params(q=1.0, rate=1.0, eps=1e-6, eps_relative=1, max_iter=1000, rng_stream=1,
+                            prec=pb.GP_BF16_SPLIT_V, refresh=3)
+    S, st = pb.ulisse_solve(h, Xd, psid, B, params)
+    params.prec, params.refresh = pb.GP_FP32, 0
+    S32, _ = pb.ulisse_solve(h, Xd, psid, B, params)
+    torch.cuda.synchronize()
+    assert not any(s["flags"] & (pb.ULISSE_FP32_RERUN | pb.ULISSE_BREAKDOWN) for s in pb.decode_stats(st))
+    assert not np.array_equal(S.cpu().numpy(), S32.cpu().numpy())

@@ -890,25 +890,33 @@ def _batch_problems(specs, nr):
     return out
 
 
-@pytest.mark.parametrize("prec,refresh", [(pb.GP_FP32, 0), (pb.GP_BF16_SPLIT_V, 3)])
-def test_batch_reproduces_unbatched_calls(prec, refresh):
+@pytest.mark.parametrize("prec,refresh,ipg,T,period", [(pb.GP_FP32, 0, 4, 5, 2), (pb.GP_BF16_SPLIT_V, 3, 4, 5, 2),
+                                                       (pb.GP_FP32, 0, 2, 8, 3)])
+def test_batch_reproduces_unbatched_calls(prec, refresh, ipg, T, period):
     # each chain of the batch must follow exactly the trajectory of the unbatched calls with
     # the same Philox keys and counters (autotune off: identical product shapes); also with
     # BF16 products and residual replacement, whose decisions are taken on the device inside
-    # the captured iteration graph
+    # the captured iteration graph.  The last case takes two iterations per replay and a
+    # redraw every third step, so the steps need different replay counts and the replays
+    # queued from the previous step of the same kind are sometimes too many, sometimes too few
     specs = [(300, 2), (700, 4), (1500, 8), (2049, 16), (4000, 3)]
-    nr, T, period, eps = 16, 5, 2, 1e-3
+    nr, eps = 16, 1e-3
     probs = _batch_problems(specs, nr)
     params = pb.make_params(q=1.0, rate=1.0, eps=1e-6, eps_relative=1, max_iter=2000, rng_stream=3,
                             prec=prec, refresh=refresh)
     ref = [{k: (v.clone() if torch.is_tensor(v) else v) for k, v in p.items()} for p in probs]
-    batch = pb.Batch(probs, nr, params, seed=900, probe_period=period, iters_per_graph=4,
+    batch = pb.Batch(probs, nr, params, seed=900, probe_period=period, iters_per_graph=ipg,
                      autotune=False, streams=3)
     for t in range(T):
         batch.step(t, eps)
     torch.cuda.synchronize()
     st = batch.stats()
     assert st["eager_steps"] == 1 and st["graph_steps"] == T - 1 and st["captures"] == 4, st
+    assert st["iteration_graphs"] >= T - 1, st
+    if prec != pb.GP_FP32:
+        # the n = 4000, d = 3 chain's split-V solve breaks down (BF16 rounding leaves its K
+        # indefinite): the batch redoes that chain's step in FP32, as the unbatched call does
+        assert st["fp32_reruns"] >= 1, st
     for i, ((n, d), p) in enumerate(zip(specs, ref)):
         hi = pb.Handle(0, seed=900 + i)
         S_warm = torch.zeros((1 + nr, n), dtype=torch.float64, device="cuda").t()

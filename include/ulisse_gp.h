@@ -166,10 +166,12 @@ typedef struct {
 #define ULISSE_BREAKDOWN 2u  /* d^T K d <= 0 or a non-finite scalar; the system stopped    */
 #define ULISSE_FALLBACK 4u   /* the preconditioner was unusable: the plain solver ran       */
 /* A solve in a BF16 mode in which some system broke down was run again in FP32, every
- * system of it, with the same draws (ulisse_solve*, gp_stoch_grad*, not the batched
- * path): rounded to BF16, K can lose its positive definiteness where its smallest
- * eigenvalue is below the rounding error (GP_BF16_SPLIT_V: 2^-9 of each entry).  The
- * outcome, flags aside, is that of the same call in GP_FP32 with refresh = 0.          */
+ * system of it, from the same warm starts with the same draws (ulisse_solve*,
+ * gp_stoch_grad*, and a batch's chains): rounded to BF16, K can lose its positive
+ * definiteness where its smallest eigenvalue is below the rounding error
+ * (GP_BF16_SPLIT_V: 2^-9 of each entry).  The outcome, flags aside, is that of the same
+ * call in GP_FP32 with refresh = 0.  Deciding it reads a count back: these calls then
+ * return with their stream synchronised.                                               */
 #define ULISSE_FP32_RERUN 8u
 
 /*

@@ -1902,6 +1902,7 @@ gp_status gp_batch_create(gp_batch** out, int device, uint64_t seed, int32_t B,
         }
         const gp_status st = gp_create(&b->rh, device, 0);
         if (st != GP_OK) return bail(st);
+        b->rh->autotune = autotune != 0;
     }
     *out = b;
     return GP_OK;

@@ -1176,7 +1176,8 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=20)
     ap.add_argument("--batch-bf16", choices=("kv", "v"), default="kv",
                     help="batched BF16 forms: K and V split (kv, no residual replacement) or V split "
-                         "with residual replacement every 2^refresh (v)")
+                         "with residual replacement every 2^refresh (v; K rounded whole is indefinite "
+                         "for many of these GPs, whose chains are then redone in FP32 step by step)")
     ap.add_argument("--chains", action="store_true",
                     help="the paper's multi-chain protocol with PSRF and ESS (separate report)")
     ap.add_argument("--chain-count", type=int, default=10)

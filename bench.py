@@ -396,6 +396,7 @@ class Chain:
         self.stats = pb.stats_tensor(M)
         self.flagged = torch.zeros((), dtype=torch.int64, device="cuda")
         self.fallbacks = torch.zeros((), dtype=torch.int64, device="cuda")
+        self.reruns = torch.zeros((), dtype=torch.int64, device="cuda")
         self.params = pb.make_params(q=1.0, rate=1.0, eps=1e-6, eps_relative=1, max_iter=1000, rng_stream=1)
         self.coef = torch.zeros(k + 1, dtype=torch.float64, device="cuda")
         self.cvec = torch.zeros(k, dtype=torch.float64, device="cuda")
@@ -450,6 +451,7 @@ class Chain:
                      prior_a=self.prior_a, prior_b=self.prior_b, M_chol=self.M_chol)
         fl = self.stats.view(M, -1)[:, 24:28].view(torch.int32)
         self.flagged.add_(fl.bitwise_and(pb.ULISSE_NOTCONV | pb.ULISSE_BREAKDOWN).ne(0).any().to(torch.int64))
+        self.reruns.add_(fl.bitwise_and(pb.ULISSE_FP32_RERUN).ne(0).any().to(torch.int64))
 
     def timed(self, method, first, count, period, eps_t):
         import torch
@@ -518,11 +520,15 @@ def main_line(args, pb, h, X, y, w, psi0):
 
     def leg(method, period, count):
         restore()
+        ch.reruns.zero_()
         el, pr = ch.timed(method, W_, count, period, eps_t)
-        return {"grad_estimates_per_s": count / el, "steps": count, "probe_period": period,
-                "kmv_passes_per_estimate": pr["kmv_passes"] / count,
-                "kmv_avg_launch_ms": pr["kmv_ms"] / max(1, pr["kmv_launches"]),
-                "dquad_avg_ms": pr["dquad_ms"] / max(1, pr["dquad_launches"])}
+        out = {"grad_estimates_per_s": count / el, "steps": count, "probe_period": period,
+               "kmv_passes_per_estimate": pr["kmv_passes"] / count,
+               "kmv_avg_launch_ms": pr["kmv_ms"] / max(1, pr["kmv_launches"]),
+               "dquad_avg_ms": pr["dquad_ms"] / max(1, pr["dquad_launches"])}
+        if method != "plain_fp32":
+            out["steps_with_fp32_rerun"] = int(ch.reruns.item())  # BF16 solves that broke down
+        return out
 
     # the headline: plain FP32, fresh probes every step
     restore()

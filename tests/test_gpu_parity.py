@@ -955,9 +955,12 @@ def test_autotuned_products_match_oracle():
         assert 1 <= split <= 64
 
 
-def test_batch_learned_bf16_reproduces_unbatched_calls():
-    # chains with their own basis and trained network, BF16 split-K+V products: the batch
-    # evaluates the network at each chain's psi inside its captured set-up graph
+@pytest.mark.parametrize("prec,refresh", [(pb.GP_BF16_SPLIT_KV, 0), (pb.GP_BF16_SPLIT_V, 3)])
+def test_batch_learned_bf16_reproduces_unbatched_calls(prec, refresh):
+    # chains with their own basis and trained network, BF16 products: the batch evaluates
+    # the network at each chain's psi inside its captured set-up graph; with V split, the
+    # preconditioned solves of a chain that breaks down are redone in FP32 over the same
+    # preconditioner
     specs = [(1500, 2), (2500, 4), (3000, 8)]
     nr, T, period, eps, k, H = 16, 4, 2, 1e-3, 16, 64
     probs = _batch_problems(specs, nr)
@@ -977,13 +980,16 @@ def test_batch_learned_bf16_reproduces_unbatched_calls():
                         "coef": torch.zeros(k + 1, dtype=torch.float64, device="cuda")}
     torch.cuda.synchronize()
     params = pb.make_params(q=1.0, rate=1.0, eps=1e-6, eps_relative=1, max_iter=2000, rng_stream=3)
-    params.prec = pb.GP_BF16_SPLIT_KV
+    params.prec, params.refresh = prec, refresh
     psi0 = [p["psi"].clone() for p in probs]
     batch = pb.Batch(probs, nr, params, seed=900, probe_period=period, iters_per_graph=4,
                      autotune=False, streams=2)
     for t in range(T):
         batch.step(t, eps)
     torch.cuda.synchronize()
+    if prec == pb.GP_BF16_SPLIT_V:
+        # some of these preconditioned split-V solves break down (3 chain steps are redone)
+        assert batch.stats()["fp32_reruns"] >= 1
     for i, ((n, d), p) in enumerate(zip(specs, probs)):
         hi = pb.Handle(0, seed=900 + i)
         psi = psi0[i]

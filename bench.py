@@ -944,6 +944,25 @@ def batched_bench(args, pb, n_features=2048, learn_pairs=128, learn_epochs=1000,
     psi0 = [p["psi"].clone() for p in probs]
     out = {"workload": f"batch{B}_rff_n2048-32768_d2-16_m17", "chains": B, "pairs_per_product_sweep": pairs,
            "rff_features": n_features}
+    if args.batch_only_graphs:
+        # the batched FP32 form alone (autotuning off), for a kernel trace of its steps
+        batch = pb.Batch(probs, nr, params, seed=7000, probe_period=PROBE_PERIOD, iters_per_graph=8,
+                         autotune=False, streams=8)
+        for t in range(args.warmup):
+            batch.step(t, eps_t)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for t in range(args.warmup, args.warmup + args.batch_steps):
+            batch.step(t, eps_t)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out["batched_graphs"] = {"grad_estimates_per_s": B * args.batch_steps / el,
+                                 "ms_per_step": 1e3 * el / args.batch_steps, "stats": batch.stats(),
+                                 "first_timed_step": args.warmup, "steps": args.batch_steps}
+        batch.close()
+        if emit:
+            print(json.dumps({"batched": out}), flush=True)
+        return out
     # unbatched: the same chains one after another (own handle per chain, eager calls)
     hs = [pb.Handle(0, seed=7000 + i) for i in range(B)]
     st = []
@@ -1180,6 +1199,8 @@ def main():
                     help="64 chains over 64 GPs: batched graphs vs unbatched calls (separate report)")
     ap.add_argument("--batch-chains", type=int, default=64)
     ap.add_argument("--batch-steps", type=int, default=20)
+    ap.add_argument("--batch-only-graphs", action="store_true",
+                    help="with --batched: time only the batched FP32 form (captured graphs, no autotuning)")
     ap.add_argument("--batch-bf16", choices=("kv", "v"), default="kv",
                     help="batched BF16 forms: K and V split (kv, no residual replacement) or V split "
                          "with residual replacement every 2^refresh (v; K rounded whole is indefinite "

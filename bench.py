@@ -427,6 +427,8 @@ class Chain:
                   stats=self.stats)
         if method in ("plain_fp32", "plain_bf16"):
             pb.gp_stoch_grad(h, self.X, self.psi, self.y, prm, **kw)
+            fl = self.stats.view(M, -1)[:, 24:28].view(torch.int32)
+            self.reruns.add_(fl.bitwise_and(pb.ULISSE_FP32_RERUN).ne(0).any().to(torch.int64))
             return
         L = self.L
         if method.startswith("learned"):
@@ -442,6 +444,7 @@ class Chain:
         pb.gp_stoch_grad_pc(h, self.X, self.psi, self.y, prm, pc, **kw)
         fl = self.stats.view(M, -1)[:, 24:28].view(torch.int32)
         self.fallbacks.add_(fl.bitwise_and(pb.ULISSE_FALLBACK).ne(0).any().to(torch.int64))
+        self.reruns.add_(fl.bitwise_and(pb.ULISSE_FP32_RERUN).ne(0).any().to(torch.int64))
 
     def step(self, method, t, period, first, eps_t):
         import torch
@@ -451,7 +454,6 @@ class Chain:
                      prior_a=self.prior_a, prior_b=self.prior_b, M_chol=self.M_chol)
         fl = self.stats.view(M, -1)[:, 24:28].view(torch.int32)
         self.flagged.add_(fl.bitwise_and(pb.ULISSE_NOTCONV | pb.ULISSE_BREAKDOWN).ne(0).any().to(torch.int64))
-        self.reruns.add_(fl.bitwise_and(pb.ULISSE_FP32_RERUN).ne(0).any().to(torch.int64))
 
     def timed(self, method, first, count, period, eps_t):
         import torch
@@ -674,6 +676,7 @@ def equal_error_leg(args, pb, h, X, y, ch, psi_eval):
             ch.params.q = q
             ch.psi.copy_(psi_eval)
             ch.S_warm.zero_()
+            ch.reruns.zero_()
             errs, el = [], 0.0
             for r in range(args.equal_error_reps + 1):   # r = 0 warms the y system up, untimed
                 torch.cuda.synchronize()
@@ -689,7 +692,8 @@ def equal_error_leg(args, pb, h, X, y, ch, psi_eval):
             rows[method].append({"q": q, "reps": len(errs), "mean_log10_rel_sq_err": float(lg.mean()),
                                  "se": float(lg.std(ddof=1) / np.sqrt(len(lg))),
                                  "grad_estimates_per_s": len(errs) / el,
-                                 "var_normalised_throughput": len(errs) / el / float(np.mean(errs))})
+                                 "var_normalised_throughput": len(errs) / el / float(np.mean(errs)),
+                                 "fp32_reruns": int(ch.reruns.item())})
             say(f"equal error {method} q={q}: {rows[method][-1]['mean_log10_rel_sq_err']:.2f} "
                 f"+- {rows[method][-1]['se']:.2f}, {rows[method][-1]['grad_estimates_per_s']:.2f}/s")
     ch.params.q = q_saved

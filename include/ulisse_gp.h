@@ -399,7 +399,8 @@ gp_status precond_warm_start(gp_handle* h, const float* U, int64_t ldu, int32_t 
  * taken back to where its step began and its step redone outside the graphs in FP32 with
  * the same draws, as gp_stoch_grad does (ULISSE_FP32_RERUN), so a batch still reproduces
  * the unbatched calls; each chain's psi and warm starts are copied at the start of every
- * step for that.  The chains
+ * step for that (in the BF16 modes the batch holds d + 2 + n (1 + n_probes) FP64 values of
+ * device memory per chain for these copies, and a second handle for the reruns).  The chains
  * are spread over `streams` side streams, so the small ones run alongside the large ones.
  * The step index and step size are read by the kernels from device memory, so the graphs
  * never change.

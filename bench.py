@@ -1284,7 +1284,7 @@ def main():
         V = pb.colmajor(N, M)
         V.copy_(torch.from_numpy(workloads.gaussian_matrix(N, M, seed=11)).cuda())
         out = pb.colmajor(N, M)
-        for prec in (pb.GP_FP32, pb.GP_BF16_SPLIT_KV):
+        for prec in (pb.GP_FP32, pb.GP_BF16_SPLIT_KV, pb.GP_BF16_SPLIT_V):
             for _ in range(3):
                 pb.gp_kmv(h, X, psi0, V, out=out, prec=prec)
         # the n = 16384, d = 8 shape with y + 16 probes (one MFMA block, one VALU column)
